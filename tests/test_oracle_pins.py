@@ -1,0 +1,318 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each checks a tabulated value,
+a closed form, an identity of the continuous problem, an exact property of the
+discrete operator, or a brute-force evaluation.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.linalg as sla
+import scipy.special as sp
+
+import synth
+from oracle import basis as ob
+from oracle import hamiltonian as oh
+from oracle import precond as op
+from oracle import transforms as ot
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_basis(**kw):
+    p = dict(R=6.0, tau=5.0, alpha=0.2, ecut=6.0, eta=0.15, n_t1=12, n_t2=16, n_r=32)
+    p.update(kw)
+    return ob.make_basis(**p)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = synth.workload("tiny-helix")
+    b = ob.basis_for(w)
+    atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
+    V = synth.potential_at(b.theta1, b.theta2, b.r, w.tau, w.alpha, atoms)
+    B = ot.basis_matrix(b)
+    return w, b, V, B
+
+
+# ---------------------------------------------------------------- Bessel zeros
+def test_bessel_zeros_match_table():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "bessel_zeros.txt")) if not l.startswith("#")]
+    for p, k, v in rows:
+        z = ob.bessel_zeros(int(p), int(k))[-1]
+        assert abs(z - float(v)) < 1e-12, (p, k, z, v)
+
+
+@pytest.mark.parametrize("p", [0, 1, 7, 31, 64, 130])
+def test_bessel_zeros_are_roots_and_interlace(p):
+    z = ob.bessel_zeros(p, 60)
+    zp = ob.bessel_zeros(p + 1, 60)
+    assert np.all(np.abs(sp.jv(p, z)) < 1e-13)
+    assert np.all(z[:-1] < zp[:-1]) and np.all(zp[:-1] < z[1:])
+    # McMahon: j_{p,k} ~ beta - (4p^2 - 1)/(8 beta), beta = (k + p/2 - 1/4) pi, for k >> p
+    if p <= 7:
+        k = np.arange(40, 61)
+        beta = (k + p / 2 - 0.25) * math.pi
+        mu = 4 * p * p
+        mc = beta - (mu - 1) / (8 * beta) - 4 * (mu - 1) * (7 * mu - 31) / (3 * (8 * beta) ** 3)
+        assert np.max(np.abs(z[k - 1] - mc)) < 1e-6
+
+
+def test_negative_order_zeros_and_signed_radial_function():
+    """xi_{-n,k} equals xi_{n,k} with the paper's signed normalisation."""
+    b = small_basis()
+    r = np.linspace(0.1, b.R, 17)
+    for n in (1, 2, 5):
+        zp = ob.bessel_zeros(n, 4)
+        assert np.all(np.abs(sp.jv(-n, zp)) < 1e-13)
+        np.testing.assert_allclose(b.xi(-n, np.arange(1, 5), r), b.xi(n, np.arange(1, 5), r),
+                                   rtol=1e-13, atol=1e-15)
+
+
+# ----------------------------------------------------------- radial quadrature
+@pytest.mark.parametrize("nr", [8, 48, 160])
+def test_gauss_jacobi_moments(nr):
+    b = small_basis(n_r=nr)
+    assert np.all(b.q > 0) and np.all(b.q < 1)
+    for j in range(0, 2 * nr):
+        exact = 1.0 / (j + 2)
+        assert abs(np.sum(b.wq * b.q ** j) - exact) < 1e-14, j
+
+
+def test_bessel_orthogonality_on_grid_and_by_adaptive_quadrature():
+    """(2 pi tau / N) sum_l omega_l xi_{n,k} xi_{n,k'} = delta_kk' (App. B), and
+    the continuous integral by adaptive quadrature gives the same."""
+    w = synth.workload("tiny-helix")
+    b = ob.basis_for(w)
+    K = 12
+    for n in (0, 3, 6):
+        tab = b.xi(n, np.arange(1, K + 1))
+        gram = 2 * math.pi * b.tau * (tab * b.omega_r[:, None]).T @ tab
+        assert np.max(np.abs(gram - np.eye(K))) < 1e-13
+    # continuous normalisation of one function, independent of the grid
+    n, k = 4, 3
+    bz = ob.bessel_zeros(n, k)[-1]
+    f = lambda r: (b.xi(n, np.array([k]), np.array([r]))[0, 0]) ** 2 * r
+    val, err = si.quad(f, 0.0, b.R, epsabs=1e-14, epsrel=1e-13, limit=200)
+    assert abs(2 * math.pi * b.tau * val - 1.0) < 1e-11
+    assert bz > 0
+
+
+# ---------------------------------------------------------- index set and mask
+def test_index_set_is_exactly_the_cutoff_set():
+    b = small_basis()
+    kap = ob.kinetic_diagonal(b.bzero, b.mnk[:, 0], b.mnk[:, 1], b.R, b.tau, b.alpha, b.eta)
+    assert np.all(kap <= b.ecut)
+    have = set(map(tuple, b.mnk.tolist()))
+    # brute force over a strictly larger box
+    mmax = (b.n_t1 - 1) // 2
+    nmax = (b.n_t2 - 1) // 2
+    count = 0
+    for n in range(-nmax, nmax + 1):
+        z = sp.jn_zeros(abs(n), 40)
+        for m in range(-mmax, mmax + 1):
+            for k in range(1, 41):
+                e = 0.5 * ((z[k - 1] / b.R) ** 2 + (2 * math.pi / b.tau * (m - b.alpha * n - b.eta)) ** 2)
+                inside = e <= b.ecut
+                assert inside == ((m, n, k) in have)
+                count += inside
+    assert count == b.L
+    # paper storage order: m outermost, then n, then k
+    keys = b.mnk[:, 0] * 10 ** 8 + (b.mnk[:, 1] + 10 ** 4) * 10 ** 3 + b.mnk[:, 2]
+    assert np.all(np.diff(keys) > 0)
+
+
+@pytest.mark.parametrize("name,L", [("tiny-helix", 816), ("nanotube-ecut25", 31543)])
+def test_basis_sizes_of_workloads(name, L):
+    b = ob.basis_for(synth.workload(name))
+    assert b.L == L
+
+
+def test_kinetic_diagonal_equals_alg5_form():
+    for eta in (-0.5, -0.2, 0.0, 0.31):
+        b = small_basis(eta=eta, alpha=0.37)
+        m, n = b.mnk[:, 0], b.mnk[:, 1]
+        alg5 = ob.kinetic_alg5(b.bzero, m, n, b.R, b.tau, b.alpha, eta)
+        assert np.max(np.abs(alg5.imag)) < 1e-13
+        np.testing.assert_allclose(alg5.real, b.kappa, rtol=1e-13)
+
+
+def test_kinetic_diagonal_is_eigenvalue_of_cartesian_laplacian():
+    """-1/2 Laplacian (Cartesian, finite differences) of the Bloch wave
+    exp(-i 2 pi eta z / tau) F_{m,n,k} equals kappa times it."""
+    b = small_basis(alpha=0.3, eta=0.2)
+    rng = np.random.default_rng(3)
+    picks = rng.choice(b.L, size=6, replace=False)
+
+    def psi(i, x, y, z):
+        m, n, k = b.mnk[i]
+        r = math.hypot(x, y)
+        th1 = z / b.tau
+        th2 = math.atan2(y, x) / (2 * math.pi) - b.alpha * z / b.tau
+        rad = b.xi(int(n), np.array([k]), np.array([r]))[0, 0]
+        return np.exp(-2j * math.pi * b.eta * th1) * np.exp(2j * math.pi * (m * th1 + n * th2)) * rad
+
+    h = 1e-2
+    c = np.array([-1.0, 16.0, -30.0, 16.0, -1.0]) / (12 * h * h)
+    for i in picks:
+        for _ in range(3):
+            rr = rng.uniform(1.0, b.R - 1.0)
+            ph = rng.uniform(0, 2 * math.pi)
+            x0, y0, z0 = rr * math.cos(ph), rr * math.sin(ph), rng.uniform(0, b.tau)
+            lap = 0.0
+            for e in np.eye(3):
+                vals = [psi(i, x0 + s * h * e[0], y0 + s * h * e[1], z0 + s * h * e[2]) for s in (-2, -1, 0, 1, 2)]
+                lap += np.dot(c, vals)
+            p0 = psi(i, x0, y0, z0)
+            assert abs(-0.5 * lap - b.kappa[i] * p0) < 1e-5 * max(1.0, b.kappa[i]) * max(abs(p0), 1e-2), (i, rr)
+
+
+# ------------------------------------------------------------------ transforms
+def test_fast_equals_naive_transforms(tiny):
+    """The paper's own check: separated sums agree with the naive sums."""
+    w, b, V, B = tiny
+    x = synth.random_block(b.mnk, 3, 11)
+    g1 = ot.inverse_naive(b, x, B)
+    g2 = ot.inverse_separable(b, x)
+    assert np.max(np.abs(g1 - g2)) < 1e-13
+    y1 = ot.forward_naive(b, g1 * V[..., None], B)
+    y2 = ot.forward_separable(b, g1 * V[..., None])
+    assert np.max(np.abs(y1 - y2)) < 1e-13
+
+
+def test_round_trip_and_parseval(tiny):
+    w, b, V, B = tiny
+    x = synth.random_block(b.mnk, 4, 5)
+    g = ot.inverse_separable(b, x)
+    assert np.max(np.abs(ot.forward_separable(b, g) - x)) < 1e-13
+    W = ot.grid_weights(b)
+    for j in range(4):
+        assert abs(np.sum(W * np.abs(g[..., j]) ** 2) - np.vdot(x[:, j], x[:, j]).real) < 1e-13
+
+
+# ------------------------------------------------------------------ Hamiltonian
+def test_dense_modes_agree_and_are_hermitian(tiny):
+    w, b, V, B = tiny
+    HA = oh.dense_explicit(b, V, B)
+    HB = oh.dense_dft(b, V)
+    assert np.max(np.abs(HA - HB)) < 1e-13
+    assert np.max(np.abs(HA - HA.conj().T)) < 1e-14
+    X = synth.random_block(b.mnk, 5, 3)
+    assert np.max(np.abs(oh.apply(b, V, X) - HA @ X)) < 1e-13
+
+
+def test_matrix_free_apply_is_hermitian():
+    b = small_basis()
+    atoms = synth.atoms_for("helix6", 9, b.tau, b.R)
+    V = synth.potential_at(b.theta1, b.theta2, b.r, b.tau, b.alpha, atoms)
+    x = synth.random_block(b.mnk, 1, 1)[:, 0]
+    y = synth.random_block(b.mnk, 1, 2)[:, 0]
+    lhs = np.vdot(y, oh.apply(b, V, x))
+    rhs = np.conj(np.vdot(x, oh.apply(b, V, y)))
+    assert abs(lhs - rhs) < 1e-14
+
+
+def test_free_particle_closed_form():
+    """V = 0: H is the kinetic diagonal, eigenvalues are the sorted kappa."""
+    b = small_basis(alpha=0.41, eta=-0.3)
+    V = np.zeros((b.n_t1, b.n_t2, b.n_r))
+    H = oh.dense_dft(b, V)
+    assert np.max(np.abs(H - np.diag(b.kappa))) == 0.0
+    ev, _ = oh.lowest(oh.dense_explicit(b, V), 10)
+    # closed form from the Laplacian eigenvalues and the Bloch shift
+    lam0 = (b.bzero / b.R) ** 2 + (2 * math.pi / b.tau * (b.mnk[:, 0] - b.alpha * b.mnk[:, 1])) ** 2
+    shifted = 0.5 * lam0 - (2 * math.pi / b.tau) ** 2 * b.eta * (b.mnk[:, 0] - b.alpha * b.mnk[:, 1]) \
+        + 0.5 * (2 * math.pi / b.tau * b.eta) ** 2
+    np.testing.assert_allclose(ev, np.sort(shifted)[:10], rtol=1e-13, atol=1e-14)
+
+
+def test_constant_potential_shifts_spectrum():
+    b = small_basis()
+    V0 = -1.7
+    V = np.full((b.n_t1, b.n_t2, b.n_r), V0)
+    ev, _ = oh.lowest(oh.dense_explicit(b, V), 12)
+    np.testing.assert_allclose(ev, np.sort(b.kappa)[:12] + V0, atol=1e-12)
+
+
+def test_cosine_potential_couples_neighbouring_m_only():
+    """V = V1 cos(2 pi (theta1 - phi0)) couples (m, n, k) to (m +- 1, n, k) with
+    V1/2 exp(-+ i 2 pi phi0); eigenvalues are those of per-(n, k) tridiagonal
+    chains in m (LAPACK stev)."""
+    b = small_basis(n_t1=16)
+    V1, phi0 = 0.8, 0.13
+    V = np.broadcast_to(V1 * np.cos(2 * math.pi * (b.theta1 - phi0))[:, None, None],
+                        (b.n_t1, b.n_t2, b.n_r)).copy()
+    H = oh.dense_explicit(b, V)
+    idx = {tuple(t): i for i, t in enumerate(b.mnk.tolist())}
+    expect = np.diag(b.kappa).astype(np.complex128)
+    for (m, n, k), i in idx.items():
+        j = idx.get((m + 1, n, k))
+        if j is not None:
+            expect[j, i] = 0.5 * V1 * np.exp(-2j * math.pi * phi0)
+            expect[i, j] = np.conj(expect[j, i])
+    assert np.max(np.abs(H - expect)) < 1e-12
+    chains = {}
+    for (m, n, k), i in idx.items():
+        chains.setdefault((n, k), []).append((m, b.kappa[i]))
+    evs = []
+    for key, lst in chains.items():
+        lst.sort()
+        d = np.array([t[1] for t in lst])
+        e = np.full(len(d) - 1, 0.5 * V1)
+        evs.extend(sla.eigh_tridiagonal(d, e, eigvals_only=True, lapack_driver="stev") if len(d) > 1 else d)
+    evs = np.sort(evs)
+    ev, _ = oh.lowest(H, 15)
+    np.testing.assert_allclose(ev, evs[:15], atol=1e-12)
+
+
+def test_grid_shift_invariance():
+    b = small_basis()
+    atoms = synth.atoms_for("helix6", 4, b.tau, b.R)
+    V = synth.potential_at(b.theta1, b.theta2, b.r, b.tau, b.alpha, atoms)
+    ev0, _ = oh.lowest(oh.dense_dft(b, V), 10)
+    ev1, _ = oh.lowest(oh.dense_dft(b, np.roll(V, 5, axis=0)), 10)
+    ev2, _ = oh.lowest(oh.dense_dft(b, np.roll(V, -3, axis=1)), 10)
+    np.testing.assert_allclose(ev1, ev0, atol=1e-12)
+    np.testing.assert_allclose(ev2, ev0, atol=1e-12)
+
+
+def test_time_reversal():
+    """lambda_j(eta) = lambda_j(-eta) at nu = 0 for a real potential (Sec. 3.3)."""
+    bp = small_basis(eta=0.23)
+    bm = small_basis(eta=-0.23)
+    atoms = synth.atoms_for("helix6", 6, bp.tau, bp.R)
+    V = synth.potential_at(bp.theta1, bp.theta2, bp.r, bp.tau, bp.alpha, atoms)
+    assert bp.L == bm.L
+    evp, _ = oh.lowest(oh.dense_dft(bp, V), 10)
+    evm, _ = oh.lowest(oh.dense_dft(bm, V), 10)
+    np.testing.assert_allclose(evp, evm, atol=1e-12)
+
+
+def test_eigenvalues_converge_with_cutoff():
+    """Qualitative check: the lowest eigenvalue decreases towards a limit as the
+    cutoff grows (variational in a nested basis with an exact quadrature)."""
+    vals = []
+    for ecut in (3.0, 5.0, 8.0):
+        b = ob.make_basis(R=6.0, tau=5.0, alpha=0.0, ecut=ecut, n_t1=24, n_t2=24, n_r=64)
+        atoms = synth.atoms_for("helix6", 2, b.tau, b.R)
+        V = synth.potential_at(b.theta1, b.theta2, b.r, b.tau, b.alpha, atoms)
+        vals.append(oh.lowest(oh.dense_dft(b, V), 1)[0][0])
+    assert vals[0] >= vals[1] - 1e-9 >= vals[2] - 2e-9
+
+
+# ------------------------------------------------------------------ preconditioner
+def test_tpa_worked_values():
+    assert op.tpa_factor(0.0) == 1.0
+    assert abs(op.tpa_factor(1.0) - 65.0 / 81.0) < 1e-16
+    g = np.linspace(0, 50, 2001)
+    K = op.tpa_factor(g)
+    assert np.all(np.diff(K) < 0)
+    assert abs(op.tpa_factor(1e6) * 2e6 - 1.0) < 1e-5
+    kappa = np.array([0.5, 2.0, 7.0])
+    r = np.array([0.0, 3.0 + 4.0j, 0.0])
+    w = op.tpa_apply(kappa, r)
+    np.testing.assert_allclose(w, r * 65.0 / 81.0, rtol=1e-15)
+    assert np.all(op.tpa_apply(kappa, np.zeros((3, 2))) == 0)
