@@ -1,0 +1,165 @@
+/*
+ * helic.h -- C ABI of the MI355X helical-wave Hamiltonian library.
+ *
+ * The library applies the discrete Hamiltonian of the helical-wave spectral
+ * method (Agarwal & Banerjee, arXiv 2210.12252) to blocks of coefficient
+ * vectors on one AMD Instinct MI355X (gfx950), and solves for its lowest
+ * eigenpairs.  For a Bloch parameter eta and cyclic index nu = 0 the operator
+ * is (Alg. 5, eqs. Simplify_2 and g_mnk)
+ *
+ *     (H x)_i = kappa_i x_i + [Fwd(V * Inv(x))]_i ,
+ *     kappa_i = 1/2 [ (b_k^{|n|}/R)^2 + (2 pi/tau)^2 (m - alpha n - eta)^2 ],
+ *
+ * with Inv the inverse basis transform (Alg. 1 and 2: radial sums per angular
+ * mode, then a 2D inverse DFT per radius), V the real potential sampled on the
+ * grid and Fwd the quadrature forward transform (Alg. 3 and 4: a 2D DFT per
+ * radius, then weighted radial sums).  Basis functions are
+ * F_{m,n,k} = c_{nk} exp(i 2 pi (m theta1 + n theta2)) J_n(b_k^{|n|} r/R),
+ * c_{nk} = 1/(sqrt(pi tau) R J_{n+1}(b_k^{|n|})) (Sec. 2.3, App. B), kept
+ * when kappa_i <= E_cut (Sec. 3.2).
+ *
+ * Conventions shared by all entry points
+ * - Every pointer argument documented "device" must point to memory of the
+ *   current HIP device; "host" pointers are ordinary CPU memory.
+ * - A coefficient block is column-major: column j (one vector) starts at
+ *   element j*ld, holds L complex values as interleaved (re, im) doubles, rows
+ *   in the library's compact order (helic_basis_indices); ld >= L counts
+ *   complex elements.
+ * - A real-space array is indexed [i1][i2][ir] with ir fastest (theta1
+ *   outermost, then theta2, then r; Sec. 3.1, eq. wavefun_storage_real).
+ * - `stream` is a hipStream_t (0 = the null stream).  Calls on a stream are
+ *   asynchronous unless stated otherwise; the caller keeps buffers alive until
+ *   the stream has passed them.
+ * - Errors: every call returns a helic_status; no exception crosses the ABI.
+ *   HELIC_ERR_INVALID calls write nothing.  helic_last_error() returns the
+ *   calling thread's last message.
+ * - A handle must not be used from two host threads, or on two streams, at
+ *   the same time.
+ */
+#ifndef HELIC_H
+#define HELIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct helic_basis_s* helic_basis;
+
+typedef enum {
+  HELIC_OK = 0,
+  HELIC_ERR_INVALID = 1,      /* bad argument (null pointer, size, range)         */
+  HELIC_ERR_UNSUPPORTED = 2,  /* cyclic order != 1, nu != 0, unknown precision     */
+  HELIC_ERR_GRID = 3,         /* grid too small to resolve the index set           */
+  HELIC_ERR_NOMEM = 4,        /* device or host allocation failed                  */
+  HELIC_ERR_HIP = 5,          /* a HIP runtime or library call failed              */
+  HELIC_ERR_NOCONV = 6,       /* eigensolver stopped at maxit above tolerance      */
+  HELIC_ERR_CUTOFF_TIE = 7,   /* some kinetic energy equals E_cut within 1e-10 Ha  */
+  HELIC_ERR_STATE = 8         /* call out of order (e.g. apply before potential)   */
+} helic_status;
+
+/* Arithmetic of the transform stages of apply_H.  Inputs and outputs stay
+ * complex double in every mode; FP32 runs the radial contractions, the
+ * angular DFTs and the intermediates in single precision with FP32
+ * accumulation. */
+typedef enum { HELIC_FP64 = 0, HELIC_FP32 = 1 } helic_prec;
+
+typedef struct {
+  double R;       /* cylinder radius, Bohr (> 0); Dirichlet wall at r = R        */
+  double tau;     /* axial period of the screw operation, Bohr (> 0)             */
+  double alpha;   /* twist: rotation of 2*pi*alpha per period, 0 <= alpha < 1    */
+  int32_t ncyc;   /* cyclic order; must be 1                                      */
+  double ecut;    /* kinetic-energy cutoff, Ha (> 0), inclusive                  */
+  double eta;     /* helical Bloch parameter, -1/2 <= eta < 1/2                  */
+  int32_t nu;     /* cyclic Bloch index; must be 0                               */
+  int32_t m_max;  /* clamp |m| <= m_max (-1: what the theta1 grid resolves)      */
+  int32_t n_max;  /* clamp |n| <= n_max (-1: what the theta2 grid resolves)      */
+  int32_t k_max;  /* clamp k <= k_max   (-1: none)                               */
+  int32_t n_t1;   /* theta1 (axial) Fourier nodes; 0 with n_t2 = 0: automatic    */
+  int32_t n_t2;   /* theta2 (angular) Fourier nodes                              */
+  int32_t n_r;    /* radial Gauss-Jacobi nodes; 0: 4 * (largest k kept)          */
+} helic_params;
+
+/* Build the basis on the host: Bessel zeros b_k^{|n|} (App. B), the index
+ * set {(m,n,k): kappa <= E_cut} under the clamps (Sec. 3.2), the grid
+ * theta1_i = i/n_t1, theta2_j = j/n_t2 and the n_r-point Gauss-Jacobi rule for
+ * int_0^1 f(q) q dq (Sec. 3.1, App. D), and the radial tables xi_{|n|,k}(r_l)
+ * and (2 pi tau) omega_l xi_{|n|,k}(r_l) (Alg. 1, Alg. 3).  Automatic grids
+ * use the smallest 2,3,5-smooth sizes >= 2 max|m| + 2 and >= 2 max|n| + 2.
+ * Synchronous; allocates no device memory (device tables are uploaded by the
+ * first call that needs them).  *out receives a handle owned by the caller,
+ * released with helic_basis_destroy. */
+helic_status helic_basis_create(const helic_params* p, helic_basis* out);
+helic_status helic_basis_destroy(helic_basis h);
+
+/* Sizes: basis size L, grid sizes, number of angular modes (m, n) kept. Any
+ * output pointer may be NULL.  Host only. */
+helic_status helic_basis_info(helic_basis h, int64_t* L, int32_t* n_t1, int32_t* n_t2,
+                              int32_t* n_r, int32_t* n_modes);
+
+/* Compact row order: mnk (host, L*3 int32) receives (m, n, k) of every row;
+ * kappa (host, L doubles) the kinetic diagonal.  Rows are grouped by |n|
+ * (0, 1, 2, ...), then n = +|n| before -|n|, then m ascending, then k = 1..K.
+ * Either pointer may be NULL. */
+helic_status helic_basis_indices(helic_basis h, int32_t* mnk, double* kappa);
+
+/* Grid (host arrays): theta1 (n_t1), theta2 (n_t2), r (n_r, Bohr) and the
+ * radial weights w_r (n_r; omega_l = R^2 w_l, including the r dr Jacobian).
+ * Any pointer may be NULL. */
+helic_status helic_grid(helic_basis h, double* theta1, double* theta2, double* r, double* w_r);
+
+/* Potential V (device, n_t1*n_t2*n_r doubles, real-space order).  The
+ * library keeps its own re-laid-out copy; V may be freed after the stream
+ * passes this call. */
+helic_status helic_set_potential(helic_basis h, const double* V, void* stream);
+
+/* Y = H X for nvec columns (device blocks, see conventions; X and Y must not
+ * overlap).  Requires a potential.  The first call with a larger nvec than
+ * before grows the library's intermediate buffer (hipMalloc). */
+helic_status helic_apply_H(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                           int32_t nvec, helic_prec prec, void* stream);
+
+/* Inverse basis transform (Alg. 1 and 2) of nvec coefficient columns onto the
+ * grid: g (device) holds nvec consecutive real-space arrays of complex
+ * doubles, n_t1*n_t2*n_r each.  Forward transform (Alg. 3 and 4):
+ * coefficients of nvec such arrays, by quadrature.  FP64. */
+helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx, double* g,
+                                     int32_t nvec, void* stream);
+helic_status helic_transform_forward(helic_basis h, const double* g, double* X, int64_t ldx,
+                                     int32_t nvec, void* stream);
+
+/* Teter-Payne-Allan preconditioner (Sec. 3.5) of nvec residual columns:
+ * W_ij = K(kappa_i / T_j) R_ij, K(g) = (27+18g+12g^2+8g^3) /
+ * (27+18g+12g^2+8g^3+16g^4), T_j = sum_i kappa_i |R_ij|^2 / sum_i |R_ij|^2
+ * (zero columns stay zero).  Device blocks; W may equal R (in place). */
+helic_status helic_precondition(helic_basis h, const double* Rres, int64_t ldr, double* W,
+                                int64_t ldw, int32_t nvec, void* stream);
+
+/* Lowest nev eigenpairs by block LOBPCG (Sec. 3.5) with the preconditioner
+ * above, FP64 Rayleigh-Ritz, H applied in `prec` with a final FP64
+ * refinement when prec != HELIC_FP64.  Converged when every
+ * ||H x - lambda x||_2 <= tol with ||x||_2 = 1.  evals, resid (host, nev):
+ * eigenvalues ascending and residual norms; evecs (device, ld >= L, nev
+ * columns) may be NULL; iters (host) may be NULL.  seed fixes the random
+ * start.  Synchronises `stream` before returning.  Returns HELIC_ERR_NOCONV
+ * (with the best current results written) when maxit is reached. */
+helic_status helic_eigensolve(helic_basis h, int32_t nev, int32_t block, double tol, int32_t maxit,
+                              helic_prec prec, uint64_t seed, double* evals, double* resid,
+                              double* evecs, int64_t ldv, int32_t* iters, void* stream);
+
+/* Host utilities used by the basis set-up, exported for testing.
+ * helic_util_bessel_j: out[i] = J_p(x[i]) for integer p (any sign), x >= 0.
+ * helic_util_bessel_zeros: first `count` positive zeros of J_p.
+ * helic_util_gauss_jacobi: n-point rule for int_0^1 f(q) q dq (nodes q,
+ * weights w, ascending). */
+helic_status helic_util_bessel_j(int32_t p, int32_t n, const double* x, double* out);
+helic_status helic_util_bessel_zeros(int32_t p, int32_t count, double* out);
+helic_status helic_util_gauss_jacobi(int32_t n, double* q, double* w);
+
+const char* helic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELIC_H */

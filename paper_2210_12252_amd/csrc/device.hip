@@ -1,0 +1,591 @@
+// Device side of the helical-wave Hamiltonian library: table upload, the
+// three kernels of H*X (see kernels.hpp), the transforms on their own, the
+// Teter-Payne-Allan preconditioner and their C ABI entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device_state.hpp"
+#include "helic_internal.h"
+#include "kernels.hpp"
+
+namespace helic {
+
+// ============================================================ kernels
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, int nvec,
+                 int ngroups, int n_r, int n_modes, const DGroup* __restrict__ groups,
+                 const int32_t* __restrict__ row_ck, const T* __restrict__ tinv) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Bs = reinterpret_cast<T*>(smem_raw);
+  const int slot = xcd_slot(ngroups * nvec);
+  if (slot >= ngroups * nvec) return;
+  const int gi = slot / nvec, v = slot - gi * nvec;
+  const DGroup gr = groups[gi];
+  const int nks = (gr.Kmax + 3) / 4;
+  const int kpad = 4 * nks;
+  const int ncol = 2 * gr.nmodes;
+  const int nct = (ncol + 15) / 16;
+  const int colpad = 16 * nct;
+  for (int i = threadIdx.x; i < kpad * colpad; i += NT) Bs[i] = (T)0;
+  __syncthreads();
+  const double* xv = X + (int64_t)v * ldx * 2 + gr.row0 * 2;
+  const int nvals = (int)(2 * gr.nrows);
+  for (int i = threadIdx.x; i < nvals; i += NT) {
+    const int ck = row_ck[gr.row0 + (i >> 1)];
+    const int c = ck >> 16, k = ck & 0xffff;
+    Bs[k * colpad + 2 * c + (i & 1)] = (T)xv[i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nrt = (n_r + 15) / 16;
+  const T* tg = tinv + gr.tinv_off;
+  typedef typename Mfma<T>::acc_t acc_t;
+  for (int rt = wave; rt < nrt; rt += NT / 64) {
+    T a[KS_MAX];
+#pragma unroll
+    for (int s = 0; s < KS_MAX; ++s)
+      a[s] = (s < nks) ? tg[((int64_t)rt * nks + s) * 64 + lane] : (T)0;
+    for (int ct = 0; ct < nct; ++ct) {
+      acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS_MAX; ++s) {
+        if (s < nks) {
+          const T b = Bs[(4 * s + (lane >> 4)) * colpad + 16 * ct + (lane & 15)];
+          acc = Mfma<T>::op(a[s], b, acc);
+        }
+      }
+      const int col = 16 * ct + (lane & 15);
+      if (col < ncol) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 16 * rt + Mfma<T>::row(lane, i);
+          if (r < n_r) GH[(((int64_t)v * n_r + r) * n_modes + gr.mode0) * 2 + col] = acc[i];
+        }
+      }
+    }
+  }
+}
+
+// MODE 0: fused inverse -> V -> forward (H*X); 1: inverse only, writes the
+// real-space grid; 2: forward only, reads the real-space grid.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(NT)
+k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __restrict__ grid_out,
+          const T* __restrict__ Vs, int nvec, int n_r, int n_modes,
+          const DMode* __restrict__ modes, const int32_t* __restrict__ rows1, int nrows1,
+          const cplx<T>* __restrict__ tw1g, const cplx<T>* __restrict__ tw2g, FftPlan p1,
+          FftPlan p2, T out_scale) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n1 = p1.n, n2 = p2.n, nn = n1 * n2;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* tw1 = buf + nn;
+  cplx<T>* tw2 = tw1 + n1;
+  int32_t* rws = reinterpret_cast<int32_t*>(tw2 + n2);
+  const int slot = xcd_slot(nvec * n_r);
+  if (slot >= nvec * n_r) return;
+  const int r = slot / nvec, v = slot - r * nvec;
+  for (int i = threadIdx.x; i < n1; i += NT) tw1[i] = tw1g[i];
+  for (int i = threadIdx.x; i < n2; i += NT) tw2[i] = tw2g[i];
+  for (int i = threadIdx.x; i < nrows1; i += NT) rws[i] = rows1[i];
+  cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + ((int64_t)v * n_r + r) * n_modes;
+  if (MODE == 2) {
+    const double* gi = grid_in + (int64_t)v * nn * n_r * 2;
+    for (int i = threadIdx.x; i < nn; i += NT)
+      buf[i] = cplx<T>{(T)gi[((int64_t)i * n_r + r) * 2], (T)gi[((int64_t)i * n_r + r) * 2 + 1]};
+    __syncthreads();
+  } else {
+    for (int i = threadIdx.x; i < nn; i += NT) buf[i] = cplx<T>{(T)0, (T)0};
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_modes; i += NT) buf[modes[i].boff] = slab[i];
+    __syncthreads();
+    // inverse: theta2 lines on the occupied theta1 bins, then all theta1 lines
+    fft_lines<T>(buf, nrows1, rws, n2, 1, p2, tw2, (T)1, nullptr);
+    fft_lines<T>(buf, n2, nullptr, 1, n2, p1, tw1, (T)1, nullptr);
+  }
+  if (MODE == 1) {
+    double* go = grid_out + (int64_t)v * nn * n_r * 2;
+    for (int i = threadIdx.x; i < nn; i += NT) {
+      go[((int64_t)i * n_r + r) * 2] = (double)buf[i].x;
+      go[((int64_t)i * n_r + r) * 2 + 1] = (double)buf[i].y;
+    }
+    return;
+  }
+  // forward: theta1 lines (potential fused into the first pass), then theta2
+  // lines on the bins that are kept
+  const T* vm = (MODE == 0) ? Vs + (int64_t)r * nn : nullptr;
+  fft_lines<T>(buf, n2, nullptr, 1, n2, p1, tw1, (T)-1, vm);
+  fft_lines<T>(buf, nrows1, rws, n2, 1, p2, tw2, (T)-1, nullptr);
+  for (int i = threadIdx.x; i < n_modes; i += NT) {
+    cplx<T> x = buf[modes[i].boff];
+    slab[i] = cplx<T>{x.x * out_scale, x.y * out_scale};
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t ldx,
+                 double* __restrict__ Y, int64_t ldy, int nvec, int ngroups, int n_r, int n_modes,
+                 const DGroup* __restrict__ groups, const DMode* __restrict__ modes,
+                 const double* __restrict__ kappa, const T* __restrict__ tfwd, int add_kinetic) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Hs = reinterpret_cast<T*>(smem_raw);
+  const int slot = xcd_slot(ngroups * nvec);
+  if (slot >= ngroups * nvec) return;
+  const int gi = slot / nvec, v = slot - gi * nvec;
+  const DGroup gr = groups[gi];
+  const int ncol = 2 * gr.nmodes;
+  const int nct = (ncol + 15) / 16;
+  const int colpad = 16 * nct;
+  const int nkt = (gr.Kmax + 15) / 16;
+  const int ntiles = nkt * nct;
+  const int nrs = (n_r + 3) / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const T* tg = tfwd + gr.tfwd_off;
+  const T* hv = GH + ((int64_t)v * n_r * n_modes + gr.mode0) * 2;
+  typedef typename Mfma<T>::acc_t acc_t;
+  for (int tbase = 0; tbase < ntiles; tbase += (NT / 64) * FWD_TMAX) {
+    acc_t acc[FWD_TMAX];
+#pragma unroll
+    for (int i = 0; i < FWD_TMAX; ++i) acc[i] = acc_t{0, 0, 0, 0};
+    for (int r0 = 0; r0 < n_r; r0 += FWD_RCHUNK) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < FWD_RCHUNK * colpad; i += NT) {
+        const int rr = i / colpad, col = i - rr * colpad;
+        const int r = r0 + rr;
+        Hs[i] = (r < n_r && col < ncol) ? hv[(int64_t)r * n_modes * 2 + col] : (T)0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < FWD_TMAX; ++i) {
+        const int t = tbase + wave + (NT / 64) * i;
+        if (t < ntiles) {
+          const int kt = t / nct, ct = t - kt * nct;
+#pragma unroll
+          for (int s = 0; s < FWD_RCHUNK / 4; ++s) {
+            const int rs = r0 / 4 + s;
+            if (rs < nrs) {
+              const T a = tg[((int64_t)kt * nrs + rs) * 64 + lane];
+              const T b = Hs[(4 * s + (lane >> 4)) * colpad + 16 * ct + (lane & 15)];
+              acc[i] = Mfma<T>::op(a, b, acc[i]);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < FWD_TMAX; ++i) {
+      const int t = tbase + wave + (NT / 64) * i;
+      if (t >= ntiles) continue;
+      const int kt = t / nct, ct = t - kt * nct;
+      const int col = 16 * ct + (lane & 15);
+      const int c = col >> 1, ri = col & 1;
+      if (c >= gr.nmodes) continue;
+      const DMode md = modes[gr.mode0 + c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * kt + Mfma<T>::row(lane, j);
+        if (k < md.K) {
+          const int64_t row = md.row0 + k;
+          double y = (double)acc[i][j];
+          if (add_kinetic) y += kappa[row] * X[(int64_t)v * ldx * 2 + 2 * row + ri];
+          Y[(int64_t)v * ldy * 2 + 2 * row + ri] = y;
+        }
+      }
+    }
+  }
+}
+
+// Vs[r][i1][i2] = scale * V[i1][i2][r] (and the single-precision copy)
+__global__ void __launch_bounds__(NT)
+k_relayout_potential(const double* __restrict__ V, double* __restrict__ Vs, float* __restrict__ Vsf,
+                     int n1, int n2, int n_r, double scale) {
+  const int64_t total = (int64_t)n1 * n2 * n_r;
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < total; i += (int64_t)gridDim.x * NT) {
+    const int64_t r = i / ((int64_t)n1 * n2), rem = i - r * n1 * n2;
+    const double x = scale * V[rem * n_r + r];
+    Vs[i] = x;
+    Vsf[i] = (float)x;
+  }
+}
+
+// Teter-Payne-Allan: partial sums of kappa |r|^2 and |r|^2 per (chunk, column)
+__global__ void __launch_bounds__(NT)
+k_tpa_partial(const double* __restrict__ Rr, int64_t ldr, const double* __restrict__ kappa, int64_t L,
+              int nchunk, double* __restrict__ part) {
+  __shared__ double s_num[NT], s_den[NT];
+  const int c = blockIdx.x, j = blockIdx.y;
+  const int64_t per = (L + nchunk - 1) / nchunk;
+  const int64_t lo = c * per, hi = std::min(L, lo + per);
+  double num = 0.0, den = 0.0;
+  const double* rc = Rr + (int64_t)j * ldr * 2;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+    const double a = rc[2 * i], b = rc[2 * i + 1];
+    const double m2 = a * a + b * b;
+    den += m2;
+    num += kappa[i] * m2;
+  }
+  s_num[threadIdx.x] = num;
+  s_den[threadIdx.x] = den;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      s_num[threadIdx.x] += s_num[threadIdx.x + s];
+      s_den[threadIdx.x] += s_den[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((int64_t)j * nchunk + c) * 2] = s_num[0];
+    part[((int64_t)j * nchunk + c) * 2 + 1] = s_den[0];
+  }
+}
+
+__global__ void __launch_bounds__(NT)
+k_tpa_apply(const double* __restrict__ Rr, int64_t ldr, double* __restrict__ W, int64_t ldw,
+            const double* __restrict__ kappa, int64_t L, int nchunk, const double* __restrict__ part) {
+  const int j = blockIdx.y;
+  double num = 0.0, den = 0.0;
+  for (int c = 0; c < nchunk; ++c) {   // fixed order: deterministic
+    num += part[((int64_t)j * nchunk + c) * 2];
+    den += part[((int64_t)j * nchunk + c) * 2 + 1];
+  }
+  const double T = den > 0.0 ? num / den : 0.0;
+  const double* rc = Rr + (int64_t)j * ldr * 2;
+  double* wc = W + (int64_t)j * ldw * 2;
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < L; i += (int64_t)gridDim.x * NT) {
+    double f = 0.0;
+    if (T > 0.0) {
+      const double g = kappa[i] / T;
+      const double num3 = 27.0 + g * (18.0 + g * (12.0 + 8.0 * g));
+      f = num3 / (num3 + 16.0 * g * g * g * g);
+    }
+    wc[2 * i] = f * rc[2 * i];
+    wc[2 * i + 1] = f * rc[2 * i + 1];
+  }
+}
+
+// ============================================================ host side
+#define HIP_TRY(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(HELIC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+namespace {
+
+template <typename T>
+helic_status upload(const std::vector<T>& host, T** dptr) {
+  if (host.empty()) {
+    *dptr = nullptr;
+    return HELIC_OK;
+  }
+  HIP_TRY(hipMalloc((void**)dptr, sizeof(T) * host.size()));
+  HIP_TRY(hipMemcpy(*dptr, host.data(), sizeof(T) * host.size(), hipMemcpyHostToDevice));
+  return HELIC_OK;
+}
+
+size_t angular_lds_bytes(const helic_basis_s* h, size_t elem) {
+  return (size_t)h->n_t1 * h->n_t2 * 2 * elem + (size_t)(h->n_t1 + h->n_t2) * 2 * elem +
+         (size_t)h->rows1.size() * sizeof(int32_t);
+}
+
+template <typename T>
+helic_status set_lds_limits() {
+  const int lim = 160 * 1024;
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  return HELIC_OK;
+}
+
+FftPlan make_plan(int n, const std::vector<int32_t>& f) {
+  FftPlan p;
+  std::memset(&p, 0, sizeof(p));
+  p.n = n;
+  p.nf = (int)f.size();
+  for (size_t i = 0; i < f.size() && i < 12; ++i) p.f[i] = f[i];
+  return p;
+}
+
+}  // namespace
+
+helic_status ensure_device(helic_basis_s* h) {
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (h->dev) {
+    if (h->dev->device != cur)
+      return fail(HELIC_ERR_STATE, "handle was set up on another device");
+    return HELIC_OK;
+  }
+  if (h->n_t1 * h->n_t2 > MAXGRID)
+    return fail(HELIC_ERR_GRID, "n_t1 * n_t2 above the angular kernel's limit of 4096 points");
+  if (h->max_kpad / 4 > KS_MAX) return fail(HELIC_ERR_GRID, "more than 96 radial functions in one |n| group");
+  if (angular_lds_bytes(h, sizeof(double)) > 160 * 1024)
+    return fail(HELIC_ERR_GRID, "angular slab does not fit in LDS");
+  DeviceState* d = new DeviceState();
+  d->device = cur;
+  h->dev = d;
+  helic_status s;
+  if ((s = set_lds_limits<double>()) != HELIC_OK) return s;
+  if ((s = set_lds_limits<float>()) != HELIC_OK) return s;
+  std::vector<DGroup> dg(h->groups.size());
+  for (size_t i = 0; i < h->groups.size(); ++i) {
+    const Group& g = h->groups[i];
+    dg[i] = DGroup{g.mode0, g.nmodes, g.Kmax, 0, g.row0, g.nrows, g.tinv_off, g.tfwd_off};
+  }
+  std::vector<DMode> dm(h->modes.size());
+  for (size_t i = 0; i < h->modes.size(); ++i) {
+    const Mode& m = h->modes[i];
+    dm[i] = DMode{m.row0, m.K, m.bin1 * h->n_t2 + m.bin2};
+  }
+  std::vector<float> tinv32(h->tab_inv.begin(), h->tab_inv.end());
+  std::vector<float> tfwd32(h->tab_fwd.begin(), h->tab_fwd.end());
+  const double PI = 3.14159265358979323846;
+  std::vector<cplx<double>> tw1(h->n_t1), tw2(h->n_t2);
+  std::vector<cplx<float>> tw1f(h->n_t1), tw2f(h->n_t2);
+  for (int t = 0; t < h->n_t1; ++t) {
+    tw1[t] = {std::cos(2 * PI * t / h->n_t1), -std::sin(2 * PI * t / h->n_t1)};
+    tw1f[t] = {(float)tw1[t].x, (float)tw1[t].y};
+  }
+  for (int t = 0; t < h->n_t2; ++t) {
+    tw2[t] = {std::cos(2 * PI * t / h->n_t2), -std::sin(2 * PI * t / h->n_t2)};
+    tw2f[t] = {(float)tw2[t].x, (float)tw2[t].y};
+  }
+  if ((s = upload(dg, &d->groups)) || (s = upload(dm, &d->modes)) || (s = upload(h->row_ck, &d->row_ck)) ||
+      (s = upload(h->kappa, &d->kappa)) || (s = upload(h->rows1, &d->rows1)) ||
+      (s = upload(h->tab_inv, &d->tinv64)) || (s = upload(h->tab_fwd, &d->tfwd64)) ||
+      (s = upload(tinv32, &d->tinv32)) || (s = upload(tfwd32, &d->tfwd32)) ||
+      (s = upload(tw1, &d->tw1)) || (s = upload(tw2, &d->tw2)) || (s = upload(tw1f, &d->tw1f)) ||
+      (s = upload(tw2f, &d->tw2f)))
+    return s;
+  d->plan1 = make_plan(h->n_t1, h->fac1);
+  d->plan2 = make_plan(h->n_t2, h->fac2);
+  return HELIC_OK;
+}
+
+helic_status ensure_workspace(helic_basis_s* h, int nvec, size_t elem) {
+  DeviceState* d = h->dev;
+  const size_t need = (size_t)nvec * h->n_r * h->modes.size() * 2 * elem;
+  if (need > d->gh_bytes) {
+    if (d->gh) HIP_TRY(hipFree(d->gh));
+    d->gh = nullptr;
+    d->gh_bytes = 0;
+    HIP_TRY(hipMalloc(&d->gh, need));
+    d->gh_bytes = need;
+  }
+  return HELIC_OK;
+}
+
+void device_release(helic_basis_s* h) {
+  DeviceState* d = h->dev;
+  if (!d) return;
+  void* ptrs[] = {d->groups, d->modes, d->row_ck, d->kappa, d->rows1, d->tinv64, d->tfwd64,
+                  d->tinv32, d->tfwd32, d->tw1, d->tw2, d->tw1f, d->tw2f, d->Vs, d->Vsf,
+                  d->gh, d->part};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  release_solver_state(d);
+  delete d;
+  h->dev = nullptr;
+}
+
+// Launches of the three H*X stages for one chunk of at most `chunk` vectors.
+template <typename T>
+helic_status launch_apply(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                          int nvec, hipStream_t st, int mode) {
+  DeviceState* d = h->dev;
+  const int ng = (int)h->groups.size();
+  const int nm = (int)h->modes.size();
+  T* gh = reinterpret_cast<T*>(d->gh);
+  const T* tinv = std::is_same<T, double>::value ? (const T*)d->tinv64 : (const T*)d->tinv32;
+  const T* tfwd = std::is_same<T, double>::value ? (const T*)d->tfwd64 : (const T*)d->tfwd32;
+  const T* Vs = std::is_same<T, double>::value ? (const T*)d->Vs : (const T*)d->Vsf;
+  const cplx<T>* tw1 = std::is_same<T, double>::value ? (const cplx<T>*)d->tw1 : (const cplx<T>*)d->tw1f;
+  const cplx<T>* tw2 = std::is_same<T, double>::value ? (const cplx<T>*)d->tw2 : (const cplx<T>*)d->tw2f;
+  const int wg_rad = 8 * ((ng * nvec + 7) / 8);
+  const size_t lds_inv = (size_t)h->max_kpad * h->max_colpad * sizeof(T);
+  const size_t lds_fwd = (size_t)FWD_RCHUNK * h->max_colpad * sizeof(T);
+  const int wg_ang = 8 * ((nvec * h->n_r + 7) / 8);
+  const size_t lds_ang = angular_lds_bytes(h, sizeof(T));
+  hipLaunchKernelGGL((k_radial_inverse<T>), dim3(wg_rad), dim3(NT), lds_inv, st, X, ldx, gh, nvec, ng,
+                     h->n_r, nm, d->groups, d->row_ck, tinv);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_angular<T, 0>), dim3(wg_ang), dim3(NT), lds_ang, st, gh, nullptr, nullptr, Vs, nvec,
+                     h->n_r, nm, d->modes, d->rows1, (int)h->rows1.size(), tw1, tw2, d->plan1, d->plan2,
+                     (T)1);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_radial_forward<T>), dim3(wg_rad), dim3(NT), lds_fwd, st, gh, X, ldx, Y, ldy, nvec,
+                     ng, h->n_r, nm, d->groups, d->modes, d->kappa, tfwd, mode);
+  HIP_TRY(hipGetLastError());
+  return HELIC_OK;
+}
+
+template helic_status launch_apply<double>(helic_basis_s*, const double*, int64_t, double*, int64_t, int,
+                                           hipStream_t, int);
+template helic_status launch_apply<float>(helic_basis_s*, const double*, int64_t, double*, int64_t, int,
+                                          hipStream_t, int);
+
+helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                          int nvec, helic_prec prec, hipStream_t st) {
+  const int chunk = APPLY_CHUNK;
+  const size_t elem = prec == HELIC_FP64 ? sizeof(double) : sizeof(float);
+  helic_status s = ensure_workspace(h, std::min(nvec, chunk), elem);
+  if (s != HELIC_OK) return s;
+  for (int v0 = 0; v0 < nvec; v0 += chunk) {
+    const int nv = std::min(chunk, nvec - v0);
+    const double* Xc = X + (int64_t)v0 * ldx * 2;
+    double* Yc = Y + (int64_t)v0 * ldy * 2;
+    s = prec == HELIC_FP64 ? launch_apply<double>(h, Xc, ldx, Yc, ldy, nv, st, 1)
+                           : launch_apply<float>(h, Xc, ldx, Yc, ldy, nv, st, 1);
+    if (s != HELIC_OK) return s;
+  }
+  return HELIC_OK;
+}
+
+helic_status precondition_impl(helic_basis_s* h, const double* Rr, int64_t ldr, double* W, int64_t ldw,
+                               int nvec, hipStream_t st) {
+  DeviceState* d = h->dev;
+  const int nchunk = (int)std::min<int64_t>(64, (h->L + 1023) / 1024);
+  const size_t need = (size_t)nvec * nchunk * 2 * sizeof(double);
+  if (need > d->part_bytes) {
+    if (d->part) HIP_TRY(hipFree(d->part));
+    d->part = nullptr;
+    d->part_bytes = 0;
+    HIP_TRY(hipMalloc((void**)&d->part, need));
+    d->part_bytes = need;
+  }
+  hipLaunchKernelGGL(k_tpa_partial, dim3(nchunk, nvec), dim3(NT), 0, st, Rr, ldr, d->kappa, h->L, nchunk,
+                     d->part);
+  HIP_TRY(hipGetLastError());
+  const int nb = (int)std::min<int64_t>(64, (h->L + NT - 1) / NT);
+  hipLaunchKernelGGL(k_tpa_apply, dim3(nb, nvec), dim3(NT), 0, st, Rr, ldr, W, ldw, d->kappa, h->L, nchunk,
+                     d->part);
+  HIP_TRY(hipGetLastError());
+  return HELIC_OK;
+}
+
+}  // namespace helic
+
+using namespace helic;
+
+extern "C" {
+
+helic_status helic_set_potential(helic_basis h, const double* V, void* stream) {
+  if (!h || !V) return fail(HELIC_ERR_INVALID, "null argument");
+  helic_status s = ensure_device(h);
+  if (s != HELIC_OK) return s;
+  DeviceState* d = h->dev;
+  const size_t n = (size_t)h->n_t1 * h->n_t2 * h->n_r;
+  if (!d->Vs) {
+    HIP_TRY(hipMalloc((void**)&d->Vs, n * sizeof(double)));
+    HIP_TRY(hipMalloc((void**)&d->Vsf, n * sizeof(float)));
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int nb = (int)std::min<size_t>(4096, (n + NT - 1) / NT);
+  hipLaunchKernelGGL(k_relayout_potential, dim3(nb), dim3(NT), 0, st, V, d->Vs, d->Vsf, h->n_t1, h->n_t2,
+                     h->n_r, 1.0 / ((double)h->n_t1 * h->n_t2));
+  HIP_TRY(hipGetLastError());
+  d->have_potential = true;
+  return HELIC_OK;
+}
+
+helic_status helic_apply_H(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                           int32_t nvec, helic_prec prec, void* stream) {
+  if (!h) return fail(HELIC_ERR_INVALID, "null handle");
+  if (nvec < 0 || (nvec > 0 && (!X || !Y)) || ldx < h->L || ldy < h->L)
+    return fail(HELIC_ERR_INVALID, "bad block arguments");
+  if (prec != HELIC_FP64 && prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (nvec == 0) return HELIC_OK;
+  if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
+  helic_status s = ensure_device(h);
+  if (s != HELIC_OK) return s;
+  return apply_H_impl(h, X, ldx, Y, ldy, nvec, prec, reinterpret_cast<hipStream_t>(stream));
+}
+
+helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx, double* g, int32_t nvec,
+                                     void* stream) {
+  if (!h) return fail(HELIC_ERR_INVALID, "null handle");
+  if (nvec < 0 || (nvec > 0 && (!X || !g)) || ldx < h->L) return fail(HELIC_ERR_INVALID, "bad arguments");
+  if (nvec == 0) return HELIC_OK;
+  helic_status s = ensure_device(h);
+  if (s != HELIC_OK) return s;
+  DeviceState* d = h->dev;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int ng = (int)h->groups.size(), nm = (int)h->modes.size();
+  const int64_t grid_elems = (int64_t)h->n_t1 * h->n_t2 * h->n_r;
+  for (int v0 = 0; v0 < nvec; v0 += APPLY_CHUNK) {
+    const int nv = std::min(APPLY_CHUNK, nvec - v0);
+    if ((s = ensure_workspace(h, nv, sizeof(double))) != HELIC_OK) return s;
+    double* gh = reinterpret_cast<double*>(d->gh);
+    hipLaunchKernelGGL((k_radial_inverse<double>), dim3(8 * ((ng * nv + 7) / 8)), dim3(NT),
+                       (size_t)h->max_kpad * h->max_colpad * sizeof(double), st, X + (int64_t)v0 * ldx * 2, ldx,
+                       gh, nv, ng, h->n_r, nm, d->groups, d->row_ck, d->tinv64);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_angular<double, 1>), dim3(8 * ((nv * h->n_r + 7) / 8)), dim3(NT),
+                       angular_lds_bytes(h, sizeof(double)), st, gh, nullptr, g + v0 * grid_elems * 2,
+                       (const double*)nullptr, nv, h->n_r, nm, d->modes, d->rows1, (int)h->rows1.size(), d->tw1,
+                       d->tw2, d->plan1, d->plan2, 1.0);
+    HIP_TRY(hipGetLastError());
+  }
+  return HELIC_OK;
+}
+
+helic_status helic_transform_forward(helic_basis h, const double* g, double* X, int64_t ldx, int32_t nvec,
+                                     void* stream) {
+  if (!h) return fail(HELIC_ERR_INVALID, "null handle");
+  if (nvec < 0 || (nvec > 0 && (!X || !g)) || ldx < h->L) return fail(HELIC_ERR_INVALID, "bad arguments");
+  if (nvec == 0) return HELIC_OK;
+  helic_status s = ensure_device(h);
+  if (s != HELIC_OK) return s;
+  DeviceState* d = h->dev;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int ng = (int)h->groups.size(), nm = (int)h->modes.size();
+  const int64_t grid_elems = (int64_t)h->n_t1 * h->n_t2 * h->n_r;
+  for (int v0 = 0; v0 < nvec; v0 += APPLY_CHUNK) {
+    const int nv = std::min(APPLY_CHUNK, nvec - v0);
+    if ((s = ensure_workspace(h, nv, sizeof(double))) != HELIC_OK) return s;
+    double* gh = reinterpret_cast<double*>(d->gh);
+    hipLaunchKernelGGL((k_angular<double, 2>), dim3(8 * ((nv * h->n_r + 7) / 8)), dim3(NT),
+                       angular_lds_bytes(h, sizeof(double)), st, gh, g + v0 * grid_elems * 2, nullptr,
+                       (const double*)nullptr, nv, h->n_r, nm, d->modes, d->rows1, (int)h->rows1.size(), d->tw1,
+                       d->tw2, d->plan1, d->plan2, 1.0 / ((double)h->n_t1 * h->n_t2));
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_radial_forward<double>), dim3(8 * ((ng * nv + 7) / 8)), dim3(NT),
+                       (size_t)FWD_RCHUNK * h->max_colpad * sizeof(double), st, gh, (const double*)nullptr, ldx,
+                       X + (int64_t)v0 * ldx * 2, ldx, nv, ng, h->n_r, nm, d->groups, d->modes, d->kappa,
+                       d->tfwd64, 0);
+    HIP_TRY(hipGetLastError());
+  }
+  return HELIC_OK;
+}
+
+helic_status helic_precondition(helic_basis h, const double* Rres, int64_t ldr, double* W, int64_t ldw,
+                                int32_t nvec, void* stream) {
+  if (!h) return fail(HELIC_ERR_INVALID, "null handle");
+  if (nvec < 0 || (nvec > 0 && (!Rres || !W)) || ldr < h->L || ldw < h->L)
+    return fail(HELIC_ERR_INVALID, "bad block arguments");
+  if (nvec == 0) return HELIC_OK;
+  if (W != Rres) {
+    // W may equal R (in place) but must not partially overlap it
+    const char* a = reinterpret_cast<const char*>(Rres);
+    const char* b = reinterpret_cast<const char*>(W);
+    const size_t na = (size_t)ldr * nvec * 16, nb = (size_t)ldw * nvec * 16;
+    if (a < b + nb && b < a + na) return fail(HELIC_ERR_INVALID, "R and W overlap");
+  } else if (ldr != ldw) {
+    return fail(HELIC_ERR_INVALID, "in-place preconditioning needs ldr == ldw");
+  }
+  helic_status s = ensure_device(h);
+  if (s != HELIC_OK) return s;
+  return precondition_impl(h, Rres, ldr, W, ldw, nvec, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

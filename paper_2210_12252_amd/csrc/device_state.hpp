@@ -1,0 +1,41 @@
+// Device-resident state of a basis handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "kernels.hpp"
+
+namespace helic {
+
+// Vectors per launch of the H*X stages; bounds the intermediate buffer to
+// APPLY_CHUNK * n_r * n_modes complex values.
+constexpr int APPLY_CHUNK = 64;
+
+struct SolverState;
+
+struct DeviceState {
+  int device = 0;
+  DGroup* groups = nullptr;
+  DMode* modes = nullptr;
+  int32_t* row_ck = nullptr;
+  double* kappa = nullptr;
+  int32_t* rows1 = nullptr;
+  double *tinv64 = nullptr, *tfwd64 = nullptr;
+  float *tinv32 = nullptr, *tfwd32 = nullptr;
+  cplx<double>*tw1 = nullptr, *tw2 = nullptr;
+  cplx<float>*tw1f = nullptr, *tw2f = nullptr;
+  FftPlan plan1{}, plan2{};
+  double* Vs = nullptr;
+  float* Vsf = nullptr;
+  bool have_potential = false;
+  void* gh = nullptr;
+  size_t gh_bytes = 0;
+  double* part = nullptr;
+  size_t part_bytes = 0;
+  SolverState* solver = nullptr;
+};
+
+void release_solver_state(DeviceState* d);
+
+}  // namespace helic

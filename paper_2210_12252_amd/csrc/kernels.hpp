@@ -1,0 +1,230 @@
+// HIP kernels of the helical-wave Hamiltonian apply on gfx950 (CDNA4).
+//
+// Data layout in HBM
+//   X, Y       coefficient blocks, complex double, column-major (ld >= L), rows
+//              in the compact order: grouped by |n|, then sign of n, then m,
+//              then k = 1..K (so one group's rows are contiguous).
+//   GH         per-(vector, radius) slabs of angular-mode values,
+//              GH[v][r][mode] complex T, modes in compact order.  K-inv writes
+//              G into it, K-ang overwrites each slab in place with H, K-fwd
+//              reads H.
+//   Vs         the potential re-laid out per radius, Vs[r][i1][i2], already
+//              divided by n_t1 * n_t2 (the forward DFT normalisation).
+//   tinv/tfwd  radial tables per |n| group in MFMA fragment order.
+//
+// Kernels
+//   k_radial_inverse   G_{mn}(r_l) = sum_k xi_{|n|,k}(r_l) x_{mnk}   (Alg. 1,
+//                      radial part): one |n| group x one vector per
+//                      workgroup, a real (n_r x K) by (K x 2 modes) GEMM on
+//                      16x16x4 MFMA tiles.
+//   k_angular          per (vector, radius) slab in LDS: inverse 2D DFT of the
+//                      mode block (Alg. 2), multiply by V, forward 2D DFT and
+//                      crop back to the kept modes (Alg. 4); Stockham radix
+//                      2/3/4/5 passes through LDS, the theta2 passes only on
+//                      the theta1 bins that hold modes, V fused into the
+//                      loads of the first forward pass.
+//   k_radial_forward   y_{mnk} = kappa x_{mnk} + 2 pi tau sum_l omega_l
+//                      xi_{|n|,k}(r_l) H_{mn}(r_l)   (Alg. 3 radial part and
+//                      the diagonal terms of Alg. 5): a (K x n_r) by
+//                      (n_r x 2 modes) GEMM with the kinetic term in the
+//                      epilogue.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace helic {
+
+constexpr int NT = 256;             // threads per workgroup in every kernel
+constexpr int MAXGRID = 4096;       // n_t1 * n_t2 bound of k_angular
+constexpr int KS_MAX = 24;          // K <= 96 per |n| group
+constexpr int FWD_TMAX = 4;         // output tiles per wave per round in k_radial_forward
+constexpr int FWD_RCHUNK = 32;      // radii staged per LDS round in k_radial_forward
+
+struct DGroup {
+  int32_t mode0, nmodes, Kmax, pad;
+  int64_t row0, nrows, tinv_off, tfwd_off;
+};
+
+struct DMode {
+  int64_t row0;
+  int32_t K;
+  int32_t boff;   // LDS offset bin1 * n_t2 + bin2 of the mode in a slab
+};
+
+struct FftPlan {
+  int32_t n, nf;
+  int32_t f[12];
+};
+
+template <typename T>
+struct cplx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+// multiply by +i (s = +1) or -i (s = -1)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmuli(cplx<T> a, T s) { return {-s * a.y, s * a.x}; }
+
+template <typename T> struct Mfma;
+// 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// accumulator element i of lane l is D[row(l, i)][l % 16].  The row map
+// differs between the 64-bit and the 32-bit forms (checked on gfx950).
+template <> struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+};
+template <> struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+// Work item of an XCD-aware launch: workgroups are dealt round-robin to the 8
+// XCDs, so consecutive slots of one XCD are given contiguous work indices
+// (and share tables or potential slabs in that XCD's L2).
+__device__ __forceinline__ int xcd_slot(int nwork) {
+  const int per = (nwork + 7) / 8;
+  return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+
+// ------------------------------------------------------------------ radix DFTs
+// In-register R-point DFT, y_p = sum_q v_q exp(s 2 pi i p q / R), s = -1
+// (forward) or +1 (inverse).
+template <typename T>
+__device__ __forceinline__ void dft2(cplx<T>* v, T) {
+  cplx<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <typename T>
+__device__ __forceinline__ void dft3(cplx<T>* v, T s) {
+  const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+  cplx<T> t1 = cadd(v[1], v[2]);
+  cplx<T> t2 = {v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y};
+  cplx<T> d = csub(v[1], v[2]);
+  cplx<T> t3 = cmuli(cplx<T>{h * d.x, h * d.y}, s);
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+template <typename T>
+__device__ __forceinline__ void dft4(cplx<T>* v, T s) {
+  cplx<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  cplx<T> c = cadd(v[1], v[3]), d = cmuli(csub(v[1], v[3]), s);
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+template <typename T>
+__device__ __forceinline__ void dft5(cplx<T>* v, T s) {
+  const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;  // cos 2pi/5, cos 4pi/5
+  const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;   // sin 2pi/5, sin 4pi/5
+  cplx<T> a1 = cadd(v[1], v[4]), a2 = cadd(v[2], v[3]);
+  cplx<T> b1 = csub(v[1], v[4]), b2 = csub(v[2], v[3]);
+  cplx<T> p1 = {v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y};
+  cplx<T> p2 = {v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y};
+  cplx<T> q1 = cmuli(cplx<T>{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y}, s);
+  cplx<T> q2 = cmuli(cplx<T>{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y}, s);
+  v[0] = cadd(v[0], cadd(a1, a2));
+  v[1] = cadd(p1, q1);
+  v[4] = csub(p1, q1);
+  v[2] = cadd(p2, q2);
+  v[3] = csub(p2, q2);
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dftR(cplx<T>* v, T s) {
+  if constexpr (R == 2) dft2(v, s);
+  else if constexpr (R == 3) dft3(v, s);
+  else if constexpr (R == 4) dft4(v, s);
+  else dft5(v, s);
+}
+
+// One Stockham radix-R pass over `nlines` lines of length N held in LDS.
+// Line l starts at (rows ? rows[l] : l) * line_mul and its elements are
+// `stride` apart.  All loads of the pass complete (barrier) before any store,
+// so the pass runs in place.  tw[t] = exp(-2 pi i t / N).  When vmul is given
+// every loaded element is first multiplied by the real vmul[offset].
+template <typename T, int R>
+__device__ __forceinline__ void fft_pass(cplx<T>* buf, int nlines, const int32_t* rows, int line_mul,
+                                         int stride, int N, int Ns, const cplx<T>* tw, T sgn,
+                                         const T* __restrict__ vmul) {
+  constexpr int BMAX = (MAXGRID / R + NT - 1) / NT;
+  const int NR = N / R;
+  const int nb = nlines * NR;
+  const int tstep = N / (Ns * R);
+  cplx<T> v[BMAX][R];
+#pragma unroll
+  for (int i = 0; i < BMAX; ++i) {
+    const int b = threadIdx.x + i * NT;
+    if (b < nb) {
+      const int line = b / NR, j = b - line * NR;
+      const int base = (rows ? rows[line] : line) * line_mul;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int off = base + (j + q * NR) * stride;
+        cplx<T> x = buf[off];
+        if (vmul) {
+          const T s = vmul[off];
+          x.x *= s;
+          x.y *= s;
+        }
+        v[i][q] = x;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < BMAX; ++i) {
+    const int b = threadIdx.x + i * NT;
+    if (b < nb) {
+      const int line = b / NR, j = b - line * NR;
+      const int base = (rows ? rows[line] : line) * line_mul;
+      const int k = j % Ns;
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        cplx<T> w = tw[q * k * tstep];
+        w.y = sgn < 0 ? w.y : -w.y;
+        v[i][q] = cmul(v[i][q], w);
+      }
+      dftR<T, R>(v[i], sgn);
+      const int o = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) buf[base + (o + q * Ns) * stride] = v[i][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void fft_lines(cplx<T>* buf, int nlines, const int32_t* rows, int line_mul, int stride,
+                          const FftPlan& plan, const cplx<T>* tw, T sgn, const T* vmul) {
+  int Ns = 1;
+  for (int s = 0; s < plan.nf; ++s) {
+    const int R = plan.f[s];
+    const T* vm = (s == 0) ? vmul : nullptr;
+    switch (R) {
+      case 2: fft_pass<T, 2>(buf, nlines, rows, line_mul, stride, plan.n, Ns, tw, sgn, vm); break;
+      case 3: fft_pass<T, 3>(buf, nlines, rows, line_mul, stride, plan.n, Ns, tw, sgn, vm); break;
+      case 4: fft_pass<T, 4>(buf, nlines, rows, line_mul, stride, plan.n, Ns, tw, sgn, vm); break;
+      default: fft_pass<T, 5>(buf, nlines, rows, line_mul, stride, plan.n, Ns, tw, sgn, vm); break;
+    }
+    Ns *= R;
+  }
+}
+
+}  // namespace helic

@@ -1,0 +1,291 @@
+"""ctypes binding of libhelic (the C ABI declared in include/helic.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+blocks are torch tensors on the current HIP device; a block of nvec complex
+columns of leading dimension ld is a C-contiguous complex128 tensor of shape
+(nvec, ld) (row j of the tensor is column j of the column-major block).
+Streams default to torch's current stream.  Importing this module does not
+need a GPU; loading the library requires it to have been built
+(``python -m paper_2210_12252_amd.build``) and raises otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libhelic.so")
+
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_GRID, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_CUTOFF_TIE, ERR_STATE = range(9)
+FP64, FP32 = 0, 1
+PREC = {"fp64": FP64, "fp32": FP32}
+
+# every function declared in include/helic.h
+EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "helic_basis_indices",
+           "helic_grid", "helic_set_potential", "helic_apply_H", "helic_transform_inverse",
+           "helic_transform_forward", "helic_precondition", "helic_eigensolve",
+           "helic_util_bessel_j", "helic_util_bessel_zeros", "helic_util_gauss_jacobi",
+           "helic_last_error")
+
+
+class HelicError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"helic status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double), ("tau", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("ncyc", ctypes.c_int32), ("ecut", ctypes.c_double), ("eta", ctypes.c_double),
+                ("nu", ctypes.c_int32), ("m_max", ctypes.c_int32), ("n_max", ctypes.c_int32),
+                ("k_max", ctypes.c_int32), ("n_t1", ctypes.c_int32), ("n_t2", ctypes.c_int32),
+                ("n_r", ctypes.c_int32)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_PD = ctypes.POINTER(ctypes.c_double)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def load() -> ctypes.CDLL:
+    """Load libhelic.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"{LIBPATH} is not built; run python -m paper_2210_12252_amd.build")
+    lib = ctypes.CDLL(LIBPATH)
+    sig = {
+        "helic_basis_create": [ctypes.POINTER(Params), ctypes.POINTER(_P)],
+        "helic_basis_destroy": [_P],
+        "helic_basis_info": [_P, _PI64, _PI32, _PI32, _PI32, _PI32],
+        "helic_basis_indices": [_P, _PI32, _PD],
+        "helic_grid": [_P, _PD, _PD, _PD, _PD],
+        "helic_set_potential": [_P, _P, _P],
+        "helic_apply_H": [_P, _P, _I64, _P, _I64, _I32, _I32, _P],
+        "helic_transform_inverse": [_P, _P, _I64, _P, _I32, _P],
+        "helic_transform_forward": [_P, _P, _P, _I64, _I32, _P],
+        "helic_precondition": [_P, _P, _I64, _P, _I64, _I32, _P],
+        "helic_eigensolve": [_P, _I32, _I32, _D, _I32, _I32, ctypes.c_uint64, _PD, _PD, _P, _I64,
+                             _PI32, _P],
+        "helic_util_bessel_j": [_I32, _I32, _PD, _PD],
+        "helic_util_bessel_zeros": [_I32, _I32, _PD],
+        "helic_util_gauss_jacobi": [_I32, _PD, _PD],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.helic_last_error.argtypes = []
+    lib.helic_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise HelicError(status, load().helic_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _block(t, name):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.dim() == 2 and t.stride(1) == 1):
+        raise ValueError(f"{name} must be a complex128 HIP tensor of shape (nvec, ld), unit stride")
+    return t.shape[0], t.stride(0)
+
+
+# ------------------------------------------------------------------ host calls
+def basis_create(R, tau, alpha, ecut, eta=0.0, m_max=-1, n_max=-1, k_max=-1, n_t1=0, n_t2=0, n_r=0,
+                 ncyc=1, nu=0) -> ctypes.c_void_p:
+    p = Params(R=R, tau=tau, alpha=alpha, ncyc=ncyc, ecut=ecut, eta=eta, nu=nu, m_max=m_max,
+               n_max=n_max, k_max=k_max, n_t1=n_t1, n_t2=n_t2, n_r=n_r)
+    h = ctypes.c_void_p()
+    _check(load().helic_basis_create(ctypes.byref(p), ctypes.byref(h)))
+    return h
+
+
+def basis_destroy(h):
+    _check(load().helic_basis_destroy(h))
+
+
+def basis_info(h) -> dict:
+    L = ctypes.c_int64()
+    n1, n2, nr, nm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().helic_basis_info(h, ctypes.byref(L), ctypes.byref(n1), ctypes.byref(n2),
+                                   ctypes.byref(nr), ctypes.byref(nm)))
+    return dict(L=L.value, n_t1=n1.value, n_t2=n2.value, n_r=nr.value, n_modes=nm.value)
+
+
+def basis_indices(h):
+    L = basis_info(h)["L"]
+    mnk = np.empty((L, 3), dtype=np.int32)
+    kappa = np.empty(L, dtype=np.float64)
+    _check(load().helic_basis_indices(h, _ptr(mnk, ctypes.c_int32), _ptr(kappa, ctypes.c_double)))
+    return mnk, kappa
+
+
+def grid(h):
+    i = basis_info(h)
+    t1, t2 = np.empty(i["n_t1"]), np.empty(i["n_t2"])
+    r, w = np.empty(i["n_r"]), np.empty(i["n_r"])
+    _check(load().helic_grid(h, _ptr(t1, ctypes.c_double), _ptr(t2, ctypes.c_double),
+                             _ptr(r, ctypes.c_double), _ptr(w, ctypes.c_double)))
+    return t1, t2, r, w
+
+
+def util_bessel_j(p: int, x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    _check(load().helic_util_bessel_j(p, x.size, _ptr(x, ctypes.c_double), _ptr(out, ctypes.c_double)))
+    return out
+
+
+def util_bessel_zeros(p: int, count: int) -> np.ndarray:
+    out = np.empty(count)
+    _check(load().helic_util_bessel_zeros(p, count, _ptr(out, ctypes.c_double)))
+    return out
+
+
+def util_gauss_jacobi(n: int):
+    q, w = np.empty(n), np.empty(n)
+    _check(load().helic_util_gauss_jacobi(n, _ptr(q, ctypes.c_double), _ptr(w, ctypes.c_double)))
+    return q, w
+
+
+# ------------------------------------------------------------------ device calls
+def set_potential(h, V, stream=None):
+    import torch
+    if not (V.is_cuda and V.dtype == torch.float64 and V.is_contiguous()):
+        raise ValueError("V must be a contiguous float64 HIP tensor in real-space order")
+    i = basis_info(h)
+    if V.numel() != i["n_t1"] * i["n_t2"] * i["n_r"]:
+        raise ValueError("V has the wrong number of grid points")
+    _check(load().helic_set_potential(h, ctypes.c_void_p(V.data_ptr()), _stream(stream)))
+
+
+def apply_H(h, X, Y, prec="fp64", stream=None):
+    nx, ldx = _block(X, "X")
+    ny, ldy = _block(Y, "Y")
+    if ny < nx:
+        raise ValueError("Y has fewer columns than X")
+    _check(load().helic_apply_H(h, ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(Y.data_ptr()), ldy,
+                                nx, PREC[prec], _stream(stream)))
+
+
+def transform_inverse(h, X, g, stream=None):
+    nx, ldx = _block(X, "X")
+    i = basis_info(h)
+    if g.numel() < nx * i["n_t1"] * i["n_t2"] * i["n_r"] or not g.is_contiguous():
+        raise ValueError("g too small or not contiguous")
+    _check(load().helic_transform_inverse(h, ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(g.data_ptr()),
+                                          nx, _stream(stream)))
+
+
+def transform_forward(h, g, X, stream=None):
+    nx, ldx = _block(X, "X")
+    i = basis_info(h)
+    if g.numel() < nx * i["n_t1"] * i["n_t2"] * i["n_r"] or not g.is_contiguous():
+        raise ValueError("g too small or not contiguous")
+    _check(load().helic_transform_forward(h, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(X.data_ptr()), ldx,
+                                          nx, _stream(stream)))
+
+
+def precondition(h, R, W, stream=None):
+    nr_, ldr = _block(R, "R")
+    nw, ldw = _block(W, "W")
+    if nw < nr_:
+        raise ValueError("W has fewer columns than R")
+    _check(load().helic_precondition(h, ctypes.c_void_p(R.data_ptr()), ldr, ctypes.c_void_p(W.data_ptr()), ldw,
+                                     nr_, _stream(stream)))
+
+
+def eigensolve(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, evecs=None, stream=None):
+    """Returns (evals, resid, iters, status); raises on errors other than
+    non-convergence."""
+    evals = np.zeros(nev)
+    resid = np.zeros(nev)
+    iters = ctypes.c_int32(0)
+    if evecs is not None:
+        nv, ldv = _block(evecs, "evecs")
+        if nv < nev:
+            raise ValueError("evecs has fewer than nev columns")
+        vptr = ctypes.c_void_p(evecs.data_ptr())
+    else:
+        ldv, vptr = 0, ctypes.c_void_p(0)
+    st = load().helic_eigensolve(h, nev, block, tol, maxit, PREC[prec], seed, _ptr(evals, ctypes.c_double),
+                                 _ptr(resid, ctypes.c_double), vptr, ldv, ctypes.byref(iters), _stream(stream))
+    if st not in (OK, ERR_NOCONV):
+        _check(st)
+    return evals, resid, iters.value, st
+
+
+class Basis:
+    """Owning wrapper of a basis handle."""
+
+    def __init__(self, **params):
+        self.h = basis_create(**params)
+        info = basis_info(self.h)
+        self.L = info["L"]
+        self.n_t1, self.n_t2, self.n_r, self.n_modes = info["n_t1"], info["n_t2"], info["n_r"], info["n_modes"]
+
+    @classmethod
+    def from_workload(cls, w, **over):
+        p = dict(R=w.R, tau=w.tau, alpha=w.alpha, ecut=w.ecut, eta=w.eta, m_max=w.m_max, n_max=w.n_max,
+                 k_max=w.k_max, n_t1=w.n_t1, n_t2=w.n_t2, n_r=w.n_r)
+        p.update(over)
+        return cls(**p)
+
+    def close(self):
+        if self.h is not None:
+            basis_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def indices(self):
+        return basis_indices(self.h)
+
+    def grid(self):
+        return grid(self.h)
+
+    def set_potential(self, V, stream=None):
+        set_potential(self.h, V, stream)
+
+    def apply_H(self, X, Y, prec="fp64", stream=None):
+        apply_H(self.h, X, Y, prec, stream)
+
+    def transform_inverse(self, X, g, stream=None):
+        transform_inverse(self.h, X, g, stream)
+
+    def transform_forward(self, g, X, stream=None):
+        transform_forward(self.h, g, X, stream)
+
+    def precondition(self, R, W, stream=None):
+        precondition(self.h, R, W, stream)
+
+    def eigensolve(self, nev, **kw):
+        return eigensolve(self.h, nev, **kw)

@@ -1,0 +1,208 @@
+"""GPU parity of the H*X path and the transforms against the CPU oracle.
+
+Tolerances (derived from the arithmetic): every output element of the FP64
+path is a sum of O(K + n_r + log(n_t1 n_t2)) rounded products of terms no
+larger than max|kappa| |x| or max|V| |x|; a relative error of 1e-12 of the
+column maximum leaves a margin of ~10^2 over the worst case of such sums.
+The FP32 path computes the same sums with unit roundoff 6e-8: 2e-5 of the
+column maximum.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import basis as ob
+from oracle import hamiltonian as oh
+from oracle import precond as op
+from oracle import transforms as ot
+
+torch = pytest.importorskip("torch")
+helic = pytest.importorskip("paper_2210_12252_amd.helic")
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+class Case:
+    """A basis on both sides, the permutation between their row orders and a
+    potential sampled on the oracle's grid."""
+
+    def __init__(self, w, potential=True):
+        self.w = w
+        self.o = ob.basis_for(w)
+        self.g = helic.Basis.from_workload(w)
+        mnk, _ = self.g.indices()
+        pos = {tuple(t): i for i, t in enumerate(self.o.mnk.tolist())}
+        self.perm = np.array([pos[tuple(t)] for t in mnk.tolist()])   # gpu row -> oracle row
+        self.mnk = mnk
+        atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R) if potential else []
+        self.V = synth.potential_at(self.o.theta1, self.o.theta2, self.o.r, w.tau, w.alpha, atoms)
+        print(f"[case] {w.name} L={self.o.L} grid={self.o.n_t1}x{self.o.n_t2}x{self.o.n_r}", flush=True)
+
+    def upload_V(self, V=None):
+        V = self.V if V is None else V
+        self.g.set_potential(torch.from_numpy(np.ascontiguousarray(V)).to(_dev()))
+
+    def to_gpu_block(self, Xo, ld=None):
+        """oracle-order (L, nv) -> device tensor (nv, ld) in library order"""
+        L, nv = Xo.shape
+        ld = L if ld is None else ld
+        out = np.zeros((nv, ld), dtype=np.complex128)
+        out[:, :L] = Xo[self.perm].T
+        return torch.from_numpy(out).to(_dev())
+
+    def from_gpu_block(self, Yg):
+        Y = Yg.cpu().numpy()[:, :self.o.L].T
+        out = np.empty_like(Y)
+        out[self.perm] = Y
+        return out
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    _dev()
+    c = Case(synth.workload("tiny-helix"))
+    c.upload_V()
+    return c
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def test_inverse_transform_parity(tiny):
+    X = synth.random_block(tiny.o.mnk, 5, 21)
+    g = torch.empty((5, tiny.o.n_t1, tiny.o.n_t2, tiny.o.n_r), dtype=torch.complex128, device=_dev())
+    tiny.g.transform_inverse(tiny.to_gpu_block(X), g)
+    ref = np.moveaxis(ot.inverse_separable(tiny.o, X), -1, 0)
+    assert _rel(g.cpu().numpy(), ref) < TOL64
+
+
+def test_forward_transform_parity(tiny):
+    rng = np.random.default_rng(4)
+    shape = (3, tiny.o.n_t1, tiny.o.n_t2, tiny.o.n_r)
+    gr = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    Xg = torch.zeros((3, tiny.o.L), dtype=torch.complex128, device=_dev())
+    tiny.g.transform_forward(torch.from_numpy(gr).to(_dev()), Xg)
+    ref = ot.forward_separable(tiny.o, np.moveaxis(gr, 0, -1))
+    assert _rel(tiny.from_gpu_block(Xg), ref) < TOL64
+
+
+@pytest.mark.parametrize("nvec,ld_pad", [(1, 0), (8, 0), (67, 5)])
+def test_apply_H_parity_tiny(tiny, nvec, ld_pad):
+    HA = oh.dense_explicit(tiny.o, tiny.V)
+    X = synth.random_block(tiny.o.mnk, nvec, 100 + nvec)
+    ld = tiny.o.L + ld_pad
+    Xg = tiny.to_gpu_block(X, ld)
+    Yg = torch.full((nvec, ld), 7.0 + 0j, dtype=torch.complex128, device=_dev())
+    tiny.g.apply_H(Xg, Yg)
+    torch.cuda.synchronize()
+    ref = HA @ X
+    Y = tiny.from_gpu_block(Yg)
+    for j in range(nvec):
+        assert np.max(np.abs(Y[:, j] - ref[:, j])) <= TOL64 * np.max(np.abs(ref[:, j])), j
+    if ld_pad:   # padding rows beyond L untouched
+        assert torch.all(Yg[:, tiny.o.L:] == 7.0)
+
+
+def test_apply_H_fp32_parity_tiny(tiny):
+    HA = oh.dense_explicit(tiny.o, tiny.V)
+    X = synth.random_block(tiny.o.mnk, 16, 5)
+    Yg = torch.zeros((16, tiny.o.L), dtype=torch.complex128, device=_dev())
+    tiny.g.apply_H(tiny.to_gpu_block(X), Yg, prec="fp32")
+    ref = HA @ X
+    Y = tiny.from_gpu_block(Yg)
+    for j in range(16):
+        assert np.max(np.abs(Y[:, j] - ref[:, j])) <= TOL32 * np.max(np.abs(ref[:, j])), j
+
+
+def test_apply_H_free_particle_and_constant_potential():
+    w = synth.Workload(name="ragged", R=7.0, tau=5.5, alpha=0.3, ecut=11.0, eta=0.21,
+                       n_t1=20, n_t2=30, n_r=52)
+    c = Case(w, potential=False)
+    X = synth.random_block(c.o.mnk, 9, 3)
+    Xg = c.to_gpu_block(X)
+    Yg = torch.zeros_like(Xg)
+    c.upload_V(np.zeros_like(c.V))
+    c.g.apply_H(Xg, Yg)
+    ref = c.o.kappa[:, None] * X
+    assert _rel(c.from_gpu_block(Yg), ref) < TOL64
+    c.upload_V(np.full_like(c.V, -1.25))
+    c.g.apply_H(Xg, Yg)
+    ref = (c.o.kappa[:, None] - 1.25) * X
+    assert _rel(c.from_gpu_block(Yg), ref) < 1e-11   # radial orthogonality holds to ~1e-13 at n_r = 52
+
+
+def test_apply_H_is_hermitian_and_deterministic(tiny):
+    x = synth.random_block(tiny.o.mnk, 2, 8)
+    Xg = tiny.to_gpu_block(x)
+    Yg = torch.zeros_like(Xg)
+    tiny.g.apply_H(Xg, Yg)
+    Y2 = torch.zeros_like(Xg)
+    tiny.g.apply_H(Xg, Y2)
+    assert torch.equal(Yg, Y2)
+    Y = tiny.from_gpu_block(Yg)
+    lhs = np.vdot(x[:, 1], Y[:, 0])
+    rhs = np.conj(np.vdot(x[:, 0], Y[:, 1]))
+    assert abs(lhs - rhs) < 1e-13
+
+
+def test_apply_H_empty_and_errors(tiny):
+    Xg = torch.zeros((0, tiny.o.L), dtype=torch.complex128, device=_dev())
+    tiny.g.apply_H(Xg, Xg.clone())
+    bad = torch.zeros((2, tiny.o.L - 1), dtype=torch.complex128, device=_dev())
+    with pytest.raises(helic.HelicError) as e:
+        tiny.g.apply_H(bad, bad.clone())
+    assert e.value.status == helic.ERR_INVALID
+    fresh = helic.Basis.from_workload(tiny.w)
+    X = torch.zeros((1, tiny.o.L), dtype=torch.complex128, device=_dev())
+    with pytest.raises(helic.HelicError) as e:
+        fresh.apply_H(X, X.clone())
+    assert e.value.status == helic.ERR_STATE
+
+
+def test_precondition_parity(tiny):
+    Rr = synth.random_block(tiny.o.mnk, 6, 17, normalize=False)
+    Rr[:, 2] = 0.0
+    Rg = tiny.to_gpu_block(Rr)
+    Wg = torch.zeros_like(Rg)
+    tiny.g.precondition(Rg, Wg)
+    ref = op.tpa_apply(tiny.o.kappa, Rr)
+    assert _rel(tiny.from_gpu_block(Wg), ref) < 1e-14
+    tiny.g.precondition(Rg, Rg)   # in place
+    assert _rel(tiny.from_gpu_block(Rg), ref) < 1e-14
+
+
+@pytest.mark.parametrize("name", ["nanotube-ecut25"])
+def test_apply_H_full_size_sampled(name):
+    """Full workload size in the launch configuration of the benchmark (one
+    64-vector block); columns 0, 31 and 63 checked against the matrix-free
+    oracle, the rest through Hermiticity of sampled pairs."""
+    w = synth.workload(name)
+    c = Case(w)
+    c.upload_V()
+    X = synth.random_block(c.o.mnk, 64, 1234)
+    Xg = c.to_gpu_block(X)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        Yg = torch.zeros_like(Xg)
+        c.g.apply_H(Xg, Yg, prec=prec)
+        Y = c.from_gpu_block(Yg)
+        cols = [0, 31, 63]
+        ref = oh.apply(c.o, c.V, X[:, cols])
+        for i, j in enumerate(cols):
+            err = np.max(np.abs(Y[:, j] - ref[:, i])) / np.max(np.abs(ref[:, i]))
+            print(f"[{name} {prec}] column {j} rel err {err:.2e}", flush=True)
+            assert err <= tol
+        G = X.conj().T @ Y
+        herm = np.max(np.abs(G - G.conj().T)) / np.max(np.abs(G))
+        assert herm < (1e-12 if prec == "fp64" else 1e-5)
