@@ -1,0 +1,220 @@
+"""Benchmark of the helical-wave Hamiltonian apply on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--workload nanotube-ecut25]
+
+One step applies H to a block of 64 coefficient vectors (the whole H*X path:
+radial inverse GEMMs, angular inverse DFT / potential / forward DFT per
+radius, radial forward GEMMs with the kinetic diagonal).  The block, the
+potential and every table are resident in HBM before timing starts.  Rank 0
+prints one JSON line with the throughput in vector applications per second,
+the roofline position of the dominant kernel and the CPU oracle's throughput
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "H·X vec-applies/s (64-vec block) + time-to-n-eigenpairs, mixed vs FP64 @1e-8Ha"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector and FP64 matrix (dense)
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X FP32 matrix (dense)
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
+STAGES = ("k_radial_inverse", "k_angular", "k_radial_forward")
+KERNEL_SOURCES = ("paper_2210_12252_amd/csrc/kernels.hpp", "paper_2210_12252_amd/csrc/device.hip")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_counts(L, n_modes, n1, n2, n_r, nvec, elem):
+    """Algorithmic flops and HBM bytes per launch of each stage kernel.
+
+    Radial stages: 4 real flops per (coefficient, radius) pair (real table
+    times complex value); bytes = coefficients in (16 B each, complex double)
+    plus mode values out (2 * elem B each), the kinetic stage also reading X
+    and writing Y.  Angular stage: nominal 5 N log2 N flops per complex 2D
+    DFT of N = n1 * n2 points, two per slab, plus 2 N for the real potential;
+    bytes = mode values in and out (2 * 2 * elem B each) plus the potential
+    once (elem B per grid point)."""
+    N = n1 * n2
+    slabs = nvec * n_r
+    modes_bytes = 2 * elem * n_r * n_modes * nvec
+    inv = dict(flops=4.0 * n_r * L * nvec, bytes=16.0 * L * nvec + modes_bytes)
+    ang = dict(flops=slabs * (2 * 5.0 * N * math.log2(N) + 2.0 * N),
+               bytes=2.0 * modes_bytes + elem * N * n_r)
+    fwd = dict(flops=4.0 * n_r * L * nvec + 2.0 * L * nvec, bytes=modes_bytes + 32.0 * L * nvec)
+    return dict(zip(STAGES, (inv, ang, fwd)))
+
+
+def cpu_baseline(w, nsample: int):
+    """The CPU oracle's matrix-free H*X on `nsample` vectors of the same
+    workload, timed on the host."""
+    import numpy as np
+
+    import synth
+    from oracle import basis as ob
+    from oracle import hamiltonian as oh
+    o = ob.basis_for(w)
+    atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
+    V = synth.potential_at(o.theta1, o.theta2, o.r, w.tau, w.alpha, atoms)
+    X = synth.random_block(o.mnk, nsample, 1234)
+    c0, t0 = time.process_time(), time.perf_counter()
+    Y = oh.apply(o, V, X)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    assert np.all(np.isfinite(Y))
+    return dict(value=nsample / wall, unit="vec-applies/s", cores=max(1, round(cpu / wall)),
+                kind="oracle", sample=f"matrix-free oracle H*X (explicit DFT sums, FP64) on {nsample} of the "
+                f"64 block vectors of {w.name}, {wall:.1f} s wall on {os.cpu_count()} host cores")
+
+
+def load_traffic(name: str, nvec: int):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or
+    None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_hash") != kernel_hash() or t.get("nvec") != nvec:
+        return None
+    return t
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="nanotube-ecut25")
+    ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"))
+    ap.add_argument("--cpu-sample", type=int, default=32, help="vectors for the CPU oracle leg (0: skip)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for counter calibration)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; the helical-wave solve shards over Bloch "
+              "parameters without communication, which is not exercised here.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2210_12252_amd import helic
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    w = synth.workload(args.workload)
+    nvec = 64
+    t_setup = time.perf_counter()
+    b = helic.Basis.from_workload(w)
+    t1, t2, r, _ = b.grid()
+    atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
+    V = synth.potential_at(t1, t2, r, w.tau, w.alpha, atoms)
+    b.set_potential(torch.from_numpy(V).to(dev))
+    mnk, _ = b.indices()
+    X = torch.from_numpy(np.ascontiguousarray(synth.random_block(mnk, nvec, 1234).T)).to(dev)
+    Y = torch.empty_like(X)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print(f"[bench] {w.name}: L={b.L} modes={b.n_modes} grid={b.n_t1}x{b.n_t2}x{b.n_r} "
+          f"setup {t_setup:.2f} s", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        b.apply_H(X, Y, prec=args.prec)
+    torch.cuda.synchronize()
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # timed region: K steps bracketed by synchronisation on both sides
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_stage, ms_total = b.profile_apply(X, Y, prec=args.prec, nrep=args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = nvec * args.steps / wall
+    print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (events {ms_total:.3f} ms), stages "
+          + ", ".join(f"{s} {m:.3f} ms" for s, m in zip(STAGES, ms_stage)), file=sys.stderr, flush=True)
+
+    elem = 8 if args.prec == "fp64" else 4
+    counts = algorithmic_counts(b.L, b.n_modes, b.n_t1, b.n_t2, b.n_r, nvec, elem)
+    stage_info = {}
+    for s, ms in zip(STAGES, ms_stage):
+        c = counts[s]
+        stage_info[s] = dict(ms=round(ms, 4), GBs=round(c["bytes"] / (ms * 1e-3) / 1e9, 1),
+                             TFLOPs=round(c["flops"] / (ms * 1e-3) / 1e12, 2))
+    dom = STAGES[int(np.argmax(ms_stage))]
+    c = counts[dom]
+    ms = float(np.max(ms_stage))
+    intensity = c["flops"] / c["bytes"]
+    if dom == "k_angular":
+        peak_tf = FP64_PEAK_TFLOPS if elem == 8 else FP32_VALU_PEAK_TFLOPS
+        compute_kind = "alu"
+    else:
+        peak_tf = FP64_PEAK_TFLOPS if elem == 8 else FP32_MFMA_PEAK_TFLOPS
+        compute_kind = "mfma"
+    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
+    traffic = load_traffic(dom, nvec)
+    if intensity >= ridge:
+        achieved = c["flops"] / (ms * 1e-3) / 1e12
+        roof = dict(bound=compute_kind, achieved=round(achieved, 3), peak=peak_tf, unit="TFLOP/s",
+                    frac=round(achieved / peak_tf, 4))
+    else:
+        achieved = c["bytes"] / (ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4))
+    roof["kernel"] = dom
+    roof["traffic"] = None if traffic is None else traffic.get("bytes_per_launch")
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "vec-applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "L": b.L, "block": nvec, "grid": f"{b.n_t1}x{b.n_t2}x{b.n_r}",
+                   "modes": b.n_modes, "R": w.R, "tau": w.tau, "alpha": round(w.alpha, 6), "ecut": w.ecut,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "stages": stage_info,
+    }
+    if args.cpu_sample > 0:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    b.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

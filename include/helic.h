@@ -129,6 +129,16 @@ helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx
 helic_status helic_transform_forward(helic_basis h, const double* g, double* X, int64_t ldx,
                                      int32_t nvec, void* stream);
 
+/* Timing aid: run `nrep` applications of H to the same block exactly as
+ * helic_apply_H does (nvec <= 64), recording HIP events on `stream` around
+ * each of the three stage kernels (radial inverse, angular, radial forward).
+ * ms_stage (host, 3 doubles) receives each stage's mean duration in ms and
+ * *ms_total (host, may be NULL) the mean time of one whole application.
+ * Synchronises `stream` before returning. */
+helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                                 int32_t nvec, helic_prec prec, int32_t nrep, void* stream,
+                                 double* ms_stage, double* ms_total);
+
 /* Teter-Payne-Allan preconditioner (Sec. 3.5) of nvec residual columns:
  * W_ij = K(kappa_i / T_j) R_ij, K(g) = (27+18g+12g^2+8g^3) /
  * (27+18g+12g^2+8g^3+16g^4), T_j = sum_i kappa_i |R_ij|^2 / sum_i |R_ij|^2

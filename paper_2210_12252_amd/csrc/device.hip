@@ -401,7 +401,7 @@ void device_release(helic_basis_s* h) {
 // Launches of the three H*X stages for one chunk of at most `chunk` vectors.
 template <typename T>
 helic_status launch_apply(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
-                          int nvec, hipStream_t st, int mode) {
+                          int nvec, hipStream_t st, int mode, hipEvent_t* ev = nullptr) {
   DeviceState* d = h->dev;
   const int ng = (int)h->groups.size();
   const int nm = (int)h->modes.size();
@@ -416,23 +416,27 @@ helic_status launch_apply(helic_basis_s* h, const double* X, int64_t ldx, double
   const size_t lds_fwd = (size_t)FWD_RCHUNK * h->max_colpad * sizeof(T);
   const int wg_ang = 8 * ((nvec * h->n_r + 7) / 8);
   const size_t lds_ang = angular_lds_bytes(h, sizeof(T));
+  if (ev) HIP_TRY(hipEventRecord(ev[0], st));
   hipLaunchKernelGGL((k_radial_inverse<T>), dim3(wg_rad), dim3(NT), lds_inv, st, X, ldx, gh, nvec, ng,
                      h->n_r, nm, d->groups, d->row_ck, tinv);
   HIP_TRY(hipGetLastError());
+  if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   hipLaunchKernelGGL((k_angular<T, 0>), dim3(wg_ang), dim3(NT), lds_ang, st, gh, nullptr, nullptr, Vs, nvec,
                      h->n_r, nm, d->modes, d->rows1, (int)h->rows1.size(), tw1, tw2, d->plan1, d->plan2,
                      (T)1);
   HIP_TRY(hipGetLastError());
+  if (ev) HIP_TRY(hipEventRecord(ev[2], st));
   hipLaunchKernelGGL((k_radial_forward<T>), dim3(wg_rad), dim3(NT), lds_fwd, st, gh, X, ldx, Y, ldy, nvec,
                      ng, h->n_r, nm, d->groups, d->modes, d->kappa, tfwd, mode);
   HIP_TRY(hipGetLastError());
+  if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   return HELIC_OK;
 }
 
 template helic_status launch_apply<double>(helic_basis_s*, const double*, int64_t, double*, int64_t, int,
-                                           hipStream_t, int);
+                                           hipStream_t, int, hipEvent_t*);
 template helic_status launch_apply<float>(helic_basis_s*, const double*, int64_t, double*, int64_t, int,
-                                          hipStream_t, int);
+                                          hipStream_t, int, hipEvent_t*);
 
 helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
                           int nvec, helic_prec prec, hipStream_t st) {
@@ -509,6 +513,45 @@ helic_status helic_apply_H(helic_basis h, const double* X, int64_t ldx, double* 
   helic_status s = ensure_device(h);
   if (s != HELIC_OK) return s;
   return apply_H_impl(h, X, ldx, Y, ldy, nvec, prec, reinterpret_cast<hipStream_t>(stream));
+}
+
+helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                                 int32_t nvec, helic_prec prec, int32_t nrep, void* stream, double* ms_stage,
+                                 double* ms_total) {
+  if (!h || !ms_stage) return fail(HELIC_ERR_INVALID, "null argument");
+  if (nvec <= 0 || nvec > APPLY_CHUNK || !X || !Y || ldx < h->L || ldy < h->L || nrep <= 0)
+    return fail(HELIC_ERR_INVALID, "bad block arguments (1 <= nvec <= 64, nrep >= 1)");
+  if (prec != HELIC_FP64 && prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
+  helic_status s = ensure_device(h);
+  if (s != HELIC_OK) return s;
+  const size_t elem = prec == HELIC_FP64 ? sizeof(double) : sizeof(float);
+  if ((s = ensure_workspace(h, nvec, elem)) != HELIC_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<hipEvent_t> ev(4 * (size_t)nrep, nullptr);
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  for (int i = 0; i < nrep && s == HELIC_OK; ++i)
+    s = prec == HELIC_FP64 ? launch_apply<double>(h, X, ldx, Y, ldy, nvec, st, 1, &ev[4 * i])
+                           : launch_apply<float>(h, X, ldx, Y, ldy, nvec, st, 1, &ev[4 * i]);
+  double acc[3] = {0, 0, 0}, tot = 0;
+  if (s == HELIC_OK) {
+    hipError_t e = hipStreamSynchronize(st);
+    for (int i = 0; i < nrep && e == hipSuccess; ++i) {
+      float ms;
+      for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        e = hipEventElapsedTime(&ms, ev[4 * i + k], ev[4 * i + k + 1]);
+        acc[k] += ms;
+      }
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[4 * i], ev[4 * i + 3]);
+      tot += ms;
+    }
+    if (e != hipSuccess) s = fail(HELIC_ERR_HIP, std::string("event timing: ") + hipGetErrorString(e));
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (s != HELIC_OK) return s;
+  for (int k = 0; k < 3; ++k) ms_stage[k] = acc[k] / nrep;
+  if (ms_total) *ms_total = tot / nrep;
+  return HELIC_OK;
 }
 
 helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx, double* g, int32_t nvec,

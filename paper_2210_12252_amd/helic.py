@@ -25,7 +25,7 @@ PREC = {"fp64": FP64, "fp32": FP32}
 # every function declared in include/helic.h
 EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "helic_basis_indices",
            "helic_grid", "helic_set_potential", "helic_apply_H", "helic_transform_inverse",
-           "helic_transform_forward", "helic_precondition", "helic_eigensolve",
+           "helic_transform_forward", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
            "helic_util_bessel_j", "helic_util_bessel_zeros", "helic_util_gauss_jacobi",
            "helic_last_error")
 
@@ -73,6 +73,7 @@ def load() -> ctypes.CDLL:
         "helic_transform_inverse": [_P, _P, _I64, _P, _I32, _P],
         "helic_transform_forward": [_P, _P, _P, _I64, _I32, _P],
         "helic_precondition": [_P, _P, _I64, _P, _I64, _I32, _P],
+        "helic_profile_apply": [_P, _P, _I64, _P, _I64, _I32, _I32, _I32, _P, _PD, _PD],
         "helic_eigensolve": [_P, _I32, _I32, _D, _I32, _I32, ctypes.c_uint64, _PD, _PD, _P, _I64,
                              _PI32, _P],
         "helic_util_bessel_j": [_I32, _I32, _PD, _PD],
@@ -210,6 +211,20 @@ def transform_forward(h, g, X, stream=None):
                                           nx, _stream(stream)))
 
 
+def profile_apply(h, X, Y, prec="fp64", nrep=1, stream=None):
+    """Mean per-stage and total durations (ms) of `nrep` applications."""
+    nx, ldx = _block(X, "X")
+    ny, ldy = _block(Y, "Y")
+    if ny < nx:
+        raise ValueError("Y has fewer columns than X")
+    ms = np.zeros(3)
+    tot = ctypes.c_double(0.0)
+    _check(load().helic_profile_apply(h, ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(Y.data_ptr()), ldy,
+                                      nx, PREC[prec], nrep, _stream(stream), _ptr(ms, ctypes.c_double),
+                                      ctypes.byref(tot)))
+    return ms, tot.value
+
+
 def precondition(h, R, W, stream=None):
     nr_, ldr = _block(R, "R")
     nw, ldw = _block(W, "W")
@@ -286,6 +301,9 @@ class Basis:
 
     def precondition(self, R, W, stream=None):
         precondition(self.h, R, W, stream)
+
+    def profile_apply(self, X, Y, prec="fp64", nrep=1, stream=None):
+        return profile_apply(self.h, X, Y, prec, nrep, stream)
 
     def eigensolve(self, nev, **kw):
         return eigensolve(self.h, nev, **kw)
