@@ -1,0 +1,250 @@
+// Angular stage of H*X specialised for compile-time theta2 grid sizes.
+//
+// For one radius r the angular part of the operator maps the mode block
+// G_{m,n}(r) to H_{m,n}(r) = crop(DFT2(V(.,.,r) * IDFT2(pad(G)))) / (N1 N2)
+// (Alg. 2, the product with V, Alg. 4).  Written per theta2 column j, the
+// theta1 part (inverse DFT over m, multiply by the real V, forward DFT back
+// to m) is a circular convolution in m:
+//
+//   out[m'] = sum_m Vhat_j[m' - m] in[m],
+//   Vhat_j[d] = 1/(N1 N2) sum_i V(theta1_i, theta2_j, r) exp(-i 2 pi d i / N1),
+//
+// exact for the discrete operator (the N1-periodicity of Vhat reproduces the
+// aliasing of the grid product), and with only M = m_max - m_min + 1 rows of
+// m it costs M^2 complex multiply-adds per column and needs no theta1 FFT.
+// The theta2 direction keeps the FFT: a length N2 = P * P transform per m row
+// done as P-point DFTs in registers, a twiddle, one exchange through LDS and
+// P-point DFTs again (the four-step factorisation).
+//
+// One workgroup owns one radius and walks over a chunk of vectors, so the
+// Vhat table of that radius is read into LDS once per workgroup.
+#pragma once
+#include "kernels.hpp"
+
+namespace helic {
+
+// ---------------------------------------------------------------- constexpr trig
+// cos/sin of 2 pi t / S for integers t, S: reduce to the nearest multiple of
+// pi/2 with integer arithmetic, then Taylor series on |x| <= pi/4.
+constexpr double cx_taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 14; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 14; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_twopi_cos(long t, long S) {
+  t %= S;
+  if (t < 0) t += S;
+  long k = (4 * t + S / 2) / S;                 // nearest quadrant
+  double x = 1.5707963267948966192 * (double)(4 * t - k * S) / (double)S;
+  double c = cx_taylor_cos(x), s = cx_taylor_sin(x);
+  switch (k & 3) {
+    case 0: return c;
+    case 1: return -s;
+    case 2: return -c;
+    default: return s;
+  }
+}
+constexpr double cx_twopi_sin(long t, long S) {
+  t %= S;
+  if (t < 0) t += S;
+  long k = (4 * t + S / 2) / S;
+  double x = 1.5707963267948966192 * (double)(4 * t - k * S) / (double)S;
+  double c = cx_taylor_cos(x), s = cx_taylor_sin(x);
+  switch (k & 3) {
+    case 0: return s;
+    case 1: return c;
+    case 2: return -s;
+    default: return -c;
+  }
+}
+
+// ---------------------------------------------------------------- register DFTs
+// y_k = sum_n v_n exp(s 2 pi i n k / S), s = +1 if INV else -1, all in
+// registers (compile-time indices only).
+template <typename T, int S, bool INV>
+__device__ __forceinline__ void dft_reg(cplx<T>* v);
+
+template <int S>
+constexpr int first_radix() {
+  return (S % 4 == 0 && S != 4) ? 4 : (S % 3 == 0 && S != 3) ? 3 : (S % 2 == 0 && S != 2) ? 2 : (S % 5 == 0 && S != 5) ? 5 : S;
+}
+
+template <typename T, int S, bool INV>
+__device__ __forceinline__ void dft_reg(cplx<T>* v) {
+  constexpr T sg = INV ? (T)1 : (T)-1;
+  if constexpr (S == 1) {
+    return;
+  } else if constexpr (S == 2) {
+    dft2<T>(v, sg);
+  } else if constexpr (S == 3) {
+    dft3<T>(v, sg);
+  } else if constexpr (S == 4) {
+    dft4<T>(v, sg);
+  } else if constexpr (S == 5) {
+    dft5<T>(v, sg);
+  } else {
+    constexpr int R = first_radix<S>();
+    constexpr int Q = S / R;
+    static_assert(R * Q == S && R > 1 && Q > 1, "size must factor into 2, 3, 4, 5");
+    cplx<T> sub[R][Q];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) sub[r][q] = v[r + R * q];
+      dft_reg<T, Q, INV>(sub[r]);
+#pragma unroll
+      for (int k = 1; k < Q; ++k) {
+        if (r == 0) continue;
+        const T c = (T)cx_twopi_cos((long)r * k, S);
+        const T s = (T)(INV ? cx_twopi_sin((long)r * k, S) : -cx_twopi_sin((long)r * k, S));
+        sub[r][k] = cmul(sub[r][k], cplx<T>{c, s});
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      cplx<T> t[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) t[r] = sub[r][k];
+      dft_reg<T, R, INV>(t);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k + Q * r] = t[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- row transform
+// In-place length N2 = P * P DFT of `rows` rows of A (row stride N2) by
+// P threads per row.  Thread p of a row loads x[p + P q], does the P-point
+// DFT over q, multiplies by exp(s 2 pi i p k / N2), exchanges through LDS so
+// that thread c gets Y[.][c], does the P-point DFT over p and stores
+// X[c + P k1] at its natural position.  All threads of the block must call.
+template <typename T, int N2, int P, int NTF, bool INV>
+__device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw) {
+  static_assert(P * P == N2, "row transform expects N2 = P * P");
+  constexpr int RPB = NTF / P;              // rows per batch
+  const int t = threadIdx.x;
+  const int nb = (rows + RPB - 1) / RPB;
+  for (int b = 0; b < nb; ++b) {            // uniform trip count
+    const int row = b * RPB + t / P;
+    const int p = t % P;
+    const bool act = (t < RPB * P) && row < rows;
+    cplx<T> v[P];
+    if (act) {
+      cplx<T>* a = A + row * N2;
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = a[p + P * q];
+      dft_reg<T, P, INV>(v);
+      // twiddle exp(s 2 pi i p k / N2); tw[t] = exp(-2 pi i t / N2), p k < N2
+#pragma unroll
+      for (int k = 1; k < P; ++k) {
+        cplx<T> w = tw[p * k];
+        if (INV) w.y = -w.y;
+        v[k] = cmul(v[k], w);
+      }
+    }
+    __syncthreads();
+    if (act) {
+      cplx<T>* a = A + row * N2;
+#pragma unroll
+      for (int k = 0; k < P; ++k) a[p * P + k] = v[k];   // Y[p][k]
+    }
+    __syncthreads();
+    if (act) {
+      cplx<T>* a = A + row * N2;
+      const int c = p;
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = a[q * P + c];   // Y[q][c]
+      dft_reg<T, P, INV>(v);
+    }
+    __syncthreads();
+    if (act) {
+      cplx<T>* a = A + row * N2;
+#pragma unroll
+      for (int k1 = 0; k1 < P; ++k1) a[p + P * k1] = v[k1];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- the kernel
+// GH[v][r][mode] holds G on entry and H on exit (complex T).  Vh[r][j][d]
+// (complex T, d = 0..2 MPAD - 2 for m' - m = d - (MPAD - 1)).  mode_pos[i] =
+// (m_i - m_min) * N2 + (n_i mod N2).  Work: blockIdx -> (radius, vector chunk).
+template <typename T, int N2, int MPAD, int NTF>
+__global__ void __launch_bounds__(NTF)
+k_angular_fast(T* __restrict__ GH, const T* __restrict__ Vh, int nvec, int n_r, int n_modes,
+               const int32_t* __restrict__ mode_pos, const cplx<T>* __restrict__ tw2g, int vchunk) {
+  constexpr int P = (N2 == 16) ? 4 : (N2 == 64) ? 8 : (N2 == 81) ? 9 : (N2 == 36) ? 6 : (N2 == 100) ? 10 : 0;
+  static_assert(P > 0, "unsupported N2");
+  constexpr int ND = 2 * MPAD - 1;
+  constexpr int OG = NTF / N2;                    // threads per column in the convolution
+  constexpr int OPT = (MPAD + OG - 1) / OG;       // outputs per thread
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);          // [MPAD][N2]
+  cplx<T>* VhS = A + MPAD * N2;                                // [N2][ND]
+  cplx<T>* tw = VhS + N2 * ND;                                 // [N2]
+  const int nchunks = (nvec + vchunk - 1) / vchunk;
+  const int slot = xcd_slot(n_r * nchunks);
+  if (slot >= n_r * nchunks) return;
+  const int r = slot / nchunks, ch = slot - r * nchunks;
+  const int v0 = ch * vchunk, v1 = min(nvec, v0 + vchunk);
+  const int t = threadIdx.x;
+  {
+    const cplx<T>* src = reinterpret_cast<const cplx<T>*>(Vh) + (int64_t)r * N2 * ND;
+    for (int i = t; i < N2 * ND; i += NTF) VhS[i] = src[i];
+    for (int i = t; i < N2; i += NTF) tw[i] = tw2g[i];
+  }
+  const int j = t % N2, og = t / N2;
+  const bool conv_act = og < OG;
+  const int a0 = og * OPT;
+  for (int v = v0; v < v1; ++v) {
+    cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + ((int64_t)v * n_r + r) * n_modes;
+    for (int i = t; i < MPAD * N2; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
+    __syncthreads();
+    for (int i = t; i < n_modes; i += NTF) A[mode_pos[i]] = slab[i];
+    __syncthreads();
+    row_dft<T, N2, P, NTF, true>(A, MPAD, tw);
+    // theta1: Toeplitz convolution per column with the spectrum of V
+    cplx<T> acc[OPT];
+#pragma unroll
+    for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
+    if (conv_act) {
+      const cplx<T>* vh = VhS + j * ND + (MPAD - 1) + a0;
+#pragma unroll
+      for (int m = 0; m < MPAD; ++m) {
+        const cplx<T> x = A[m * N2 + j];
+#pragma unroll
+        for (int o = 0; o < OPT; ++o) {
+          if (a0 + o < MPAD) {
+            const cplx<T> w = vh[o - m];
+            acc[o].x += w.x * x.x - w.y * x.y;
+            acc[o].y += w.x * x.y + w.y * x.x;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (conv_act) {
+#pragma unroll
+      for (int o = 0; o < OPT; ++o)
+        if (a0 + o < MPAD) A[(a0 + o) * N2 + j] = acc[o];
+    }
+    __syncthreads();
+    row_dft<T, N2, P, NTF, false>(A, MPAD, tw);
+    for (int i = t; i < n_modes; i += NTF) slab[i] = A[mode_pos[i]];
+    __syncthreads();
+  }
+}
+
+}  // namespace helic

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -12,6 +13,7 @@
 #include "device_state.hpp"
 #include "helic_internal.h"
 #include "kernels.hpp"
+#include "angular_fast.hpp"
 
 namespace helic {
 
@@ -214,6 +216,36 @@ k_relayout_potential(const double* __restrict__ V, double* __restrict__ Vs, floa
   }
 }
 
+// Vh[r][j][d] = 1/(n1 n2) sum_i V[i][j][r] exp(-i 2 pi (d - (mpad - 1)) i / n1)
+__global__ void __launch_bounds__(NT)
+k_potential_spectrum(const double* __restrict__ V, double* __restrict__ Vh, float* __restrict__ Vhf, int n1,
+                     int n2, int n_r, int mpad) {
+  const int nd = 2 * mpad - 1;
+  const int64_t total = (int64_t)n_r * n2 * nd;
+  const double PI2 = 6.283185307179586477;
+  for (int64_t idx = blockIdx.x * (int64_t)NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
+    const int d = (int)(idx % nd);
+    const int64_t rj = idx / nd;
+    const int j = (int)(rj % n2), r = (int)(rj / n2);
+    const int dd = d - (mpad - 1);
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < n1; ++i) {
+      int t = (dd * i) % n1;
+      if (t < 0) t += n1;
+      double sn, cs;
+      sincos(PI2 * t / n1, &sn, &cs);
+      const double x = V[((int64_t)i * n2 + j) * n_r + r];
+      re += x * cs;
+      im -= x * sn;
+    }
+    const double sc = 1.0 / ((double)n1 * n2);
+    Vh[2 * idx] = re * sc;
+    Vh[2 * idx + 1] = im * sc;
+    Vhf[2 * idx] = (float)(re * sc);
+    Vhf[2 * idx + 1] = (float)(im * sc);
+  }
+}
+
 // Teter-Payne-Allan: partial sums of kappa |r|^2 and |r|^2 per (chunk, column)
 __global__ void __launch_bounds__(NT)
 k_tpa_partial(const double* __restrict__ Rr, int64_t ldr, const double* __restrict__ kappa, int64_t L,
@@ -296,6 +328,59 @@ size_t angular_lds_bytes(const helic_basis_s* h, size_t elem) {
          (size_t)h->rows1.size() * sizeof(int32_t);
 }
 
+// Instantiated (n_t2, padded m count, block size) of the specialised angular kernel.
+struct FastVariant { int n2, mpad, ntf; };
+constexpr FastVariant FAST_VARIANTS[] = {{16, 12, 256}, {16, 16, 256}, {64, 24, 256}, {64, 32, 256},
+                                         {81, 24, 512}, {81, 32, 512}};
+
+template <typename T>
+size_t fast_lds_bytes(int n2, int mpad) {
+  return ((size_t)mpad * n2 + (size_t)n2 * (2 * mpad - 1) + n2) * sizeof(cplx<T>);
+}
+
+template <typename T, int N2, int MPAD, int NTF>
+helic_status set_fast_limit() {
+  HIP_TRY(hipFuncSetAttribute((const void*)k_angular_fast<T, N2, MPAD, NTF>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  return HELIC_OK;
+}
+
+template <typename T>
+helic_status set_fast_limits() {
+  helic_status s;
+  if ((s = set_fast_limit<T, 16, 12, 256>()) || (s = set_fast_limit<T, 16, 16, 256>()) ||
+      (s = set_fast_limit<T, 64, 24, 256>()) || (s = set_fast_limit<T, 64, 32, 256>()) ||
+      (s = set_fast_limit<T, 81, 24, 512>()) || (s = set_fast_limit<T, 81, 32, 512>()))
+    return s;
+  return HELIC_OK;
+}
+
+template <typename T>
+helic_status launch_fast(helic_basis_s* h, T* gh, int nvec, hipStream_t st, const cplx<T>* tw2) {
+  DeviceState* d = h->dev;
+  const T* Vh = std::is_same<T, double>::value ? (const T*)d->Vh : (const T*)d->Vhf;
+  const int vchunk = 4;
+  const int work = h->n_r * ((nvec + vchunk - 1) / vchunk);
+  const dim3 grid(8 * ((work + 7) / 8));
+  const size_t lds = fast_lds_bytes<T>(h->n_t2, d->fast_mpad);
+  const int nm = (int)h->modes.size();
+#define HELIC_FAST_CASE(N2_, MP_, NTF_)                                                                   \
+  if (h->n_t2 == N2_ && d->fast_mpad == MP_) {                                                          \
+    hipLaunchKernelGGL((k_angular_fast<T, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, gh, Vh, nvec, h->n_r, \
+                       nm, d->mode_pos, tw2, vchunk);                                                   \
+    HIP_TRY(hipGetLastError());                                                                         \
+    return HELIC_OK;                                                                                    \
+  }
+  HELIC_FAST_CASE(16, 12, 256)
+  HELIC_FAST_CASE(16, 16, 256)
+  HELIC_FAST_CASE(64, 24, 256)
+  HELIC_FAST_CASE(64, 32, 256)
+  HELIC_FAST_CASE(81, 24, 512)
+  HELIC_FAST_CASE(81, 32, 512)
+#undef HELIC_FAST_CASE
+  return fail(HELIC_ERR_STATE, "no specialised angular kernel for this grid");
+}
+
 template <typename T>
 helic_status set_lds_limits() {
   const int lim = 160 * 1024;
@@ -305,6 +390,12 @@ helic_status set_lds_limits() {
   HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   return HELIC_OK;
+}
+
+// HELIC_GENERIC_ANGULAR=1 forces the general angular kernel (for comparison).
+bool fast_disabled() {
+  const char* e = std::getenv("HELIC_GENERIC_ANGULAR");
+  return e && e[0] == '1';
 }
 
 FftPlan make_plan(int n, const std::vector<int32_t>& f) {
@@ -369,6 +460,30 @@ helic_status ensure_device(helic_basis_s* h) {
     return s;
   d->plan1 = make_plan(h->n_t1, h->fac1);
   d->plan2 = make_plan(h->n_t2, h->fac2);
+  // specialised angular kernel: smallest instantiated padding of the m count
+  int mlo = 1 << 30, mhi = -(1 << 30);
+  for (const Mode& m : h->modes) { mlo = std::min(mlo, m.m); mhi = std::max(mhi, m.m); }
+  d->m_min = mlo;
+  d->m_count = mhi - mlo + 1;
+  d->fast_mpad = 0;
+  if (!fast_disabled()) {
+    for (const FastVariant& fv : FAST_VARIANTS) {
+      if (fv.n2 == h->n_t2 && fv.mpad >= d->m_count && fast_lds_bytes<double>(fv.n2, fv.mpad) <= 160 * 1024 &&
+          (d->fast_mpad == 0 || fv.mpad < d->fast_mpad)) {
+        d->fast_mpad = fv.mpad;
+        d->fast_ntf = fv.ntf;
+      }
+    }
+  }
+  if (d->fast_mpad) {
+    if ((s = set_fast_limits<double>()) || (s = set_fast_limits<float>())) return s;
+    std::vector<int32_t> mp(h->modes.size());
+    for (size_t i = 0; i < h->modes.size(); ++i) mp[i] = (h->modes[i].m - mlo) * h->n_t2 + h->modes[i].bin2;
+    if ((s = upload(mp, &d->mode_pos))) return s;
+    const size_t nvh = (size_t)h->n_r * h->n_t2 * (2 * d->fast_mpad - 1) * 2;
+    HIP_TRY(hipMalloc((void**)&d->Vh, nvh * sizeof(double)));
+    HIP_TRY(hipMalloc((void**)&d->Vhf, nvh * sizeof(float)));
+  }
   return HELIC_OK;
 }
 
@@ -390,7 +505,7 @@ void device_release(helic_basis_s* h) {
   if (!d) return;
   void* ptrs[] = {d->groups, d->modes, d->row_ck, d->kappa, d->rows1, d->tinv64, d->tfwd64,
                   d->tinv32, d->tfwd32, d->tw1, d->tw2, d->tw1f, d->tw2f, d->Vs, d->Vsf,
-                  d->gh, d->part};
+                  d->gh, d->part, d->mode_pos, d->Vh, d->Vhf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   release_solver_state(d);
@@ -421,10 +536,15 @@ helic_status launch_apply(helic_basis_s* h, const double* X, int64_t ldx, double
                      h->n_r, nm, d->groups, d->row_ck, tinv);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-  hipLaunchKernelGGL((k_angular<T, 0>), dim3(wg_ang), dim3(NT), lds_ang, st, gh, nullptr, nullptr, Vs, nvec,
-                     h->n_r, nm, d->modes, d->rows1, (int)h->rows1.size(), tw1, tw2, d->plan1, d->plan2,
-                     (T)1);
-  HIP_TRY(hipGetLastError());
+  if (d->fast_mpad) {
+    helic_status s = launch_fast<T>(h, gh, nvec, st, tw2);
+    if (s != HELIC_OK) return s;
+  } else {
+    hipLaunchKernelGGL((k_angular<T, 0>), dim3(wg_ang), dim3(NT), lds_ang, st, gh, nullptr, nullptr, Vs, nvec,
+                       h->n_r, nm, d->modes, d->rows1, (int)h->rows1.size(), tw1, tw2, d->plan1, d->plan2,
+                       (T)1);
+    HIP_TRY(hipGetLastError());
+  }
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
   hipLaunchKernelGGL((k_radial_forward<T>), dim3(wg_rad), dim3(NT), lds_fwd, st, gh, X, ldx, Y, ldy, nvec,
                      ng, h->n_r, nm, d->groups, d->modes, d->kappa, tfwd, mode);
@@ -498,6 +618,13 @@ helic_status helic_set_potential(helic_basis h, const double* V, void* stream) {
   hipLaunchKernelGGL(k_relayout_potential, dim3(nb), dim3(NT), 0, st, V, d->Vs, d->Vsf, h->n_t1, h->n_t2,
                      h->n_r, 1.0 / ((double)h->n_t1 * h->n_t2));
   HIP_TRY(hipGetLastError());
+  if (d->fast_mpad) {
+    const size_t nvh = (size_t)h->n_r * h->n_t2 * (2 * d->fast_mpad - 1);
+    const int nbh = (int)std::min<size_t>(4096, (nvh + NT - 1) / NT);
+    hipLaunchKernelGGL(k_potential_spectrum, dim3(nbh), dim3(NT), 0, st, V, d->Vh, d->Vhf, h->n_t1, h->n_t2,
+                       h->n_r, d->fast_mpad);
+    HIP_TRY(hipGetLastError());
+  }
   d->have_potential = true;
   return HELIC_OK;
 }

@@ -31,6 +31,13 @@ struct DeviceState {
   bool have_potential = false;
   void* gh = nullptr;
   size_t gh_bytes = 0;
+  // specialised angular stage (theta1 convolution with the spectrum of V)
+  int fast_mpad = 0;              // 0: use the general angular kernel
+  int fast_ntf = 256;
+  int m_min = 0, m_count = 0;
+  int32_t* mode_pos = nullptr;    // (m - m_min) * n_t2 + (n mod n_t2) per mode
+  double* Vh = nullptr;           // [n_r][n_t2][2 * fast_mpad - 1] complex
+  float* Vhf = nullptr;
   double* part = nullptr;
   size_t part_bytes = 0;
   SolverState* solver = nullptr;

@@ -206,3 +206,22 @@ def test_apply_H_full_size_sampled(name):
         G = X.conj().T @ Y
         herm = np.max(np.abs(G - G.conj().T)) / np.max(np.abs(G))
         assert herm < (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_general_and_specialised_angular_kernels_agree(tiny, monkeypatch):
+    """The general LDS-FFT angular kernel and the specialised convolution
+    kernel compute the same operator (both are checked against the oracle
+    elsewhere; here on the same inputs, FP64 and FP32)."""
+    monkeypatch.setenv("HELIC_GENERIC_ANGULAR", "1")
+    gen = helic.Basis.from_workload(tiny.w)
+    gen.set_potential(torch.from_numpy(tiny.V).to(_dev()))
+    monkeypatch.delenv("HELIC_GENERIC_ANGULAR")
+    X = tiny.to_gpu_block(synth.random_block(tiny.o.mnk, 12, 77))
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        Y1 = torch.zeros_like(X)
+        Y2 = torch.zeros_like(X)
+        gen.apply_H(X, Y1, prec=prec)
+        tiny.g.apply_H(X, Y2, prec=prec)
+        err = (torch.abs(Y1 - Y2).max() / torch.abs(Y1).max()).item()
+        assert err < tol, (prec, err)
+    gen.close()
