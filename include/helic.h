@@ -158,6 +158,35 @@ helic_status helic_eigensolve(helic_basis h, int32_t nev, int32_t block, double 
                               helic_prec prec, uint64_t seed, double* evals, double* resid,
                               double* evecs, int64_t ldv, int32_t* iters, void* stream);
 
+/* Options and statistics of helic_eigensolve_ex. */
+typedef struct {
+  int32_t nev;        /* wanted eigenpairs (lowest), 1 <= nev <= L                     */
+  int32_t block;      /* columns per H*X launch, 1..64                                 */
+  double tol;         /* target ||H x - lambda x||_2 for ||x||_2 = 1 (Ha)              */
+  int32_t maxit;      /* iteration limit                                               */
+  int32_t prec;       /* helic_prec of the H*X applications (FP32: FP64 takes over)    */
+  uint64_t seed;      /* random start                                                  */
+  int32_t precond;    /* 0: Teter-Payne-Allan, 1: none, 2: learned (helic_lpc_*)       */
+  int32_t guard;      /* extra iterated columns beyond nev (-1: automatic)             */
+  double switch_tol;  /* FP32 mode: residual below which FP64 applications take over  */
+} helic_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* iterations run                                             */
+  int32_t iters_low;    /* of which with FP32 H*X                                     */
+  int64_t n_apply;      /* H*X column applications                                    */
+  int32_t n_fallback;   /* iterations where the learned preconditioner fell back      */
+  double t_apply_ms;    /* time in H*X                                                */
+  double t_rr_ms;       /* time in orthogonalisation and Rayleigh-Ritz                */
+  double t_precond_ms;  /* time in residuals and the preconditioner                   */
+  double t_total_ms;    /* wall time of the call                                      */
+} helic_solve_stats;
+
+/* As helic_eigensolve with all options; stats (host) may be NULL. */
+helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* opts, double* evals,
+                                 double* resid, double* evecs, int64_t ldv, helic_solve_stats* stats,
+                                 void* stream);
+
 /* Host utilities used by the basis set-up, exported for testing.
  * helic_util_bessel_j: out[i] = J_p(x[i]) for integer p (any sign), x >= 0.
  * helic_util_bessel_zeros: first `count` positive zeros of J_p.

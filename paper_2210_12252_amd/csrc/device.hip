@@ -307,7 +307,8 @@ k_tpa_apply(const double* __restrict__ Rr, int64_t ldr, double* __restrict__ W, 
   do {                                                                                  \
     hipError_t e_ = (call);                                                             \
     if (e_ != hipSuccess)                                                               \
-      return fail(HELIC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+      return fail(HELIC_ERR_HIP, std::string(#call) + " (line " + std::to_string(__LINE__) + "): " + \
+                                     hipGetErrorString(e_));                            \
   } while (0)
 
 namespace {
@@ -559,8 +560,8 @@ template helic_status launch_apply<float>(helic_basis_s*, const double*, int64_t
                                           hipStream_t, int, hipEvent_t*);
 
 helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
-                          int nvec, helic_prec prec, hipStream_t st) {
-  const int chunk = APPLY_CHUNK;
+                          int nvec, helic_prec prec, hipStream_t st, int chunk) {
+  chunk = std::max(1, std::min(chunk, APPLY_CHUNK));
   const size_t elem = prec == HELIC_FP64 ? sizeof(double) : sizeof(float);
   helic_status s = ensure_workspace(h, std::min(nvec, chunk), elem);
   if (s != HELIC_OK) return s;
@@ -639,7 +640,7 @@ helic_status helic_apply_H(helic_basis h, const double* X, int64_t ldx, double* 
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
   helic_status s = ensure_device(h);
   if (s != HELIC_OK) return s;
-  return apply_H_impl(h, X, ldx, Y, ldy, nvec, prec, reinterpret_cast<hipStream_t>(stream));
+  return apply_H_impl(h, X, ldx, Y, ldy, nvec, prec, reinterpret_cast<hipStream_t>(stream), APPLY_CHUNK);
 }
 
 helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,

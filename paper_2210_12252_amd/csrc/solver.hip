@@ -1,15 +1,529 @@
-// Block eigensolver (placeholder until the LOBPCG driver lands).
+// Block eigensolver for the lowest eigenpairs of H: LOBPCG (Sec. 3.5) with
+// soft locking, the Teter-Payne-Allan preconditioner, and an FP64
+// Rayleigh-Ritz step on the trial space S = [X, W, P]:
+//   Gram matrices S^H S and S^H (H S) by ZGEMM (rocBLAS), orthonormalisation
+//   of S by SVQB (eigen-decomposition of the scaled Gram matrix, dropping
+//   directions below a relative 1e-14), then the small Hermitian
+//   eigenproblem of the projected H (rocSOLVER QR-iteration zheev).
+// W is projected against X (twice) before the Rayleigh-Ritz step.  With
+// FP32 H*X the iteration runs until every wanted residual is below
+// switch_tol, recomputes H X and H P in FP64 and continues in FP64 to tol.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
 
 #include "device_state.hpp"
 #include "helic_internal.h"
 
 namespace helic {
+
+helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy, int nvec,
+                          helic_prec prec, hipStream_t st, int chunk);
+helic_status precondition_impl(helic_basis_s* h, const double* Rr, int64_t ldr, double* W, int64_t ldw,
+                               int nvec, hipStream_t st);
+helic_status lpc_precondition(helic_basis_s* h, const double* Rr, int64_t ldr, const double* X, int64_t ldx,
+                              const double* lam, double* W, int64_t ldw, int nvec, hipStream_t st, bool* used);
+
 void release_solver_state(DeviceState*) {}
+
+namespace {
+
+typedef rocblas_double_complex zc;
+constexpr int NTS = 256;
+
+#define HIP_TRY_S(call)                                                               \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(HELIC_ERR_HIP, std::string(#call) + " (solver line " + std::to_string(__LINE__) + "): " + \
+                                     hipGetErrorString(e_));                          \
+  } while (0)
+#define RB_TRY(call)                                                                  \
+  do {                                                                                \
+    rocblas_status e_ = (call);                                                       \
+    if (e_ != rocblas_status_success)                                                 \
+      return fail(HELIC_ERR_HIP, std::string(#call) + ": rocblas status " +          \
+                                     std::to_string((int)e_));                        \
+  } while (0)
+
+// R_j = AX_j - lam_j X_j and partial sums of |R_j|^2 over row chunks
+__global__ void __launch_bounds__(NTS)
+k_residual(const double* __restrict__ AX, const double* __restrict__ X, const double* __restrict__ lam,
+           double* __restrict__ R, int64_t L, int nchunk, double* __restrict__ part) {
+  __shared__ double red[NTS];
+  const int c = blockIdx.x, j = blockIdx.y;
+  const int64_t per = (L + nchunk - 1) / nchunk;
+  const int64_t lo = c * per, hi = std::min(L, lo + per);
+  const double l = lam[j];
+  double s = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += NTS) {
+    const int64_t o = ((int64_t)j * L + i) * 2;
+    const double re = AX[o] - l * X[o], im = AX[o + 1] - l * X[o + 1];
+    R[o] = re;
+    R[o + 1] = im;
+    s += re * re + im * im;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = NTS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)j * nchunk + c] = red[0];
+}
+
+__global__ void k_finish_norms(const double* __restrict__ part, int nchunk, int ncol, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncol) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)j * nchunk + c];
+  out[j] = std::sqrt(s);
+}
+
+// dst[:, c] = src[:, idx[c]] for c < ncol (columns of length L complex)
+__global__ void __launch_bounds__(NTS)
+k_gather_cols(const double* __restrict__ src, double* __restrict__ dst, const int32_t* __restrict__ idx,
+              int64_t L, int ncol) {
+  const int c = blockIdx.y;
+  if (c >= ncol) return;
+  const double* s = src + (int64_t)idx[c] * L * 2;
+  double* d = dst + (int64_t)c * L * 2;
+  for (int64_t i = blockIdx.x * (int64_t)NTS + threadIdx.x; i < 2 * L; i += (int64_t)gridDim.x * NTS) d[i] = s[i];
+}
+
+// d_i = 1 / sqrt(Re G_ii) (0 if not positive); G_ij <- d_i d_j G_ij
+__global__ void k_svqb_scale(double* __restrict__ G, int k, int ld, double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) {
+    const double g = G[((int64_t)i * ld + i) * 2];
+    d[i] = g > 0.0 ? 1.0 / std::sqrt(g) : 0.0;
+  }
+}
+__global__ void k_scale_sym(double* __restrict__ G, int k, int ld, const double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i < k && j < k) {
+    const double s = d[i] * d[j];
+    G[((int64_t)j * ld + i) * 2] *= s;
+    G[((int64_t)j * ld + i) * 2 + 1] *= s;
+  }
+}
+// Z[:, c] = D U[:, i0 + c] / sqrt(theta[i0 + c]), c < kk
+__global__ void k_make_Z(const double* __restrict__ U, int ldu, const double* __restrict__ d,
+                         const double* __restrict__ theta, int i0, int k, int kk, double* __restrict__ Z, int ldz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (i < k && c < kk) {
+    const double s = d[i] / std::sqrt(theta[i0 + c]);
+    Z[((int64_t)c * ldz + i) * 2] = U[((int64_t)(i0 + c) * ldu + i) * 2] * s;
+    Z[((int64_t)c * ldz + i) * 2 + 1] = U[((int64_t)(i0 + c) * ldu + i) * 2 + 1] * s;
+  }
+}
+
+// T[c * ldt + r] = C[(idx[c]) * ldc + r0 + r], r < nr, c < nc (complex)
+__global__ void k_gather_sub(const double* __restrict__ Cm, int ldc, int r0, int nr, const int32_t* __restrict__ idx,
+                             int nc, double* __restrict__ T, int ldt) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (r < nr && c < nc) {
+    const int64_t so = ((int64_t)idx[c] * ldc + r0 + r) * 2, dO = ((int64_t)c * ldt + r) * 2;
+    T[dO] = Cm[so];
+    T[dO + 1] = Cm[so + 1];
+  }
+}
+
+struct Bufs {
+  std::vector<void*> owned;
+  ~Bufs() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+  helic_status get(double** p, size_t n) {
+    HIP_TRY_S(hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(double)));
+    owned.push_back(*p);
+    return HELIC_OK;
+  }
+};
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+}  // namespace
+
+helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double* evals, double* resid,
+                             double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st) {
+  Timer total;
+  helic_solve_stats S_;
+  std::memset(&S_, 0, sizeof(S_));
+  const int64_t L = h->L;
+  const int nev = o.nev;
+  const int guard = o.guard >= 0 ? o.guard : std::max(4, nev / 8);
+  const int n = (int)std::min<int64_t>(L, (int64_t)nev + guard);
+  const int chunk = std::max(1, std::min(o.block, 64));
+  const int kmax = 3 * n;
+  helic_prec prec = (helic_prec)o.prec;
+  const double switch_tol = o.switch_tol > 0 ? o.switch_tol : 1e-4;
+
+  Bufs B;
+  double *S, *AS, *Pb, *APb, *Xn, *AXn, *R, *GA, *Z, *T1, *C, *theta, *E, *d, *lam, *part, *norms, *jres;
+  const size_t Lc = (size_t)L * 2;   // doubles per complex column
+  const size_t KK = (size_t)kmax * kmax * 2;
+  helic_status s;
+  if ((s = B.get(&S, Lc * kmax)) || (s = B.get(&AS, Lc * kmax)) || (s = B.get(&Pb, Lc * n)) ||
+      (s = B.get(&APb, Lc * n)) || (s = B.get(&Xn, Lc * n)) || (s = B.get(&AXn, Lc * n)) ||
+      (s = B.get(&R, Lc * n)) || (s = B.get(&GA, KK)) || (s = B.get(&Z, KK)) || (s = B.get(&T1, KK)) ||
+      (s = B.get(&C, KK)) || (s = B.get(&theta, kmax)) || (s = B.get(&E, kmax)) || (s = B.get(&d, kmax)) ||
+      (s = B.get(&lam, kmax)) || (s = B.get(&norms, kmax)) || (s = B.get(&jres, 1)))
+    return s;
+  const int nchunk = (int)std::min<int64_t>(64, (L + 2047) / 2048);
+  if ((s = B.get(&part, (size_t)nchunk * n))) return s;
+  int32_t *d_idx = nullptr, *d_info = nullptr, *d_sweeps = nullptr;
+  HIP_TRY_S(hipMalloc((void**)&d_idx, sizeof(int32_t) * n));
+  B.owned.push_back(d_idx);
+  HIP_TRY_S(hipMalloc((void**)&d_info, sizeof(int32_t)));
+  B.owned.push_back(d_info);
+  HIP_TRY_S(hipMalloc((void**)&d_sweeps, sizeof(int32_t)));
+  B.owned.push_back(d_sweeps);
+
+  rocblas_handle rb = nullptr;
+  RB_TRY(rocblas_create_handle(&rb));
+  struct HandleGuard {
+    rocblas_handle h;
+    ~HandleGuard() { rocblas_destroy_handle(h); }
+  } hg{rb};
+  RB_TRY(rocblas_set_stream(rb, st));
+  const zc one{1.0, 0.0}, zero{0.0, 0.0}, mone{-1.0, 0.0};
+  auto col = [&](double* base, int c) { return base + (size_t)c * Lc; };
+  auto sync = [&]() -> helic_status {
+    HIP_TRY_S(hipStreamSynchronize(st));
+    return HELIC_OK;
+  };
+
+  auto apply = [&](const double* X, double* Y, int nv) -> helic_status {
+    if (nv == 0) return HELIC_OK;
+    Timer t;
+    helic_status r = apply_H_impl(h, X, L, Y, L, nv, prec, st, chunk);
+    if (r != HELIC_OK) return r;
+    HIP_TRY_S(hipStreamSynchronize(st));
+    S_.t_apply_ms += t.ms();
+    S_.n_apply += nv;
+    return HELIC_OK;
+  };
+
+  // Hermitian eigen-decomposition of the k x k matrix A (ld kmax) in place,
+  // eigenvalues ascending in w (device) and wh (host).  Divide and conquer
+  // first; it returns NaN on exactly deflating (identity-block) matrices of
+  // order >= 90, so a non-finite or failed result is redone by Jacobi from a
+  // copy of the input.
+  auto heev = [&](int k, double* A, double* w, std::vector<double>& wh) -> helic_status {
+    const size_t bytes = (size_t)kmax * k * 2 * sizeof(double);
+    HIP_TRY_S(hipMemcpyAsync(Z, A, bytes, hipMemcpyDeviceToDevice, st));
+    RB_TRY(rocsolver_zheevd(rb, rocblas_evect_original, rocblas_fill_upper, k, (zc*)A, kmax, w, E, d_info));
+    wh.resize(k);
+    int32_t info = 0;
+    HIP_TRY_S(hipMemcpyAsync(wh.data(), w, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    HIP_TRY_S(hipMemcpyAsync(&info, d_info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY_S(hipStreamSynchronize(st));
+    bool ok = info == 0;
+    for (int i = 0; i < k && ok; ++i) ok = std::isfinite(wh[i]);
+    if (ok) return HELIC_OK;
+    HIP_TRY_S(hipMemcpyAsync(A, Z, bytes, hipMemcpyDeviceToDevice, st));
+    RB_TRY(rocsolver_zheevj(rb, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, k, (zc*)A,
+                            kmax, 0.0, jres, 100, d_sweeps, w, d_info));
+    HIP_TRY_S(hipMemcpyAsync(wh.data(), w, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    HIP_TRY_S(hipMemcpyAsync(&info, d_info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY_S(hipStreamSynchronize(st));
+    ok = info == 0;
+    for (int i = 0; i < k && ok; ++i) ok = std::isfinite(wh[i]);
+    if (!ok) return fail(HELIC_ERR_NOCONV, "small Hermitian eigenproblem failed");
+    return HELIC_OK;
+  };
+
+  // Orthonormalise the ncols columns at Y (same transform on AY when given):
+  // Cholesky QR twice; if the Gram matrix is not numerically positive
+  // definite, SVQB (scaled Gram eigen-decomposition, directions below 1e-12
+  // of the largest dropped).  *kept receives the new column count.
+  auto ortho_block = [&](double* Y, double* AY, int ncols, int* kept) -> helic_status {
+    bool svqb_done = false;
+    for (int pass = 0; pass < 2 && ncols > 0; ++pass) {
+      RB_TRY(rocblas_zgemm(rb, rocblas_operation_conjugate_transpose, rocblas_operation_none, ncols, ncols, (int)L,
+                           &one, (const zc*)Y, (int)L, (const zc*)Y, (int)L, &zero, (zc*)T1, kmax));
+      HIP_TRY_S(hipMemcpyAsync(GA, T1, (size_t)kmax * ncols * 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+      RB_TRY(rocsolver_zpotrf(rb, rocblas_fill_upper, ncols, (zc*)T1, kmax, d_info));
+      int32_t info = 0;
+      HIP_TRY_S(hipMemcpyAsync(&info, d_info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY_S(hipStreamSynchronize(st));
+      if (info == 0) {
+        RB_TRY(rocblas_ztrsm(rb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                             rocblas_diagonal_non_unit, (int)L, ncols, &one, (const zc*)T1, kmax, (zc*)Y, (int)L));
+        if (AY)
+          RB_TRY(rocblas_ztrsm(rb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                               rocblas_diagonal_non_unit, (int)L, ncols, &one, (const zc*)T1, kmax, (zc*)AY, (int)L));
+        continue;
+      }
+      if (svqb_done) return fail(HELIC_ERR_NOCONV, "block orthonormalisation failed");
+      // SVQB on the saved Gram matrix, then the two Cholesky passes again
+      hipLaunchKernelGGL(k_svqb_scale, dim3((ncols + 63) / 64), dim3(64), 0, st, GA, ncols, kmax, d);
+      hipLaunchKernelGGL(k_scale_sym, dim3((ncols + 63) / 64, ncols), dim3(64), 0, st, GA, ncols, kmax, d);
+      HIP_TRY_S(hipGetLastError());
+      std::vector<double> th;
+      if ((s = heev(ncols, GA, theta, th))) return s;
+      const double tmax = th[ncols - 1];
+      svqb_done = true;
+      if (!(tmax > 0)) {
+        ncols = 0;
+        break;
+      }
+      int i0 = 0;
+      while (i0 < ncols && th[i0] <= 1e-12 * tmax) ++i0;
+      const int kk = ncols - i0;
+      hipLaunchKernelGGL(k_make_Z, dim3((ncols + 63) / 64, kk), dim3(64), 0, st, GA, kmax, d, theta, i0, ncols, kk,
+                         Z, kmax);
+      HIP_TRY_S(hipGetLastError());
+      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, kk, ncols, &one, (const zc*)Y,
+                           (int)L, (const zc*)Z, kmax, &zero, (zc*)Xn, (int)L));
+      HIP_TRY_S(hipMemcpyAsync(Y, Xn, sizeof(double) * Lc * kk, hipMemcpyDeviceToDevice, st));
+      if (AY) {
+        RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, kk, ncols, &one,
+                             (const zc*)AY, (int)L, (const zc*)Z, kmax, &zero, (zc*)AXn, (int)L));
+        HIP_TRY_S(hipMemcpyAsync(AY, AXn, sizeof(double) * Lc * kk, hipMemcpyDeviceToDevice, st));
+      }
+      ncols = kk;
+      pass = -1;
+    }
+    *kept = ncols;
+    return HELIC_OK;
+  };
+
+  // Y -= B (B^H Y) and AY -= AB (B^H Y) for an orthonormal block B (nb columns)
+  auto project = [&](const double* Bm, const double* ABm, int nb, double* Y, double* AY, int ny) -> helic_status {
+    if (nb == 0 || ny == 0) return HELIC_OK;
+    RB_TRY(rocblas_zgemm(rb, rocblas_operation_conjugate_transpose, rocblas_operation_none, nb, ny, (int)L, &one,
+                         (const zc*)Bm, (int)L, (const zc*)Y, (int)L, &zero, (zc*)T1, kmax));
+    RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, ny, nb, &mone, (const zc*)Bm,
+                         (int)L, (const zc*)T1, kmax, &one, (zc*)Y, (int)L));
+    if (AY)
+      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, ny, nb, &mone, (const zc*)ABm,
+                           (int)L, (const zc*)T1, kmax, &one, (zc*)AY, (int)L));
+    return HELIC_OK;
+  };
+
+  // Rayleigh-Ritz on the orthonormal S[:, :k]: C = lowest `nout` eigenvectors
+  // of S^H (H S), lam their eigenvalues; then X <- S C, AX <- AS C (in Xn/AXn).
+  std::vector<double> lam_h;
+  auto rayleigh_ritz = [&](int k, int nout) -> helic_status {
+    Timer t;
+    RB_TRY(rocblas_zgemm(rb, rocblas_operation_conjugate_transpose, rocblas_operation_none, k, k, (int)L, &one,
+                         (const zc*)S, (int)L, (const zc*)AS, (int)L, &zero, (zc*)C, kmax));
+    if ((s = heev(k, C, lam, lam_h))) return s;
+    RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, nout, k, &one, (const zc*)S,
+                         (int)L, (const zc*)C, kmax, &zero, (zc*)Xn, (int)L));
+    RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, nout, k, &one, (const zc*)AS,
+                         (int)L, (const zc*)C, kmax, &zero, (zc*)AXn, (int)L));
+    if ((s = sync())) return s;
+    S_.t_rr_ms += t.ms();
+    return HELIC_OK;
+  };
+
+  auto residuals = [&](std::vector<double>& nrm) -> helic_status {
+    Timer t;
+    hipLaunchKernelGGL(k_residual, dim3(nchunk, n), dim3(NTS), 0, st, AS, S, lam, R, L, nchunk, part);
+    hipLaunchKernelGGL(k_finish_norms, dim3((n + 63) / 64), dim3(64), 0, st, part, nchunk, n, norms);
+    HIP_TRY_S(hipGetLastError());
+    nrm.resize(n);
+    HIP_TRY_S(hipMemcpyAsync(nrm.data(), norms, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIP_TRY_S(hipStreamSynchronize(st));
+    S_.t_precond_ms += t.ms();
+    return HELIC_OK;
+  };
+
+  // ---- random start: orthonormalise, H X, first Rayleigh-Ritz
+  {
+    std::mt19937_64 gen(o.seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    std::vector<double> h0(Lc * n);
+    for (auto& x : h0) x = nd(gen);
+    HIP_TRY_S(hipMemcpyAsync(S, h0.data(), sizeof(double) * h0.size(), hipMemcpyHostToDevice, st));
+    int kept = 0;
+    if ((s = ortho_block(S, nullptr, n, &kept))) return s;
+    if (kept < n) return fail(HELIC_ERR_NOCONV, "random start is rank deficient");
+  }
+  if ((s = apply(S, AS, n))) return s;
+  if ((s = rayleigh_ritz(n, n))) return s;
+  HIP_TRY_S(hipMemcpyAsync(S, Xn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
+  HIP_TRY_S(hipMemcpyAsync(AS, AXn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
+
+  int np = 0;   // columns held in Pb / APb
+  std::vector<double> nrm;
+  std::vector<int32_t> active;
+  bool converged = false;
+  int it = 0;
+  for (it = 0; it < o.maxit; ++it) {
+    if ((s = residuals(nrm))) return s;
+    for (int j = 0; j < n; ++j)
+      if (!std::isfinite(nrm[j]))
+        return fail(HELIC_ERR_NOCONV, "residual of column " + std::to_string(j) + " is not finite at iteration " +
+                                          std::to_string(it));
+    bool all = true;
+    double worst = 0.0;
+    for (int j = 0; j < nev; ++j) {
+      all = all && nrm[j] <= o.tol;
+      worst = std::max(worst, nrm[j]);
+    }
+    if (all && prec == HELIC_FP64) {
+      converged = true;
+      break;
+    }
+    if (prec != HELIC_FP64 && worst <= switch_tol) {
+      // precision ladder: recompute H X and H P in FP64 and go on in FP64
+      prec = HELIC_FP64;
+      if ((s = apply(S, AS, n))) return s;
+      if ((s = apply(Pb, APb, np))) return s;
+      --it;
+      continue;
+    }
+    if (prec != HELIC_FP64) ++S_.iters_low;
+    active.clear();
+    for (int j = 0; j < n; ++j)
+      if (nrm[j] > o.tol) active.push_back(j);
+    const int na = (int)active.size();
+    if (na == 0) return fail(HELIC_ERR_NOCONV, "no active column left below the target");
+    // W = T(R_active) into S columns [n, n + na)
+    Timer tp;
+    HIP_TRY_S(hipMemcpyAsync(d_idx, active.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
+    double* W = col(S, n);
+    hipLaunchKernelGGL(k_gather_cols, dim3(64, na), dim3(NTS), 0, st, R, W, d_idx, L, na);
+    HIP_TRY_S(hipGetLastError());
+    if (o.precond == 0) {
+      if ((s = precondition_impl(h, W, L, W, L, na, st))) return s;
+    } else if (o.precond == 2) {
+      // learned preconditioner; it falls back to the TPA one by itself
+      hipLaunchKernelGGL(k_gather_cols, dim3(64, na), dim3(NTS), 0, st, S, Xn, d_idx, L, na);
+      std::vector<double> lam_a(na);
+      for (int c = 0; c < na; ++c) lam_a[c] = lam_h[active[c]];
+      HIP_TRY_S(hipMemcpyAsync(d, lam_a.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
+      bool used = false;
+      if ((s = lpc_precondition(h, W, L, Xn, L, d, W, L, na, st, &used))) return s;
+      if (!used) ++S_.n_fallback;
+    }
+    if ((s = sync())) return s;
+    S_.t_precond_ms += tp.ms();
+    // W: project against X twice, orthonormalise, then apply H
+    int nw = 0;
+    {
+      Timer t;
+      for (int rep = 0; rep < 2; ++rep)
+        if ((s = project(S, nullptr, n, W, nullptr, na))) return s;
+      if ((s = ortho_block(W, nullptr, na, &nw))) return s;
+      if ((s = sync())) return s;
+      S_.t_rr_ms += t.ms();
+    }
+    if ((s = apply(W, col(AS, n), nw))) return s;
+    // P after W: project against X and W twice, orthonormalise with H P
+    int npk = 0;
+    if (np > 0) {
+      Timer t;
+      double* P = col(S, n + nw);
+      double* AP = col(AS, n + nw);
+      HIP_TRY_S(hipMemcpyAsync(P, Pb, sizeof(double) * Lc * np, hipMemcpyDeviceToDevice, st));
+      HIP_TRY_S(hipMemcpyAsync(AP, APb, sizeof(double) * Lc * np, hipMemcpyDeviceToDevice, st));
+      for (int rep = 0; rep < 2; ++rep) {
+        if ((s = project(S, AS, n, P, AP, np))) return s;
+        if ((s = project(W, col(AS, n), nw, P, AP, np))) return s;
+      }
+      if ((s = ortho_block(P, AP, np, &npk))) return s;
+      if ((s = sync())) return s;
+      S_.t_rr_ms += t.ms();
+    }
+    const int k = n + nw + npk;
+    if ((s = rayleigh_ritz(k, n))) return s;
+    {
+      Timer t;
+      // new P = [W P] C[n:k, active], H P likewise
+      hipLaunchKernelGGL(k_gather_sub, dim3((k - n + 63) / 64, na), dim3(64), 0, st, C, kmax, n, k - n, d_idx, na,
+                         T1, kmax);
+      HIP_TRY_S(hipGetLastError());
+      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - n, &one,
+                           (const zc*)col(S, n), (int)L, (const zc*)T1, kmax, &zero, (zc*)Pb, (int)L));
+      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - n, &one,
+                           (const zc*)col(AS, n), (int)L, (const zc*)T1, kmax, &zero, (zc*)APb, (int)L));
+      np = na;
+      HIP_TRY_S(hipMemcpyAsync(S, Xn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
+      HIP_TRY_S(hipMemcpyAsync(AS, AXn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
+      if ((s = sync())) return s;
+      S_.t_rr_ms += t.ms();
+    }
+  }
+  if (!converged) {
+    if ((s = residuals(nrm))) return s;
+    converged = prec == HELIC_FP64;
+    for (int j = 0; j < nev; ++j) converged = converged && nrm[j] <= o.tol;
+  }
+  if (evecs)
+    HIP_TRY_S(hipMemcpy2DAsync(evecs, sizeof(double) * 2 * ldv, S, sizeof(double) * Lc, sizeof(double) * Lc, nev,
+                               hipMemcpyDeviceToDevice, st));
+  if ((s = sync())) return s;
+  for (int j = 0; j < nev; ++j) {
+    evals[j] = lam_h[j];
+    resid[j] = nrm[j];
+  }
+  S_.iters = it;
+  S_.t_total_ms = total.ms();
+  if (stats) *stats = S_;
+  if (!converged) return fail(HELIC_ERR_NOCONV, "iteration limit reached above tolerance");
+  return HELIC_OK;
+}
+
 }  // namespace helic
 
-extern "C" helic_status helic_eigensolve(helic_basis h, int32_t, int32_t, double, int32_t, helic_prec,
-                                         uint64_t, double*, double*, double*, int64_t, int32_t*, void*) {
-  if (!h) return helic::fail(HELIC_ERR_INVALID, "null handle");
-  return helic::fail(HELIC_ERR_UNSUPPORTED, "eigensolver not built yet");
+using namespace helic;
+
+extern "C" {
+
+helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* o, double* evals, double* resid,
+                                 double* evecs, int64_t ldv, helic_solve_stats* stats, void* stream) {
+  if (!h || !o || !evals || !resid) return fail(HELIC_ERR_INVALID, "null argument");
+  if (o->nev < 1 || o->nev > h->L || o->block < 1 || !(o->tol > 0) || o->maxit < 0 ||
+      (evecs && ldv < h->L))
+    return fail(HELIC_ERR_INVALID, "bad solver options");
+  if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (o->precond < 0 || o->precond > 2) return fail(HELIC_ERR_UNSUPPORTED, "unknown preconditioner");
+  if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
+  try {
+    return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    return fail(HELIC_ERR_NOMEM, "host allocation failed");
+  }
 }
+
+helic_status helic_eigensolve(helic_basis h, int32_t nev, int32_t block, double tol, int32_t maxit, helic_prec prec,
+                              uint64_t seed, double* evals, double* resid, double* evecs, int64_t ldv, int32_t* iters,
+                              void* stream) {
+  helic_solve_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.nev = nev;
+  o.block = block;
+  o.tol = tol;
+  o.maxit = maxit;
+  o.prec = prec;
+  o.seed = seed;
+  o.precond = 0;
+  o.guard = -1;
+  o.switch_tol = 1e-4;
+  helic_solve_stats st;
+  std::memset(&st, 0, sizeof(st));
+  helic_status s = helic_eigensolve_ex(h, &o, evals, resid, evecs, ldv, &st, stream);
+  if (iters) *iters = st.iters;
+  return s;
+}
+
+}  // extern "C"

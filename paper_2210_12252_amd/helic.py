@@ -26,6 +26,7 @@ PREC = {"fp64": FP64, "fp32": FP32}
 EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "helic_basis_indices",
            "helic_grid", "helic_set_potential", "helic_apply_H", "helic_transform_inverse",
            "helic_transform_forward", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
+           "helic_eigensolve_ex",
            "helic_util_bessel_j", "helic_util_bessel_zeros", "helic_util_gauss_jacobi",
            "helic_last_error")
 
@@ -34,6 +35,24 @@ class HelicError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"helic status {status}: {msg}")
         self.status = status
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int32), ("block", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int32), ("prec", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("precond", ctypes.c_int32), ("guard", ctypes.c_int32), ("switch_tol", ctypes.c_double)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("iters_low", ctypes.c_int32), ("n_apply", ctypes.c_int64),
+                ("n_fallback", ctypes.c_int32), ("t_apply_ms", ctypes.c_double), ("t_rr_ms", ctypes.c_double),
+                ("t_precond_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+PRECOND = {"tpa": 0, "none": 1, "learned": 2}
 
 
 class Params(ctypes.Structure):
@@ -76,6 +95,7 @@ def load() -> ctypes.CDLL:
         "helic_profile_apply": [_P, _P, _I64, _P, _I64, _I32, _I32, _I32, _P, _PD, _PD],
         "helic_eigensolve": [_P, _I32, _I32, _D, _I32, _I32, ctypes.c_uint64, _PD, _PD, _P, _I64,
                              _PI32, _P],
+        "helic_eigensolve_ex": [_P, ctypes.POINTER(SolveOpts), _PD, _PD, _P, _I64, ctypes.POINTER(SolveStats), _P],
         "helic_util_bessel_j": [_I32, _I32, _PD, _PD],
         "helic_util_bessel_zeros": [_I32, _I32, _PD],
         "helic_util_gauss_jacobi": [_I32, _PD, _PD],
@@ -254,6 +274,31 @@ def eigensolve(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, evecs
     return evals, resid, iters.value, st
 
 
+def eigensolve_ex(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa", guard=-1,
+                  switch_tol=1e-4, evecs=None, stream=None):
+    """Returns (evals, resid, stats dict, status); raises on errors other
+    than non-convergence."""
+    o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=PREC[prec], seed=seed,
+                  precond=PRECOND[precond], guard=guard, switch_tol=switch_tol)
+    evals = np.zeros(nev)
+    resid = np.zeros(nev)
+    st = SolveStats()
+    if evecs is not None:
+        nv, ldv = _block(evecs, "evecs")
+        if nv < nev:
+            raise ValueError("evecs has fewer than nev columns")
+        vptr = ctypes.c_void_p(evecs.data_ptr())
+    else:
+        ldv, vptr = 0, ctypes.c_void_p(0)
+    status = load().helic_eigensolve_ex(h, ctypes.byref(o), _ptr(evals, ctypes.c_double),
+                                        _ptr(resid, ctypes.c_double), vptr, ldv, ctypes.byref(st), _stream(stream))
+    if status not in (OK, ERR_NOCONV):
+        _check(status)
+    stats = st.as_dict()
+    stats["message"] = load().helic_last_error().decode() if status != OK else ""
+    return evals, resid, stats, status
+
+
 class Basis:
     """Owning wrapper of a basis handle."""
 
@@ -307,3 +352,6 @@ class Basis:
 
     def eigensolve(self, nev, **kw):
         return eigensolve(self.h, nev, **kw)
+
+    def eigensolve_ex(self, nev, **kw):
+        return eigensolve_ex(self.h, nev, **kw)

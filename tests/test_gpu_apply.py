@@ -225,3 +225,24 @@ def test_general_and_specialised_angular_kernels_agree(tiny, monkeypatch):
         err = (torch.abs(Y1 - Y2).max() / torch.abs(Y1).max()).item()
         assert err < tol, (prec, err)
     gen.close()
+
+
+@pytest.mark.parametrize("generic", [False, True])
+def test_apply_H_parity_radix2_grid(generic, monkeypatch):
+    """Nanotube geometry at a reduced cutoff on a 24 x 32 x 64 grid (radix-2
+    passes in both angular directions, general angular kernel), and the tiny
+    workload forced onto the general kernel."""
+    if generic:
+        monkeypatch.setenv("HELIC_GENERIC_ANGULAR", "1")
+        w = synth.workload("tiny-helix")
+    else:
+        w = synth.workload("nanotube-ecut25").with_(name="nanotube-ecut6", ecut=6.0, n_t1=24, n_t2=32, n_r=64)
+    c = Case(w)
+    c.upload_V()
+    X = synth.random_block(c.o.mnk, 5, 9)
+    Yg = torch.zeros((5, c.o.L), dtype=torch.complex128, device=_dev())
+    c.g.apply_H(c.to_gpu_block(X), Yg)
+    ref = oh.apply(c.o, c.V, X)
+    err = _rel(c.from_gpu_block(Yg), ref)
+    print(f"[radix2 generic={generic}] rel err {err:.2e}", flush=True)
+    assert err < TOL64
