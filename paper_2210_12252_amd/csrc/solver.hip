@@ -1,13 +1,13 @@
 // Block eigensolver for the lowest eigenpairs of H: LOBPCG (Sec. 3.5) with
-// soft locking, the Teter-Payne-Allan preconditioner, and an FP64
-// Rayleigh-Ritz step on the trial space S = [X, W, P]:
-//   Gram matrices S^H S and S^H (H S) by ZGEMM (rocBLAS), orthonormalisation
-//   of S by SVQB (eigen-decomposition of the scaled Gram matrix, dropping
-//   directions below a relative 1e-14), then the small Hermitian
-//   eigenproblem of the projected H (rocSOLVER QR-iteration zheev).
-// W is projected against X (twice) before the Rayleigh-Ritz step.  With
-// FP32 H*X the iteration runs until every wanted residual is below
-// switch_tol, recomputes H X and H P in FP64 and continues in FP64 to tol.
+// soft locking and the Teter-Payne-Allan preconditioner.  Each iteration
+// forms the trial space S = [X, W, P] (Ritz vectors, preconditioned
+// residuals, previous update directions); W is projected against X and P
+// against [X, W] (twice each) and both are orthonormalised (Cholesky QR
+// twice, SVQB if rank deficient), so S is orthonormal and the FP64
+// Rayleigh-Ritz step is the Hermitian eigenproblem of S^H (H S) (ZGEMM by
+// rocBLAS, eigen-decomposition by rocSOLVER).  With FP32 H*X the iteration
+// locks columns at switch_tol until every wanted residual is below it,
+// recomputes H X and H P in FP64 and continues in FP64 to tol.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -138,6 +138,21 @@ __global__ void k_gather_sub(const double* __restrict__ Cm, int ldc, int r0, int
   }
 }
 
+// C[i + j ldc] = beta C + sum_b P[b][i + j m] (complex), the split-K partials
+__global__ void k_reduce_partials(const double* __restrict__ P, int nb, int m, int nn, double* __restrict__ Cm,
+                                  int ldc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= m || j >= nn) return;
+  double re = 0.0, im = 0.0;
+  const size_t stride = (size_t)m * nn * 2;
+  for (int b = 0; b < nb; ++b) {
+    re += P[b * stride + ((size_t)j * m + i) * 2];
+    im += P[b * stride + ((size_t)j * m + i) * 2 + 1];
+  }
+  Cm[((size_t)j * ldc + i) * 2] = re;
+  Cm[((size_t)j * ldc + i) * 2 + 1] = im;
+}
+
 struct Bufs {
   std::vector<void*> owned;
   ~Bufs() {
@@ -186,6 +201,12 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     return s;
   const int nchunk = (int)std::min<int64_t>(64, (L + 2047) / 2048);
   if ((s = B.get(&part, (size_t)nchunk * n))) return s;
+  // split-K Gram products: the long row dimension L is cut into nsplit slices
+  // (one batched ZGEMM), partial k x k results are summed by a small kernel
+  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(32, L / 1024));
+  const int64_t slice = L / nsplit;   // the last slice also takes L - nsplit * slice rows
+  double* gpart = nullptr;
+  if ((s = B.get(&gpart, (size_t)(nsplit + 1) * kmax * kmax * 2))) return s;
   int32_t *d_idx = nullptr, *d_info = nullptr, *d_sweeps = nullptr;
   HIP_TRY_S(hipMalloc((void**)&d_idx, sizeof(int32_t) * n));
   B.owned.push_back(d_idx);
@@ -205,6 +226,26 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   auto col = [&](double* base, int c) { return base + (size_t)c * Lc; };
   auto sync = [&]() -> helic_status {
     HIP_TRY_S(hipStreamSynchronize(st));
+    return HELIC_OK;
+  };
+
+  // Cm (m x nn, ld ldc) = A^H Bm for L-row blocks A (m columns) and Bm (nn columns)
+  auto gemm_h = [&](int m, int nn, const double* A, const double* Bm, double* Cm, int ldc) -> helic_status {
+    if (m == 0 || nn == 0) return HELIC_OK;
+    RB_TRY(rocblas_zgemm_strided_batched(rb, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, nn,
+                                         (int)slice, &one, (const zc*)A, (int)L, slice, (const zc*)Bm, (int)L, slice,
+                                         &zero, (zc*)gpart, m, (int64_t)m * nn, nsplit));
+    int nb = nsplit;
+    const int64_t rem = L - (int64_t)nsplit * slice;
+    if (rem > 0) {
+      const size_t off = (size_t)nsplit * slice * 2;
+      RB_TRY(rocblas_zgemm(rb, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, nn, (int)rem, &one,
+                           (const zc*)(A + off), (int)L, (const zc*)(Bm + off), (int)L, &zero,
+                           (zc*)(gpart + (size_t)nsplit * m * nn * 2), m));
+      ++nb;
+    }
+    hipLaunchKernelGGL(k_reduce_partials, dim3((m + 63) / 64, nn), dim3(64), 0, st, gpart, nb, m, nn, Cm, ldc);
+    HIP_TRY_S(hipGetLastError());
     return HELIC_OK;
   };
 
@@ -255,8 +296,7 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   auto ortho_block = [&](double* Y, double* AY, int ncols, int* kept) -> helic_status {
     bool svqb_done = false;
     for (int pass = 0; pass < 2 && ncols > 0; ++pass) {
-      RB_TRY(rocblas_zgemm(rb, rocblas_operation_conjugate_transpose, rocblas_operation_none, ncols, ncols, (int)L,
-                           &one, (const zc*)Y, (int)L, (const zc*)Y, (int)L, &zero, (zc*)T1, kmax));
+      if ((s = gemm_h(ncols, ncols, Y, Y, T1, kmax))) return s;
       HIP_TRY_S(hipMemcpyAsync(GA, T1, (size_t)kmax * ncols * 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
       RB_TRY(rocsolver_zpotrf(rb, rocblas_fill_upper, ncols, (zc*)T1, kmax, d_info));
       int32_t info = 0;
@@ -307,8 +347,7 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   // Y -= B (B^H Y) and AY -= AB (B^H Y) for an orthonormal block B (nb columns)
   auto project = [&](const double* Bm, const double* ABm, int nb, double* Y, double* AY, int ny) -> helic_status {
     if (nb == 0 || ny == 0) return HELIC_OK;
-    RB_TRY(rocblas_zgemm(rb, rocblas_operation_conjugate_transpose, rocblas_operation_none, nb, ny, (int)L, &one,
-                         (const zc*)Bm, (int)L, (const zc*)Y, (int)L, &zero, (zc*)T1, kmax));
+    if ((s = gemm_h(nb, ny, Bm, Y, T1, kmax))) return s;
     RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, ny, nb, &mone, (const zc*)Bm,
                          (int)L, (const zc*)T1, kmax, &one, (zc*)Y, (int)L));
     if (AY)
@@ -322,8 +361,7 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   std::vector<double> lam_h;
   auto rayleigh_ritz = [&](int k, int nout) -> helic_status {
     Timer t;
-    RB_TRY(rocblas_zgemm(rb, rocblas_operation_conjugate_transpose, rocblas_operation_none, k, k, (int)L, &one,
-                         (const zc*)S, (int)L, (const zc*)AS, (int)L, &zero, (zc*)C, kmax));
+    if ((s = gemm_h(k, k, S, AS, C, kmax))) return s;
     if ((s = heev(k, C, lam, lam_h))) return s;
     RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, nout, k, &one, (const zc*)S,
                          (int)L, (const zc*)C, kmax, &zero, (zc*)Xn, (int)L));
@@ -392,9 +430,13 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
       continue;
     }
     if (prec != HELIC_FP64) ++S_.iters_low;
+    // In the FP32 phase columns are locked at switch_tol: iterating a column
+    // whose residual is at the FP32 noise floor makes its normalised update
+    // directions amplify the rounding inconsistency between S and H S.
+    const double lock_tol = prec == HELIC_FP64 ? o.tol : std::max(o.tol, switch_tol);
     active.clear();
     for (int j = 0; j < n; ++j)
-      if (nrm[j] > o.tol) active.push_back(j);
+      if (nrm[j] > lock_tol) active.push_back(j);
     const int na = (int)active.size();
     if (na == 0) return fail(HELIC_ERR_NOCONV, "no active column left below the target");
     // W = T(R_active) into S columns [n, n + na)

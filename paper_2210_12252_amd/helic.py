@@ -132,7 +132,8 @@ def _block(t, name):
     import torch
     if not (t.is_cuda and t.dtype == torch.complex128 and t.dim() == 2 and t.stride(1) == 1):
         raise ValueError(f"{name} must be a complex128 HIP tensor of shape (nvec, ld), unit stride")
-    return t.shape[0], t.stride(0)
+    # a single column's leading dimension is immaterial (and torch may report any stride for it)
+    return t.shape[0], (t.shape[1] if t.shape[0] <= 1 else t.stride(0))
 
 
 # ------------------------------------------------------------------ host calls
