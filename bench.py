@@ -83,6 +83,33 @@ def cpu_baseline(w, nsample: int):
                 f"64 block vectors of {w.name}, {wall:.1f} s wall on {os.cpu_count()} host cores")
 
 
+def time_to_eigenpairs(b, w, torch, tol=1e-8):
+    """Lowest w.nev eigenpairs to ||H x - lambda x|| <= tol from the same
+    seeded random start, FP64 H*X and mixed (FP32 H*X, FP64 refinement); both
+    keep the FP64 Rayleigh-Ritz.  Reports wall time, iterations, the H*X and
+    Rayleigh-Ritz shares and the per-eigenvalue difference of mixed vs FP64."""
+    import numpy as np
+    out = {"nev": w.nev, "tol_Ha": tol}
+    evs = {}
+    for prec in ("fp64", "fp32"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, res, st, status = b.eigensolve_ex(w.nev, block=64, tol=tol, maxit=1000, prec=prec, seed=7)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        key = "fp64" if prec == "fp64" else "mixed_fp32_fp64"
+        out[key] = dict(seconds=round(wall, 3), converged=bool(status == 0), iters=st["iters"],
+                        iters_fp32=st["iters_low"], hx_columns=st["n_apply"], hx_s=round(st["t_apply_ms"] / 1e3, 3),
+                        rayleigh_ritz_s=round(st["t_rr_ms"] / 1e3, 3), max_resid=float(np.max(res)))
+        evs[key] = ev
+        print(f"[bench] eigensolve {key}: {wall:.2f} s, {st['iters']} iterations, converged {status == 0}",
+              file=sys.stderr, flush=True)
+    d = np.abs(evs["mixed_fp32_fp64"] - evs["fp64"])
+    out["mixed_vs_fp64_max_abs_Ha"] = float(d.max())
+    out["speedup_mixed"] = round(out["fp64"]["seconds"] / out["mixed_fp32_fp64"]["seconds"], 3)
+    return out
+
+
 def load_traffic(name: str, nvec: int):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or
     None when absent or taken on other kernel sources."""
@@ -103,7 +130,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="nanotube-ecut25")
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"))
-    ap.add_argument("--cpu-sample", type=int, default=32, help="vectors for the CPU oracle leg (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="vectors for the CPU oracle leg (0: skip)")
+    ap.add_argument("--eig", type=int, default=1, help="also time the eigensolve (FP64 and mixed) (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args(argv)
@@ -209,6 +237,8 @@ def main(argv=None):
         "roofline": roof,
         "stages": stage_info,
     }
+    if args.eig:
+        line["eigensolve"] = time_to_eigenpairs(b, w, torch)
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     b.close()
