@@ -16,8 +16,9 @@
 // done as P-point DFTs in registers, a twiddle, one exchange through LDS and
 // P-point DFTs again (the four-step factorisation).
 //
-// One workgroup owns one radius and walks over a chunk of vectors, so the
-// Vhat table of that radius is read into LDS once per workgroup.
+// One workgroup owns one radius and walks over a chunk of vectors; each
+// thread keeps the window of Vhat its outputs need in registers for the whole
+// chunk, so LDS holds only the mode block and the twiddles.
 #pragma once
 #include "kernels.hpp"
 
@@ -124,7 +125,7 @@ __device__ __forceinline__ void dft_reg(cplx<T>* v) {
 }
 
 // ---------------------------------------------------------------- row transform
-// In-place length N2 = P * P DFT of `rows` rows of A (row stride N2) by
+// In-place length N2 = P * P DFT of `rows` rows of A (row stride N2 + 1) by
 // P threads per row.  Thread p of a row loads x[p + P q], does the P-point
 // DFT over q, multiplies by exp(s 2 pi i p k / N2), exchanges through LDS so
 // that thread c gets Y[.][c], does the P-point DFT over p and stores
@@ -132,6 +133,7 @@ __device__ __forceinline__ void dft_reg(cplx<T>* v) {
 template <typename T, int N2, int P, int NTF, bool INV>
 __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw) {
   static_assert(P * P == N2, "row transform expects N2 = P * P");
+  constexpr int RS = N2 + 1;                // padded row stride: rows start on different LDS banks
   constexpr int RPB = NTF / P;              // rows per batch
   const int t = threadIdx.x;
   const int nb = (rows + RPB - 1) / RPB;
@@ -141,7 +143,7 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
     const bool act = (t < RPB * P) && row < rows;
     cplx<T> v[P];
     if (act) {
-      cplx<T>* a = A + row * N2;
+      cplx<T>* a = A + row * RS;
 #pragma unroll
       for (int q = 0; q < P; ++q) v[q] = a[p + P * q];
       dft_reg<T, P, INV>(v);
@@ -154,22 +156,33 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
       }
     }
     __syncthreads();
+    // exchange Y[p][k] through LDS; element (p, k) is stored at p*P +
+    // (k + p) mod P so that both the row-wise writes and the column-wise
+    // reads of the P threads of a row fall on distinct banks
     if (act) {
-      cplx<T>* a = A + row * N2;
+      cplx<T>* a = A + row * RS;
 #pragma unroll
-      for (int k = 0; k < P; ++k) a[p * P + k] = v[k];   // Y[p][k]
+      for (int k = 0; k < P; ++k) {
+        int kk = k + p;
+        kk -= (kk >= P) ? P : 0;
+        a[p * P + kk] = v[k];
+      }
     }
     __syncthreads();
     if (act) {
-      cplx<T>* a = A + row * N2;
+      cplx<T>* a = A + row * RS;
       const int c = p;
 #pragma unroll
-      for (int q = 0; q < P; ++q) v[q] = a[q * P + c];   // Y[q][c]
+      for (int q = 0; q < P; ++q) {
+        int cc = c + q;
+        cc -= (cc >= P) ? P : 0;
+        v[q] = a[q * P + cc];   // Y[q][c]
+      }
       dft_reg<T, P, INV>(v);
     }
     __syncthreads();
     if (act) {
-      cplx<T>* a = A + row * N2;
+      cplx<T>* a = A + row * RS;
 #pragma unroll
       for (int k1 = 0; k1 < P; ++k1) a[p + P * k1] = v[k1];
     }
@@ -180,7 +193,7 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
 // ---------------------------------------------------------------- the kernel
 // GH[v][r][mode] holds G on entry and H on exit (complex T).  Vh[r][j][d]
 // (complex T, d = 0..2 MPAD - 2 for m' - m = d - (MPAD - 1)).  mode_pos[i] =
-// (m_i - m_min) * N2 + (n_i mod N2).  Work: blockIdx -> (radius, vector chunk).
+// (m_i - m_min) * (N2 + 1) + (n_i mod N2).  Work: blockIdx -> (radius, vector chunk).
 template <typename T, int N2, int MPAD, int NTF>
 __global__ void __launch_bounds__(NTF)
 k_angular_fast(T* __restrict__ GH, const T* __restrict__ Vh, int nvec, int n_r, int n_modes,
@@ -191,26 +204,33 @@ k_angular_fast(T* __restrict__ GH, const T* __restrict__ Vh, int nvec, int n_r, 
   constexpr int OG = NTF / N2;                    // threads per column in the convolution
   constexpr int OPT = (MPAD + OG - 1) / OG;       // outputs per thread
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);          // [MPAD][N2]
-  cplx<T>* VhS = A + MPAD * N2;                                // [N2][ND]
-  cplx<T>* tw = VhS + N2 * ND;                                 // [N2]
+  constexpr int RS = N2 + 1;                                   // padded row stride of A
+  constexpr int WN = OPT + MPAD - 1;                           // Vhat window of one thread
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);          // [MPAD][RS]
+  cplx<T>* tw = A + MPAD * RS;                                 // [N2]
   const int nchunks = (nvec + vchunk - 1) / vchunk;
   const int slot = xcd_slot(n_r * nchunks);
   if (slot >= n_r * nchunks) return;
   const int r = slot / nchunks, ch = slot - r * nchunks;
   const int v0 = ch * vchunk, v1 = min(nvec, v0 + vchunk);
   const int t = threadIdx.x;
-  {
-    const cplx<T>* src = reinterpret_cast<const cplx<T>*>(Vh) + (int64_t)r * N2 * ND;
-    for (int i = t; i < N2 * ND; i += NTF) VhS[i] = src[i];
-    for (int i = t; i < N2; i += NTF) tw[i] = tw2g[i];
-  }
+  for (int i = t; i < N2; i += NTF) tw[i] = tw2g[i];
   const int j = t % N2, og = t / N2;
   const bool conv_act = og < OG;
   const int a0 = og * OPT;
+  // Vhat_j[d] for d - (MPAD - 1) = m' - m over this thread's outputs m' in
+  // [a0, a0 + OPT) and all m: w[q] = Vhat[r][j][a0 + q], read once and kept
+  // in registers for every vector of the chunk
+  cplx<T> w[WN];
+  {
+    const cplx<T>* src = reinterpret_cast<const cplx<T>*>(Vh) + ((int64_t)r * N2 + j) * ND;
+#pragma unroll
+    for (int q = 0; q < WN; ++q)
+      w[q] = (conv_act && a0 + q < ND) ? src[a0 + q] : cplx<T>{(T)0, (T)0};
+  }
   for (int v = v0; v < v1; ++v) {
     cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + ((int64_t)v * n_r + r) * n_modes;
-    for (int i = t; i < MPAD * N2; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
+    for (int i = t; i < MPAD * RS; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
     __syncthreads();
     for (int i = t; i < n_modes; i += NTF) A[mode_pos[i]] = slab[i];
     __syncthreads();
@@ -220,17 +240,14 @@ k_angular_fast(T* __restrict__ GH, const T* __restrict__ Vh, int nvec, int n_r, 
 #pragma unroll
     for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
     if (conv_act) {
-      const cplx<T>* vh = VhS + j * ND + (MPAD - 1) + a0;
 #pragma unroll
       for (int m = 0; m < MPAD; ++m) {
-        const cplx<T> x = A[m * N2 + j];
+        const cplx<T> x = A[m * RS + j];
 #pragma unroll
         for (int o = 0; o < OPT; ++o) {
-          if (a0 + o < MPAD) {
-            const cplx<T> w = vh[o - m];
-            acc[o].x += w.x * x.x - w.y * x.y;
-            acc[o].y += w.x * x.y + w.y * x.x;
-          }
+          const cplx<T> wv = w[o - m + MPAD - 1];
+          acc[o].x += wv.x * x.x - wv.y * x.y;
+          acc[o].y += wv.x * x.y + wv.y * x.x;
         }
       }
     }
@@ -238,7 +255,7 @@ k_angular_fast(T* __restrict__ GH, const T* __restrict__ Vh, int nvec, int n_r, 
     if (conv_act) {
 #pragma unroll
       for (int o = 0; o < OPT; ++o)
-        if (a0 + o < MPAD) A[(a0 + o) * N2 + j] = acc[o];
+        if (a0 + o < MPAD) A[(a0 + o) * RS + j] = acc[o];
     }
     __syncthreads();
     row_dft<T, N2, P, NTF, false>(A, MPAD, tw);

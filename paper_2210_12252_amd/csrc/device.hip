@@ -142,6 +142,7 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
   const int gi = slot / nvec, v = slot - gi * nvec;
   const DGroup gr = groups[gi];
   const int ncol = 2 * gr.nmodes;
+  T* As = Hs + FWD_RCHUNK * (16 * ((ncol + 15) / 16));     // [k tile][step][64]
   const int nct = (ncol + 15) / 16;
   const int colpad = 16 * nct;
   const int nkt = (gr.Kmax + 15) / 16;
@@ -162,6 +163,13 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
         const int r = r0 + rr;
         Hs[i] = (r < n_r && col < ncol) ? hv[(int64_t)r * n_modes * 2 + col] : (T)0;
       }
+      // the table fragments of this chunk (all k tiles, FWD_RCHUNK / 4 steps)
+      for (int i = threadIdx.x; i < nkt * (FWD_RCHUNK / 4) * 64; i += NT) {
+        const int ln = i & 63, q = i >> 6;
+        const int kt = q / (FWD_RCHUNK / 4), s = q - kt * (FWD_RCHUNK / 4);
+        const int rs = r0 / 4 + s;
+        As[i] = rs < nrs ? tg[((int64_t)kt * nrs + rs) * 64 + ln] : (T)0;
+      }
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < FWD_TMAX; ++i) {
@@ -172,7 +180,7 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
           for (int s = 0; s < FWD_RCHUNK / 4; ++s) {
             const int rs = r0 / 4 + s;
             if (rs < nrs) {
-              const T a = tg[((int64_t)kt * nrs + rs) * 64 + lane];
+              const T a = As[(kt * (FWD_RCHUNK / 4) + s) * 64 + lane];
               const T b = Hs[(4 * s + (lane >> 4)) * colpad + 16 * ct + (lane & 15)];
               acc[i] = Mfma<T>::op(a, b, acc[i]);
             }
@@ -324,6 +332,11 @@ helic_status upload(const std::vector<T>& host, T** dptr) {
   return HELIC_OK;
 }
 
+size_t fwd_lds_bytes(const helic_basis_s* h, size_t elem) {
+  const int nkt_max = (h->max_kpad + 15) / 16;
+  return ((size_t)FWD_RCHUNK * h->max_colpad + (size_t)nkt_max * (FWD_RCHUNK / 4) * 64) * elem;
+}
+
 size_t angular_lds_bytes(const helic_basis_s* h, size_t elem) {
   return (size_t)h->n_t1 * h->n_t2 * 2 * elem + (size_t)(h->n_t1 + h->n_t2) * 2 * elem +
          (size_t)h->rows1.size() * sizeof(int32_t);
@@ -336,7 +349,15 @@ constexpr FastVariant FAST_VARIANTS[] = {{16, 12, 256}, {16, 16, 256}, {64, 24, 
 
 template <typename T>
 size_t fast_lds_bytes(int n2, int mpad) {
-  return ((size_t)mpad * n2 + (size_t)n2 * (2 * mpad - 1) + n2) * sizeof(cplx<T>);
+  return ((size_t)mpad * (n2 + 1) + n2) * sizeof(cplx<T>);
+}
+
+// Tuning knobs (environment, read once per handle): vectors per angular
+// workgroup and vectors per launch of the three stages.
+int env_int(const char* name, int dflt, int lo, int hi) {
+  const char* e = std::getenv(name);
+  if (!e || !*e) return dflt;
+  return std::max(lo, std::min(hi, std::atoi(e)));
 }
 
 template <typename T, int N2, int MPAD, int NTF>
@@ -360,7 +381,7 @@ template <typename T>
 helic_status launch_fast(helic_basis_s* h, T* gh, int nvec, hipStream_t st, const cplx<T>* tw2) {
   DeviceState* d = h->dev;
   const T* Vh = std::is_same<T, double>::value ? (const T*)d->Vh : (const T*)d->Vhf;
-  const int vchunk = 4;
+  const int vchunk = d->vchunk;
   const int work = h->n_r * ((nvec + vchunk - 1) / vchunk);
   const dim3 grid(8 * ((work + 7) / 8));
   const size_t lds = fast_lds_bytes<T>(h->n_t2, d->fast_mpad);
@@ -459,6 +480,8 @@ helic_status ensure_device(helic_basis_s* h) {
       (s = upload(tw1, &d->tw1)) || (s = upload(tw2, &d->tw2)) || (s = upload(tw1f, &d->tw1f)) ||
       (s = upload(tw2f, &d->tw2f)))
     return s;
+  d->vchunk = env_int("HELIC_VCHUNK", 8, 1, 64);
+  d->apply_chunk = env_int("HELIC_APPLY_CHUNK", APPLY_CHUNK, 1, APPLY_CHUNK);
   d->plan1 = make_plan(h->n_t1, h->fac1);
   d->plan2 = make_plan(h->n_t2, h->fac2);
   // specialised angular kernel: smallest instantiated padding of the m count
@@ -479,7 +502,7 @@ helic_status ensure_device(helic_basis_s* h) {
   if (d->fast_mpad) {
     if ((s = set_fast_limits<double>()) || (s = set_fast_limits<float>())) return s;
     std::vector<int32_t> mp(h->modes.size());
-    for (size_t i = 0; i < h->modes.size(); ++i) mp[i] = (h->modes[i].m - mlo) * h->n_t2 + h->modes[i].bin2;
+    for (size_t i = 0; i < h->modes.size(); ++i) mp[i] = (h->modes[i].m - mlo) * (h->n_t2 + 1) + h->modes[i].bin2;
     if ((s = upload(mp, &d->mode_pos))) return s;
     const size_t nvh = (size_t)h->n_r * h->n_t2 * (2 * d->fast_mpad - 1) * 2;
     HIP_TRY(hipMalloc((void**)&d->Vh, nvh * sizeof(double)));
@@ -529,7 +552,7 @@ helic_status launch_apply(helic_basis_s* h, const double* X, int64_t ldx, double
   const cplx<T>* tw2 = std::is_same<T, double>::value ? (const cplx<T>*)d->tw2 : (const cplx<T>*)d->tw2f;
   const int wg_rad = 8 * ((ng * nvec + 7) / 8);
   const size_t lds_inv = (size_t)h->max_kpad * h->max_colpad * sizeof(T);
-  const size_t lds_fwd = (size_t)FWD_RCHUNK * h->max_colpad * sizeof(T);
+  const size_t lds_fwd = fwd_lds_bytes(h, sizeof(T));
   const int wg_ang = 8 * ((nvec * h->n_r + 7) / 8);
   const size_t lds_ang = angular_lds_bytes(h, sizeof(T));
   if (ev) HIP_TRY(hipEventRecord(ev[0], st));
@@ -561,7 +584,7 @@ template helic_status launch_apply<float>(helic_basis_s*, const double*, int64_t
 
 helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
                           int nvec, helic_prec prec, hipStream_t st, int chunk) {
-  chunk = std::max(1, std::min(chunk, APPLY_CHUNK));
+  chunk = std::max(1, std::min(chunk, h->dev->apply_chunk));
   const size_t elem = prec == HELIC_FP64 ? sizeof(double) : sizeof(float);
   helic_status s = ensure_workspace(h, std::min(nvec, chunk), elem);
   if (s != HELIC_OK) return s;
@@ -656,21 +679,31 @@ helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, do
   const size_t elem = prec == HELIC_FP64 ? sizeof(double) : sizeof(float);
   if ((s = ensure_workspace(h, nvec, elem)) != HELIC_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  std::vector<hipEvent_t> ev(4 * (size_t)nrep, nullptr);
+  const int chunk = h->dev->apply_chunk;
+  const int nch = (nvec + chunk - 1) / chunk;
+  std::vector<hipEvent_t> ev(4 * (size_t)nrep * nch, nullptr);
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   for (int i = 0; i < nrep && s == HELIC_OK; ++i)
-    s = prec == HELIC_FP64 ? launch_apply<double>(h, X, ldx, Y, ldy, nvec, st, 1, &ev[4 * i])
-                           : launch_apply<float>(h, X, ldx, Y, ldy, nvec, st, 1, &ev[4 * i]);
+    for (int c = 0; c < nch && s == HELIC_OK; ++c) {
+      const int v0 = c * chunk, nv = std::min(chunk, nvec - v0);
+      hipEvent_t* e4 = &ev[4 * ((size_t)i * nch + c)];
+      s = prec == HELIC_FP64
+              ? launch_apply<double>(h, X + (int64_t)v0 * ldx * 2, ldx, Y + (int64_t)v0 * ldy * 2, ldy, nv, st, 1, e4)
+              : launch_apply<float>(h, X + (int64_t)v0 * ldx * 2, ldx, Y + (int64_t)v0 * ldy * 2, ldy, nv, st, 1, e4);
+    }
   double acc[3] = {0, 0, 0}, tot = 0;
   if (s == HELIC_OK) {
     hipError_t e = hipStreamSynchronize(st);
-    for (int i = 0; i < nrep && e == hipSuccess; ++i) {
+    for (size_t i = 0; i < (size_t)nrep * nch && e == hipSuccess; ++i) {
       float ms;
       for (int k = 0; k < 3 && e == hipSuccess; ++k) {
         e = hipEventElapsedTime(&ms, ev[4 * i + k], ev[4 * i + k + 1]);
         acc[k] += ms;
       }
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[4 * i], ev[4 * i + 3]);
+    }
+    for (int i = 0; i < nrep && e == hipSuccess; ++i) {
+      float ms;
+      e = hipEventElapsedTime(&ms, ev[4 * (size_t)i * nch], ev[4 * ((size_t)i * nch + nch - 1) + 3]);
       tot += ms;
     }
     if (e != hipSuccess) s = fail(HELIC_ERR_HIP, std::string("event timing: ") + hipGetErrorString(e));
@@ -731,7 +764,7 @@ helic_status helic_transform_forward(helic_basis h, const double* g, double* X, 
                        d->tw2, d->plan1, d->plan2, 1.0 / ((double)h->n_t1 * h->n_t2));
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_radial_forward<double>), dim3(8 * ((ng * nv + 7) / 8)), dim3(NT),
-                       (size_t)FWD_RCHUNK * h->max_colpad * sizeof(double), st, gh, (const double*)nullptr, ldx,
+                       fwd_lds_bytes(h, sizeof(double)), st, gh, (const double*)nullptr, ldx,
                        X + (int64_t)v0 * ldx * 2, ldx, nv, ng, h->n_r, nm, d->groups, d->modes, d->kappa,
                        d->tfwd64, 0);
     HIP_TRY(hipGetLastError());

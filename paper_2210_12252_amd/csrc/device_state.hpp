@@ -35,6 +35,8 @@ struct DeviceState {
   int fast_mpad = 0;              // 0: use the general angular kernel
   int fast_ntf = 256;
   int m_min = 0, m_count = 0;
+  int vchunk = 8;                 // vectors per workgroup of the specialised angular kernel
+  int apply_chunk = APPLY_CHUNK;  // vectors per launch of the three stages
   int32_t* mode_pos = nullptr;    // (m - m_min) * n_t2 + (n mod n_t2) per mode
   double* Vh = nullptr;           // [n_r][n_t2][2 * fast_mpad - 1] complex
   float* Vhf = nullptr;

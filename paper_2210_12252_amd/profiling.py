@@ -29,13 +29,13 @@ def kernel_stats(db: str):
 
 
 def counter_means(db: str):
+    """Mean over dispatches of each counter, per kernel (a dispatch's rows,
+    e.g. one per XCD or instance, are summed first)."""
     c = sqlite3.connect(db)
-    cols = [d[0] for d in c.execute("select * from counters_collection limit 1").description]
-    name_col = "kernel_name" if "kernel_name" in cols else "name"
-    val_col = "value" if "value" in cols else "counter_value"
-    cnt_col = "counter_name"
-    rows = c.execute(f"select {name_col}, {cnt_col}, avg({val_col}), count(*) from counters_collection "
-                     f"group by {name_col}, {cnt_col} order by {name_col}").fetchall()
+    rows = c.execute("select kernel_name, counter_name, avg(s), count(*) from ("
+                     "  select kernel_name, counter_name, dispatch_id, sum(value) as s from counters_collection"
+                     "  group by kernel_name, counter_name, dispatch_id) "
+                     "group by kernel_name, counter_name order by kernel_name, counter_name").fetchall()
     return [(short_name(n), cn, v, k) for n, cn, v, k in rows]
 
 
