@@ -187,6 +187,39 @@ helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* opts, do
                                  double* resid, double* evecs, int64_t ldv, helic_solve_stats* stats,
                                  void* stream);
 
+/* ---- batches of Bloch parameters / structures (Sec. 3.3) ----------------
+ * A batch groups problems (basis handles, each with its potential set) that
+ * share the grid (n_t1, n_t2, n_r) and the angular kernel variant -- e.g. the
+ * Bloch parameters eta_b of one structure -- so that each H*X stage runs as
+ * one launch over the ragged work of all problems.  The batch borrows the
+ * handles (they must outlive it).  Batched blocks are concatenated: problem
+ * p's nvec columns (ld = L_p, column-major, complex) start at complex offset
+ * nvec * offsets[p], offsets from helic_batch_info (nprob + 1 entries). */
+typedef struct helic_batch_s* helic_batch;
+helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_batch* out);
+helic_status helic_batch_destroy(helic_batch b);
+helic_status helic_batch_info(helic_batch b, int64_t* offsets /* host, nprob + 1 */);
+/* Y = H X for every problem of the batch, 1 <= nvec <= 64 (device blocks). */
+helic_status helic_batch_apply(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec,
+                               void* stream);
+/* Capture the batched apply on these buffers into a HIP graph (replaces any
+ * previous one); helic_batch_replay launches it on `stream`.  A replay reads
+ * X and writes Y as captured. */
+helic_status helic_batch_capture(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec);
+helic_status helic_batch_replay(helic_batch b, void* stream);
+/* Tuner: times the batched apply for each candidate number of vectors per
+ * workgroup of the angular stage and keeps the fastest (*chosen, *ms_best:
+ * host, may be NULL).  Synchronises `stream`. */
+helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec,
+                              void* stream, int32_t* chosen, double* ms_best);
+/* Lowest opts->nev eigenpairs of every problem, solved concurrently on
+ * `nstreams` streams.  evals, resid: host, nprob * nev (problem-major);
+ * stats, status: host, nprob entries, may be NULL.  Returns the first hard
+ * error, else HELIC_ERR_NOCONV if some problem did not converge. */
+helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* opts, int32_t nstreams,
+                                    double* evals, double* resid, helic_solve_stats* stats,
+                                    int32_t* status);
+
 /* Host utilities used by the basis set-up, exported for testing.
  * helic_util_bessel_j: out[i] = J_p(x[i]) for integer p (any sign), x >= 0.
  * helic_util_bessel_zeros: first `count` positive zeros of J_p.

@@ -196,8 +196,8 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
 // (m_i - m_min) * (N2 + 1) + (n_i mod N2).  Work: blockIdx -> (radius, vector chunk).
 template <typename T, int N2, int MPAD, int NTF>
 __global__ void __launch_bounds__(NTF)
-k_angular_fast(T* __restrict__ GH, const T* __restrict__ Vh, int nvec, int n_r, int n_modes,
-               const int32_t* __restrict__ mode_pos, const cplx<T>* __restrict__ tw2g, int vchunk) {
+k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
+               const cplx<T>* __restrict__ tw2g, int vchunk) {
   constexpr int P = (N2 == 16) ? 4 : (N2 == 64) ? 8 : (N2 == 81) ? 9 : (N2 == 36) ? 6 : (N2 == 100) ? 10 : 0;
   static_assert(P > 0, "unsupported N2");
   constexpr int ND = 2 * MPAD - 1;
@@ -209,9 +209,15 @@ k_angular_fast(T* __restrict__ GH, const T* __restrict__ Vh, int nvec, int n_r, 
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);          // [MPAD][RS]
   cplx<T>* tw = A + MPAD * RS;                                 // [N2]
   const int nchunks = (nvec + vchunk - 1) / vchunk;
-  const int slot = xcd_slot(n_r * nchunks);
-  if (slot >= n_r * nchunks) return;
-  const int r = slot / nchunks, ch = slot - r * nchunks;
+  const int per = n_r * nchunks;
+  const int slot = xcd_slot(nprob * per);
+  if (slot >= nprob * per) return;
+  const int pi = slot / per, rem = slot - pi * per;
+  const int r = rem / nchunks, ch = rem - r * nchunks;
+  const DProb& pb = probs[pi];
+  const int n_modes = pb.n_modes;
+  const int32_t* mode_pos = pb.mode_pos;
+  const T* Vh = reinterpret_cast<const T*>(pb.Vh);
   const int v0 = ch * vchunk, v1 = min(nvec, v0 + vchunk);
   const int t = threadIdx.x;
   for (int i = t; i < N2; i += NTF) tw[i] = tw2g[i];
@@ -229,7 +235,7 @@ k_angular_fast(T* __restrict__ GH, const T* __restrict__ Vh, int nvec, int n_r, 
       w[q] = (conv_act && a0 + q < ND) ? src[a0 + q] : cplx<T>{(T)0, (T)0};
   }
   for (int v = v0; v < v1; ++v) {
-    cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + ((int64_t)v * n_r + r) * n_modes;
+    cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
     for (int i = t; i < MPAD * RS; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
     __syncthreads();
     for (int i = t; i < n_modes; i += NTF) A[mode_pos[i]] = slab[i];

@@ -1,0 +1,304 @@
+// Batches of grid-compatible problems (many Bloch parameters of one structure,
+// Sec. 3.3): one launch per H*X stage for the whole batch over ragged work
+// lists, capture of those launches in a HIP graph for replay, a tuner that
+// times the angular stage's vectors-per-workgroup choices, and concurrent
+// eigensolves of all problems on a pool of streams.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "device_state.hpp"
+#include "helic_internal.h"
+
+namespace helic {
+
+helic_status ensure_device(helic_basis_s* h);
+DProb problem_entry(const helic_basis_s* h, bool fp64, int64_t Lpre, int64_t mpre);
+LaunchSet launch_set(const helic_basis_s* h);
+template <typename T>
+helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, double* Y, int64_t ldy, int nvec,
+                           hipStream_t st, int mode, hipEvent_t* ev);
+helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double* evals, double* resid,
+                             double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st);
+
+}  // namespace helic
+
+struct helic_batch_s {
+  std::vector<helic_basis> bases;     // not owned
+  int device = 0;
+  std::vector<int64_t> Lpre;          // nprob + 1
+  int64_t mtot = 0;
+  helic::DGroup* groups = nullptr;
+  helic::DProb* probs64 = nullptr;
+  helic::DProb* probs32 = nullptr;
+  int32_t* rows1 = nullptr;
+  helic::LaunchSet ls;
+  void* gh = nullptr;
+  size_t gh_bytes = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+using namespace helic;
+
+#define HIP_TRY_B(call)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(HELIC_ERR_HIP, std::string(#call) + " (batch): " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+template <typename T>
+helic_status upload_vec(const std::vector<T>& v, T** d) {
+  HIP_TRY_B(hipMalloc((void**)d, sizeof(T) * std::max<size_t>(v.size(), 1)));
+  if (!v.empty()) HIP_TRY_B(hipMemcpy(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return HELIC_OK;
+}
+
+helic_status batch_workspace(helic_batch_s* b, int nvec, size_t elem) {
+  const size_t need = (size_t)nvec * b->ls.n_r * b->mtot * 2 * elem;
+  if (need > b->gh_bytes) {
+    if (b->gh) HIP_TRY_B(hipFree(b->gh));
+    b->gh = nullptr;
+    b->gh_bytes = 0;
+    HIP_TRY_B(hipMalloc(&b->gh, need));
+    b->gh_bytes = need;
+  }
+  b->ls.gh = b->gh;
+  return HELIC_OK;
+}
+
+void release_graph(helic_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+helic_status batch_launch(helic_batch_s* b, const double* X, double* Y, int nvec, helic_prec prec, hipStream_t st,
+                          hipEvent_t* ev) {
+  return prec == HELIC_FP64 ? launch_stages<double>(b->ls, X, -1, Y, -1, nvec, st, 1, ev)
+                            : launch_stages<float>(b->ls, X, -1, Y, -1, nvec, st, 1, ev);
+}
+
+helic_status check_block(helic_batch_s* b, const double* X, double* Y, int nvec, helic_prec prec) {
+  if (!X || !Y || nvec < 1 || nvec > APPLY_CHUNK) return fail(HELIC_ERR_INVALID, "bad batch block (1 <= nvec <= 64)");
+  if (prec != HELIC_FP64 && prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  const char* a = reinterpret_cast<const char*>(X);
+  const char* c = reinterpret_cast<const char*>(Y);
+  const size_t n = (size_t)nvec * b->Lpre.back() * 16;
+  if (a < c + n && c < a + n) return fail(HELIC_ERR_INVALID, "X and Y overlap");
+  return HELIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_batch* out) {
+  if (!bases || !out || nprob < 1) return fail(HELIC_ERR_INVALID, "bad arguments");
+  *out = nullptr;
+  const helic_basis_s* h0 = bases[0];
+  if (!h0) return fail(HELIC_ERR_INVALID, "null handle");
+  for (int p = 0; p < nprob; ++p) {
+    const helic_basis_s* h = bases[p];
+    if (!h) return fail(HELIC_ERR_INVALID, "null handle");
+    if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "every problem needs a potential first");
+    if (h->n_t1 != h0->n_t1 || h->n_t2 != h0->n_t2 || h->n_r != h0->n_r)
+      return fail(HELIC_ERR_GRID, "problems of a batch must share the grid");
+    if (h->dev->fast_mpad != h0->dev->fast_mpad || h->dev->device != h0->dev->device)
+      return fail(HELIC_ERR_GRID, "problems of a batch must share the angular kernel variant and device");
+  }
+  helic_batch_s* b = new helic_batch_s();
+  b->bases.assign(bases, bases + nprob);
+  b->device = h0->dev->device;
+  b->Lpre.assign(nprob + 1, 0);
+  std::vector<DGroup> groups;
+  std::vector<DProb> p64(nprob), p32(nprob);
+  std::vector<char> row_used(h0->n_t1, 0);
+  int64_t mpre = 0;
+  size_t lds_inv = 0, lds_fwd = 0, lds_ang = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const helic_basis_s* h = bases[p];
+    b->Lpre[p + 1] = b->Lpre[p] + h->L;
+    p64[p] = problem_entry(h, true, b->Lpre[p], mpre);
+    p32[p] = problem_entry(h, false, b->Lpre[p], mpre);
+    for (const Group& g : h->groups)
+      groups.push_back(DGroup{g.mode0, g.nmodes, g.Kmax, p, g.row0, g.nrows, g.tinv_off, g.tfwd_off});
+    for (int r : h->rows1) row_used[r] = 1;
+    mpre += (int64_t)h->modes.size();
+    const LaunchSet one = launch_set(h);
+    lds_inv = std::max(lds_inv, one.lds_inv64);
+    lds_fwd = std::max(lds_fwd, one.lds_fwd64);
+    lds_ang = std::max(lds_ang, one.lds_ang64);
+  }
+  b->mtot = mpre;
+  std::vector<int32_t> rows1;
+  for (int i = 0; i < h0->n_t1; ++i)
+    if (row_used[i]) rows1.push_back(i);
+  helic_status s;
+  if ((s = upload_vec(groups, &b->groups)) || (s = upload_vec(p64, &b->probs64)) ||
+      (s = upload_vec(p32, &b->probs32)) || (s = upload_vec(rows1, &b->rows1))) {
+    helic_batch_destroy(b);
+    return s;
+  }
+  b->ls = launch_set(h0);
+  b->ls.groups = b->groups;
+  b->ls.ngroups = (int)groups.size();
+  b->ls.probs64 = b->probs64;
+  b->ls.probs32 = b->probs32;
+  b->ls.nprob = nprob;
+  b->ls.lds_inv64 = lds_inv;
+  b->ls.lds_fwd64 = lds_fwd;
+  b->ls.lds_ang64 = lds_ang + rows1.size() * sizeof(int32_t);
+  b->ls.rows1 = b->rows1;
+  b->ls.nrows1 = (int)rows1.size();
+  b->ls.gh = nullptr;
+  *out = b;
+  return HELIC_OK;
+}
+
+helic_status helic_batch_destroy(helic_batch b) {
+  if (!b) return HELIC_OK;
+  release_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  void* ptrs[] = {b->groups, b->probs64, b->probs32, b->rows1, b->gh};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete b;
+  return HELIC_OK;
+}
+
+helic_status helic_batch_info(helic_batch b, int64_t* offsets) {
+  if (!b || !offsets) return fail(HELIC_ERR_INVALID, "null argument");
+  std::copy(b->Lpre.begin(), b->Lpre.end(), offsets);
+  return HELIC_OK;
+}
+
+helic_status helic_batch_apply(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec,
+                               void* stream) {
+  if (!b) return fail(HELIC_ERR_INVALID, "null batch");
+  helic_status s = check_block(b, X, Y, nvec, prec);
+  if (s != HELIC_OK) return s;
+  if ((s = batch_workspace(b, nvec, prec == HELIC_FP64 ? 8 : 4))) return s;
+  return batch_launch(b, X, Y, nvec, prec, reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+helic_status helic_batch_capture(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec) {
+  if (!b) return fail(HELIC_ERR_INVALID, "null batch");
+  helic_status s = check_block(b, X, Y, nvec, prec);
+  if (s != HELIC_OK) return s;
+  if ((s = batch_workspace(b, nvec, prec == HELIC_FP64 ? 8 : 4))) return s;
+  release_graph(b);
+  if (!b->cap_stream) HIP_TRY_B(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  HIP_TRY_B(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  s = batch_launch(b, X, Y, nvec, prec, b->cap_stream, nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (s != HELIC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(HELIC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  b->graph = g;
+  HIP_TRY_B(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return HELIC_OK;
+}
+
+helic_status helic_batch_replay(helic_batch b, void* stream) {
+  if (!b) return fail(HELIC_ERR_INVALID, "null batch");
+  if (!b->exec) return fail(HELIC_ERR_STATE, "no captured graph");
+  HIP_TRY_B(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
+  return HELIC_OK;
+}
+
+helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec, void* stream,
+                              int32_t* chosen, double* ms_best) {
+  if (!b) return fail(HELIC_ERR_INVALID, "null batch");
+  helic_status s = check_block(b, X, Y, nvec, prec);
+  if (s != HELIC_OK) return s;
+  if ((s = batch_workspace(b, nvec, prec == HELIC_FP64 ? 8 : 4))) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int cands[] = {1, 2, 4, 8, 16};
+  hipEvent_t e0, e1;
+  HIP_TRY_B(hipEventCreate(&e0));
+  HIP_TRY_B(hipEventCreate(&e1));
+  int best = b->ls.vchunk;
+  float best_ms = 1e30f;
+  for (int c : cands) {
+    if (!b->ls.fast_mpad && c != b->ls.vchunk) continue;   // only the specialised kernel has the knob
+    b->ls.vchunk = c;
+    for (int rep = 0; rep < 2 && s == HELIC_OK; ++rep) s = batch_launch(b, X, Y, nvec, prec, st, nullptr);  // warm
+    if (s != HELIC_OK) break;
+    (void)hipEventRecord(e0, st);
+    for (int rep = 0; rep < 5 && s == HELIC_OK; ++rep) s = batch_launch(b, X, Y, nvec, prec, st, nullptr);
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= 5;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->ls.vchunk = best;
+  if (chosen) *chosen = best;
+  if (ms_best) *ms_best = best_ms;
+  return s;
+}
+
+helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* o, int32_t nstreams, double* evals,
+                                    double* resid, helic_solve_stats* stats, int32_t* status) {
+  if (!b || !o || !evals || !resid || nstreams < 1) return fail(HELIC_ERR_INVALID, "bad arguments");
+  const int nprob = (int)b->bases.size();
+  for (helic_basis h : b->bases)
+    if (o->nev < 1 || o->nev > h->L) return fail(HELIC_ERR_INVALID, "nev out of range for a problem");
+  std::atomic<int> next(0);
+  std::vector<helic_status> st(nprob, HELIC_OK);
+  std::vector<std::string> msg(nprob);
+  auto worker = [&]() {
+    (void)hipSetDevice(b->device);
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    for (;;) {
+      const int p = next.fetch_add(1);
+      if (p >= nprob) break;
+      helic_solve_stats ss;
+      std::memset(&ss, 0, sizeof(ss));
+      st[p] = s ? eigensolve_impl(b->bases[p], *o, evals + (size_t)p * o->nev, resid + (size_t)p * o->nev, nullptr, 0,
+                                  &ss, s)
+                : HELIC_ERR_HIP;
+      if (st[p] != HELIC_OK) msg[p] = helic_last_error();
+      if (stats) stats[p] = ss;
+    }
+    if (s) (void)hipStreamDestroy(s);
+  };
+  std::vector<std::thread> pool;
+  const int nt = std::min(nstreams, nprob);
+  for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  helic_status ret = HELIC_OK;
+  for (int p = 0; p < nprob; ++p) {
+    if (status) status[p] = st[p];
+    if (st[p] != HELIC_OK && st[p] != HELIC_ERR_NOCONV && ret == HELIC_OK) {
+      ret = fail(st[p], "problem " + std::to_string(p) + ": " + msg[p]);
+    }
+  }
+  if (ret == HELIC_OK)
+    for (int p = 0; p < nprob; ++p)
+      if (st[p] == HELIC_ERR_NOCONV) return fail(HELIC_ERR_NOCONV, "problem " + std::to_string(p) + " did not converge");
+  return ret;
+}
+
+}  // extern "C"

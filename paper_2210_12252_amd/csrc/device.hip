@@ -20,15 +20,15 @@ namespace helic {
 // ============================================================ kernels
 template <typename T>
 __global__ void __launch_bounds__(NT)
-k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, int nvec,
-                 int ngroups, int n_r, int n_modes, const DGroup* __restrict__ groups,
-                 const int32_t* __restrict__ row_ck, const T* __restrict__ tinv) {
+k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, int nvec, int ngroups, int n_r,
+                 const DGroup* __restrict__ groups, const DProb* __restrict__ probs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Bs = reinterpret_cast<T*>(smem_raw);
   const int slot = xcd_slot(ngroups * nvec);
   if (slot >= ngroups * nvec) return;
   const int gi = slot / nvec, v = slot - gi * nvec;
   const DGroup gr = groups[gi];
+  const DProb& pb = probs[gr.prob];
   const int nks = (gr.Kmax + 3) / 4;
   const int kpad = 4 * nks;
   const int ncol = 2 * gr.nmodes;
@@ -36,7 +36,8 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   const int colpad = 16 * nct;
   for (int i = threadIdx.x; i < kpad * colpad; i += NT) Bs[i] = (T)0;
   __syncthreads();
-  const double* xv = X + (int64_t)v * ldx * 2 + gr.row0 * 2;
+  const double* xv = X + col_off(pb, ldx, nvec, v) * 2 + gr.row0 * 2;
+  const int32_t* row_ck = pb.row_ck;
   const int nvals = (int)(2 * gr.nrows);
   for (int i = threadIdx.x; i < nvals; i += NT) {
     const int ck = row_ck[gr.row0 + (i >> 1)];
@@ -46,7 +47,8 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nrt = (n_r + 15) / 16;
-  const T* tg = tinv + gr.tinv_off;
+  const T* tg = reinterpret_cast<const T*>(pb.tinv) + gr.tinv_off;
+  T* gv = GH + (slab_off(pb, nvec, n_r, v, 0) + gr.mode0) * 2;
   typedef typename Mfma<T>::acc_t acc_t;
   for (int rt = wave; rt < nrt; rt += NT / 64) {
     T a[KS_MAX];
@@ -67,35 +69,36 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int r = 16 * rt + Mfma<T>::row(lane, i);
-          if (r < n_r) GH[(((int64_t)v * n_r + r) * n_modes + gr.mode0) * 2 + col] = acc[i];
+          if (r < n_r) gv[(int64_t)r * pb.n_modes * 2 + col] = acc[i];
         }
       }
     }
   }
 }
 
-// MODE 0: fused inverse -> V -> forward (H*X); 1: inverse only, writes the
-// real-space grid; 2: forward only, reads the real-space grid.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(NT)
-k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __restrict__ grid_out,
-          const T* __restrict__ Vs, int nvec, int n_r, int n_modes,
-          const DMode* __restrict__ modes, const int32_t* __restrict__ rows1, int nrows1,
-          const cplx<T>* __restrict__ tw1g, const cplx<T>* __restrict__ tw2g, FftPlan p1,
-          FftPlan p2, T out_scale) {
+k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __restrict__ grid_out, int nprob, int nvec,
+          int n_r, const DProb* __restrict__ probs, const int32_t* __restrict__ rows1, int nrows1,
+          const cplx<T>* __restrict__ tw1g, const cplx<T>* __restrict__ tw2g, FftPlan p1, FftPlan p2, T out_scale) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n1 = p1.n, n2 = p2.n, nn = n1 * n2;
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* tw1 = buf + nn;
   cplx<T>* tw2 = tw1 + n1;
   int32_t* rws = reinterpret_cast<int32_t*>(tw2 + n2);
-  const int slot = xcd_slot(nvec * n_r);
-  if (slot >= nvec * n_r) return;
-  const int r = slot / nvec, v = slot - r * nvec;
+  const int per = nvec * n_r;
+  const int slot = xcd_slot(nprob * per);
+  if (slot >= nprob * per) return;
+  const int pi = slot / per, rem = slot - pi * per;
+  const int r = rem / nvec, v = rem - r * nvec;
+  const DProb& pb = probs[pi];
+  const int n_modes = pb.n_modes;
+  const DMode* modes = pb.modes;
   for (int i = threadIdx.x; i < n1; i += NT) tw1[i] = tw1g[i];
   for (int i = threadIdx.x; i < n2; i += NT) tw2[i] = tw2g[i];
   for (int i = threadIdx.x; i < nrows1; i += NT) rws[i] = rows1[i];
-  cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + ((int64_t)v * n_r + r) * n_modes;
+  cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
   if (MODE == 2) {
     const double* gi = grid_in + (int64_t)v * nn * n_r * 2;
     for (int i = threadIdx.x; i < nn; i += NT)
@@ -120,7 +123,7 @@ k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __rest
   }
   // forward: theta1 lines (potential fused into the first pass), then theta2
   // lines on the bins that are kept
-  const T* vm = (MODE == 0) ? Vs + (int64_t)r * nn : nullptr;
+  const T* vm = (MODE == 0) ? reinterpret_cast<const T*>(pb.Vs) + (int64_t)r * nn : nullptr;
   fft_lines<T>(buf, n2, nullptr, 1, n2, p1, tw1, (T)-1, vm);
   fft_lines<T>(buf, nrows1, rws, n2, 1, p2, tw2, (T)-1, nullptr);
   for (int i = threadIdx.x; i < n_modes; i += NT) {
@@ -131,16 +134,16 @@ k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __rest
 
 template <typename T>
 __global__ void __launch_bounds__(NT)
-k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t ldx,
-                 double* __restrict__ Y, int64_t ldy, int nvec, int ngroups, int n_r, int n_modes,
-                 const DGroup* __restrict__ groups, const DMode* __restrict__ modes,
-                 const double* __restrict__ kappa, const T* __restrict__ tfwd, int add_kinetic) {
+k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
+                 int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* __restrict__ groups,
+                 const DProb* __restrict__ probs, int add_kinetic) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Hs = reinterpret_cast<T*>(smem_raw);
   const int slot = xcd_slot(ngroups * nvec);
   if (slot >= ngroups * nvec) return;
   const int gi = slot / nvec, v = slot - gi * nvec;
   const DGroup gr = groups[gi];
+  const DProb& pb = probs[gr.prob];
   const int ncol = 2 * gr.nmodes;
   T* As = Hs + FWD_RCHUNK * (16 * ((ncol + 15) / 16));     // [k tile][step][64]
   const int nct = (ncol + 15) / 16;
@@ -148,9 +151,14 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
   const int nkt = (gr.Kmax + 15) / 16;
   const int ntiles = nkt * nct;
   const int nrs = (n_r + 3) / 4;
+  const int n_modes = pb.n_modes;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const T* tg = tfwd + gr.tfwd_off;
-  const T* hv = GH + ((int64_t)v * n_r * n_modes + gr.mode0) * 2;
+  const T* tg = reinterpret_cast<const T*>(pb.tfwd) + gr.tfwd_off;
+  const T* hv = GH + (slab_off(pb, nvec, n_r, v, 0) + gr.mode0) * 2;
+  const DMode* modes = pb.modes;
+  const double* kappa = pb.kappa;
+  const double* xv = add_kinetic ? X + col_off(pb, ldx, nvec, v) * 2 : nullptr;
+  double* yv = Y + col_off(pb, ldy, nvec, v) * 2;
   typedef typename Mfma<T>::acc_t acc_t;
   for (int tbase = 0; tbase < ntiles; tbase += (NT / 64) * FWD_TMAX) {
     acc_t acc[FWD_TMAX];
@@ -203,8 +211,8 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
         if (k < md.K) {
           const int64_t row = md.row0 + k;
           double y = (double)acc[i][j];
-          if (add_kinetic) y += kappa[row] * X[(int64_t)v * ldx * 2 + 2 * row + ri];
-          Y[(int64_t)v * ldy * 2 + 2 * row + ri] = y;
+          if (add_kinetic) y += kappa[row] * xv[2 * row + ri];
+          yv[2 * row + ri] = y;
         }
       }
     }
@@ -378,18 +386,17 @@ helic_status set_fast_limits() {
 }
 
 template <typename T>
-helic_status launch_fast(helic_basis_s* h, T* gh, int nvec, hipStream_t st, const cplx<T>* tw2) {
-  DeviceState* d = h->dev;
-  const T* Vh = std::is_same<T, double>::value ? (const T*)d->Vh : (const T*)d->Vhf;
-  const int vchunk = d->vchunk;
-  const int work = h->n_r * ((nvec + vchunk - 1) / vchunk);
+helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
+  const DProb* probs = std::is_same<T, double>::value ? ls.probs64 : ls.probs32;
+  const cplx<T>* tw2 = (const cplx<T>*)(std::is_same<T, double>::value ? ls.tw2_64 : ls.tw2_32);
+  const int vchunk = ls.vchunk;
+  const int work = ls.nprob * ls.n_r * ((nvec + vchunk - 1) / vchunk);
   const dim3 grid(8 * ((work + 7) / 8));
-  const size_t lds = fast_lds_bytes<T>(h->n_t2, d->fast_mpad);
-  const int nm = (int)h->modes.size();
+  const size_t lds = fast_lds_bytes<T>(ls.n_t2, ls.fast_mpad);
 #define HELIC_FAST_CASE(N2_, MP_, NTF_)                                                                   \
-  if (h->n_t2 == N2_ && d->fast_mpad == MP_) {                                                          \
-    hipLaunchKernelGGL((k_angular_fast<T, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, gh, Vh, nvec, h->n_r, \
-                       nm, d->mode_pos, tw2, vchunk);                                                   \
+  if (ls.n_t2 == N2_ && ls.fast_mpad == MP_) {                                                          \
+    hipLaunchKernelGGL((k_angular_fast<T, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, gh, ls.nprob, nvec, \
+                       ls.n_r, probs, tw2, vchunk);                                                     \
     HIP_TRY(hipGetLastError());                                                                         \
     return HELIC_OK;                                                                                    \
   }
@@ -431,6 +438,8 @@ FftPlan make_plan(int n, const std::vector<int32_t>& f) {
 
 }  // namespace
 
+DProb problem_entry(const helic_basis_s* h, bool fp64, int64_t Lpre, int64_t mpre);
+
 helic_status ensure_device(helic_basis_s* h) {
   int cur = 0;
   HIP_TRY(hipGetDevice(&cur));
@@ -453,7 +462,7 @@ helic_status ensure_device(helic_basis_s* h) {
   std::vector<DGroup> dg(h->groups.size());
   for (size_t i = 0; i < h->groups.size(); ++i) {
     const Group& g = h->groups[i];
-    dg[i] = DGroup{g.mode0, g.nmodes, g.Kmax, 0, g.row0, g.nrows, g.tinv_off, g.tfwd_off};
+    dg[i] = DGroup{g.mode0, g.nmodes, g.Kmax, /*prob*/ 0, g.row0, g.nrows, g.tinv_off, g.tfwd_off};
   }
   std::vector<DMode> dm(h->modes.size());
   for (size_t i = 0; i < h->modes.size(); ++i) {
@@ -508,7 +517,60 @@ helic_status ensure_device(helic_basis_s* h) {
     HIP_TRY(hipMalloc((void**)&d->Vh, nvh * sizeof(double)));
     HIP_TRY(hipMalloc((void**)&d->Vhf, nvh * sizeof(float)));
   }
+  const size_t nv = (size_t)h->n_t1 * h->n_t2 * h->n_r;
+  HIP_TRY(hipMalloc((void**)&d->Vs, nv * sizeof(double)));
+  HIP_TRY(hipMalloc((void**)&d->Vsf, nv * sizeof(float)));
+  std::vector<DProb> p64{problem_entry(h, true, 0, 0)}, p32{problem_entry(h, false, 0, 0)};
+  if ((s = upload(p64, &d->probs64)) || (s = upload(p32, &d->probs32))) return s;
   return HELIC_OK;
+}
+
+DProb problem_entry(const helic_basis_s* h, bool fp64, int64_t Lpre, int64_t mpre) {
+  const DeviceState* d = h->dev;
+  DProb p;
+  std::memset(&p, 0, sizeof(p));
+  p.groups = d->groups;
+  p.modes = d->modes;
+  p.row_ck = d->row_ck;
+  p.kappa = d->kappa;
+  p.tinv = fp64 ? (const void*)d->tinv64 : (const void*)d->tinv32;
+  p.tfwd = fp64 ? (const void*)d->tfwd64 : (const void*)d->tfwd32;
+  p.Vs = fp64 ? (const void*)d->Vs : (const void*)d->Vsf;
+  p.Vh = fp64 ? (const void*)d->Vh : (const void*)d->Vhf;
+  p.mode_pos = d->mode_pos;
+  p.Lpre = Lpre;
+  p.L = h->L;
+  p.mpre = mpre;
+  p.n_modes = (int32_t)h->modes.size();
+  return p;
+}
+
+LaunchSet launch_set(const helic_basis_s* h) {
+  const DeviceState* d = h->dev;
+  LaunchSet ls;
+  ls.groups = d->groups;
+  ls.ngroups = (int)h->groups.size();
+  ls.probs64 = d->probs64;
+  ls.probs32 = d->probs32;
+  ls.nprob = 1;
+  ls.n_r = h->n_r;
+  ls.n_t1 = h->n_t1;
+  ls.n_t2 = h->n_t2;
+  ls.lds_inv64 = (size_t)h->max_kpad * h->max_colpad * sizeof(double);
+  ls.lds_fwd64 = fwd_lds_bytes(h, sizeof(double));
+  ls.lds_ang64 = angular_lds_bytes(h, sizeof(double));
+  ls.fast_mpad = d->fast_mpad;
+  ls.vchunk = d->vchunk;
+  ls.rows1 = d->rows1;
+  ls.nrows1 = (int)h->rows1.size();
+  ls.plan1 = d->plan1;
+  ls.plan2 = d->plan2;
+  ls.tw1_64 = d->tw1;
+  ls.tw2_64 = d->tw2;
+  ls.tw1_32 = d->tw1f;
+  ls.tw2_32 = d->tw2f;
+  ls.gh = d->gh;
+  return ls;
 }
 
 helic_status ensure_workspace(helic_basis_s* h, int nvec, size_t elem) {
@@ -529,7 +591,7 @@ void device_release(helic_basis_s* h) {
   if (!d) return;
   void* ptrs[] = {d->groups, d->modes, d->row_ck, d->kappa, d->rows1, d->tinv64, d->tfwd64,
                   d->tinv32, d->tfwd32, d->tw1, d->tw2, d->tw1f, d->tw2f, d->Vs, d->Vsf,
-                  d->gh, d->part, d->mode_pos, d->Vh, d->Vhf};
+                  d->gh, d->part, d->mode_pos, d->Vh, d->Vhf, d->probs64, d->probs32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   release_solver_state(d);
@@ -537,50 +599,50 @@ void device_release(helic_basis_s* h) {
   h->dev = nullptr;
 }
 
-// Launches of the three H*X stages for one chunk of at most `chunk` vectors.
+// The three H*X stages over a launch set (one handle or a batch) for nvec
+// vectors; ldx / ldy < 0 selects the concatenated batch layout.
 template <typename T>
-helic_status launch_apply(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
-                          int nvec, hipStream_t st, int mode, hipEvent_t* ev = nullptr) {
-  DeviceState* d = h->dev;
-  const int ng = (int)h->groups.size();
-  const int nm = (int)h->modes.size();
-  T* gh = reinterpret_cast<T*>(d->gh);
-  const T* tinv = std::is_same<T, double>::value ? (const T*)d->tinv64 : (const T*)d->tinv32;
-  const T* tfwd = std::is_same<T, double>::value ? (const T*)d->tfwd64 : (const T*)d->tfwd32;
-  const T* Vs = std::is_same<T, double>::value ? (const T*)d->Vs : (const T*)d->Vsf;
-  const cplx<T>* tw1 = std::is_same<T, double>::value ? (const cplx<T>*)d->tw1 : (const cplx<T>*)d->tw1f;
-  const cplx<T>* tw2 = std::is_same<T, double>::value ? (const cplx<T>*)d->tw2 : (const cplx<T>*)d->tw2f;
-  const int wg_rad = 8 * ((ng * nvec + 7) / 8);
-  const size_t lds_inv = (size_t)h->max_kpad * h->max_colpad * sizeof(T);
-  const size_t lds_fwd = fwd_lds_bytes(h, sizeof(T));
-  const int wg_ang = 8 * ((nvec * h->n_r + 7) / 8);
-  const size_t lds_ang = angular_lds_bytes(h, sizeof(T));
+helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, double* Y, int64_t ldy, int nvec,
+                           hipStream_t st, int mode, hipEvent_t* ev) {
+  const bool f64 = std::is_same<T, double>::value;
+  const DProb* probs = f64 ? ls.probs64 : ls.probs32;
+  T* gh = reinterpret_cast<T*>(ls.gh);
+  const size_t sc = f64 ? 1 : 2;
+  const int wg_rad = 8 * ((ls.ngroups * nvec + 7) / 8);
   if (ev) HIP_TRY(hipEventRecord(ev[0], st));
-  hipLaunchKernelGGL((k_radial_inverse<T>), dim3(wg_rad), dim3(NT), lds_inv, st, X, ldx, gh, nvec, ng,
-                     h->n_r, nm, d->groups, d->row_ck, tinv);
+  hipLaunchKernelGGL((k_radial_inverse<T>), dim3(wg_rad), dim3(NT), ls.lds_inv64 / sc, st, X, ldx, gh, nvec,
+                     ls.ngroups, ls.n_r, ls.groups, probs);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-  if (d->fast_mpad) {
-    helic_status s = launch_fast<T>(h, gh, nvec, st, tw2);
+  if (ls.fast_mpad) {
+    helic_status s = launch_fast<T>(ls, gh, nvec, st);
     if (s != HELIC_OK) return s;
   } else {
-    hipLaunchKernelGGL((k_angular<T, 0>), dim3(wg_ang), dim3(NT), lds_ang, st, gh, nullptr, nullptr, Vs, nvec,
-                       h->n_r, nm, d->modes, d->rows1, (int)h->rows1.size(), tw1, tw2, d->plan1, d->plan2,
-                       (T)1);
+    const int wg_ang = 8 * ((ls.nprob * nvec * ls.n_r + 7) / 8);
+    const cplx<T>* tw1 = (const cplx<T>*)(f64 ? ls.tw1_64 : ls.tw1_32);
+    const cplx<T>* tw2 = (const cplx<T>*)(f64 ? ls.tw2_64 : ls.tw2_32);
+    hipLaunchKernelGGL((k_angular<T, 0>), dim3(wg_ang), dim3(NT), ls.lds_ang64 / sc, st, gh, nullptr, nullptr,
+                       ls.nprob, nvec, ls.n_r, probs, ls.rows1, ls.nrows1, tw1, tw2, ls.plan1, ls.plan2, (T)1);
     HIP_TRY(hipGetLastError());
   }
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-  hipLaunchKernelGGL((k_radial_forward<T>), dim3(wg_rad), dim3(NT), lds_fwd, st, gh, X, ldx, Y, ldy, nvec,
-                     ng, h->n_r, nm, d->groups, d->modes, d->kappa, tfwd, mode);
+  hipLaunchKernelGGL((k_radial_forward<T>), dim3(wg_rad), dim3(NT), ls.lds_fwd64 / sc, st, gh, X, ldx, Y, ldy, nvec,
+                     ls.ngroups, ls.n_r, ls.groups, probs, mode);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   return HELIC_OK;
 }
 
-template helic_status launch_apply<double>(helic_basis_s*, const double*, int64_t, double*, int64_t, int,
+template helic_status launch_stages<double>(const LaunchSet&, const double*, int64_t, double*, int64_t, int,
+                                            hipStream_t, int, hipEvent_t*);
+template helic_status launch_stages<float>(const LaunchSet&, const double*, int64_t, double*, int64_t, int,
                                            hipStream_t, int, hipEvent_t*);
-template helic_status launch_apply<float>(helic_basis_s*, const double*, int64_t, double*, int64_t, int,
-                                          hipStream_t, int, hipEvent_t*);
+
+template <typename T>
+helic_status launch_apply(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy, int nvec,
+                          hipStream_t st, int mode, hipEvent_t* ev = nullptr) {
+  return launch_stages<T>(launch_set(h), X, ldx, Y, ldy, nvec, st, mode, ev);
+}
 
 helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
                           int nvec, helic_prec prec, hipStream_t st, int chunk) {
@@ -633,10 +695,7 @@ helic_status helic_set_potential(helic_basis h, const double* V, void* stream) {
   if (s != HELIC_OK) return s;
   DeviceState* d = h->dev;
   const size_t n = (size_t)h->n_t1 * h->n_t2 * h->n_r;
-  if (!d->Vs) {
-    HIP_TRY(hipMalloc((void**)&d->Vs, n * sizeof(double)));
-    HIP_TRY(hipMalloc((void**)&d->Vsf, n * sizeof(float)));
-  }
+
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int nb = (int)std::min<size_t>(4096, (n + NT - 1) / NT);
   hipLaunchKernelGGL(k_relayout_potential, dim3(nb), dim3(NT), 0, st, V, d->Vs, d->Vsf, h->n_t1, h->n_t2,
@@ -732,12 +791,11 @@ helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx
     double* gh = reinterpret_cast<double*>(d->gh);
     hipLaunchKernelGGL((k_radial_inverse<double>), dim3(8 * ((ng * nv + 7) / 8)), dim3(NT),
                        (size_t)h->max_kpad * h->max_colpad * sizeof(double), st, X + (int64_t)v0 * ldx * 2, ldx,
-                       gh, nv, ng, h->n_r, nm, d->groups, d->row_ck, d->tinv64);
+                       gh, nv, ng, h->n_r, d->groups, d->probs64);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_angular<double, 1>), dim3(8 * ((nv * h->n_r + 7) / 8)), dim3(NT),
-                       angular_lds_bytes(h, sizeof(double)), st, gh, nullptr, g + v0 * grid_elems * 2,
-                       (const double*)nullptr, nv, h->n_r, nm, d->modes, d->rows1, (int)h->rows1.size(), d->tw1,
-                       d->tw2, d->plan1, d->plan2, 1.0);
+                       angular_lds_bytes(h, sizeof(double)), st, gh, nullptr, g + v0 * grid_elems * 2, 1, nv,
+                       h->n_r, d->probs64, d->rows1, (int)h->rows1.size(), d->tw1, d->tw2, d->plan1, d->plan2, 1.0);
     HIP_TRY(hipGetLastError());
   }
   return HELIC_OK;
@@ -759,14 +817,13 @@ helic_status helic_transform_forward(helic_basis h, const double* g, double* X, 
     if ((s = ensure_workspace(h, nv, sizeof(double))) != HELIC_OK) return s;
     double* gh = reinterpret_cast<double*>(d->gh);
     hipLaunchKernelGGL((k_angular<double, 2>), dim3(8 * ((nv * h->n_r + 7) / 8)), dim3(NT),
-                       angular_lds_bytes(h, sizeof(double)), st, gh, g + v0 * grid_elems * 2, nullptr,
-                       (const double*)nullptr, nv, h->n_r, nm, d->modes, d->rows1, (int)h->rows1.size(), d->tw1,
-                       d->tw2, d->plan1, d->plan2, 1.0 / ((double)h->n_t1 * h->n_t2));
+                       angular_lds_bytes(h, sizeof(double)), st, gh, g + v0 * grid_elems * 2, nullptr, 1, nv,
+                       h->n_r, d->probs64, d->rows1, (int)h->rows1.size(), d->tw1, d->tw2, d->plan1, d->plan2,
+                       1.0 / ((double)h->n_t1 * h->n_t2));
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_radial_forward<double>), dim3(8 * ((ng * nv + 7) / 8)), dim3(NT),
                        fwd_lds_bytes(h, sizeof(double)), st, gh, (const double*)nullptr, ldx,
-                       X + (int64_t)v0 * ldx * 2, ldx, nv, ng, h->n_r, nm, d->groups, d->modes, d->kappa,
-                       d->tfwd64, 0);
+                       X + (int64_t)v0 * ldx * 2, ldx, nv, ng, h->n_r, d->groups, d->probs64, 0);
     HIP_TRY(hipGetLastError());
   }
   return HELIC_OK;

@@ -40,11 +40,32 @@ struct DeviceState {
   int32_t* mode_pos = nullptr;    // (m - m_min) * n_t2 + (n mod n_t2) per mode
   double* Vh = nullptr;           // [n_r][n_t2][2 * fast_mpad - 1] complex
   float* Vhf = nullptr;
+  DProb* probs64 = nullptr;       // one-entry problem tables of this handle
+  DProb* probs32 = nullptr;
   double* part = nullptr;
   size_t part_bytes = 0;
   SolverState* solver = nullptr;
 };
 
 void release_solver_state(DeviceState* d);
+
+// Everything one launch of the three H*X stages needs, for a single handle
+// or a batch of grid-compatible handles.
+struct LaunchSet {
+  const DGroup* groups = nullptr;   // all groups of all problems (prob field set)
+  int ngroups = 0;
+  const DProb* probs64 = nullptr;
+  const DProb* probs32 = nullptr;
+  int nprob = 1;
+  int n_r = 0, n_t1 = 0, n_t2 = 0;
+  size_t lds_inv64 = 0, lds_fwd64 = 0, lds_ang64 = 0, lds_fast64 = 0;   // FP32 uses half
+  int fast_mpad = 0, vchunk = 8;
+  const int32_t* rows1 = nullptr;
+  int nrows1 = 0;
+  FftPlan plan1{}, plan2{};
+  const void* tw1_64 = nullptr; const void* tw2_64 = nullptr;
+  const void* tw1_32 = nullptr; const void* tw2_32 = nullptr;
+  void* gh = nullptr;               // intermediate buffer (large enough for the call)
+};
 
 }  // namespace helic

@@ -35,13 +35,13 @@
 namespace helic {
 
 constexpr int NT = 256;             // threads per workgroup in every kernel
-constexpr int MAXGRID = 4096;       // n_t1 * n_t2 bound of k_angular
+constexpr int MAXGRID = 8192;       // n_t1 * n_t2 bound of k_angular
 constexpr int KS_MAX = 24;          // K <= 96 per |n| group
 constexpr int FWD_TMAX = 4;         // output tiles per wave per round in k_radial_forward
 constexpr int FWD_RCHUNK = 32;      // radii staged per LDS round in k_radial_forward
 
 struct DGroup {
-  int32_t mode0, nmodes, Kmax, pad;
+  int32_t mode0, nmodes, Kmax, prob;   // modes relative to the problem; prob indexes DProb
   int64_t row0, nrows, tinv_off, tfwd_off;
 };
 
@@ -50,6 +50,34 @@ struct DMode {
   int32_t K;
   int32_t boff;   // LDS offset bin1 * n_t2 + bin2 of the mode in a slab
 };
+
+// One problem (basis + potential) of a launch.  A launch covers one problem
+// (leading dimensions given by the caller) or a batch of problems whose
+// blocks are concatenated: problem p's nvec columns of L_p rows start at
+// complex offset nvec * Lpre_p, and its slabs at nvec * n_r * mpre_p.
+// Table and potential pointers are in the launch's precision.
+struct DProb {
+  const DGroup* groups;
+  const DMode* modes;
+  const int32_t* row_ck;
+  const double* kappa;
+  const void* tinv;
+  const void* tfwd;
+  const void* Vs;
+  const void* Vh;
+  const int32_t* mode_pos;
+  int64_t Lpre, L, mpre;
+  int32_t n_modes, pad;
+};
+
+// complex offset of column v of problem pb: ld >= 0 for a single problem,
+// ld < 0 for the concatenated batch layout
+__device__ __forceinline__ int64_t col_off(const DProb& pb, int64_t ld, int nvec, int v) {
+  return ld >= 0 ? (int64_t)v * ld : (int64_t)nvec * pb.Lpre + (int64_t)v * pb.L;
+}
+__device__ __forceinline__ int64_t slab_off(const DProb& pb, int nvec, int n_r, int v, int r) {
+  return (int64_t)nvec * n_r * pb.mpre + ((int64_t)v * n_r + r) * pb.n_modes;
+}
 
 struct FftPlan {
   int32_t n, nf;

@@ -26,7 +26,9 @@ PREC = {"fp64": FP64, "fp32": FP32}
 EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "helic_basis_indices",
            "helic_grid", "helic_set_potential", "helic_apply_H", "helic_transform_inverse",
            "helic_transform_forward", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
-           "helic_eigensolve_ex",
+           "helic_eigensolve_ex", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
+           "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
+           "helic_batch_eigensolve",
            "helic_util_bessel_j", "helic_util_bessel_zeros", "helic_util_gauss_jacobi",
            "helic_last_error")
 
@@ -96,6 +98,15 @@ def load() -> ctypes.CDLL:
         "helic_eigensolve": [_P, _I32, _I32, _D, _I32, _I32, ctypes.c_uint64, _PD, _PD, _P, _I64,
                              _PI32, _P],
         "helic_eigensolve_ex": [_P, ctypes.POINTER(SolveOpts), _PD, _PD, _P, _I64, ctypes.POINTER(SolveStats), _P],
+        "helic_batch_create": [ctypes.POINTER(_P), _I32, ctypes.POINTER(_P)],
+        "helic_batch_destroy": [_P],
+        "helic_batch_info": [_P, _PI64],
+        "helic_batch_apply": [_P, _P, _P, _I32, _I32, _P],
+        "helic_batch_capture": [_P, _P, _P, _I32, _I32],
+        "helic_batch_replay": [_P, _P],
+        "helic_batch_tune": [_P, _P, _P, _I32, _I32, _P, _PI32, _PD],
+        "helic_batch_eigensolve": [_P, ctypes.POINTER(SolveOpts), _I32, _PD, _PD, ctypes.POINTER(SolveStats),
+                                   _PI32],
         "helic_util_bessel_j": [_I32, _I32, _PD, _PD],
         "helic_util_bessel_zeros": [_I32, _I32, _PD],
         "helic_util_gauss_jacobi": [_I32, _PD, _PD],
@@ -298,6 +309,77 @@ def eigensolve_ex(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, pr
     stats = st.as_dict()
     stats["message"] = load().helic_last_error().decode() if status != OK else ""
     return evals, resid, stats, status
+
+
+class Batch:
+    """A batch of grid-compatible problems (borrows the Basis objects, which
+    must stay alive).  Batched blocks are complex128 device tensors of
+    nvec * offsets[-1] elements: problem p's block is the slice
+    [nvec * offsets[p], nvec * offsets[p + 1]) viewed as (nvec, L_p)."""
+
+    def __init__(self, bases):
+        self.bases = list(bases)
+        arr = (_P * len(self.bases))(*[b.h for b in self.bases])
+        self.h = ctypes.c_void_p()
+        _check(load().helic_batch_create(arr, len(self.bases), ctypes.byref(self.h)))
+        off = np.zeros(len(self.bases) + 1, dtype=np.int64)
+        _check(load().helic_batch_info(self.h, _ptr(off, ctypes.c_int64)))
+        self.offsets = off
+
+    def close(self):
+        if self.h is not None:
+            load().helic_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def view(self, buf, nvec, p):
+        """(nvec, L_p) view of problem p in a concatenated buffer."""
+        a, b = nvec * int(self.offsets[p]), nvec * int(self.offsets[p + 1])
+        return buf[a:b].view(nvec, int(self.offsets[p + 1] - self.offsets[p]))
+
+    @staticmethod
+    def _flat(t, name):
+        import torch
+        if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous complex128 HIP tensor")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def apply(self, X, Y, nvec, prec="fp64", stream=None):
+        _check(load().helic_batch_apply(self.h, self._flat(X, "X"), self._flat(Y, "Y"), nvec, PREC[prec],
+                                        _stream(stream)))
+
+    def capture(self, X, Y, nvec, prec="fp64"):
+        _check(load().helic_batch_capture(self.h, self._flat(X, "X"), self._flat(Y, "Y"), nvec, PREC[prec]))
+
+    def replay(self, stream=None):
+        _check(load().helic_batch_replay(self.h, _stream(stream)))
+
+    def tune(self, X, Y, nvec, prec="fp64", stream=None):
+        chosen = ctypes.c_int32(0)
+        ms = ctypes.c_double(0)
+        _check(load().helic_batch_tune(self.h, self._flat(X, "X"), self._flat(Y, "Y"), nvec, PREC[prec],
+                                       _stream(stream), ctypes.byref(chosen), ctypes.byref(ms)))
+        return chosen.value, ms.value
+
+    def eigensolve(self, nev, nstreams=8, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa",
+                   guard=-1, switch_tol=1e-4):
+        n = len(self.bases)
+        o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=PREC[prec], seed=seed,
+                      precond=PRECOND[precond], guard=guard, switch_tol=switch_tol)
+        evals = np.zeros((n, nev))
+        resid = np.zeros((n, nev))
+        stats = (SolveStats * n)()
+        status = np.zeros(n, dtype=np.int32)
+        st = load().helic_batch_eigensolve(self.h, ctypes.byref(o), nstreams, _ptr(evals, ctypes.c_double),
+                                           _ptr(resid, ctypes.c_double), stats, _ptr(status, ctypes.c_int32))
+        if st not in (OK, ERR_NOCONV):
+            _check(st)
+        return evals, resid, [s.as_dict() for s in stats], status
 
 
 class Basis:

@@ -1,0 +1,143 @@
+"""Batched problems (many Bloch parameters of one structure): one launch per
+H*X stage over all problems, HIP-graph capture and replay, the tuner, and the
+concurrent batched eigensolve -- each problem checked against the CPU oracle.
+Tolerances as in test_gpu_apply.py / test_gpu_eigensolve.py."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import basis as ob
+from oracle import hamiltonian as oh
+
+torch = pytest.importorskip("torch")
+helic = pytest.importorskip("paper_2210_12252_amd.helic")
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+class Problem:
+    def __init__(self, w, V=None):
+        self.w = w
+        self.o = ob.basis_for(w)
+        self.g = helic.Basis.from_workload(w)
+        mnk, _ = self.g.indices()
+        pos = {tuple(t): i for i, t in enumerate(self.o.mnk.tolist())}
+        self.perm = np.array([pos[tuple(t)] for t in mnk.tolist()])
+        if V is None:
+            atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
+            V = synth.potential_at(self.o.theta1, self.o.theta2, self.o.r, w.tau, w.alpha, atoms)
+        self.V = V
+        self.g.set_potential(torch.from_numpy(V).to(_dev()))
+
+
+def make_batch(base, etas):
+    probs = [Problem(base.with_(name=f"{base.name}-eta{e:+.3f}", eta=e)) for e in etas]
+    print(f"[batch] {base.name} L = {[p.o.L for p in probs]}", flush=True)
+    return probs, helic.Batch([p.g for p in probs])
+
+
+def pack(batch, probs, nvec, seed):
+    """Concatenated device block and the per-problem oracle-order inputs."""
+    xs = [synth.random_block(p.o.mnk, nvec, seed + i) for i, p in enumerate(probs)]
+    total = nvec * int(batch.offsets[-1])
+    X = torch.zeros(total, dtype=torch.complex128, device=_dev())
+    for i, (p, x) in enumerate(zip(probs, xs)):
+        batch.view(X, nvec, i).copy_(torch.from_numpy(np.ascontiguousarray(x[p.perm].T)))
+    return X, xs
+
+
+def unpack(batch, probs, Y, nvec, i):
+    y = batch.view(Y, nvec, i).cpu().numpy().T
+    out = np.empty_like(y)
+    out[probs[i].perm] = y
+    return out
+
+
+TINY = synth.workload("tiny-helix")
+# a structure on a grid without a specialised angular kernel (general LDS FFT)
+GENERAL = synth.Workload(name="blob-20x30", R=7.0, tau=6.0, alpha=0.0, ecut=9.0, n_t1=20, n_t2=30, n_r=40,
+                         structure="blob:0", seed=40, nev=6)
+
+
+@pytest.mark.parametrize("base,etas", [(TINY, (-0.5, -0.2, 0.0, 0.13, 0.41)), (GENERAL, (-0.3, 0.0, 0.25))])
+def test_batched_apply_matches_oracle_per_problem(base, etas):
+    probs, batch = make_batch(base, etas)
+    nvec = 7
+    X, xs = pack(batch, probs, nvec, 300)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        Y = torch.full_like(X, 3.0)
+        batch.apply(X, Y, nvec, prec=prec)
+        for i, p in enumerate(probs):
+            ref = oh.apply(p.o, p.V, xs[i])
+            y = unpack(batch, probs, Y, nvec, i)
+            for j in range(nvec):
+                err = np.max(np.abs(y[:, j] - ref[:, j])) / np.max(np.abs(ref[:, j]))
+                assert err <= tol, (prec, i, j, err)
+    batch.close()
+
+
+def test_graph_replay_matches_eager_apply():
+    probs, batch = make_batch(TINY, (-0.25, 0.0, 0.25, 0.375))
+    nvec = 16
+    X, _ = pack(batch, probs, nvec, 11)
+    Y_eager = torch.zeros_like(X)
+    batch.apply(X, Y_eager, nvec)
+    torch.cuda.synchronize()
+    Y = torch.zeros_like(X)
+    batch.capture(X, Y, nvec)
+    scratch = torch.zeros_like(X)
+    for rep in range(4):
+        Y.zero_()
+        batch.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Y, Y_eager), rep
+        # eager work between replays on the same buffers' neighbours
+        batch.apply(X, scratch, nvec)
+        torch.cuda.synchronize()
+        assert torch.equal(scratch, Y_eager)
+    batch.close()
+
+
+def test_tuner_keeps_results_exact():
+    probs, batch = make_batch(TINY, (-0.1, 0.2))
+    nvec = 32
+    X, _ = pack(batch, probs, nvec, 5)
+    Y0 = torch.zeros_like(X)
+    batch.apply(X, Y0, nvec)
+    chosen, ms = batch.tune(X, torch.zeros_like(X), nvec)
+    print(f"[tune] vectors per angular workgroup {chosen}, {ms:.3f} ms", flush=True)
+    assert chosen in (1, 2, 4, 8, 16) and ms > 0
+    Y1 = torch.zeros_like(X)
+    batch.apply(X, Y1, nvec)
+    torch.cuda.synchronize()
+    assert (torch.abs(Y1 - Y0).max() / torch.abs(Y0).max()).item() < 1e-14
+    batch.close()
+
+
+def test_batched_eigensolve_matches_lapack_per_problem():
+    etas = (-0.5, -0.25, 0.0, 0.25)
+    probs, batch = make_batch(TINY, etas)
+    ev, res, stats, status = batch.eigensolve(TINY.nev, nstreams=3, tol=1e-9, maxit=400)
+    assert np.all(status == helic.OK), status
+    for i, p in enumerate(probs):
+        ref, _ = oh.lowest(oh.dense_explicit(p.o, p.V), TINY.nev)
+        assert np.max(np.abs(ev[i] - ref)) < 1e-8, (i, ev[i] - ref)
+    # time reversal across the batch: lambda(eta) = lambda(-eta)
+    np.testing.assert_allclose(ev[1], ev[3], atol=1e-8)
+    batch.close()
+
+
+def test_incompatible_grids_are_rejected():
+    a = Problem(TINY)
+    b = Problem(TINY.with_(n_r=40))
+    with pytest.raises(helic.HelicError) as e:
+        helic.Batch([a.g, b.g])
+    assert e.value.status == helic.ERR_GRID
