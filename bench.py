@@ -110,6 +110,78 @@ def time_to_eigenpairs(b, w, torch, tol=1e-8):
     return out
 
 
+def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e-8):
+    """Many Bloch parameters of seeded structures (64 eta each, R ~ U[5, 12],
+    E_cut ~ U[15, 35]): per structure one batch with a common grid (the
+    largest automatic grid over its eta), tuned, captured in a HIP graph and
+    replayed; and the lowest `nev` eigenpairs of every `eig_every`-th eta,
+    solved concurrently on 8 streams."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import synth
+    from synth.configs import batched_problems
+    from paper_2210_12252_amd import helic
+    allp = batched_problems()
+    out = []
+    for s in structures:
+        probs = allp[64 * s: 64 * (s + 1)]
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(8) as ex:
+            auto = list(ex.map(lambda w: helic.Basis.from_workload(w), probs))
+        n1 = max(b.n_t1 for b in auto)
+        n2 = max(b.n_t2 for b in auto)
+        nr = max(b.n_r for b in auto)
+        for b in auto:
+            b.close()
+        grid_w = [w.with_(n_t1=n1, n_t2=n2, n_r=nr, m_max=(n1 - 1) // 2, n_max=(n2 - 1) // 2) for w in probs]
+        with cf.ThreadPoolExecutor(8) as ex:
+            bases = list(ex.map(lambda w: helic.Basis.from_workload(w), grid_w))
+        t1, t2, r, _ = bases[0].grid()
+        w0 = probs[0]
+        V = torch.from_numpy(synth.potential_at(t1, t2, r, w0.tau, w0.alpha,
+                                                synth.atoms_for(w0.structure, w0.seed, w0.tau, w0.R))).cuda()
+        for b in bases:
+            b.set_potential(V)
+        batch = helic.Batch(bases)
+        setup = time.perf_counter() - t0
+        total = nvec * int(batch.offsets[-1])
+        X = torch.randn(total, dtype=torch.complex128, device="cuda")
+        Y = torch.zeros_like(X)
+        chosen, _ = batch.tune(X, Y, nvec)
+        batch.capture(X, Y, nvec)
+        batch.replay()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(steps):
+            batch.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - ta) / steps
+        Ls = np.diff(batch.offsets)
+        rec = dict(structure=s, R=round(w0.R, 3), ecut=round(w0.ecut, 3), n_eta=len(probs),
+                   grid=f"{n1}x{n2}x{nr}", L_min=int(Ls.min()), L_max=int(Ls.max()),
+                   kernel="specialised" if n2 in (16, 64, 81) else "general",
+                   setup_s=round(setup, 2), tuned_vectors_per_wg=chosen, ms_per_batched_apply=round(1e3 * dt, 3),
+                   vec_applies_per_s=round(len(probs) * nvec / dt, 1))
+        sub = bases[::eig_every]
+        eb = helic.Batch(sub)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        ev, res, st, status = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000)
+        te = time.perf_counter() - te
+        rec.update(eig_problems=len(sub), eig_nev=nev, eig_seconds=round(te, 2),
+                   eig_converged=int(np.sum(status == 0)), eig_iters_mean=float(np.mean([x["iters"] for x in st])))
+        print(f"[bench] batched structure {s}: {rec}", file=sys.stderr, flush=True)
+        out.append(rec)
+        eb.close()
+        batch.close()
+        for b in bases:
+            b.close()
+        del X, Y
+    return out
+
+
 def load_traffic(name: str, nvec: int):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or
     None when absent or taken on other kernel sources."""
@@ -132,6 +204,8 @@ def main(argv=None):
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"))
     ap.add_argument("--cpu-sample", type=int, default=64, help="vectors for the CPU oracle leg (0: skip)")
     ap.add_argument("--eig", type=int, default=1, help="also time the eigensolve (FP64 and mixed) (0: skip)")
+    ap.add_argument("--batched", default="4",
+                    help="structures (0..7, comma list, 'all' or 'none') for the batched Bloch-parameter leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args(argv)
@@ -239,6 +313,9 @@ def main(argv=None):
     }
     if args.eig:
         line["eigensolve"] = time_to_eigenpairs(b, w, torch)
+    if args.batched != "none":
+        structs = list(range(8)) if args.batched == "all" else [int(x) for x in args.batched.split(",")]
+        line["batched"] = batched_leg(torch, structs)
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     b.close()

@@ -25,6 +25,7 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
                            hipStream_t st, int mode, hipEvent_t* ev);
 helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double* evals, double* resid,
                              double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st);
+void release_workspace(helic_basis_s* h);
 
 }  // namespace helic
 
@@ -63,9 +64,17 @@ helic_status upload_vec(const std::vector<T>& v, T** d) {
   return HELIC_OK;
 }
 
+void release_graph(helic_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
 helic_status batch_workspace(helic_batch_s* b, int nvec, size_t elem) {
   const size_t need = (size_t)nvec * b->ls.n_r * b->mtot * 2 * elem;
   if (need > b->gh_bytes) {
+    release_graph(b);   // a captured graph refers to the old buffer
     if (b->gh) HIP_TRY_B(hipFree(b->gh));
     b->gh = nullptr;
     b->gh_bytes = 0;
@@ -74,13 +83,6 @@ helic_status batch_workspace(helic_batch_s* b, int nvec, size_t elem) {
   }
   b->ls.gh = b->gh;
   return HELIC_OK;
-}
-
-void release_graph(helic_batch_s* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
 }
 
 helic_status batch_launch(helic_batch_s* b, const double* X, double* Y, int nvec, helic_prec prec, hipStream_t st,
@@ -281,6 +283,9 @@ helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* o, in
                 : HELIC_ERR_HIP;
       if (st[p] != HELIC_OK) msg[p] = helic_last_error();
       if (stats) stats[p] = ss;
+      // keep device memory bounded by the number of concurrent solves
+      if (s) (void)hipStreamSynchronize(s);
+      release_workspace(b->bases[p]);
     }
     if (s) (void)hipStreamDestroy(s);
   };

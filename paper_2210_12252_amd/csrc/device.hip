@@ -586,6 +586,15 @@ helic_status ensure_workspace(helic_basis_s* h, int nvec, size_t elem) {
   return HELIC_OK;
 }
 
+// Free a handle's intermediate buffer (it is re-created by the next apply).
+void release_workspace(helic_basis_s* h) {
+  DeviceState* d = h->dev;
+  if (!d || !d->gh) return;
+  (void)hipFree(d->gh);
+  d->gh = nullptr;
+  d->gh_bytes = 0;
+}
+
 void device_release(helic_basis_s* h) {
   DeviceState* d = h->dev;
   if (!d) return;
