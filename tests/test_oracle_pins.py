@@ -316,3 +316,47 @@ def test_tpa_worked_values():
     w = op.tpa_apply(kappa, r)
     np.testing.assert_allclose(w, r * 65.0 / 81.0, rtol=1e-15)
     assert np.all(op.tpa_apply(kappa, np.zeros((3, 2))) == 0)
+
+
+# ------------------------------------------------------------------ learned preconditioner
+def _mlp_case(seed=0, L=40, ncol=3):
+    from oracle import mlp
+    rng = np.random.default_rng(seed)
+    kappa = np.sort(rng.uniform(0.05, 9.0, L))
+    vdiag = rng.uniform(-2.0, 0.0, L)
+    R = rng.standard_normal((L, ncol)) + 1j * rng.standard_normal((L, ncol))
+    Tt = rng.standard_normal((L, ncol)) + 1j * rng.standard_normal((L, ncol))
+    lam = rng.uniform(-1.0, 0.5, ncol)
+    F, K = mlp.features(kappa, vdiag, R, lam)
+    theta = mlp.init_params(seed)
+    theta[-65:] = rng.standard_normal(65) * 0.3      # non-zero last layer
+    return mlp, F, K, R, Tt, theta
+
+
+def test_mlp_gradient_matches_finite_differences():
+    mlp, F, K, R, Tt, theta = _mlp_case()
+    loss, grad = mlp.loss_and_grad(theta, F, K, R, Tt)
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([rng.choice(mlp.NPARAM, 40, replace=False), [mlp.NPARAM - 1]])
+    h = 1e-6
+    for i in idx:
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        fd = (mlp.loss_and_grad(tp, F, K, R, Tt)[0] - mlp.loss_and_grad(tm, F, K, R, Tt)[0]) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(grad[i])) + 1e-9, (i, fd, grad[i])
+
+
+def test_mlp_untrained_network_is_tpa_and_loss_invariances():
+    from oracle import precond as op
+    mlp, F, K, R, Tt, theta = _mlp_case(2)
+    theta0 = mlp.init_params(5)
+    s, _ = mlp.forward(theta0, F, K)
+    np.testing.assert_allclose(s, K, rtol=1e-15)
+    kappa = np.exp(F[:, 0, 2])
+    np.testing.assert_allclose(s * R, op.tpa_apply(kappa, R), rtol=1e-12)
+    l1, _ = mlp.loss_and_grad(theta, F, K, R, Tt)
+    l2, _ = mlp.loss_and_grad(theta, F, K, R, (2.5 - 1.5j) * Tt)   # target scale and phase do not matter
+    assert abs(l1 - l2) < 1e-14 and 0.0 <= l1 <= 1.0
+    sr = mlp.forward(theta, F, K)[0] * R
+    l0, g0 = mlp.loss_and_grad(theta, F, K, R, sr)                  # target along s r: zero loss, zero gradient
+    assert abs(l0) < 1e-14 and np.max(np.abs(g0)) < 1e-12
