@@ -182,6 +182,61 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
     return out
 
 
+def learned_leg(torch, b, w, tol=1e-8, train_eta=0.25, n_snap=12, steps=400, batch=16, lr=3e-3):
+    """Learned preconditioner against the plain one at equal residual: the
+    network is trained on pairs harvested from one solve at another Bloch
+    parameter (eta = train_eta) of the same structure, then both solve the
+    benchmark problem `b` from the same seeded start."""
+    import numpy as np
+
+    import synth
+    from paper_2210_12252_amd import helic
+    wt = w.with_(name=f"{w.name}-eta{train_eta}", eta=train_eta)
+    bt = helic.Basis.from_workload(wt)
+    t1, t2, r, _ = bt.grid()
+    atoms = synth.atoms_for(wt.structure, wt.seed, wt.tau, wt.R)
+    bt.set_potential(torch.from_numpy(synth.potential_at(t1, t2, r, wt.tau, wt.alpha, atoms)).cuda())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R, T, lam, ncol, hst = bt.lpc_harvest(w.nev, n_snap=n_snap, tol=tol, maxit=1000, seed=3)
+    torch.cuda.synchronize()
+    t_h = time.perf_counter() - t0
+    net = helic.Lpc(seed=0)
+    t0 = time.perf_counter()
+    losses = bt.lpc_train(net, R, T, lam, ncol, batch=min(batch, ncol), steps=steps, lr=lr, seed=0)
+    torch.cuda.synchronize()
+    t_t = time.perf_counter() - t0
+    print(f"[bench] learned: harvested {ncol} pairs in {t_h:.2f} s, trained {steps} steps in {t_t:.2f} s, "
+          f"loss {losses[:10].mean():.4f} -> {losses[-20:].mean():.4f}", file=sys.stderr, flush=True)
+    del R, T, lam
+    bt.close()
+    b.attach(net)
+    out = dict(workload=w.name, train_problem=wt.name, harvest_pairs=ncol, harvest_seconds=round(t_h, 2),
+               train_steps=steps, train_batch_columns=min(batch, ncol), train_seconds=round(t_t, 2),
+               ms_per_train_step=round(1e3 * t_t / max(steps, 1), 3),
+               loss_first=round(float(losses[:10].mean()), 4), loss_last=round(float(losses[-20:].mean()), 4),
+               tol_Ha=tol, nev=w.nev)
+    evs = {}
+    for pc in ("tpa", "learned"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, res, st, status = b.eigensolve_ex(w.nev, tol=tol, maxit=1000, precond=pc, seed=7)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[pc] = dict(seconds=round(wall, 3), converged=bool(status == 0), iters=st["iters"],
+                       fallback_iters=st["n_fallback"], precond_s=round(st["t_precond_ms"] / 1e3, 3),
+                       max_resid=float(np.max(res)))
+        evs[pc] = ev
+        print(f"[bench] eigensolve precond={pc}: {wall:.2f} s, {st['iters']} iterations", file=sys.stderr,
+              flush=True)
+    b.attach(None)
+    net.close()
+    out["max_abs_dlambda_Ha"] = float(np.max(np.abs(evs["learned"] - evs["tpa"])))
+    out["speedup_time"] = round(out["tpa"]["seconds"] / out["learned"]["seconds"], 3)
+    out["iteration_ratio"] = round(out["learned"]["iters"] / max(out["tpa"]["iters"], 1), 3)
+    return out
+
+
 def load_traffic(name: str, nvec: int):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or
     None when absent or taken on other kernel sources."""
@@ -206,6 +261,8 @@ def main(argv=None):
     ap.add_argument("--eig", type=int, default=1, help="also time the eigensolve (FP64 and mixed) (0: skip)")
     ap.add_argument("--batched", default="4",
                     help="structures (0..7, comma list, 'all' or 'none') for the batched Bloch-parameter leg")
+    ap.add_argument("--learned", default="same",
+                    help="learned-preconditioner leg: 'same' (the benchmark workload), a workload name, or 'none'")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args(argv)
@@ -316,6 +373,18 @@ def main(argv=None):
     if args.batched != "none":
         structs = list(range(8)) if args.batched == "all" else [int(x) for x in args.batched.split(",")]
         line["batched"] = batched_leg(torch, structs)
+    if args.learned != "none":
+        if args.learned in ("same", w.name):
+            lw, lb = w, b
+        else:
+            lw = synth.workload(args.learned)
+            lb = helic.Basis.from_workload(lw)
+            t1, t2, r, _ = lb.grid()
+            lb.set_potential(torch.from_numpy(synth.potential_at(
+                t1, t2, r, lw.tau, lw.alpha, synth.atoms_for(lw.structure, lw.seed, lw.tau, lw.R))).cuda())
+        line["learned_preconditioner"] = learned_leg(torch, lb, lw)
+        if lb is not b:
+            lb.close()
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     b.close()

@@ -220,6 +220,71 @@ helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* opts,
                                     double* evals, double* resid, helic_solve_stats* stats,
                                     int32_t* status);
 
+/* ---- learned diagonal preconditioner -----------------------------------
+ * Not in the paper, which only remarks (Sec. 5) that the method lends itself
+ * to coupling with machine learning.  For residual column j and row i a
+ * network of three layers (8 -> 64 -> 64 -> 1, SiLU) maps the features
+ *   K(g), log g, log kappa_i, (V_ii - lambda_j) / T_j, lambda_j / T_j,
+ *   log(|R_ij| sqrt(L) / ||R_j|| + 1e-30), 0, 0      (g = kappa_i / T_j)
+ * (K, T_j as for helic_precondition; V_ii the potential's diagonal in the
+ * basis; lambda_j the column's Ritz value) to z, and the correction is
+ *   W_ij = s_ij R_ij,  s_ij = K(g) softplus(z) / log 2 > 0:
+ * diagonal, positive and phase-equivariant, so LOBPCG stays valid; a zero
+ * last layer gives the Teter-Payne-Allan preconditioner exactly.  Training
+ * minimises the mean over columns of 1 - |<s R_j, T_j>|^2 / (||s R_j||^2
+ * ||T_j||^2) against target corrections T_j, with Adam.  Parameters (FP32,
+ * HELIC_LPC_NPARAM): W1 (64 x 8, row-major), b1 (64), W2 (64 x 64, row-major),
+ * b2 (64), w3 (64), b3 (1).  A network handle lives on the device current at
+ * creation; calls on one network must not overlap (they share its training
+ * buffers), and it must outlive the bases it is attached to.  Device blocks
+ * are column-major complex FP64 (ld >= L), lambda / lam arrays are device
+ * FP64 (one per column). */
+#define HELIC_LPC_NPARAM 4801
+typedef struct helic_lpc_s* helic_lpc;
+/* New network with He-initialised hidden layers and a zero last layer. */
+helic_status helic_lpc_create(uint64_t seed, helic_lpc* out);
+helic_status helic_lpc_destroy(helic_lpc net);
+/* Copy the parameters out / in (host, HELIC_LPC_NPARAM floats); setting
+ * them restarts Adam. */
+helic_status helic_lpc_get_params(helic_lpc net, float* params);
+helic_status helic_lpc_set_params(helic_lpc net, const float* params);
+/* Use `net` for helic_eigensolve_ex with precond = 2 on this basis (NULL
+ * detaches).  The solver falls back to the Teter-Payne-Allan preconditioner
+ * for the rest of a solve once the largest residual of the wanted pairs has
+ * not reached a new minimum for three iterations in a row. */
+helic_status helic_lpc_attach(helic_basis h, helic_lpc net);
+/* V_ii per row in the compact order (host, L doubles); needs the potential. */
+helic_status helic_lpc_vdiag(helic_basis h, double* vdiag);
+/* W = s * R for nvec columns with Ritz values lam (W may equal R). */
+helic_status helic_lpc_apply(helic_basis h, helic_lpc net, const double* R, int64_t ldr, const double* lam,
+                             double* W, int64_t ldw, int32_t nvec, void* stream);
+/* Direction loss of nvec (R, T, lam) columns and its gradient: *loss (host)
+ * the mean over columns; grad (host, HELIC_LPC_NPARAM doubles) may be NULL.
+ * The gradient also stays in the network for helic_lpc_adam_step.
+ * Synchronises `stream`. */
+helic_status helic_lpc_loss_grad(helic_basis h, helic_lpc net, const double* R, int64_t ldr, const double* T,
+                                 int64_t ldt, const double* lam, int32_t nvec, double* loss, double* grad,
+                                 void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradient. */
+helic_status helic_lpc_adam_step(helic_lpc net, double lr, void* stream);
+/* `steps` Adam steps, each on `batch` columns drawn without replacement
+ * (seeded) from the ncol training columns; losses (host, steps) may be
+ * NULL.  Synchronises `stream`. */
+helic_status helic_lpc_train(helic_basis h, helic_lpc net, const double* R, int64_t ldr, const double* T,
+                             int64_t ldt, const double* lam, int32_t ncol, int32_t batch, int32_t steps,
+                             double lr, uint64_t seed, double* losses, void* stream);
+/* Training pairs from one eigensolve (opts as helic_eigensolve_ex, run with
+ * the preconditioner opts->precond): at up to n_snap iterations spread
+ * geometrically over the run, the residuals R_j of the unconverged wanted
+ * columns and their Ritz values are kept together with the Ritz block X;
+ * after convergence each target is T_j = (1 - X X^H) X* X*^H x_j, the part of
+ * the final eigenspace X* (nev columns) that the column still has to gain.
+ * R, T: device, ld = L, max_cols columns; lam: device, max_cols; *ncol
+ * (host): columns written.  stats may be NULL. */
+helic_status helic_lpc_harvest(helic_basis h, const helic_solve_opts* opts, int32_t n_snap, int32_t max_cols,
+                               double* R, double* T, double* lam, int32_t* ncol, helic_solve_stats* stats,
+                               void* stream);
+
 /* Host utilities used by the basis set-up, exported for testing.
  * helic_util_bessel_j: out[i] = J_p(x[i]) for integer p (any sign), x >= 0.
  * helic_util_bessel_zeros: first `count` positive zeros of J_p.

@@ -55,6 +55,15 @@ def dense_dft(b: Basis, V: np.ndarray) -> np.ndarray:
     return H
 
 
+def potential_diagonal(b: Basis, V: np.ndarray) -> np.ndarray:
+    """V_ii: the diagonal of the potential term, i.e. mode B at m_i = m_j,
+    n_i = n_j, where the DFT coefficient is the angular mean of V."""
+    rad = radial_values(b)                                      # (nr, L)
+    vbar = V.mean(axis=(0, 1))                                  # (nr,)
+    pref = 2.0 * math.pi * b.tau / b.ncyc
+    return pref * ((b.omega_r * vbar)[:, None] * rad ** 2).sum(0)
+
+
 def apply(b: Basis, V: np.ndarray, X: np.ndarray) -> np.ndarray:
     """Matrix-free H @ X for X of shape (L,) or (L, nv)."""
     single = X.ndim == 1

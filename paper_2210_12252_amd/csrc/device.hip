@@ -600,7 +600,7 @@ void device_release(helic_basis_s* h) {
   if (!d) return;
   void* ptrs[] = {d->groups, d->modes, d->row_ck, d->kappa, d->rows1, d->tinv64, d->tfwd64,
                   d->tinv32, d->tfwd32, d->tw1, d->tw2, d->tw1f, d->tw2f, d->Vs, d->Vsf,
-                  d->gh, d->part, d->mode_pos, d->Vh, d->Vhf, d->probs64, d->probs32};
+                  d->gh, d->part, d->mode_pos, d->Vh, d->Vhf, d->probs64, d->probs32, d->vdiag, d->lpc_ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   release_solver_state(d);
@@ -718,6 +718,7 @@ helic_status helic_set_potential(helic_basis h, const double* V, void* stream) {
     HIP_TRY(hipGetLastError());
   }
   d->have_potential = true;
+  d->vdiag_valid = false;
   return HELIC_OK;
 }
 

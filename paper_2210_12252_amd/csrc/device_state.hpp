@@ -13,6 +13,9 @@ namespace helic {
 constexpr int APPLY_CHUNK = 64;
 
 struct SolverState;
+}  // namespace helic
+struct helic_lpc_s;
+namespace helic {
 
 struct DeviceState {
   int device = 0;
@@ -45,6 +48,13 @@ struct DeviceState {
   double* part = nullptr;
   size_t part_bytes = 0;
   SolverState* solver = nullptr;
+  // learned preconditioner: attached network, potential diagonal V_ii per
+  // row (recomputed after a new potential), per-call column workspace
+  helic_lpc_s* lpc = nullptr;
+  double* vdiag = nullptr;
+  bool vdiag_valid = false;
+  double* lpc_ws = nullptr;
+  size_t lpc_ws_bytes = 0;
 };
 
 void release_solver_state(DeviceState* d);

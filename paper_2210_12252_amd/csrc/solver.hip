@@ -30,8 +30,30 @@ helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double
                           helic_prec prec, hipStream_t st, int chunk);
 helic_status precondition_impl(helic_basis_s* h, const double* Rr, int64_t ldr, double* W, int64_t ldw,
                                int nvec, hipStream_t st);
-helic_status lpc_precondition(helic_basis_s* h, const double* Rr, int64_t ldr, const double* X, int64_t ldx,
-                              const double* lam, double* W, int64_t ldw, int nvec, hipStream_t st, bool* used);
+helic_status lpc_precondition(helic_basis_s* h, const double* Rr, int64_t ldr, const double* lam, double* W,
+                              int64_t ldw, int nvec, hipStream_t st);
+bool lpc_attached(const helic_basis_s* h);
+
+// Training pairs for the learned preconditioner taken during a solve: at the
+// scheduled iterations the residuals of the unconverged wanted columns (and
+// the Ritz block) are kept; targets are formed after convergence.
+struct Harvest {
+  int n_snap = 0, max_cols = 0;
+  double *R = nullptr, *T = nullptr, *lam = nullptr;   // outputs (device, ld = L)
+  int ncol = 0;
+  int next_iter = 0;                  // next scheduled iteration
+  struct Snap {
+    int col0, ncols;
+    double* X;                        // Ritz block at the snapshot (n columns)
+    std::vector<int32_t> ritz;        // Ritz index of each kept column
+  };
+  std::vector<Snap> snaps;
+  std::vector<double> lam_h;
+  ~Harvest() {
+    for (Snap& s : snaps)
+      if (s.X) (void)hipFree(s.X);
+  }
+};
 
 void release_solver_state(DeviceState*) {}
 
@@ -175,7 +197,7 @@ struct Timer {
 }  // namespace
 
 helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double* evals, double* resid,
-                             double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st) {
+                             double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st, Harvest* hv) {
   Timer total;
   helic_solve_stats S_;
   std::memset(&S_, 0, sizeof(S_));
@@ -384,6 +406,55 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     return HELIC_OK;
   };
 
+  // Harvest: keep the residuals of the unconverged wanted columns (a prefix
+  // of the ascending active list, gathered at W) and the Ritz block; the
+  // next snapshot is due about 1.5 times later.
+  auto snapshot = [&](int itn, const std::vector<int32_t>& act, const double* Wres, int na_) -> helic_status {
+    hv->next_iter = std::max(itn + 1, (3 * itn) / 2);
+    int m = 0;
+    while (m < na_ && act[m] < nev) ++m;
+    m = std::min(m, hv->max_cols - hv->ncol);
+    if (m <= 0) return HELIC_OK;
+    hv->snaps.push_back(Harvest::Snap{hv->ncol, m, nullptr, {}});
+    Harvest::Snap& sp = hv->snaps.back();
+    HIP_TRY_S(hipMalloc((void**)&sp.X, sizeof(double) * Lc * n));
+    HIP_TRY_S(hipMemcpyAsync(sp.X, S, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
+    HIP_TRY_S(hipMemcpyAsync(hv->R + (size_t)hv->ncol * Lc, Wres, sizeof(double) * Lc * m,
+                             hipMemcpyDeviceToDevice, st));
+    for (int c = 0; c < m; ++c) {
+      sp.ritz.push_back(act[c]);
+      hv->lam_h.push_back(lam_h[act[c]]);
+    }
+    hv->ncol += m;
+    return HELIC_OK;
+  };
+
+  // Harvest targets T = (1 - Xs Xs^H) X* X*^H x for each kept column x of a
+  // snapshot Xs, X* the converged wanted block (projection applied twice).
+  auto harvest_targets = [&]() -> helic_status {
+    for (const Harvest::Snap& sp : hv->snaps) {
+      const int m = sp.ncols;
+      double* T = hv->T + (size_t)sp.col0 * Lc;
+      HIP_TRY_S(hipMemcpyAsync(d_idx, sp.ritz.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_gather_cols, dim3(64, m), dim3(NTS), 0, st, sp.X, R, d_idx, L, m);
+      HIP_TRY_S(hipGetLastError());
+      if ((s = gemm_h(nev, m, S, R, GA, kmax))) return s;
+      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, m, nev, &one,
+                           (const zc*)S, (int)L, (const zc*)GA, kmax, &zero, (zc*)T, (int)L));
+      for (int rep = 0; rep < 2; ++rep) {
+        if ((s = gemm_h(n, m, sp.X, T, Z, kmax))) return s;
+        RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, m, n, &mone,
+                             (const zc*)sp.X, (int)L, (const zc*)Z, kmax, &one, (zc*)T, (int)L));
+      }
+      if ((s = sync())) return s;   // d_idx is reused by the next snapshot
+    }
+    if (hv->ncol > 0) {
+      HIP_TRY_S(hipMemcpyAsync(hv->lam, hv->lam_h.data(), sizeof(double) * hv->ncol, hipMemcpyHostToDevice, st));
+      if ((s = sync())) return s;
+    }
+    return HELIC_OK;
+  };
+
   // ---- random start: orthonormalise, H X, first Rayleigh-Ritz
   {
     std::mt19937_64 gen(o.seed);
@@ -401,6 +472,11 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   HIP_TRY_S(hipMemcpyAsync(AS, AXn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
 
   int np = 0;   // columns held in Pb / APb
+  // learned preconditioner: dropped for the rest of the solve once the worst
+  // wanted residual has not reached a new minimum for three iterations
+  bool learned = o.precond == 2;
+  double best_worst = HUGE_VAL;
+  int stall = 0;
   std::vector<double> nrm;
   std::vector<int32_t> active;
   bool converged = false;
@@ -429,6 +505,14 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
       --it;
       continue;
     }
+    if (learned) {
+      if (worst < best_worst) {
+        best_worst = worst;
+        stall = 0;
+      } else if (++stall >= 3) {
+        learned = false;
+      }
+    }
     if (prec != HELIC_FP64) ++S_.iters_low;
     // In the FP32 phase columns are locked at switch_tol: iterating a column
     // whose residual is at the FP32 noise floor makes its normalised update
@@ -445,17 +529,18 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     double* W = col(S, n);
     hipLaunchKernelGGL(k_gather_cols, dim3(64, na), dim3(NTS), 0, st, R, W, d_idx, L, na);
     HIP_TRY_S(hipGetLastError());
-    if (o.precond == 0) {
+    if (hv && it >= hv->next_iter && hv->ncol < hv->max_cols && (int)hv->snaps.size() < hv->n_snap) {
+      if ((s = snapshot(it, active, W, na))) return s;
+    }
+    if (o.precond == 0 || (o.precond == 2 && !learned)) {
       if ((s = precondition_impl(h, W, L, W, L, na, st))) return s;
+      if (o.precond == 2) ++S_.n_fallback;
     } else if (o.precond == 2) {
-      // learned preconditioner; it falls back to the TPA one by itself
-      hipLaunchKernelGGL(k_gather_cols, dim3(64, na), dim3(NTS), 0, st, S, Xn, d_idx, L, na);
       std::vector<double> lam_a(na);
       for (int c = 0; c < na; ++c) lam_a[c] = lam_h[active[c]];
       HIP_TRY_S(hipMemcpyAsync(d, lam_a.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
-      bool used = false;
-      if ((s = lpc_precondition(h, W, L, Xn, L, d, W, L, na, st, &used))) return s;
-      if (!used) ++S_.n_fallback;
+      if ((s = lpc_precondition(h, W, L, d, W, L, na, st))) return s;
+      if ((s = sync())) return s;   // lam_a is read by the copy above
     }
     if ((s = sync())) return s;
     S_.t_precond_ms += tp.ms();
@@ -510,6 +595,8 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     converged = prec == HELIC_FP64;
     for (int j = 0; j < nev; ++j) converged = converged && nrm[j] <= o.tol;
   }
+  if (hv && converged)
+    if ((s = harvest_targets())) return s;
   if (evecs)
     HIP_TRY_S(hipMemcpy2DAsync(evecs, sizeof(double) * 2 * ldv, S, sizeof(double) * Lc, sizeof(double) * Lc, nev,
                                hipMemcpyDeviceToDevice, st));
@@ -540,8 +627,39 @@ helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* o, doubl
   if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
   if (o->precond < 0 || o->precond > 2) return fail(HELIC_ERR_UNSUPPORTED, "unknown preconditioner");
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
+  if (o->precond == 2 && !lpc_attached(h)) return fail(HELIC_ERR_STATE, "no learned preconditioner attached");
   try {
-    return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream));
+    return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream), nullptr);
+  } catch (const std::bad_alloc&) {
+    return fail(HELIC_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+helic_status helic_lpc_harvest(helic_basis h, const helic_solve_opts* o, int32_t n_snap, int32_t max_cols,
+                               double* R, double* T, double* lam, int32_t* ncol, helic_solve_stats* stats,
+                               void* stream) {
+  if (!h || !o || !R || !T || !lam || !ncol) return fail(HELIC_ERR_INVALID, "null argument");
+  *ncol = 0;
+  if (n_snap < 1 || max_cols < 1) return fail(HELIC_ERR_INVALID, "bad harvest sizes");
+  if (o->nev < 1 || o->nev > h->L || o->block < 1 || !(o->tol > 0) || o->maxit < 0)
+    return fail(HELIC_ERR_INVALID, "bad solver options");
+  if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (o->precond < 0 || o->precond > 2) return fail(HELIC_ERR_UNSUPPORTED, "unknown preconditioner");
+  if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
+  if (o->precond == 2 && !lpc_attached(h)) return fail(HELIC_ERR_STATE, "no learned preconditioner attached");
+  try {
+    Harvest hv;
+    hv.n_snap = n_snap;
+    hv.max_cols = max_cols;
+    hv.R = R;
+    hv.T = T;
+    hv.lam = lam;
+    std::vector<double> ev(o->nev), rs(o->nev);
+    helic_status s = eigensolve_impl(h, *o, ev.data(), rs.data(), nullptr, 0, stats,
+                                     reinterpret_cast<hipStream_t>(stream), &hv);
+    if (s) return s;
+    *ncol = hv.ncol;
+    return HELIC_OK;
   } catch (const std::bad_alloc&) {
     return fail(HELIC_ERR_NOMEM, "host allocation failed");
   }

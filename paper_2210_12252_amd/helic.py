@@ -20,6 +20,7 @@ LIBPATH = os.path.join(HERE, "libhelic.so")
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_GRID, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_CUTOFF_TIE, ERR_STATE = range(9)
 FP64, FP32 = 0, 1
+LPC_NPARAM = 4801
 PREC = {"fp64": FP64, "fp32": FP32}
 
 # every function declared in include/helic.h
@@ -29,6 +30,9 @@ EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "hel
            "helic_eigensolve_ex", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
            "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
            "helic_batch_eigensolve",
+           "helic_lpc_create", "helic_lpc_destroy", "helic_lpc_get_params", "helic_lpc_set_params",
+           "helic_lpc_attach", "helic_lpc_vdiag", "helic_lpc_apply", "helic_lpc_loss_grad", "helic_lpc_adam_step",
+           "helic_lpc_train", "helic_lpc_harvest",
            "helic_util_bessel_j", "helic_util_bessel_zeros", "helic_util_gauss_jacobi",
            "helic_last_error")
 
@@ -107,6 +111,18 @@ def load() -> ctypes.CDLL:
         "helic_batch_tune": [_P, _P, _P, _I32, _I32, _P, _PI32, _PD],
         "helic_batch_eigensolve": [_P, ctypes.POINTER(SolveOpts), _I32, _PD, _PD, ctypes.POINTER(SolveStats),
                                    _PI32],
+        "helic_lpc_create": [ctypes.c_uint64, ctypes.POINTER(_P)],
+        "helic_lpc_destroy": [_P],
+        "helic_lpc_get_params": [_P, ctypes.POINTER(ctypes.c_float)],
+        "helic_lpc_set_params": [_P, ctypes.POINTER(ctypes.c_float)],
+        "helic_lpc_attach": [_P, _P],
+        "helic_lpc_vdiag": [_P, _PD],
+        "helic_lpc_apply": [_P, _P, _P, _I64, _P, _P, _I64, _I32, _P],
+        "helic_lpc_loss_grad": [_P, _P, _P, _I64, _P, _I64, _P, _I32, _PD, _PD, _P],
+        "helic_lpc_adam_step": [_P, _D, _P],
+        "helic_lpc_train": [_P, _P, _P, _I64, _P, _I64, _P, _I32, _I32, _I32, _D, ctypes.c_uint64, _PD, _P],
+        "helic_lpc_harvest": [_P, ctypes.POINTER(SolveOpts), _I32, _I32, _P, _P, _P, _PI32,
+                              ctypes.POINTER(SolveStats), _P],
         "helic_util_bessel_j": [_I32, _I32, _PD, _PD],
         "helic_util_bessel_zeros": [_I32, _I32, _PD],
         "helic_util_gauss_jacobi": [_I32, _PD, _PD],
@@ -311,6 +327,49 @@ def eigensolve_ex(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, pr
     return evals, resid, stats, status
 
 
+def _lam(lam, n):
+    import torch
+    if not (lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous() and lam.numel() >= n):
+        raise ValueError("lam must be a contiguous float64 HIP tensor with one value per column")
+    return ctypes.c_void_p(lam.data_ptr())
+
+
+class Lpc:
+    """Learned diagonal preconditioner network (device-resident parameters
+    and Adam state)."""
+
+    def __init__(self, seed=0):
+        self.h = ctypes.c_void_p()
+        _check(load().helic_lpc_create(seed, ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h is not None:
+            load().helic_lpc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self) -> np.ndarray:
+        p = np.empty(LPC_NPARAM, dtype=np.float32)
+        _check(load().helic_lpc_get_params(self.h, _ptr(p, ctypes.c_float)))
+        return p
+
+    @params.setter
+    def params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != LPC_NPARAM:
+            raise ValueError(f"expected {LPC_NPARAM} parameters")
+        _check(load().helic_lpc_set_params(self.h, _ptr(p, ctypes.c_float)))
+
+    def adam_step(self, lr, stream=None):
+        _check(load().helic_lpc_adam_step(self.h, lr, _stream(stream)))
+
+
 class Batch:
     """A batch of grid-compatible problems (borrows the Basis objects, which
     must stay alive).  Batched blocks are complex128 device tensors of
@@ -438,3 +497,66 @@ class Basis:
 
     def eigensolve_ex(self, nev, **kw):
         return eigensolve_ex(self.h, nev, **kw)
+
+    # ---- learned preconditioner
+    def attach(self, net):
+        _check(load().helic_lpc_attach(self.h, net.h if net is not None else None))
+        self._lpc = net   # keep the network alive while attached
+
+    def lpc_vdiag(self):
+        out = np.empty(self.L)
+        _check(load().helic_lpc_vdiag(self.h, _ptr(out, ctypes.c_double)))
+        return out
+
+    def lpc_apply(self, net, R, lam, W, stream=None):
+        nr_, ldr = _block(R, "R")
+        nw, ldw = _block(W, "W")
+        if nw < nr_:
+            raise ValueError("W has fewer columns than R")
+        _check(load().helic_lpc_apply(self.h, net.h, ctypes.c_void_p(R.data_ptr()), ldr, _lam(lam, nr_),
+                                      ctypes.c_void_p(W.data_ptr()), ldw, nr_, _stream(stream)))
+
+    def lpc_loss_grad(self, net, R, T, lam, stream=None):
+        """(mean loss, gradient as a float64 array)."""
+        nr_, ldr = _block(R, "R")
+        nt, ldt = _block(T, "T")
+        if nt != nr_:
+            raise ValueError("R and T differ in column count")
+        loss = ctypes.c_double(0.0)
+        grad = np.empty(LPC_NPARAM)
+        _check(load().helic_lpc_loss_grad(self.h, net.h, ctypes.c_void_p(R.data_ptr()), ldr,
+                                          ctypes.c_void_p(T.data_ptr()), ldt, _lam(lam, nr_), nr_,
+                                          ctypes.byref(loss), _ptr(grad, ctypes.c_double), _stream(stream)))
+        return loss.value, grad
+
+    def lpc_train(self, net, R, T, lam, ncol, batch, steps, lr=3e-3, seed=0, stream=None):
+        """Adam steps on column batches of the first ncol training columns;
+        returns the per-step losses."""
+        nr_, ldr = _block(R, "R")
+        nt, ldt = _block(T, "T")
+        if min(nr_, nt) < ncol:
+            raise ValueError("fewer stored columns than ncol")
+        losses = np.zeros(max(steps, 1))
+        _check(load().helic_lpc_train(self.h, net.h, ctypes.c_void_p(R.data_ptr()), ldr,
+                                      ctypes.c_void_p(T.data_ptr()), ldt, _lam(lam, ncol), ncol, batch, steps, lr,
+                                      seed, _ptr(losses, ctypes.c_double), _stream(stream)))
+        return losses[:steps]
+
+    def lpc_harvest(self, nev, n_snap=12, max_cols=None, block=64, tol=1e-8, maxit=500, seed=7, precond="tpa",
+                    guard=-1, stream=None):
+        """Training pairs from one FP64 eigensolve: (R, T, lam, ncol, stats)
+        with R, T of shape (max_cols, L) and the first ncol rows filled."""
+        import torch
+        max_cols = max_cols or n_snap * nev
+        dev = torch.device("cuda", torch.cuda.current_device())
+        R = torch.zeros((max_cols, self.L), dtype=torch.complex128, device=dev)
+        T = torch.zeros_like(R)
+        lam = torch.zeros(max_cols, dtype=torch.float64, device=dev)
+        o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=FP64, seed=seed,
+                      precond=PRECOND[precond], guard=guard, switch_tol=1e-4)
+        ncol = ctypes.c_int32(0)
+        st = SolveStats()
+        _check(load().helic_lpc_harvest(self.h, ctypes.byref(o), n_snap, max_cols, ctypes.c_void_p(R.data_ptr()),
+                                        ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                        ctypes.byref(ncol), ctypes.byref(st), _stream(stream)))
+        return R, T, lam, ncol.value, st.as_dict()

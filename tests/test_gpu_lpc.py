@@ -1,0 +1,221 @@
+"""Learned diagonal preconditioner on the GPU against the FP64 oracle
+(oracle/mlp.py): potential diagonal, forward scale, direction loss and its
+gradient, Adam; then the solver-level behaviour (training on pairs the
+solver harvests, fewer LOBPCG iterations than the plain preconditioner with
+unchanged eigenvalues, fallback when the network is bad).
+
+Tolerances: the network runs in FP32 on FP64 features, so forward values
+agree to ~1e-6 relative and the gradient (FP32 sums over one tile, FP64
+across workgroups) to ~1e-4 of its norm; stated per test."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import basis as ob
+from oracle import hamiltonian as oh
+from oracle import mlp
+from oracle import precond as op
+
+torch = pytest.importorskip("torch")
+helic = pytest.importorskip("paper_2210_12252_amd.helic")
+
+pytestmark = pytest.mark.gpu
+TINY = synth.workload("tiny-helix")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+class Problem:
+    def __init__(self, w):
+        self.w = w
+        self.o = ob.basis_for(w)
+        self.g = helic.Basis.from_workload(w)
+        mnk, _ = self.g.indices()
+        pos = {tuple(t): i for i, t in enumerate(self.o.mnk.tolist())}
+        self.perm = np.array([pos[tuple(t)] for t in mnk.tolist()])   # gpu row -> oracle row
+        atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
+        self.V = synth.potential_at(self.o.theta1, self.o.theta2, self.o.r, w.tau, w.alpha, atoms)
+        self.g.set_potential(torch.from_numpy(self.V).to(_dev()))
+        self.vdiag = oh.potential_diagonal(self.o, self.V)
+
+    def to_dev(self, A):
+        """Oracle-order (L, n) complex array -> device block (n, L) in GPU row order."""
+        return torch.from_numpy(np.ascontiguousarray(A[self.perm].T)).to(_dev())
+
+    def from_dev(self, B):
+        b = B.cpu().numpy().T
+        out = np.empty_like(b)
+        out[self.perm] = b
+        return out
+
+
+def _cplx(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _theta(seed, last=0.3):
+    rng = np.random.default_rng(seed)
+    th = mlp.init_params(seed)
+    th[-(2 * mlp.H + 1):] = rng.standard_normal(2 * mlp.H + 1) * last   # b2 stays He-scale free; w3, b3 random
+    th[mlp.NPARAM - 2 * mlp.H - 1:mlp.NPARAM - mlp.H - 1] *= 0.2        # modest b2
+    return th.astype(np.float32).astype(np.float64)
+
+
+def test_potential_diagonal_matches_oracle():
+    p = Problem(TINY.with_(alpha=0.15, eta=0.2))
+    vd = np.empty(p.o.L)
+    vd[p.perm] = p.g.lpc_vdiag()
+    err = np.max(np.abs(vd - p.vdiag)) / np.max(np.abs(p.V))
+    print(f"[vdiag] L={p.o.L} max rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
+def test_untrained_network_is_the_tpa_preconditioner():
+    p = Problem(TINY)
+    rng = np.random.default_rng(3)
+    nvec = 6
+    R = _cplx(rng, (p.o.L, nvec))
+    lam = torch.from_numpy(rng.uniform(-1, 0, nvec)).to(_dev())
+    net = helic.Lpc(seed=4)
+    W = torch.zeros_like(p.to_dev(R))
+    p.g.lpc_apply(net, p.to_dev(R), lam, W)
+    ref = op.tpa_apply(p.o.kappa, R)
+    err = np.max(np.abs(p.from_dev(W) - ref)) / np.max(np.abs(ref))
+    print(f"[lpc=tpa] max rel err {err:.2e}", flush=True)
+    assert err < 1e-6
+    net.close()
+
+
+@pytest.mark.parametrize("nvec", [5, 170])   # 16 tiles (ragged), and > 2 tiles per workgroup
+def test_forward_loss_and_gradient_match_oracle(nvec):
+    p = Problem(TINY)
+    rng = np.random.default_rng(nvec)
+    R = _cplx(rng, (p.o.L, nvec)) * np.exp(-0.3 * p.o.kappa)[:, None]
+    T = _cplx(rng, (p.o.L, nvec)) * np.exp(-0.5 * p.o.kappa)[:, None]
+    lam_h = rng.uniform(-0.8, 0.2, nvec)
+    lam = torch.from_numpy(lam_h).to(_dev())
+    theta = _theta(11)
+    net = helic.Lpc(seed=0)
+    net.params = theta
+    F, K = mlp.features(p.o.kappa, p.vdiag, R, lam_h)
+    s_ref, _ = mlp.forward(theta, F, K)
+    W = torch.zeros_like(p.to_dev(R))
+    p.g.lpc_apply(net, p.to_dev(R), lam, W)
+    werr = np.max(np.abs(p.from_dev(W) - s_ref * R) / (np.abs(s_ref * R) + 1e-300))
+    loss_ref, g_ref = mlp.loss_and_grad(theta, F, K, R, T)
+    loss, g = p.g.lpc_loss_grad(net, p.to_dev(R), p.to_dev(T), lam)
+    gerr = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    gmax = np.max(np.abs(g - g_ref)) / np.max(np.abs(g_ref))
+    print(f"[lpc grad] nvec={nvec} W rel {werr:.2e} loss {loss:.8f} vs {loss_ref:.8f} "
+          f"grad rel-norm {gerr:.2e} max {gmax:.2e}", flush=True)
+    assert werr < 2e-5
+    assert abs(loss - loss_ref) < 2e-6
+    assert gerr < 5e-4 and gmax < 5e-4
+    net.close()
+
+
+def test_adam_step_matches_oracle():
+    p = Problem(TINY)
+    rng = np.random.default_rng(8)
+    nvec = 4
+    R, T = _cplx(rng, (p.o.L, nvec)), _cplx(rng, (p.o.L, nvec))
+    lam = torch.from_numpy(rng.uniform(-0.8, 0.2, nvec)).to(_dev())
+    theta = _theta(5)
+    net = helic.Lpc(seed=0)
+    net.params = theta
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    th = theta.copy()
+    for step in (1, 2, 3):
+        _, g = p.g.lpc_loss_grad(net, p.to_dev(R), p.to_dev(T), lam)
+        net.adam_step(1e-3)
+        torch.cuda.synchronize()
+        th, m, v = mlp.adam_step(th, g, m, v, step, 1e-3)
+        got = net.params.astype(np.float64)
+        th_err = np.max(np.abs(got - th))
+        assert th_err < 1e-6, (step, th_err)
+        th = got   # continue from the device state (FP32 rounding)
+    net.close()
+
+
+def _harvest_and_train(w_train, steps=300, seed=0):
+    p = Problem(w_train)
+    R, T, lam, ncol, st = p.g.lpc_harvest(w_train.nev, n_snap=12, tol=1e-9, maxit=400, seed=3)
+    print(f"[harvest] {w_train.name} L={p.o.L} columns {ncol} its {st['iters']}", flush=True)
+    assert ncol > 0
+    net = helic.Lpc(seed=seed)
+    losses = p.g.lpc_train(net, R, T, lam, ncol, batch=min(16, ncol), steps=steps, lr=3e-3, seed=seed)
+    print(f"[train] loss first {losses[:10].mean():.4f} last {losses[-20:].mean():.4f}", flush=True)
+    return p, net, (R, T, lam, ncol), losses
+
+
+def test_harvested_pairs_are_consistent():
+    p = Problem(TINY.with_(eta=0.25))
+    R, T, lam, ncol, st = p.g.lpc_harvest(TINY.nev, n_snap=6, tol=1e-9, maxit=400, seed=3)
+    assert 0 < ncol <= 6 * TINY.nev
+    ref, Xs = oh.lowest(oh.dense_explicit(p.o, p.V), TINY.nev)
+    lam_h = lam[:ncol].cpu().numpy()
+    # Ritz values bound the eigenvalue of the same index from above; every
+    # target lies in span(X*) + span(snapshot block) and is not zero
+    assert np.all(lam_h >= ref.min() - 1e-9)
+    Tn = np.linalg.norm(T[:ncol].cpu().numpy(), axis=1)
+    Rn = np.linalg.norm(R[:ncol].cpu().numpy(), axis=1)
+    assert np.all(Tn > 0) and np.all(Tn <= 1 + 1e-9) and np.all(Rn > 1e-9)
+
+
+def test_trained_network_needs_fewer_iterations_same_eigenvalues():
+    p, net, _, losses = _harvest_and_train(TINY.with_(name="tiny-helix-eta0.25", eta=0.25))
+    assert losses[-20:].mean() < losses[:10].mean()
+    q = Problem(TINY)   # a different Bloch parameter than the training one
+    q.g.attach(net)
+    ref, _ = oh.lowest(oh.dense_explicit(q.o, q.V), TINY.nev)
+    ev_t, res_t, st_t, s_t = q.g.eigensolve_ex(TINY.nev, tol=1e-9, maxit=400, precond="tpa", seed=21)
+    ev_l, res_l, st_l, s_l = q.g.eigensolve_ex(TINY.nev, tol=1e-9, maxit=400, precond="learned", seed=21)
+    print(f"[A/B] TPA its {st_t['iters']} ({st_t['t_total_ms']:.0f} ms) learned its {st_l['iters']} "
+          f"({st_l['t_total_ms']:.0f} ms) fallback {st_l['n_fallback']}", flush=True)
+    assert s_t == helic.OK and s_l == helic.OK
+    assert np.max(np.abs(ev_l - ref)) < 1e-8 and np.max(np.abs(ev_t - ref)) < 1e-8
+    assert np.max(np.abs(ev_l - ev_t)) < 1e-9
+    assert st_l["iters"] < st_t["iters"]
+    net.close()
+
+
+def _high_pass_network():
+    """A deliberately bad network: s is ~1e-17 of the TPA factor below
+    kappa ~ 2.5 Ha and large above, so corrections never reach the low
+    kinetic-energy components the wanted states are made of."""
+    H, NIN = mlp.H, mlp.NIN
+    th = np.zeros(mlp.NPARAM)
+    th[0 * NIN + 2] = 1.0                     # W1[0][log kappa]
+    th[H * NIN + 0] = -np.log(2.0)            # b1[0]
+    o_w2 = H * NIN + H
+    th[o_w2 + 0] = 50.0                       # W2[0][0]
+    th[o_w2 + H * H + 0] = -5.0               # b2[0]
+    th[o_w2 + H * H + H + 0] = 20.0           # w3[0]
+    th[-1] = -40.0                            # b3
+    return th
+
+
+def test_bad_network_falls_back_and_still_converges():
+    p = Problem(TINY)
+    net = helic.Lpc(seed=0)
+    net.params = _high_pass_network()
+    p.g.attach(net)
+    ref, _ = oh.lowest(oh.dense_explicit(p.o, p.V), TINY.nev)
+    ev, res, st, status = p.g.eigensolve_ex(TINY.nev, tol=1e-9, maxit=600, precond="learned", seed=5)
+    print(f"[fallback] its {st['iters']} fallback iterations {st['n_fallback']}", flush=True)
+    assert status == helic.OK
+    assert 0 < st["n_fallback"] <= st["iters"]
+    assert np.max(np.abs(ev - ref)) < 1e-8
+    net.close()
+
+
+def test_learned_without_network_is_a_state_error():
+    p = Problem(TINY)
+    with pytest.raises(helic.HelicError) as e:
+        p.g.eigensolve_ex(TINY.nev, precond="learned")
+    assert e.value.status == helic.ERR_STATE

@@ -360,3 +360,15 @@ def test_mlp_untrained_network_is_tpa_and_loss_invariances():
     sr = mlp.forward(theta, F, K)[0] * R
     l0, g0 = mlp.loss_and_grad(theta, F, K, R, sr)                  # target along s r: zero loss, zero gradient
     assert abs(l0) < 1e-14 and np.max(np.abs(g0)) < 1e-12
+
+
+def test_potential_diagonal_is_the_dense_diagonal():
+    """V_ii (input feature of the learned preconditioner) against the
+    diagonal of the mode-A matrix built from the explicit basis matrix."""
+    w = synth.workload("tiny-helix").with_(alpha=0.2, eta=0.3)
+    b = ob.basis_for(w)
+    atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
+    V = synth.potential_at(b.theta1, b.theta2, b.r, w.tau, w.alpha, atoms)
+    H = oh.dense_explicit(b, V)
+    vd = oh.potential_diagonal(b, V)
+    np.testing.assert_allclose(vd, np.real(np.diag(H)) - b.kappa, rtol=0, atol=1e-12 * np.abs(V).max())
