@@ -33,6 +33,9 @@ STAGES = ("k_radial_inverse", "k_angular", "k_radial_forward")
 KERNEL_SOURCES = ("paper_2210_12252_amd/csrc/kernels.hpp", "paper_2210_12252_amd/csrc/device.hip")
 
 
+LOG_EVERY = 50   # eigensolver progress line (stderr) every this many iterations
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -94,7 +97,8 @@ def time_to_eigenpairs(b, w, torch, tol=1e-8):
     for prec in ("fp64", "fp32"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ev, res, st, status = b.eigensolve_ex(w.nev, block=64, tol=tol, maxit=1000, prec=prec, seed=7)
+        ev, res, st, status = b.eigensolve_ex(w.nev, block=64, tol=tol, maxit=1000, prec=prec, seed=7,
+                                              log_every=LOG_EVERY)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         key = "fp64" if prec == "fp64" else "mixed_fp32_fp64"
@@ -198,7 +202,7 @@ def learned_leg(torch, b, w, tol=1e-8, train_eta=0.25, n_snap=12, steps=400, bat
     bt.set_potential(torch.from_numpy(synth.potential_at(t1, t2, r, wt.tau, wt.alpha, atoms)).cuda())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    R, T, lam, ncol, hst = bt.lpc_harvest(w.nev, n_snap=n_snap, tol=tol, maxit=1000, seed=3)
+    R, T, lam, ncol, hst = bt.lpc_harvest(w.nev, n_snap=n_snap, tol=tol, maxit=1000, seed=3, log_every=LOG_EVERY)
     torch.cuda.synchronize()
     t_h = time.perf_counter() - t0
     net = helic.Lpc(seed=0)
@@ -220,7 +224,7 @@ def learned_leg(torch, b, w, tol=1e-8, train_eta=0.25, n_snap=12, steps=400, bat
     for pc in ("tpa", "learned"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ev, res, st, status = b.eigensolve_ex(w.nev, tol=tol, maxit=1000, precond=pc, seed=7)
+        ev, res, st, status = b.eigensolve_ex(w.nev, tol=tol, maxit=1000, precond=pc, seed=7, log_every=LOG_EVERY)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         out[pc] = dict(seconds=round(wall, 3), converged=bool(status == 0), iters=st["iters"],

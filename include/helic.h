@@ -169,6 +169,7 @@ typedef struct {
   int32_t precond;    /* 0: Teter-Payne-Allan, 1: none, 2: learned (helic_lpc_*)       */
   int32_t guard;      /* extra iterated columns beyond nev (-1: automatic)             */
   double switch_tol;  /* FP32 mode: residual below which FP64 applications take over  */
+  int32_t log_every;  /* > 0: one progress line on stderr every log_every iterations   */
 } helic_solve_opts;
 
 typedef struct {

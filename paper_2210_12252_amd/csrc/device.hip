@@ -33,8 +33,8 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   const int kpad = 4 * nks;
   const int ncol = 2 * gr.nmodes;
   const int nct = (ncol + 15) / 16;
-  const int colpad = 16 * nct;
-  for (int i = threadIdx.x; i < kpad * colpad; i += NT) Bs[i] = (T)0;
+  const int hs = lds_stride(16 * nct);
+  for (int i = threadIdx.x; i < kpad * hs; i += NT) Bs[i] = (T)0;
   __syncthreads();
   const double* xv = X + col_off(pb, ldx, nvec, v) * 2 + gr.row0 * 2;
   const int32_t* row_ck = pb.row_ck;
@@ -42,7 +42,7 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   for (int i = threadIdx.x; i < nvals; i += NT) {
     const int ck = row_ck[gr.row0 + (i >> 1)];
     const int c = ck >> 16, k = ck & 0xffff;
-    Bs[k * colpad + 2 * c + (i & 1)] = (T)xv[i];
+    Bs[k * hs + 2 * c + (i & 1)] = (T)xv[i];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -50,26 +50,32 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   const T* tg = reinterpret_cast<const T*>(pb.tinv) + gr.tinv_off;
   T* gv = GH + (slab_off(pb, nvec, n_r, v, 0) + gr.mode0) * 2;
   typedef typename Mfma<T>::acc_t acc_t;
+  const T* brow = Bs + (lane >> 4) * hs + (lane & 15);
   for (int rt = wave; rt < nrt; rt += NT / 64) {
     T a[KS_MAX];
 #pragma unroll
     for (int s = 0; s < KS_MAX; ++s)
       a[s] = (s < nks) ? tg[((int64_t)rt * nks + s) * 64 + lane] : (T)0;
-    for (int ct = 0; ct < nct; ++ct) {
-      acc_t acc = {0, 0, 0, 0};
+    // two column tiles at a time: independent accumulators interleave
+    for (int ct = 0; ct < nct; ct += 2) {
+      const bool two = ct + 1 < nct;
+      acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < KS_MAX; ++s) {
         if (s < nks) {
-          const T b = Bs[(4 * s + (lane >> 4)) * colpad + 16 * ct + (lane & 15)];
-          acc = Mfma<T>::op(a[s], b, acc);
+          acc0 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct], acc0);
+          if (two) acc1 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct + 16], acc1);
         }
       }
-      const int col = 16 * ct + (lane & 15);
-      if (col < ncol) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = 16 * rt + Mfma<T>::row(lane, i);
-          if (r < n_r) gv[(int64_t)r * pb.n_modes * 2 + col] = acc[i];
+      for (int q = 0; q < 2; ++q) {
+        const int col = 16 * (ct + q) + (lane & 15);
+        if (col < ncol && (q == 0 || two)) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = 16 * rt + Mfma<T>::row(lane, i);
+            if (r < n_r) gv[(int64_t)r * pb.n_modes * 2 + col] = q == 0 ? acc0[i] : acc1[i];
+          }
         }
       }
     }
@@ -132,7 +138,7 @@ k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __rest
   }
 }
 
-template <typename T>
+template <typename T, int TMAX>
 __global__ void __launch_bounds__(NT)
 k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
                  int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* __restrict__ groups,
@@ -145,9 +151,10 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
   const DGroup gr = groups[gi];
   const DProb& pb = probs[gr.prob];
   const int ncol = 2 * gr.nmodes;
-  T* As = Hs + FWD_RCHUNK * (16 * ((ncol + 15) / 16));     // [k tile][step][64]
   const int nct = (ncol + 15) / 16;
   const int colpad = 16 * nct;
+  const int hs = lds_stride(colpad);
+  T* As = Hs + FWD_RCHUNK * hs;     // [k tile][step][64]
   const int nkt = (gr.Kmax + 15) / 16;
   const int ntiles = nkt * nct;
   const int nrs = (n_r + 3) / 4;
@@ -160,16 +167,23 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
   const double* xv = add_kinetic ? X + col_off(pb, ldx, nvec, v) * 2 : nullptr;
   double* yv = Y + col_off(pb, ldy, nvec, v) * 2;
   typedef typename Mfma<T>::acc_t acc_t;
-  for (int tbase = 0; tbase < ntiles; tbase += (NT / 64) * FWD_TMAX) {
-    acc_t acc[FWD_TMAX];
+  for (int tbase = 0; tbase < ntiles; tbase += (NT / 64) * TMAX) {
+    acc_t acc[TMAX];
+    int aoff[TMAX], boff[TMAX];   // per tile: LDS offsets of its A rows and B columns
 #pragma unroll
-    for (int i = 0; i < FWD_TMAX; ++i) acc[i] = acc_t{0, 0, 0, 0};
+    for (int i = 0; i < TMAX; ++i) {
+      acc[i] = acc_t{0, 0, 0, 0};
+      const int t = tbase + wave + (NT / 64) * i;
+      const int kt = t / nct, ct = t - kt * nct;
+      aoff[i] = kt * (FWD_RCHUNK / 4) * 64 + lane;
+      boff[i] = (lane >> 4) * hs + 16 * ct + (lane & 15);
+    }
     for (int r0 = 0; r0 < n_r; r0 += FWD_RCHUNK) {
       __syncthreads();
       for (int i = threadIdx.x; i < FWD_RCHUNK * colpad; i += NT) {
         const int rr = i / colpad, col = i - rr * colpad;
         const int r = r0 + rr;
-        Hs[i] = (r < n_r && col < ncol) ? hv[(int64_t)r * n_modes * 2 + col] : (T)0;
+        Hs[rr * hs + col] = (r < n_r && col < ncol) ? hv[(int64_t)r * n_modes * 2 + col] : (T)0;
       }
       // the table fragments of this chunk (all k tiles, FWD_RCHUNK / 4 steps)
       for (int i = threadIdx.x; i < nkt * (FWD_RCHUNK / 4) * 64; i += NT) {
@@ -179,25 +193,136 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
         As[i] = rs < nrs ? tg[((int64_t)kt * nrs + rs) * 64 + ln] : (T)0;
       }
       __syncthreads();
+      const int steps = min(FWD_RCHUNK / 4, nrs - r0 / 4);
 #pragma unroll
-      for (int i = 0; i < FWD_TMAX; ++i) {
-        const int t = tbase + wave + (NT / 64) * i;
-        if (t < ntiles) {
-          const int kt = t / nct, ct = t - kt * nct;
+      for (int i = 0; i < TMAX; ++i) {
+        if (tbase + wave + (NT / 64) * i < ntiles) {
 #pragma unroll
-          for (int s = 0; s < FWD_RCHUNK / 4; ++s) {
-            const int rs = r0 / 4 + s;
-            if (rs < nrs) {
-              const T a = As[(kt * (FWD_RCHUNK / 4) + s) * 64 + lane];
-              const T b = Hs[(4 * s + (lane >> 4)) * colpad + 16 * ct + (lane & 15)];
-              acc[i] = Mfma<T>::op(a, b, acc[i]);
-            }
-          }
+          for (int s = 0; s < FWD_RCHUNK / 4; ++s)
+            if (s < steps) acc[i] = Mfma<T>::op(As[aoff[i] + s * 64], Hs[boff[i] + 4 * s * hs], acc[i]);
         }
       }
     }
 #pragma unroll
-    for (int i = 0; i < FWD_TMAX; ++i) {
+    for (int i = 0; i < TMAX; ++i) {
+      const int t = tbase + wave + (NT / 64) * i;
+      if (t >= ntiles) continue;
+      const int kt = t / nct, ct = t - kt * nct;
+      const int col = 16 * ct + (lane & 15);
+      const int c = col >> 1, ri = col & 1;
+      if (c >= gr.nmodes) continue;
+      const DMode md = modes[gr.mode0 + c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * kt + Mfma<T>::row(lane, j);
+        if (k < md.K) {
+          const int64_t row = md.row0 + k;
+          double y = (double)acc[i][j];
+          if (add_kinetic) y += kappa[row] * xv[2 * row + ri];
+          yv[2 * row + ri] = y;
+        }
+      }
+    }
+  }
+}
+
+// Radial forward stage with software pipelining: the slab rows and table
+// fragments of the next FWD_PF_RC radii are fetched into registers while the
+// MFMAs run on the current ones from LDS, so global-memory latency overlaps
+// the contractions.  Same tiles, layout and epilogue as k_radial_forward
+// with 4 register tiles per wave.  Staging: wave w moves radii
+// w * RC/4 ... of each chunk, lane l columns l + 64 b (b < CB), so colpad
+// <= 64 CB; at most FWD_PF_KT k tiles per group.
+template <typename T, int CB>
+__global__ void __launch_bounds__(NT)
+k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
+                    int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* __restrict__ groups,
+                    const DProb* __restrict__ probs, int add_kinetic) {
+  constexpr int RC = FWD_PF_RC, TM = 4, RW = FWD_PF_RC / (NT / 64), KTM = FWD_PF_KT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Hs = reinterpret_cast<T*>(smem_raw);
+  const int slot = xcd_slot(ngroups * nvec);
+  if (slot >= ngroups * nvec) return;
+  const int gi = slot / nvec, v = slot - gi * nvec;
+  const DGroup gr = groups[gi];
+  const DProb& pb = probs[gr.prob];
+  const int ncol = 2 * gr.nmodes;
+  const int nct = (ncol + 15) / 16;
+  const int colpad = 16 * nct;
+  const int hs = lds_stride(colpad);
+  T* As = Hs + RC * hs;     // [k tile][step][64]
+  const int nkt = (gr.Kmax + 15) / 16;
+  const int ntiles = nkt * nct;
+  const int nrs = (n_r + 3) / 4;
+  const int64_t rstride = (int64_t)pb.n_modes * 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const T* tg = reinterpret_cast<const T*>(pb.tfwd) + gr.tfwd_off;
+  const T* hv = GH + (slab_off(pb, nvec, n_r, v, 0) + gr.mode0) * 2;
+  const DMode* modes = pb.modes;
+  const double* kappa = pb.kappa;
+  const double* xv = add_kinetic ? X + col_off(pb, ldx, nvec, v) * 2 : nullptr;
+  double* yv = Y + col_off(pb, ldy, nvec, v) * 2;
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int nchunk = (n_r + RC - 1) / RC;
+  T hreg[RW][CB], areg[KTM];
+  auto fetch = [&](int r0) {
+#pragma unroll
+    for (int a = 0; a < RW; ++a) {
+      const int r = r0 + wave * RW + a;
+      const T* src = hv + (int64_t)r * rstride;
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int col = lane + 64 * b;
+        hreg[a][b] = (r < n_r && col < ncol) ? src[col] : (T)0;
+      }
+    }
+    // table fragments: thread (wave, lane) takes step `wave` of every k tile
+    const int rs = r0 / 4 + wave;
+#pragma unroll
+    for (int kt = 0; kt < KTM; ++kt)
+      areg[kt] = (kt < nkt && rs < nrs) ? tg[((int64_t)kt * nrs + rs) * 64 + lane] : (T)0;
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int a = 0; a < RW; ++a)
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int col = lane + 64 * b;
+        if (col < colpad) Hs[(wave * RW + a) * hs + col] = hreg[a][b];
+      }
+#pragma unroll
+    for (int kt = 0; kt < KTM; ++kt)
+      if (kt < nkt) As[(kt * (RC / 4) + wave) * 64 + lane] = areg[kt];
+  };
+  for (int tbase = 0; tbase < ntiles; tbase += (NT / 64) * TM) {
+    acc_t acc[TM];
+    int aoff[TM], boff[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      acc[i] = acc_t{0, 0, 0, 0};
+      const int t = tbase + wave + (NT / 64) * i;
+      const int kt = t / nct, ct = t - kt * nct;
+      aoff[i] = kt * (RC / 4) * 64 + lane;
+      boff[i] = (lane >> 4) * hs + 16 * ct + (lane & 15);
+    }
+    fetch(0);
+    for (int c = 0; c < nchunk; ++c) {
+      __syncthreads();
+      store();
+      __syncthreads();
+      if (c + 1 < nchunk) fetch((c + 1) * RC);
+      const int steps = min(RC / 4, nrs - c * (RC / 4));
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        if (tbase + wave + (NT / 64) * i < ntiles) {
+#pragma unroll
+          for (int s = 0; s < RC / 4; ++s)
+            if (s < steps) acc[i] = Mfma<T>::op(As[aoff[i] + s * 64], Hs[boff[i] + 4 * s * hs], acc[i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
       const int t = tbase + wave + (NT / 64) * i;
       if (t >= ntiles) continue;
       const int kt = t / nct, ct = t - kt * nct;
@@ -340,9 +465,77 @@ helic_status upload(const std::vector<T>& host, T** dptr) {
   return HELIC_OK;
 }
 
+// Output tiles of the widest group (16 k x 16 columns each); the radial
+// forward kernel keeps 4 * TMAX of them in registers per pass over r.
+int fwd_tiles_max(const helic_basis_s* h) {
+  int t = 0;
+  for (const Group& g : h->groups) t = std::max(t, ((g.Kmax + 15) / 16) * ((2 * g.nmodes + 15) / 16));
+  return t;
+}
+
+// Register tiles per wave: 4 by default.  Measured on MI355X, covering the
+// widest group in one pass (8-16 tiles) costs more in occupancy than the
+// extra passes over the LDS-staged slab.  HELIC_FWD_TMAX = 8, 12 or 16
+// selects a larger variant (for comparison).
+int fwd_tmax_for(int tiles) {
+  (void)tiles;
+  if (const char* e = std::getenv("HELIC_FWD_TMAX")) {
+    const int v = std::atoi(e);
+    if (v == 4 || v == 8 || v == 12 || v == 16) return v;
+  }
+  return 4;
+}
+
+// The pipelined radial forward kernel (variant 0) when the basis fits its
+// register staging; HELIC_FWD_PF=0 keeps the plain one.
+bool fwd_pf_ok(const helic_basis_s* h) {
+  if (const char* e = std::getenv("HELIC_FWD_PF"))
+    if (e[0] == '0') return false;
+  return h->max_colpad <= FWD_PF_COLS && (h->max_kpad + 15) / 16 <= FWD_PF_KT;
+}
+
+size_t fwd_pf_lds_bytes(const helic_basis_s* h, size_t elem) {
+  const int nkt_max = (h->max_kpad + 15) / 16;
+  return ((size_t)FWD_PF_RC * lds_stride(h->max_colpad) + (size_t)nkt_max * (FWD_PF_RC / 4) * 64) * elem;
+}
+
+// One launch of the radial forward stage with the smallest register tile
+// count that covers every group in one pass.
+template <typename T>
+void launch_radial_forward(int tmax, int nwg, size_t lds, hipStream_t st, const T* gh, const double* X, int64_t ldx,
+                           double* Y, int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* groups,
+                           const DProb* probs, int mode) {
+  switch (tmax) {
+    case 0:   // pipelined variants (columns staged per lane: 2 or 4 of 64)
+      hipLaunchKernelGGL((k_radial_forward_pf<T, 2>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+                         ngroups, n_r, groups, probs, mode);
+      break;
+    case -1:
+      hipLaunchKernelGGL((k_radial_forward_pf<T, 4>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+                         ngroups, n_r, groups, probs, mode);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_radial_forward<T, 4>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec, ngroups,
+                         n_r, groups, probs, mode);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_radial_forward<T, 8>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec, ngroups,
+                         n_r, groups, probs, mode);
+      break;
+    case 12:
+      hipLaunchKernelGGL((k_radial_forward<T, 12>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+                         ngroups, n_r, groups, probs, mode);
+      break;
+    default:
+      hipLaunchKernelGGL((k_radial_forward<T, 16>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+                         ngroups, n_r, groups, probs, mode);
+      break;
+  }
+}
+
 size_t fwd_lds_bytes(const helic_basis_s* h, size_t elem) {
   const int nkt_max = (h->max_kpad + 15) / 16;
-  return ((size_t)FWD_RCHUNK * h->max_colpad + (size_t)nkt_max * (FWD_RCHUNK / 4) * 64) * elem;
+  return ((size_t)FWD_RCHUNK * lds_stride(h->max_colpad) + (size_t)nkt_max * (FWD_RCHUNK / 4) * 64) * elem;
 }
 
 size_t angular_lds_bytes(const helic_basis_s* h, size_t elem) {
@@ -414,7 +607,14 @@ template <typename T>
 helic_status set_lds_limits() {
   const int lim = 160 * 1024;
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 12>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
@@ -449,10 +649,14 @@ helic_status ensure_device(helic_basis_s* h) {
     return HELIC_OK;
   }
   if (h->n_t1 * h->n_t2 > MAXGRID)
-    return fail(HELIC_ERR_GRID, "n_t1 * n_t2 above the angular kernel's limit of 4096 points");
+    return fail(HELIC_ERR_GRID, "n_t1 * n_t2 above the angular kernel's limit of " + std::to_string(MAXGRID) +
+                                    " points");
   if (h->max_kpad / 4 > KS_MAX) return fail(HELIC_ERR_GRID, "more than 96 radial functions in one |n| group");
   if (angular_lds_bytes(h, sizeof(double)) > 160 * 1024)
     return fail(HELIC_ERR_GRID, "angular slab does not fit in LDS");
+  if ((size_t)h->max_kpad * lds_stride(h->max_colpad) * sizeof(double) > 160 * 1024 ||
+      fwd_lds_bytes(h, sizeof(double)) > 160 * 1024)
+    return fail(HELIC_ERR_GRID, "a radial tile of the widest |n| group does not fit in LDS");
   DeviceState* d = new DeviceState();
   d->device = cur;
   h->dev = d;
@@ -556,8 +760,15 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.n_r = h->n_r;
   ls.n_t1 = h->n_t1;
   ls.n_t2 = h->n_t2;
-  ls.lds_inv64 = (size_t)h->max_kpad * h->max_colpad * sizeof(double);
+  ls.lds_inv64 = (size_t)h->max_kpad * lds_stride(h->max_colpad) * sizeof(double);
   ls.lds_fwd64 = fwd_lds_bytes(h, sizeof(double));
+  ls.fwd_tmax = fwd_tmax_for(fwd_tiles_max(h));
+  ls.fwd_tmax_plain = ls.fwd_tmax;
+  ls.lds_fwd_plain64 = ls.lds_fwd64;
+  if (ls.fwd_tmax == 4 && fwd_pf_ok(h)) {
+    ls.fwd_tmax = h->max_colpad <= 128 ? 0 : -1;
+    ls.lds_fwd64 = fwd_pf_lds_bytes(h, sizeof(double));
+  }
   ls.lds_ang64 = angular_lds_bytes(h, sizeof(double));
   ls.fast_mpad = d->fast_mpad;
   ls.vchunk = d->vchunk;
@@ -635,8 +846,8 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
     HIP_TRY(hipGetLastError());
   }
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-  hipLaunchKernelGGL((k_radial_forward<T>), dim3(wg_rad), dim3(NT), ls.lds_fwd64 / sc, st, gh, X, ldx, Y, ldy, nvec,
-                     ls.ngroups, ls.n_r, ls.groups, probs, mode);
+  launch_radial_forward<T>(ls.fwd_tmax, wg_rad, ls.lds_fwd64 / sc, st, gh, X, ldx, Y, ldy, nvec, ls.ngroups, ls.n_r,
+                           ls.groups, probs, mode);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   return HELIC_OK;
@@ -800,7 +1011,8 @@ helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx
     if ((s = ensure_workspace(h, nv, sizeof(double))) != HELIC_OK) return s;
     double* gh = reinterpret_cast<double*>(d->gh);
     hipLaunchKernelGGL((k_radial_inverse<double>), dim3(8 * ((ng * nv + 7) / 8)), dim3(NT),
-                       (size_t)h->max_kpad * h->max_colpad * sizeof(double), st, X + (int64_t)v0 * ldx * 2, ldx,
+                       (size_t)h->max_kpad * lds_stride(h->max_colpad) * sizeof(double), st,
+                       X + (int64_t)v0 * ldx * 2, ldx,
                        gh, nv, ng, h->n_r, d->groups, d->probs64);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_angular<double, 1>), dim3(8 * ((nv * h->n_r + 7) / 8)), dim3(NT),
@@ -831,9 +1043,9 @@ helic_status helic_transform_forward(helic_basis h, const double* g, double* X, 
                        h->n_r, d->probs64, d->rows1, (int)h->rows1.size(), d->tw1, d->tw2, d->plan1, d->plan2,
                        1.0 / ((double)h->n_t1 * h->n_t2));
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL((k_radial_forward<double>), dim3(8 * ((ng * nv + 7) / 8)), dim3(NT),
-                       fwd_lds_bytes(h, sizeof(double)), st, gh, (const double*)nullptr, ldx,
-                       X + (int64_t)v0 * ldx * 2, ldx, nv, ng, h->n_r, d->groups, d->probs64, 0);
+    launch_radial_forward<double>(4, 8 * ((ng * nv + 7) / 8),
+                                  fwd_lds_bytes(h, sizeof(double)), st, gh, (const double*)nullptr, ldx,
+                                  X + (int64_t)v0 * ldx * 2, ldx, nv, ng, h->n_r, d->groups, d->probs64, 0);
     HIP_TRY(hipGetLastError());
   }
   return HELIC_OK;

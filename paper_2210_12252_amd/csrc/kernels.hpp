@@ -37,8 +37,14 @@ namespace helic {
 constexpr int NT = 256;             // threads per workgroup in every kernel
 constexpr int MAXGRID = 8192;       // n_t1 * n_t2 bound of k_angular
 constexpr int KS_MAX = 24;          // K <= 96 per |n| group
-constexpr int FWD_TMAX = 4;         // output tiles per wave per round in k_radial_forward
-constexpr int FWD_RCHUNK = 32;      // radii staged per LDS round in k_radial_forward
+constexpr int FWD_RCHUNK = 32;
+constexpr int FWD_PF_RC = 16;       // radii per chunk of the pipelined radial forward kernel
+constexpr int FWD_PF_COLS = 256;    // widest staged group (columns) it supports
+constexpr int FWD_PF_KT = 6;        // k tiles (of 16) per group it supports
+// LDS row stride (elements) of a staged radial tile of colpad columns
+// (colpad a multiple of 16): congruent to 16 mod 32, so that the four rows an
+// MFMA B operand reads (16 lanes each) fall on disjoint bank ranges.
+__host__ __device__ constexpr int lds_stride(int colpad) { return (colpad & 16) ? colpad : colpad + 16; }      // radii staged per LDS round in k_radial_forward
 
 struct DGroup {
   int32_t mode0, nmodes, Kmax, prob;   // modes relative to the problem; prob indexes DProb

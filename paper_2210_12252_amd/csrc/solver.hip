@@ -15,9 +15,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <random>
 #include <string>
 #include <vector>
 
@@ -173,6 +173,27 @@ __global__ void k_reduce_partials(const double* __restrict__ P, int nb, int m, i
   }
   Cm[((size_t)j * ldc + i) * 2] = re;
   Cm[((size_t)j * ldc + i) * 2 + 1] = im;
+}
+
+// Standard normal numbers from a counter-based generator, the same for any
+// launch shape: the SplitMix64 finaliser (Steele, Lea and Flood 2014) of the
+// seed and the element index gives two 53-bit uniforms, and the Box-Muller
+// transform maps them to one normal.
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(NTS) k_random_normal(double* __restrict__ out, int64_t n, uint64_t seed) {
+  const uint64_t key = mix64(seed);
+  for (int64_t i = blockIdx.x * (int64_t)NTS + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTS) {
+    const uint64_t a = mix64(key ^ (2 * (uint64_t)i)), b = mix64(key ^ (2 * (uint64_t)i + 1));
+    const double u1 = (double)((a >> 11) + 1) * 0x1.0p-53;   // (0, 1]
+    const double u2 = (double)(b >> 11) * 0x1.0p-53;         // [0, 1)
+    out[i] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+  }
 }
 
 struct Bufs {
@@ -457,11 +478,10 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
 
   // ---- random start: orthonormalise, H X, first Rayleigh-Ritz
   {
-    std::mt19937_64 gen(o.seed);
-    std::normal_distribution<double> nd(0.0, 1.0);
-    std::vector<double> h0(Lc * n);
-    for (auto& x : h0) x = nd(gen);
-    HIP_TRY_S(hipMemcpyAsync(S, h0.data(), sizeof(double) * h0.size(), hipMemcpyHostToDevice, st));
+    const int64_t nn = (int64_t)Lc * n;
+    hipLaunchKernelGGL(k_random_normal, dim3((int)std::min<int64_t>(4096, (nn + NTS - 1) / NTS)), dim3(NTS), 0, st,
+                       S, nn, o.seed);
+    HIP_TRY_S(hipGetLastError());
     int kept = 0;
     if ((s = ortho_block(S, nullptr, n, &kept))) return s;
     if (kept < n) return fail(HELIC_ERR_NOCONV, "random start is rank deficient");
@@ -504,6 +524,11 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
       if ((s = apply(Pb, APb, np))) return s;
       --it;
       continue;
+    }
+    if (o.log_every > 0 && it % o.log_every == 0) {
+      std::fprintf(stderr, "[helic] iteration %d: worst wanted residual %.3e, %s H*X, %.1f s\n", it, worst,
+                   prec == HELIC_FP64 ? "FP64" : "FP32", total.ms() / 1e3);
+      std::fflush(stderr);
     }
     if (learned) {
       if (worst < best_worst) {
@@ -679,6 +704,7 @@ helic_status helic_eigensolve(helic_basis h, int32_t nev, int32_t block, double 
   o.precond = 0;
   o.guard = -1;
   o.switch_tol = 1e-4;
+  o.log_every = 0;
   helic_solve_stats st;
   std::memset(&st, 0, sizeof(st));
   helic_status s = helic_eigensolve_ex(h, &o, evals, resid, evecs, ldv, &st, stream);

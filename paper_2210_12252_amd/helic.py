@@ -46,7 +46,8 @@ class HelicError(RuntimeError):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int32), ("block", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int32), ("prec", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("precond", ctypes.c_int32), ("guard", ctypes.c_int32), ("switch_tol", ctypes.c_double)]
+                ("precond", ctypes.c_int32), ("guard", ctypes.c_int32), ("switch_tol", ctypes.c_double),
+                ("log_every", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -303,11 +304,11 @@ def eigensolve(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, evecs
 
 
 def eigensolve_ex(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa", guard=-1,
-                  switch_tol=1e-4, evecs=None, stream=None):
+                  switch_tol=1e-4, evecs=None, log_every=0, stream=None):
     """Returns (evals, resid, stats dict, status); raises on errors other
     than non-convergence."""
     o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=PREC[prec], seed=seed,
-                  precond=PRECOND[precond], guard=guard, switch_tol=switch_tol)
+                  precond=PRECOND[precond], guard=guard, switch_tol=switch_tol, log_every=log_every)
     evals = np.zeros(nev)
     resid = np.zeros(nev)
     st = SolveStats()
@@ -426,10 +427,10 @@ class Batch:
         return chosen.value, ms.value
 
     def eigensolve(self, nev, nstreams=8, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa",
-                   guard=-1, switch_tol=1e-4):
+                   guard=-1, switch_tol=1e-4, log_every=0):
         n = len(self.bases)
         o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=PREC[prec], seed=seed,
-                      precond=PRECOND[precond], guard=guard, switch_tol=switch_tol)
+                      precond=PRECOND[precond], guard=guard, switch_tol=switch_tol, log_every=log_every)
         evals = np.zeros((n, nev))
         resid = np.zeros((n, nev))
         stats = (SolveStats * n)()
@@ -543,7 +544,7 @@ class Basis:
         return losses[:steps]
 
     def lpc_harvest(self, nev, n_snap=12, max_cols=None, block=64, tol=1e-8, maxit=500, seed=7, precond="tpa",
-                    guard=-1, stream=None):
+                    guard=-1, log_every=0, stream=None):
         """Training pairs from one FP64 eigensolve: (R, T, lam, ncol, stats)
         with R, T of shape (max_cols, L) and the first ncol rows filled."""
         import torch
@@ -553,7 +554,7 @@ class Basis:
         T = torch.zeros_like(R)
         lam = torch.zeros(max_cols, dtype=torch.float64, device=dev)
         o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=FP64, seed=seed,
-                      precond=PRECOND[precond], guard=guard, switch_tol=1e-4)
+                      precond=PRECOND[precond], guard=guard, switch_tol=1e-4, log_every=log_every)
         ncol = ctypes.c_int32(0)
         st = SolveStats()
         _check(load().helic_lpc_harvest(self.h, ctypes.byref(o), n_snap, max_cols, ctypes.c_void_p(R.data_ptr()),
