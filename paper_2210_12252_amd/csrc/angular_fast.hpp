@@ -234,12 +234,31 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
     for (int q = 0; q < WN; ++q)
       w[q] = (conv_act && a0 + q < ND) ? src[a0 + q] : cplx<T>{(T)0, (T)0};
   }
+  // the mode slab of the next vector is fetched into registers while the
+  // current one is transformed (all modes of a radius fit the M x N2 block)
+  constexpr int MS = (MPAD * N2 + NTF - 1) / NTF;
+  int mp[MS];
+  cplx<T> pre[MS];
+#pragma unroll
+  for (int q = 0; q < MS; ++q) {
+    const int i = t + NTF * q;
+    mp[q] = i < n_modes ? mode_pos[i] : -1;
+  }
+  auto fetch = [&](int v) {
+    const cplx<T>* slab = reinterpret_cast<const cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+#pragma unroll
+    for (int q = 0; q < MS; ++q) pre[q] = mp[q] >= 0 ? slab[t + NTF * q] : cplx<T>{(T)0, (T)0};
+  };
+  if (v0 < v1) fetch(v0);
   for (int v = v0; v < v1; ++v) {
     cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
     for (int i = t; i < MPAD * RS; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
     __syncthreads();
-    for (int i = t; i < n_modes; i += NTF) A[mode_pos[i]] = slab[i];
+#pragma unroll
+    for (int q = 0; q < MS; ++q)
+      if (mp[q] >= 0) A[mp[q]] = pre[q];
     __syncthreads();
+    if (v + 1 < v1) fetch(v + 1);
     row_dft<T, N2, P, NTF, true>(A, MPAD, tw);
     // theta1: Toeplitz convolution per column with the spectrum of V
     cplx<T> acc[OPT];
@@ -265,7 +284,9 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
     }
     __syncthreads();
     row_dft<T, N2, P, NTF, false>(A, MPAD, tw);
-    for (int i = t; i < n_modes; i += NTF) slab[i] = A[mode_pos[i]];
+#pragma unroll
+    for (int q = 0; q < MS; ++q)
+      if (mp[q] >= 0) slab[t + NTF * q] = A[mp[q]];
     __syncthreads();
   }
 }

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -194,6 +195,14 @@ __global__ void __launch_bounds__(NTS) k_random_normal(double* __restrict__ out,
     const double u2 = (double)(b >> 11) * 0x1.0p-53;         // [0, 1)
     out[i] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
   }
+}
+
+// C[0:m, 0:m] (ld ldc, complex) = diag(lam)
+__global__ void k_diag_block(double* __restrict__ Cm, int ldc, const double* __restrict__ lam, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= m) return;
+  Cm[((size_t)j * ldc + i) * 2] = i == j ? lam[i] : 0.0;
+  Cm[((size_t)j * ldc + i) * 2 + 1] = 0.0;
 }
 
 struct Bufs {
@@ -399,17 +408,30 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     return HELIC_OK;
   };
 
-  // Rayleigh-Ritz on the orthonormal S[:, :k]: C = lowest `nout` eigenvectors
-  // of S^H (H S), lam their eigenvalues; then X <- S C, AX <- AS C (in Xn/AXn).
-  std::vector<double> lam_h;
-  auto rayleigh_ritz = [&](int k, int nout) -> helic_status {
+  // Rayleigh-Ritz on the orthonormal S[:, base:base+k]: C = lowest `nout`
+  // eigenvectors of S'^H (H S'), their eigenvalues into lam[base:] (device)
+  // and lam_h[base:] (host); then X' <- S' C, AX' <- AS' C (in Xn/AXn from
+  // column base).
+  std::vector<double> lam_h(n, 0.0);
+  auto rayleigh_ritz = [&](int base, int k, int nout, int nknown) -> helic_status {
     Timer t;
-    if ((s = gemm_h(k, k, S, AS, C, kmax))) return s;
-    if ((s = heev(k, C, lam, lam_h))) return s;
-    RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, nout, k, &one, (const zc*)S,
-                         (int)L, (const zc*)C, kmax, &zero, (zc*)Xn, (int)L));
-    RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, nout, k, &one, (const zc*)AS,
-                         (int)L, (const zc*)C, kmax, &zero, (zc*)AXn, (int)L));
+    // The leading nknown columns of S' are Ritz vectors with H X consistent,
+    // so that block of S'^H (H S') is diag(lam); the eigensolver reads the
+    // upper triangle only, so the Gram product needs columns nknown.. only.
+    if (nknown > 0) {
+      hipLaunchKernelGGL(k_diag_block, dim3((nknown + 63) / 64, nknown), dim3(64), 0, st, C, kmax, lam + base,
+                         nknown);
+      HIP_TRY_S(hipGetLastError());
+    }
+    if ((s = gemm_h(k, k - nknown, col(S, base), col(AS, base + nknown), C + (size_t)nknown * kmax * 2, kmax)))
+      return s;
+    std::vector<double> wh;
+    if ((s = heev(k, C, lam + base, wh))) return s;
+    for (int i = 0; i < nout; ++i) lam_h[base + i] = wh[i];
+    RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, nout, k, &one,
+                         (const zc*)col(S, base), (int)L, (const zc*)C, kmax, &zero, (zc*)col(Xn, base), (int)L));
+    RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, nout, k, &one,
+                         (const zc*)col(AS, base), (int)L, (const zc*)C, kmax, &zero, (zc*)col(AXn, base), (int)L));
     if ((s = sync())) return s;
     S_.t_rr_ms += t.ms();
     return HELIC_OK;
@@ -487,7 +509,7 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     if (kept < n) return fail(HELIC_ERR_NOCONV, "random start is rank deficient");
   }
   if ((s = apply(S, AS, n))) return s;
-  if ((s = rayleigh_ritz(n, n))) return s;
+  if ((s = rayleigh_ritz(0, n, n, 0))) return s;
   HIP_TRY_S(hipMemcpyAsync(S, Xn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
   HIP_TRY_S(hipMemcpyAsync(AS, AXn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
 
@@ -498,7 +520,18 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   double best_worst = HUGE_VAL;
   int stall = 0;
   std::vector<double> nrm;
-  std::vector<int32_t> active;
+  std::vector<int32_t> active, rel;
+  // hard locking (FP64 phase): the leading nl columns, converged to tol, are
+  // frozen; they stay in the projections of W and P but leave the
+  // Rayleigh-Ritz problem, which shrinks to the other columns
+  int nl = 0;
+  bool exact_x = true;   // X^H (H X) = diag(lam) for the current Ritz block
+  auto lowest_order = [&]() {   // columns by ascending Ritz value
+    std::vector<int> ord(n);
+    for (int j = 0; j < n; ++j) ord[j] = j;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return lam_h[a] < lam_h[b]; });
+    return ord;
+  };
   bool converged = false;
   int it = 0;
   for (it = 0; it < o.maxit; ++it) {
@@ -507,11 +540,15 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
       if (!std::isfinite(nrm[j]))
         return fail(HELIC_ERR_NOCONV, "residual of column " + std::to_string(j) + " is not finite at iteration " +
                                           std::to_string(it));
+    // the nev lowest by value (the locked prefix and the rest may interleave)
     bool all = true;
     double worst = 0.0;
-    for (int j = 0; j < nev; ++j) {
-      all = all && nrm[j] <= o.tol;
-      worst = std::max(worst, nrm[j]);
+    {
+      const std::vector<int> ord = lowest_order();
+      for (int q = 0; q < nev; ++q) {
+        all = all && nrm[ord[q]] <= o.tol;
+        worst = std::max(worst, nrm[ord[q]]);
+      }
     }
     if (all && prec == HELIC_FP64) {
       converged = true;
@@ -520,6 +557,7 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     if (prec != HELIC_FP64 && worst <= switch_tol) {
       // precision ladder: recompute H X and H P in FP64 and go on in FP64
       prec = HELIC_FP64;
+      exact_x = false;   // H X recomputed: X^H H X is no longer exactly diagonal
       if ((s = apply(S, AS, n))) return s;
       if ((s = apply(Pb, APb, np))) return s;
       --it;
@@ -543,8 +581,10 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     // whose residual is at the FP32 noise floor makes its normalised update
     // directions amplify the rounding inconsistency between S and H S.
     const double lock_tol = prec == HELIC_FP64 ? o.tol : std::max(o.tol, switch_tol);
+    if (prec == HELIC_FP64)
+      while (nl < n - 1 && nrm[nl] <= o.tol) ++nl;
     active.clear();
-    for (int j = 0; j < n; ++j)
+    for (int j = nl; j < n; ++j)
       if (nrm[j] > lock_tol) active.push_back(j);
     const int na = (int)active.size();
     if (na == 0) return fail(HELIC_ERR_NOCONV, "no active column left below the target");
@@ -588,35 +628,58 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
       double* AP = col(AS, n + nw);
       HIP_TRY_S(hipMemcpyAsync(P, Pb, sizeof(double) * Lc * np, hipMemcpyDeviceToDevice, st));
       HIP_TRY_S(hipMemcpyAsync(AP, APb, sizeof(double) * Lc * np, hipMemcpyDeviceToDevice, st));
-      for (int rep = 0; rep < 2; ++rep) {
-        if ((s = project(S, AS, n, P, AP, np))) return s;
-        if ((s = project(W, col(AS, n), nw, P, AP, np))) return s;
-      }
+      // [X W] is orthonormal (W was projected against X and orthonormalised):
+      // one projection against the joint block, twice
+      for (int rep = 0; rep < 2; ++rep)
+        if ((s = project(S, AS, n + nw, P, AP, np))) return s;
       if ((s = ortho_block(P, AP, np, &npk))) return s;
       if ((s = sync())) return s;
       S_.t_rr_ms += t.ms();
     }
-    const int k = n + nw + npk;
-    if ((s = rayleigh_ritz(k, n))) return s;
+    const int nx = n - nl;            // unlocked Ritz vectors
+    const int k = nx + nw + npk;
+    if ((s = rayleigh_ritz(nl, k, nx, exact_x ? nx : 0))) return s;
+    exact_x = true;
     {
       Timer t;
-      // new P = [W P] C[n:k, active], H P likewise
-      hipLaunchKernelGGL(k_gather_sub, dim3((k - n + 63) / 64, na), dim3(64), 0, st, C, kmax, n, k - n, d_idx, na,
-                         T1, kmax);
+      // new P = [W P] C[nx:k, active - nl], H P likewise
+      rel.resize(na);
+      for (int c = 0; c < na; ++c) rel[c] = active[c] - nl;
+      HIP_TRY_S(hipMemcpyAsync(d_idx, rel.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_gather_sub, dim3((k - nx + 63) / 64, na), dim3(64), 0, st, C, kmax, nx, k - nx, d_idx,
+                         na, T1, kmax);
       HIP_TRY_S(hipGetLastError());
-      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - n, &one,
+      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - nx, &one,
                            (const zc*)col(S, n), (int)L, (const zc*)T1, kmax, &zero, (zc*)Pb, (int)L));
-      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - n, &one,
+      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - nx, &one,
                            (const zc*)col(AS, n), (int)L, (const zc*)T1, kmax, &zero, (zc*)APb, (int)L));
       np = na;
-      HIP_TRY_S(hipMemcpyAsync(S, Xn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
-      HIP_TRY_S(hipMemcpyAsync(AS, AXn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
-      if ((s = sync())) return s;
+      HIP_TRY_S(hipMemcpyAsync(col(S, nl), col(Xn, nl), sizeof(double) * Lc * nx, hipMemcpyDeviceToDevice, st));
+      HIP_TRY_S(hipMemcpyAsync(col(AS, nl), col(AXn, nl), sizeof(double) * Lc * nx, hipMemcpyDeviceToDevice, st));
+      if ((s = sync())) return s;   // rel is read by the copy above
       S_.t_rr_ms += t.ms();
     }
   }
+  if (!converged && (s = residuals(nrm))) return s;
+  {
+    // columns in ascending order of their Ritz values (locking may have
+    // left them out of order)
+    const std::vector<int> ord = lowest_order();
+    std::vector<int32_t> ord32(ord.begin(), ord.end());
+    HIP_TRY_S(hipMemcpyAsync(d_idx, ord32.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gather_cols, dim3(64, n), dim3(NTS), 0, st, S, Xn, d_idx, L, n);
+    HIP_TRY_S(hipGetLastError());
+    HIP_TRY_S(hipMemcpyAsync(S, Xn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
+    if ((s = sync())) return s;
+    std::vector<double> l2(n), r2(n);
+    for (int q = 0; q < n; ++q) {
+      l2[q] = lam_h[ord[q]];
+      r2[q] = nrm[ord[q]];
+    }
+    lam_h.swap(l2);
+    nrm.swap(r2);
+  }
   if (!converged) {
-    if ((s = residuals(nrm))) return s;
     converged = prec == HELIC_FP64;
     for (int j = 0; j < nev; ++j) converged = converged && nrm[j] <= o.tol;
   }
