@@ -30,7 +30,8 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector and FP64 matrix (dense)
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X FP32 matrix (dense)
 FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
 STAGES = ("k_radial_inverse", "k_angular", "k_radial_forward")
-KERNEL_SOURCES = ("paper_2210_12252_amd/csrc/kernels.hpp", "paper_2210_12252_amd/csrc/device.hip")
+KERNEL_SOURCES = ("paper_2210_12252_amd/csrc/kernels.hpp", "paper_2210_12252_amd/csrc/angular_fast.hpp",
+                  "paper_2210_12252_amd/csrc/device.hip")
 
 
 LOG_EVERY = 50   # eigensolver progress line (stderr) every this many iterations
