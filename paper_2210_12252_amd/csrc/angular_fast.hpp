@@ -124,19 +124,48 @@ __device__ __forceinline__ void dft_reg(cplx<T>* v) {
   }
 }
 
+// Row stride (complex elements) of the LDS mode block for N2 = P * P: the P
+// threads of a row and the rows next to it then touch disjoint LDS banks in
+// every phase of the row transform when P divides 16 (N2 + P is P mod 16);
+// otherwise N2 + 1.
+__host__ __device__ constexpr int ang_rs(int n2) {
+  return n2 == 16 ? 20 : n2 == 64 ? 72 : n2 + 1;
+}
+
+template <typename T>
+__device__ __forceinline__ T fmac(T a, T b, T c) {
+  if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+  else return __builtin_fmaf(a, b, c);
+}
+
+// Orders LDS accesses among the lanes of one wave (they execute in issue
+// order); enough where only lanes of the same wave exchange data.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- row transform
-// In-place length N2 = P * P DFT of `rows` rows of A (row stride N2 + 1) by
+// In-place length N2 = P * P DFT of `rows` rows of A (row stride ang_rs(N2)) by
 // P threads per row.  Thread p of a row loads x[p + P q], does the P-point
 // DFT over q, multiplies by exp(s 2 pi i p k / N2), exchanges through LDS so
 // that thread c gets Y[.][c], does the P-point DFT over p and stores
-// X[c + P k1] at its natural position.  All threads of the block must call.
+// X[c + P k1] at its natural position.  All threads of the block must call;
+// A must be synchronised on entry and is on exit.  When a wave holds whole
+// rows (P divides 64) the exchanges inside need only wave-level ordering.
 template <typename T, int N2, int P, int NTF, bool INV>
 __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw) {
   static_assert(P * P == N2, "row transform expects N2 = P * P");
-  constexpr int RS = N2 + 1;                // padded row stride: rows start on different LDS banks
+  constexpr int RS = ang_rs(N2);
   constexpr int RPB = NTF / P;              // rows per batch
+  constexpr bool WAVE_ROWS = (64 % P) == 0;
   const int t = threadIdx.x;
   const int nb = (rows + RPB - 1) / RPB;
+  auto inner_sync = [&]() {
+    if constexpr (WAVE_ROWS) wave_sync();
+    else __syncthreads();
+  };
   for (int b = 0; b < nb; ++b) {            // uniform trip count
     const int row = b * RPB + t / P;
     const int p = t % P;
@@ -155,7 +184,7 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
         v[k] = cmul(v[k], w);
       }
     }
-    __syncthreads();
+    inner_sync();
     // exchange Y[p][k] through LDS; element (p, k) is stored at p*P +
     // (k + p) mod P so that both the row-wise writes and the column-wise
     // reads of the P threads of a row fall on distinct banks
@@ -168,7 +197,7 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
         a[p * P + kk] = v[k];
       }
     }
-    __syncthreads();
+    inner_sync();
     if (act) {
       cplx<T>* a = A + row * RS;
       const int c = p;
@@ -180,20 +209,22 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
       }
       dft_reg<T, P, INV>(v);
     }
-    __syncthreads();
+    inner_sync();
     if (act) {
       cplx<T>* a = A + row * RS;
 #pragma unroll
       for (int k1 = 0; k1 < P; ++k1) a[p + P * k1] = v[k1];
     }
-    __syncthreads();
+    inner_sync();
   }
+  if constexpr (WAVE_ROWS) __syncthreads();
 }
 
 // ---------------------------------------------------------------- the kernel
 // GH[v][r][mode] holds G on entry and H on exit (complex T).  Vh[r][j][d]
 // (complex T, d = 0..2 MPAD - 2 for m' - m = d - (MPAD - 1)).  mode_pos[i] =
-// (m_i - m_min) * (N2 + 1) + (n_i mod N2).  Work: blockIdx -> (radius, vector chunk).
+// (m_i - m_min) * ang_rs(N2) + (n_i mod N2).  Work: blockIdx -> (radius,
+// vector chunk).
 template <typename T, int N2, int MPAD, int NTF>
 __global__ void __launch_bounds__(NTF)
 k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
@@ -204,7 +235,7 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
   constexpr int OG = NTF / N2;                    // threads per column in the convolution
   constexpr int OPT = (MPAD + OG - 1) / OG;       // outputs per thread
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int RS = N2 + 1;                                   // padded row stride of A
+  constexpr int RS = ang_rs(N2);                               // padded row stride of A
   constexpr int WN = OPT + MPAD - 1;                           // Vhat window of one thread
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);          // [MPAD][RS]
   cplx<T>* tw = A + MPAD * RS;                                 // [N2]
@@ -216,7 +247,6 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
   const int r = rem / nchunks, ch = rem - r * nchunks;
   const DProb& pb = probs[pi];
   const int n_modes = pb.n_modes;
-  const int32_t* mode_pos = pb.mode_pos;
   const T* Vh = reinterpret_cast<const T*>(pb.Vh);
   const int v0 = ch * vchunk, v1 = min(nvec, v0 + vchunk);
   const int t = threadIdx.x;
@@ -234,16 +264,18 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
     for (int q = 0; q < WN; ++q)
       w[q] = (conv_act && a0 + q < ND) ? src[a0 + q] : cplx<T>{(T)0, (T)0};
   }
-  // the mode slab of the next vector is fetched into registers while the
-  // current one is transformed (all modes of a radius fit the M x N2 block)
-  constexpr int MS = (MPAD * N2 + NTF - 1) / NTF;
+  // The mode slab of the next vector is fetched into registers while the
+  // current one is transformed: thread t owns modes t + NTF q (coalesced
+  // global access) and writes them to their block positions mode_pos after
+  // the block has been cleared.
+  constexpr int MS = (MPAD * N2 + NTF - 1) / NTF;   // every mode of a radius fits the block
   int mp[MS];
-  cplx<T> pre[MS];
 #pragma unroll
   for (int q = 0; q < MS; ++q) {
     const int i = t + NTF * q;
-    mp[q] = i < n_modes ? mode_pos[i] : -1;
+    mp[q] = i < n_modes ? pb.mode_pos[i] : -1;
   }
+  cplx<T> pre[MS];
   auto fetch = [&](int v) {
     const cplx<T>* slab = reinterpret_cast<const cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
 #pragma unroll
@@ -271,8 +303,10 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
 #pragma unroll
         for (int o = 0; o < OPT; ++o) {
           const cplx<T> wv = w[o - m + MPAD - 1];
-          acc[o].x += wv.x * x.x - wv.y * x.y;
-          acc[o].y += wv.x * x.y + wv.y * x.x;
+          acc[o].x = fmac(wv.x, x.x, acc[o].x);
+          acc[o].x = fmac(-wv.y, x.y, acc[o].x);
+          acc[o].y = fmac(wv.x, x.y, acc[o].y);
+          acc[o].y = fmac(wv.y, x.x, acc[o].y);
         }
       }
     }

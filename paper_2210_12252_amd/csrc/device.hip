@@ -550,7 +550,7 @@ constexpr FastVariant FAST_VARIANTS[] = {{16, 12, 256}, {16, 16, 256}, {64, 24, 
 
 template <typename T>
 size_t fast_lds_bytes(int n2, int mpad) {
-  return ((size_t)mpad * (n2 + 1) + n2) * sizeof(cplx<T>);
+  return ((size_t)mpad * ang_rs(n2) + n2) * sizeof(cplx<T>);
 }
 
 // Tuning knobs (environment, read once per handle): vectors per angular
@@ -714,8 +714,9 @@ helic_status ensure_device(helic_basis_s* h) {
   }
   if (d->fast_mpad) {
     if ((s = set_fast_limits<double>()) || (s = set_fast_limits<float>())) return s;
+    const int rs = ang_rs(h->n_t2);
     std::vector<int32_t> mp(h->modes.size());
-    for (size_t i = 0; i < h->modes.size(); ++i) mp[i] = (h->modes[i].m - mlo) * (h->n_t2 + 1) + h->modes[i].bin2;
+    for (size_t i = 0; i < h->modes.size(); ++i) mp[i] = (h->modes[i].m - mlo) * rs + h->modes[i].bin2;
     if ((s = upload(mp, &d->mode_pos))) return s;
     const size_t nvh = (size_t)h->n_r * h->n_t2 * (2 * d->fast_mpad - 1) * 2;
     HIP_TRY(hipMalloc((void**)&d->Vh, nvh * sizeof(double)));

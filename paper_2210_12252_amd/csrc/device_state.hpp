@@ -40,7 +40,7 @@ struct DeviceState {
   int m_min = 0, m_count = 0;
   int vchunk = 8;                 // vectors per workgroup of the specialised angular kernel
   int apply_chunk = APPLY_CHUNK;  // vectors per launch of the three stages
-  int32_t* mode_pos = nullptr;    // (m - m_min) * n_t2 + (n mod n_t2) per mode
+  int32_t* mode_pos = nullptr;    // mode -> (m - m_min) * ang_rs(n_t2) + (n mod n_t2)
   double* Vh = nullptr;           // [n_r][n_t2][2 * fast_mpad - 1] complex
   float* Vhf = nullptr;
   DProb* probs64 = nullptr;       // one-entry problem tables of this handle

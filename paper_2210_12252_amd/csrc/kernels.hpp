@@ -71,7 +71,7 @@ struct DProb {
   const void* tfwd;
   const void* Vs;
   const void* Vh;
-  const int32_t* mode_pos;
+  const int32_t* mode_pos;    // mode -> LDS position in the angular block (specialised kernel)
   int64_t Lpre, L, mpre;
   int32_t n_modes, pad;
 };
