@@ -129,7 +129,7 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
   std::vector<char> row_used(h0->n_t1, 0);
   int64_t mpre = 0;
   size_t lds_inv = 0, lds_fwd = 0, lds_ang = 0, lds_fwd_plain = 0;
-  int fwd_tmax_plain = 4;
+  int fwd_tmax_plain = 4, inv_ks = 8;
   bool all_pf = true, pf_wide = false;
   for (int p = 0; p < nprob; ++p) {
     const helic_basis_s* h = bases[p];
@@ -146,6 +146,7 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
     lds_fwd_plain = std::max(lds_fwd_plain, one.lds_fwd_plain64);
     lds_ang = std::max(lds_ang, one.lds_ang64);
     fwd_tmax_plain = std::max(fwd_tmax_plain, one.fwd_tmax_plain);
+    inv_ks = std::max(inv_ks, one.inv_ks);
     all_pf = all_pf && one.fwd_tmax <= 0;
     pf_wide = pf_wide || one.fwd_tmax < 0;
   }
@@ -167,6 +168,7 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
   b->ls.nprob = nprob;
   b->ls.lds_inv64 = lds_inv;
   // the pipelined radial forward variant only if every problem fits it
+  b->ls.inv_ks = inv_ks;
   b->ls.fwd_tmax = all_pf ? (pf_wide ? -1 : 0) : fwd_tmax_plain;
   b->ls.lds_fwd64 = all_pf ? lds_fwd : lds_fwd_plain;
   b->ls.lds_ang64 = lds_ang + rows1.size() * sizeof(int32_t);

@@ -18,7 +18,13 @@
 namespace helic {
 
 // ============================================================ kernels
-template <typename T>
+// Radial inverse stage: one |n| group x one vector per workgroup.  The
+// group's coefficients are staged in LDS as [k][2 * modes] (real columns),
+// each wave takes 16-radius tiles.  KS bounds the k steps (of 4) of the
+// widest group; up to 16 steps the table fragments of the wave's next tile
+// are fetched into registers while the current tile's MFMAs run (beyond, the
+// doubled registers cost more occupancy than the prefetch gains).
+template <typename T, int KS>
 __global__ void __launch_bounds__(NT)
 k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, int nvec, int ngroups, int n_r,
                  const DGroup* __restrict__ groups, const DProb* __restrict__ probs) {
@@ -34,6 +40,17 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   const int ncol = 2 * gr.nmodes;
   const int nct = (ncol + 15) / 16;
   const int hs = lds_stride(16 * nct);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nrt = (n_r + 15) / 16;
+  const T* tg = reinterpret_cast<const T*>(pb.tinv) + gr.tinv_off;
+  constexpr bool PF = KS <= 16;
+  T anext[PF ? KS : 1];
+  auto fetch = [&](int rt, T* dst) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      dst[s] = (rt < nrt && s < nks) ? tg[((int64_t)rt * nks + s) * 64 + lane] : (T)0;
+  };
+  if constexpr (PF) fetch(wave, anext);   // in flight while the coefficients are staged
   for (int i = threadIdx.x; i < kpad * hs; i += NT) Bs[i] = (T)0;
   __syncthreads();
   const double* xv = X + col_off(pb, ldx, nvec, v) * 2 + gr.row0 * 2;
@@ -45,23 +62,24 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
     Bs[k * hs + 2 * c + (i & 1)] = (T)xv[i];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nrt = (n_r + 15) / 16;
-  const T* tg = reinterpret_cast<const T*>(pb.tinv) + gr.tinv_off;
   T* gv = GH + (slab_off(pb, nvec, n_r, v, 0) + gr.mode0) * 2;
   typedef typename Mfma<T>::acc_t acc_t;
   const T* brow = Bs + (lane >> 4) * hs + (lane & 15);
   for (int rt = wave; rt < nrt; rt += NT / 64) {
-    T a[KS_MAX];
+    T a[KS];
+    if constexpr (PF) {
 #pragma unroll
-    for (int s = 0; s < KS_MAX; ++s)
-      a[s] = (s < nks) ? tg[((int64_t)rt * nks + s) * 64 + lane] : (T)0;
+      for (int s = 0; s < KS; ++s) a[s] = anext[s];
+      fetch(rt + NT / 64, anext);
+    } else {
+      fetch(rt, a);
+    }
     // two column tiles at a time: independent accumulators interleave
     for (int ct = 0; ct < nct; ct += 2) {
       const bool two = ct + 1 < nct;
       acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
-      for (int s = 0; s < KS_MAX; ++s) {
+      for (int s = 0; s < KS; ++s) {
         if (s < nks) {
           acc0 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct], acc0);
           if (two) acc1 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct + 16], acc1);
@@ -499,6 +517,27 @@ size_t fwd_pf_lds_bytes(const helic_basis_s* h, size_t elem) {
   return ((size_t)FWD_PF_RC * lds_stride(h->max_colpad) + (size_t)nkt_max * (FWD_PF_RC / 4) * 64) * elem;
 }
 
+// Register k steps of the inverse kernel: the smallest of 8, 16, 24 that
+// covers the widest group.
+int inv_ks_for(const helic_basis_s* h) {
+  const int nks = h->max_kpad / 4;
+  return nks <= 8 ? 8 : nks <= 16 ? 16 : 24;
+}
+
+template <typename T>
+void launch_radial_inverse(int ks, int nwg, size_t lds, hipStream_t st, const double* X, int64_t ldx, T* gh,
+                           int nvec, int ngroups, int n_r, const DGroup* groups, const DProb* probs) {
+  if (ks <= 8)
+    hipLaunchKernelGGL((k_radial_inverse<T, 8>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r, groups,
+                       probs);
+  else if (ks <= 16)
+    hipLaunchKernelGGL((k_radial_inverse<T, 16>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r,
+                       groups, probs);
+  else
+    hipLaunchKernelGGL((k_radial_inverse<T, 24>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r,
+                       groups, probs);
+}
+
 // One launch of the radial forward stage with the smallest register tile
 // count that covers every group in one pass.
 template <typename T>
@@ -606,7 +645,9 @@ helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
 template <typename T>
 helic_status set_lds_limits() {
   const int lim = 160 * 1024;
-  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T, 24>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lim));
@@ -763,6 +804,7 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.n_t2 = h->n_t2;
   ls.lds_inv64 = (size_t)h->max_kpad * lds_stride(h->max_colpad) * sizeof(double);
   ls.lds_fwd64 = fwd_lds_bytes(h, sizeof(double));
+  ls.inv_ks = inv_ks_for(h);
   ls.fwd_tmax = fwd_tmax_for(fwd_tiles_max(h));
   ls.fwd_tmax_plain = ls.fwd_tmax;
   ls.lds_fwd_plain64 = ls.lds_fwd64;
@@ -831,8 +873,8 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
   const size_t sc = f64 ? 1 : 2;
   const int wg_rad = 8 * ((ls.ngroups * nvec + 7) / 8);
   if (ev) HIP_TRY(hipEventRecord(ev[0], st));
-  hipLaunchKernelGGL((k_radial_inverse<T>), dim3(wg_rad), dim3(NT), ls.lds_inv64 / sc, st, X, ldx, gh, nvec,
-                     ls.ngroups, ls.n_r, ls.groups, probs);
+  launch_radial_inverse<T>(ls.inv_ks, wg_rad, ls.lds_inv64 / sc, st, X, ldx, gh, nvec, ls.ngroups, ls.n_r,
+                           ls.groups, probs);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   if (ls.fast_mpad) {
@@ -1011,10 +1053,9 @@ helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx
     const int nv = std::min(APPLY_CHUNK, nvec - v0);
     if ((s = ensure_workspace(h, nv, sizeof(double))) != HELIC_OK) return s;
     double* gh = reinterpret_cast<double*>(d->gh);
-    hipLaunchKernelGGL((k_radial_inverse<double>), dim3(8 * ((ng * nv + 7) / 8)), dim3(NT),
-                       (size_t)h->max_kpad * lds_stride(h->max_colpad) * sizeof(double), st,
-                       X + (int64_t)v0 * ldx * 2, ldx,
-                       gh, nv, ng, h->n_r, d->groups, d->probs64);
+    launch_radial_inverse<double>(inv_ks_for(h), 8 * ((ng * nv + 7) / 8),
+                                  (size_t)h->max_kpad * lds_stride(h->max_colpad) * sizeof(double), st,
+                                  X + (int64_t)v0 * ldx * 2, ldx, gh, nv, ng, h->n_r, d->groups, d->probs64);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_angular<double, 1>), dim3(8 * ((nv * h->n_r + 7) / 8)), dim3(NT),
                        angular_lds_bytes(h, sizeof(double)), st, gh, nullptr, g + v0 * grid_elems * 2, 1, nv,

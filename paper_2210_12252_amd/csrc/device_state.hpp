@@ -70,6 +70,7 @@ struct LaunchSet {
   int n_r = 0, n_t1 = 0, n_t2 = 0;
   size_t lds_inv64 = 0, lds_fwd64 = 0, lds_ang64 = 0, lds_fast64 = 0;   // FP32 uses half
   int fast_mpad = 0, vchunk = 8;
+  int inv_ks = 24;                  // register k steps of the radial inverse stage
   int fwd_tmax = 4;                 // radial forward variant: register tiles per wave; 0, -1 = pipelined
                                     // with 2 or 4 staged columns per lane
   int fwd_tmax_plain = 4;           // the non-pipelined variant and its LDS bytes (FP64)
