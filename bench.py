@@ -28,7 +28,7 @@ METRIC = "H·X vec-applies/s (64-vec block) + time-to-n-eigenpairs, mixed vs FP6
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector and FP64 matrix (dense)
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X FP32 matrix (dense)
-FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published (packed FP32 counted; these kernels issue none)
 STAGES = ("k_radial_inverse", "k_angular", "k_radial_forward")
 KERNEL_SOURCES = ("paper_2210_12252_amd/csrc/kernels.hpp", "paper_2210_12252_amd/csrc/angular_fast.hpp",
                   "paper_2210_12252_amd/csrc/device.hip")
@@ -242,15 +242,16 @@ def learned_leg(torch, b, w, tol=1e-8, train_eta=0.25, n_snap=12, steps=400, bat
     return out
 
 
-def load_traffic(name: str, nvec: int):
+def load_traffic(name: str, nvec: int, workload: str):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or
-    None when absent or taken on other kernel sources."""
+    None when absent or taken on other kernel sources, block size or
+    workload."""
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_hash") != kernel_hash() or t.get("nvec") != nvec:
+    if t.get("kernel_hash") != kernel_hash() or t.get("nvec") != nvec or t.get("workload") != workload:
         return None
     return t
 
@@ -342,7 +343,7 @@ def main(argv=None):
         peak_tf = FP64_PEAK_TFLOPS if elem == 8 else FP32_MFMA_PEAK_TFLOPS
         compute_kind = "mfma"
     ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
-    traffic = load_traffic(dom, nvec)
+    traffic = load_traffic(dom, nvec, w.name)
     if intensity >= ridge:
         achieved = c["flops"] / (ms * 1e-3) / 1e12
         roof = dict(bound=compute_kind, achieved=round(achieved, 3), peak=peak_tf, unit="TFLOP/s",

@@ -3,7 +3,7 @@
     python -m paper_2210_12252_amd.profiling stats  <results.db> [--title T] [--command C]
     python -m paper_2210_12252_amd.profiling counters <results.db> [--title T] [--command C]
     python -m paper_2210_12252_amd.profiling traffic --fetch <db> --write <db> --kernel K --name N
-        --copy-bytes B --nvec V --hash H [--command C]
+        --copy-bytes B --nvec V --hash H --workload W [--command C]
 
 Prints a short markdown table: per kernel the dispatch count and the mean /
 min / max duration in microseconds (``stats``), or the mean of every
@@ -80,7 +80,7 @@ def traffic(a) -> dict:
     if not kf or not kw:
         raise SystemExit(f"kernel {a.kernel!r} not found in the counter runs")
     fb, wb = kf[0] * 1024.0 * rf, kw[0] * 1024.0 * wf
-    return dict(name=a.name, kernel=a.kernel, bytes_per_launch=round(fb + wb), read_bytes=round(fb),
+    return dict(name=a.name, kernel=a.kernel, workload=a.workload, bytes_per_launch=round(fb + wb), read_bytes=round(fb),
                 write_bytes=round(wb), fetch_kib=kf[0], write_kib=kw[0], read_scale=round(rf, 4),
                 write_scale=round(wf, 4), copy_bytes=a.copy_bytes, nvec=a.nvec, kernel_hash=a.hash,
                 command=a.command)
@@ -97,6 +97,7 @@ def main(argv=None):
     ap.add_argument("--copy-bytes", type=float)
     ap.add_argument("--nvec", type=int)
     ap.add_argument("--hash")
+    ap.add_argument("--workload")
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default="")
     a = ap.parse_args(argv)
