@@ -249,6 +249,13 @@ helic_status helic_lpc_destroy(helic_lpc net);
  * them restarts Adam. */
 helic_status helic_lpc_get_params(helic_lpc net, float* params);
 helic_status helic_lpc_set_params(helic_lpc net, const float* params);
+/* Weights file: a 16-byte header ("HELICLPC", format version 1 and the
+ * parameter count as little-endian int32) followed by the HELIC_LPC_NPARAM
+ * FP32 parameters, little-endian.  Loading validates the header and the
+ * values (finite) and restarts Adam; a failed load leaves the network as it
+ * was.  Host file I/O; errors: HELIC_ERR_INVALID (bad path or file). */
+helic_status helic_lpc_save(helic_lpc net, const char* path);
+helic_status helic_lpc_load(helic_lpc net, const char* path);
 /* Use `net` for helic_eigensolve_ex with precond = 2 on this basis (NULL
  * detaches).  The solver falls back to the Teter-Payne-Allan preconditioner
  * for the rest of a solve once the largest residual of the wanted pairs has

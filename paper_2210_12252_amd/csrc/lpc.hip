@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <random>
@@ -666,6 +667,56 @@ helic_status helic_lpc_set_params(helic_lpc net, const float* params) {
   HIP_TRY_L(hipMemset(net->grad, 0, NPAD * sizeof(double)));
   net->step = 0;
   return HELIC_OK;
+}
+
+helic_status helic_lpc_save(helic_lpc net, const char* path) {
+  if (!net || !path) return fail(HELIC_ERR_INVALID, "null argument");
+  std::vector<float> p(NPARAM);
+  helic_status s = helic_lpc_get_params(net, p.data());
+  if (s) return s;
+  unsigned char head[16] = {'H', 'E', 'L', 'I', 'C', 'L', 'P', 'C'};
+  const int32_t version = 1, count = NPARAM;
+  for (int b = 0; b < 4; ++b) {
+    head[8 + b] = (unsigned char)((version >> (8 * b)) & 0xff);
+    head[12 + b] = (unsigned char)((count >> (8 * b)) & 0xff);
+  }
+  std::vector<unsigned char> body((size_t)NPARAM * 4);
+  for (int i = 0; i < NPARAM; ++i) {
+    uint32_t u;
+    std::memcpy(&u, &p[i], 4);
+    for (int b = 0; b < 4; ++b) body[(size_t)4 * i + b] = (unsigned char)((u >> (8 * b)) & 0xff);
+  }
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(HELIC_ERR_INVALID, std::string("cannot open ") + path + " for writing");
+  const bool ok = std::fwrite(head, 1, 16, f) == 16 && std::fwrite(body.data(), 1, body.size(), f) == body.size();
+  const bool closed = std::fclose(f) == 0;
+  if (!ok || !closed) return fail(HELIC_ERR_INVALID, std::string("cannot write ") + path);
+  return HELIC_OK;
+}
+
+helic_status helic_lpc_load(helic_lpc net, const char* path) {
+  if (!net || !path) return fail(HELIC_ERR_INVALID, "null argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(HELIC_ERR_INVALID, std::string("cannot open ") + path);
+  unsigned char head[16];
+  std::vector<unsigned char> body((size_t)NPARAM * 4 + 1);
+  const size_t nh = std::fread(head, 1, 16, f);
+  const size_t nb = nh == 16 ? std::fread(body.data(), 1, body.size(), f) : 0;
+  std::fclose(f);
+  auto le32 = [&](int o) {
+    return (int32_t)((uint32_t)head[o] | ((uint32_t)head[o + 1] << 8) | ((uint32_t)head[o + 2] << 16) |
+                     ((uint32_t)head[o + 3] << 24));
+  };
+  if (nh != 16 || std::memcmp(head, "HELICLPC", 8) != 0 || le32(8) != 1 || le32(12) != NPARAM ||
+      nb != (size_t)NPARAM * 4)
+    return fail(HELIC_ERR_INVALID, std::string(path) + " is not a weights file of this network");
+  std::vector<float> p(NPARAM);
+  for (int i = 0; i < NPARAM; ++i) {
+    uint32_t u = 0;
+    for (int b = 0; b < 4; ++b) u |= (uint32_t)body[(size_t)4 * i + b] << (8 * b);
+    std::memcpy(&p[i], &u, 4);
+  }
+  return helic_lpc_set_params(net, p.data());
 }
 
 helic_status helic_lpc_attach(helic_basis h, helic_lpc net) {

@@ -31,6 +31,7 @@ EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "hel
            "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
            "helic_batch_eigensolve",
            "helic_lpc_create", "helic_lpc_destroy", "helic_lpc_get_params", "helic_lpc_set_params",
+           "helic_lpc_save", "helic_lpc_load",
            "helic_lpc_attach", "helic_lpc_vdiag", "helic_lpc_apply", "helic_lpc_loss_grad", "helic_lpc_adam_step",
            "helic_lpc_train", "helic_lpc_harvest",
            "helic_util_bessel_j", "helic_util_bessel_zeros", "helic_util_gauss_jacobi",
@@ -116,6 +117,8 @@ def load() -> ctypes.CDLL:
         "helic_lpc_destroy": [_P],
         "helic_lpc_get_params": [_P, ctypes.POINTER(ctypes.c_float)],
         "helic_lpc_set_params": [_P, ctypes.POINTER(ctypes.c_float)],
+        "helic_lpc_save": [_P, ctypes.c_char_p],
+        "helic_lpc_load": [_P, ctypes.c_char_p],
         "helic_lpc_attach": [_P, _P],
         "helic_lpc_vdiag": [_P, _PD],
         "helic_lpc_apply": [_P, _P, _P, _I64, _P, _P, _I64, _I32, _P],
@@ -369,6 +372,12 @@ class Lpc:
 
     def adam_step(self, lr, stream=None):
         _check(load().helic_lpc_adam_step(self.h, lr, _stream(stream)))
+
+    def save(self, path):
+        _check(load().helic_lpc_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        _check(load().helic_lpc_load(self.h, os.fsencode(path)))
 
 
 class Batch:

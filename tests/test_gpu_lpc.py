@@ -219,3 +219,27 @@ def test_learned_without_network_is_a_state_error():
     with pytest.raises(helic.HelicError) as e:
         p.g.eigensolve_ex(TINY.nev, precond="learned")
     assert e.value.status == helic.ERR_STATE
+
+
+def test_weights_file_round_trip_and_rejects_bad_files(tmp_path):
+    _dev()
+    a = helic.Lpc(seed=3)
+    a.params = _theta(4)
+    path = tmp_path / "net.lpc"
+    a.save(str(path))
+    assert path.stat().st_size == 16 + 4 * helic.LPC_NPARAM
+    b = helic.Lpc(seed=9)
+    before = b.params.copy()
+    b.load(str(path))
+    assert np.array_equal(b.params, a.params)
+    bad = tmp_path / "bad.lpc"
+    bad.write_bytes(path.read_bytes()[:-4])          # truncated
+    c = helic.Lpc(seed=9)
+    with pytest.raises(helic.HelicError) as e:
+        c.load(str(bad))
+    assert e.value.status == helic.ERR_INVALID
+    assert np.array_equal(c.params, before)
+    with pytest.raises(helic.HelicError):
+        c.load(str(tmp_path / "missing.lpc"))
+    for n in (a, b, c):
+        n.close()
