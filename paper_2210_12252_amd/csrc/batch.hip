@@ -117,7 +117,8 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
     if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "every problem needs a potential first");
     if (h->n_t1 != h0->n_t1 || h->n_t2 != h0->n_t2 || h->n_r != h0->n_r)
       return fail(HELIC_ERR_GRID, "problems of a batch must share the grid");
-    if (h->dev->fast_mpad != h0->dev->fast_mpad || h->dev->device != h0->dev->device)
+    if (h->dev->fast_mpad != h0->dev->fast_mpad || h->dev->grid_var != h0->dev->grid_var ||
+        h->dev->device != h0->dev->device)
       return fail(HELIC_ERR_GRID, "problems of a batch must share the angular kernel variant and device");
   }
   helic_batch_s* b = new helic_batch_s();
@@ -247,7 +248,7 @@ helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t
   int best = b->ls.vchunk;
   float best_ms = 1e30f;
   for (int c : cands) {
-    if (!b->ls.fast_mpad && c != b->ls.vchunk) continue;   // only the specialised kernel has the knob
+    if (!b->ls.fast_mpad && !b->ls.grid_var && c != b->ls.vchunk) continue;   // only these kernels have the knob
     b->ls.vchunk = c;
     for (int rep = 0; rep < 2 && s == HELIC_OK; ++rep) s = batch_launch(b, X, Y, nvec, prec, st, nullptr);  // warm
     if (s != HELIC_OK) break;

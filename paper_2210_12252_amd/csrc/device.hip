@@ -14,6 +14,7 @@
 #include "helic_internal.h"
 #include "kernels.hpp"
 #include "angular_fast.hpp"
+#include "angular_grid.hpp"
 
 namespace helic {
 
@@ -642,6 +643,60 @@ helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
   return fail(HELIC_ERR_STATE, "no specialised angular kernel for this grid");
 }
 
+// Grids served by the register-FFT angular kernel (theta1 size, theta2 size
+// and its four-step factors): the automatic grids of the batched workload.
+struct GridVariant {
+  int n1, n2, pa, pb;
+};
+constexpr GridVariant GRID_VARIANTS[] = {{20, 96, 8, 12},  {20, 120, 8, 15}, {24, 120, 8, 15},
+                                         {24, 135, 9, 15}, {27, 144, 12, 12}, {27, 180, 12, 15}};
+constexpr int GRID_NTF = 256;
+
+template <typename T>
+size_t grid_lds_bytes(int n1, int n2) {
+  return ((size_t)n1 * grid_rs(n2) + n2) * sizeof(cplx<T>);
+}
+
+template <typename T>
+helic_status set_grid_limits() {
+#define HELIC_GRID_ATTR(N1_, N2_, PA_, PB_)                                                              \
+  HIP_TRY(hipFuncSetAttribute((const void*)k_angular_grid<T, N1_, N2_, PA_, PB_, GRID_NTF>,            \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HELIC_GRID_ATTR(20, 96, 8, 12)
+  HELIC_GRID_ATTR(20, 120, 8, 15)
+  HELIC_GRID_ATTR(24, 120, 8, 15)
+  HELIC_GRID_ATTR(24, 135, 9, 15)
+  HELIC_GRID_ATTR(27, 144, 12, 12)
+  HELIC_GRID_ATTR(27, 180, 12, 15)
+#undef HELIC_GRID_ATTR
+  return HELIC_OK;
+}
+
+template <typename T>
+helic_status launch_grid(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
+  const DProb* probs = std::is_same<T, double>::value ? ls.probs64 : ls.probs32;
+  const cplx<T>* tw2 = (const cplx<T>*)(std::is_same<T, double>::value ? ls.tw2_64 : ls.tw2_32);
+  const int vchunk = ls.vchunk;
+  const int work = ls.nprob * ls.n_r * ((nvec + vchunk - 1) / vchunk);
+  const dim3 grid(8 * ((work + 7) / 8));
+  const size_t lds = grid_lds_bytes<T>(ls.n_t1, ls.n_t2);
+#define HELIC_GRID_CASE(N1_, N2_, PA_, PB_)                                                              \
+  if (ls.n_t1 == N1_ && ls.n_t2 == N2_) {                                                               \
+    hipLaunchKernelGGL((k_angular_grid<T, N1_, N2_, PA_, PB_, GRID_NTF>), grid, dim3(GRID_NTF), lds, st, gh, \
+                       ls.nprob, nvec, ls.n_r, probs, tw2, vchunk);                                     \
+    HIP_TRY(hipGetLastError());                                                                         \
+    return HELIC_OK;                                                                                    \
+  }
+  HELIC_GRID_CASE(20, 96, 8, 12)
+  HELIC_GRID_CASE(20, 120, 8, 15)
+  HELIC_GRID_CASE(24, 120, 8, 15)
+  HELIC_GRID_CASE(24, 135, 9, 15)
+  HELIC_GRID_CASE(27, 144, 12, 12)
+  HELIC_GRID_CASE(27, 180, 12, 15)
+#undef HELIC_GRID_CASE
+  return fail(HELIC_ERR_STATE, "no register-FFT angular kernel for this grid");
+}
+
 template <typename T>
 helic_status set_lds_limits() {
   const int lim = 160 * 1024;
@@ -753,6 +808,13 @@ helic_status ensure_device(helic_basis_s* h) {
       }
     }
   }
+  d->grid_var = false;
+  if (!d->fast_mpad && !fast_disabled()) {
+    for (const GridVariant& gv : GRID_VARIANTS)
+      if (gv.n1 == h->n_t1 && gv.n2 == h->n_t2 && grid_lds_bytes<double>(gv.n1, gv.n2) <= 160 * 1024)
+        d->grid_var = true;
+    if (d->grid_var && ((s = set_grid_limits<double>()) || (s = set_grid_limits<float>()))) return s;
+  }
   if (d->fast_mpad) {
     if ((s = set_fast_limits<double>()) || (s = set_fast_limits<float>())) return s;
     const int rs = ang_rs(h->n_t2);
@@ -814,6 +876,7 @@ LaunchSet launch_set(const helic_basis_s* h) {
   }
   ls.lds_ang64 = angular_lds_bytes(h, sizeof(double));
   ls.fast_mpad = d->fast_mpad;
+  ls.grid_var = d->grid_var;
   ls.vchunk = d->vchunk;
   ls.rows1 = d->rows1;
   ls.nrows1 = (int)h->rows1.size();
@@ -879,6 +942,9 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   if (ls.fast_mpad) {
     helic_status s = launch_fast<T>(ls, gh, nvec, st);
+    if (s != HELIC_OK) return s;
+  } else if (ls.grid_var) {
+    helic_status s = launch_grid<T>(ls, gh, nvec, st);
     if (s != HELIC_OK) return s;
   } else {
     const int wg_ang = 8 * ((ls.nprob * nvec * ls.n_r + 7) / 8);

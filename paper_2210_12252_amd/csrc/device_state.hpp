@@ -38,7 +38,8 @@ struct DeviceState {
   int fast_mpad = 0;              // 0: use the general angular kernel
   int fast_ntf = 256;
   int m_min = 0, m_count = 0;
-  int vchunk = 8;                 // vectors per workgroup of the specialised angular kernel
+  bool grid_var = false;          // the register-FFT angular kernel serves this grid
+  int vchunk = 8;                 // vectors per workgroup of the specialised angular kernels
   int apply_chunk = APPLY_CHUNK;  // vectors per launch of the three stages
   int32_t* mode_pos = nullptr;    // mode -> (m - m_min) * ang_rs(n_t2) + (n mod n_t2)
   double* Vh = nullptr;           // [n_r][n_t2][2 * fast_mpad - 1] complex
@@ -70,6 +71,7 @@ struct LaunchSet {
   int n_r = 0, n_t1 = 0, n_t2 = 0;
   size_t lds_inv64 = 0, lds_fwd64 = 0, lds_ang64 = 0, lds_fast64 = 0;   // FP32 uses half
   int fast_mpad = 0, vchunk = 8;
+  bool grid_var = false;
   int inv_ks = 24;                  // register k steps of the radial inverse stage
   int fwd_tmax = 4;                 // radial forward variant: register tiles per wave; 0, -1 = pipelined
                                     // with 2 or 4 staged columns per lane

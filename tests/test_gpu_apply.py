@@ -246,3 +246,36 @@ def test_apply_H_parity_radix2_grid(generic, monkeypatch):
     err = _rel(c.from_gpu_block(Yg), ref)
     print(f"[radix2 generic={generic}] rel err {err:.2e}", flush=True)
     assert err < TOL64
+
+
+@pytest.mark.parametrize("grid", [(20, 96, 24), (27, 144, 24), (24, 135, 24)])
+def test_register_fft_angular_kernel_parity(grid, monkeypatch):
+    """Grids of the batched workload served by the register-FFT angular
+    kernel (theta1 column DFTs in registers, non-square theta2 four-step):
+    against the oracle (FP64) and against the general LDS-FFT kernel on the
+    same inputs (FP64 and FP32)."""
+    n1, n2, nr = grid
+    w = synth.Workload(name=f"blob-{n1}x{n2}", R=6.0, tau=10.0, alpha=0.0, ecut=6.0, n_t1=n1, n_t2=n2, n_r=nr,
+                       m_max=(n1 - 1) // 2, n_max=(n2 - 1) // 2, structure="blob:1", seed=41, nev=4)
+    c = Case(w)
+    c.upload_V()
+    X = synth.random_block(c.o.mnk, 6, 21)
+    Yg = torch.zeros((6, c.o.L), dtype=torch.complex128, device=_dev())
+    c.g.apply_H(c.to_gpu_block(X), Yg)
+    ref = oh.apply(c.o, c.V, X)
+    err = _rel(c.from_gpu_block(Yg), ref)
+    print(f"[grid kernel {grid}] L={c.o.L} rel err vs oracle {err:.2e}", flush=True)
+    assert err < TOL64
+    monkeypatch.setenv("HELIC_GENERIC_ANGULAR", "1")
+    gen = helic.Basis.from_workload(w)
+    gen.set_potential(torch.from_numpy(c.V).to(_dev()))
+    monkeypatch.delenv("HELIC_GENERIC_ANGULAR")
+    Xd = c.to_gpu_block(X)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        Y1 = torch.zeros_like(Xd)
+        Y2 = torch.zeros_like(Xd)
+        gen.apply_H(Xd, Y1, prec=prec)
+        c.g.apply_H(Xd, Y2, prec=prec)
+        e2 = (torch.abs(Y1 - Y2).max() / torch.abs(Y1).max()).item()
+        assert e2 < tol, (prec, e2)
+    gen.close()
