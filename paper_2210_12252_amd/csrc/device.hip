@@ -645,6 +645,9 @@ helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
 
 // Grids served by the register-FFT angular kernel (theta1 size, theta2 size
 // and its four-step factors): the automatic grids of the batched workload.
+// Where the convolution kernel also applies (48 x 64, 32 x 81) it measured
+// faster (the m range there is half of theta1 or the column DFT would not
+// fit the registers), so it keeps precedence.
 struct GridVariant {
   int n1, n2, pa, pb;
 };
