@@ -115,6 +115,19 @@ def time_to_eigenpairs(b, w, torch, tol=1e-8):
     return out
 
 
+# Angular-stage kernel the library selects for a grid (its variant tables:
+# convolution kernel for theta2 sizes 16, 64, 81; register-FFT kernel for the
+# listed (theta1, theta2) grids; the general LDS FFT otherwise).
+CONV_N2 = (16, 64, 81)
+REGFFT_GRIDS = ((20, 96), (20, 120), (24, 120), (24, 135), (27, 144), (27, 180))
+
+
+def angular_kernel_name(n1, n2):
+    if n2 in CONV_N2:
+        return "convolution"
+    return "register-fft" if (n1, n2) in REGFFT_GRIDS else "general"
+
+
 def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e-8):
     """Many Bloch parameters of seeded structures (64 eta each, R ~ U[5, 12],
     E_cut ~ U[15, 35]): per structure one batch with a common grid (the
@@ -166,7 +179,7 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
         Ls = np.diff(batch.offsets)
         rec = dict(structure=s, R=round(w0.R, 3), ecut=round(w0.ecut, 3), n_eta=len(probs),
                    grid=f"{n1}x{n2}x{nr}", L_min=int(Ls.min()), L_max=int(Ls.max()),
-                   kernel="specialised" if n2 in (16, 64, 81) else "general",
+                   kernel=angular_kernel_name(n1, n2),
                    setup_s=round(setup, 2), tuned_vectors_per_wg=chosen, ms_per_batched_apply=round(1e3 * dt, 3),
                    vec_applies_per_s=round(len(probs) * nvec / dt, 1))
         sub = bases[::eig_every]
