@@ -792,7 +792,12 @@ helic_status ensure_device(helic_basis_s* h) {
       (s = upload(tw1, &d->tw1)) || (s = upload(tw2, &d->tw2)) || (s = upload(tw1f, &d->tw1f)) ||
       (s = upload(tw2f, &d->tw2f)))
     return s;
-  d->vchunk = env_int("HELIC_VCHUNK", 8, 1, 64);
+  // vectors per angular workgroup: the largest power of two (<= 16) that
+  // still gives >= 1024 workgroups for a 64-vector launch (measured best on
+  // the nanotube and nanowire grids); HELIC_VCHUNK overrides
+  int vc = 16;
+  while (vc > 1 && (int64_t)h->n_r * 64 / vc < 1024) vc /= 2;
+  d->vchunk = env_int("HELIC_VCHUNK", vc, 1, 64);
   d->apply_chunk = env_int("HELIC_APPLY_CHUNK", APPLY_CHUNK, 1, APPLY_CHUNK);
   d->plan1 = make_plan(h->n_t1, h->fac1);
   d->plan2 = make_plan(h->n_t2, h->fac2);
