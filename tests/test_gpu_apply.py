@@ -183,7 +183,7 @@ def test_precondition_parity(tiny):
     assert _rel(tiny.from_gpu_block(Rg), ref) < 1e-14
 
 
-@pytest.mark.parametrize("name", ["nanotube-ecut25"])
+@pytest.mark.parametrize("name", ["nanotube-ecut25", "nanotube-ecut40", "nanowire-ecut30"])
 def test_apply_H_full_size_sampled(name):
     """Full workload size in the launch configuration of the benchmark (one
     64-vector block); columns 0, 31 and 63 checked against the matrix-free
@@ -279,3 +279,23 @@ def test_register_fft_angular_kernel_parity(grid, monkeypatch):
         e2 = (torch.abs(Y1 - Y2).max() / torch.abs(Y1).max()).item()
         assert e2 < tol, (prec, e2)
     gen.close()
+
+
+def test_apply_H_widest_radial_groups_and_ragged_block():
+    """The widest radial group the kernels take (K = 96 per |n|: 24 k steps in
+    the inverse stage, 6 k tiles in the forward stage), 24 radial tiles, and a
+    ragged block of 67 vectors (one 64-vector launch and a 3-vector tail),
+    FP64 and FP32, against the oracle."""
+    w = synth.Workload(name="wide-K", R=40.0, tau=6.0, alpha=0.0, ecut=60.0, m_max=1, n_max=2, k_max=96,
+                       n_t1=8, n_t2=8, n_r=384, structure="blob:2", seed=43, nev=4)
+    c = Case(w)
+    assert int(c.o.mnk[:, 2].max()) == 96
+    c.upload_V()
+    X = synth.random_block(c.o.mnk, 67, 5)
+    ref = oh.apply(c.o, c.V, X)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        Yg = torch.zeros((67, c.o.L), dtype=torch.complex128, device=_dev())
+        c.g.apply_H(c.to_gpu_block(X), Yg, prec=prec)
+        err = _rel(c.from_gpu_block(Yg), ref)
+        print(f"[wide K {prec}] L={c.o.L} rel err {err:.2e}", flush=True)
+        assert err < tol
