@@ -128,12 +128,13 @@ def angular_kernel_name(n1, n2):
     return "register-fft" if (n1, n2) in REGFFT_GRIDS else "general"
 
 
-def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e-8):
+def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e-8, learned=True):
     """Many Bloch parameters of seeded structures (64 eta each, R ~ U[5, 12],
     E_cut ~ U[15, 35]): per structure one batch with a common grid (the
     largest automatic grid over its eta), tuned, captured in a HIP graph and
     replayed; and the lowest `nev` eigenpairs of every `eig_every`-th eta,
-    solved concurrently on 8 streams."""
+    solved concurrently on 8 streams, with the plain preconditioner and (if
+    `learned`) with a network trained on one other eta of the structure."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -190,6 +191,29 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
         te = time.perf_counter() - te
         rec.update(eig_problems=len(sub), eig_nev=nev, eig_seconds=round(te, 2),
                    eig_converged=int(np.sum(status == 0)), eig_iters_mean=float(np.mean([x["iters"] for x in st])))
+        if learned:
+            # one network per structure, trained on pairs from the solve at an
+            # eta outside the solved subset, attached to every solved problem
+            tl = time.perf_counter()
+            tb = bases[eig_every // 2]
+            Rh, Th, lh, ncol, _ = tb.lpc_harvest(nev, n_snap=12, tol=tol, maxit=1000, seed=3)
+            net = helic.Lpc(seed=0)
+            tb.lpc_train(net, Rh, Th, lh, ncol, batch=min(16, ncol), steps=400, lr=3e-3, seed=0)
+            torch.cuda.synchronize()
+            tl = time.perf_counter() - tl
+            del Rh, Th, lh
+            for sb in sub:
+                sb.attach(net)
+            te = time.perf_counter()
+            evl, resl, stl, statusl = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000, precond="learned")
+            te = time.perf_counter() - te
+            for sb in sub:
+                sb.attach(None)
+            net.close()
+            rec.update(learned_train_s=round(tl, 2), learned_eig_seconds=round(te, 2),
+                       learned_converged=int(np.sum(statusl == 0)),
+                       learned_iters_mean=float(np.mean([x["iters"] for x in stl])),
+                       learned_max_abs_dlambda=float(np.max(np.abs(evl - ev))))
         print(f"[bench] batched structure {s}: {rec}", file=sys.stderr, flush=True)
         out.append(rec)
         eb.close()
