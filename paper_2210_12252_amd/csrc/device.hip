@@ -426,7 +426,7 @@ k_tpa_partial(const double* __restrict__ Rr, int64_t ldr, const double* __restri
   s_den[threadIdx.x] = den;
   __syncthreads();
   for (int s = NT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
       s_num[threadIdx.x] += s_num[threadIdx.x + s];
       s_den[threadIdx.x] += s_den[threadIdx.x + s];
     }
@@ -1121,7 +1121,7 @@ helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx
   if (s != HELIC_OK) return s;
   DeviceState* d = h->dev;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int ng = (int)h->groups.size(), nm = (int)h->modes.size();
+  const int ng = (int)h->groups.size();
   const int64_t grid_elems = (int64_t)h->n_t1 * h->n_t2 * h->n_r;
   for (int v0 = 0; v0 < nvec; v0 += APPLY_CHUNK) {
     const int nv = std::min(APPLY_CHUNK, nvec - v0);
@@ -1148,7 +1148,7 @@ helic_status helic_transform_forward(helic_basis h, const double* g, double* X, 
   if (s != HELIC_OK) return s;
   DeviceState* d = h->dev;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int ng = (int)h->groups.size(), nm = (int)h->modes.size();
+  const int ng = (int)h->groups.size();
   const int64_t grid_elems = (int64_t)h->n_t1 * h->n_t2 * h->n_r;
   for (int v0 = 0; v0 < nvec; v0 += APPLY_CHUNK) {
     const int nv = std::min(APPLY_CHUNK, nvec - v0);

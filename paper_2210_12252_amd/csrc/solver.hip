@@ -98,7 +98,7 @@ k_residual(const double* __restrict__ AX, const double* __restrict__ X, const do
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = NTS / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[(int64_t)j * nchunk + c] = red[0];
