@@ -151,25 +151,24 @@ __device__ __forceinline__ void wave_sync() {
 // P threads per row.  Thread p of a row loads x[p + P q], does the P-point
 // DFT over q, multiplies by exp(s 2 pi i p k / N2), exchanges through LDS so
 // that thread c gets Y[.][c], does the P-point DFT over p and stores
-// X[c + P k1] at its natural position.  All threads of the block must call;
-// A must be synchronised on entry and is on exit.  When a wave holds whole
-// rows (P divides 64) the exchanges inside need only wave-level ordering.
+// X[c + P k1] at its natural position.  Rows are packed whole into waves
+// (64 / P rows per wave, the remaining lanes idle), so the exchanges need only
+// wave-level ordering.  All threads of the block must call; A must be
+// synchronised on entry and is on exit.
 template <typename T, int N2, int P, int NTF, bool INV>
 __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw) {
   static_assert(P * P == N2, "row transform expects N2 = P * P");
+  static_assert(P <= 64 && NTF % 64 == 0, "rows must fit in a wave");
   constexpr int RS = ang_rs(N2);
-  constexpr int RPB = NTF / P;              // rows per batch
-  constexpr bool WAVE_ROWS = (64 % P) == 0;
+  constexpr int RPW = 64 / P;                 // rows per wave
+  constexpr int RPB = RPW * (NTF / 64);       // rows per batch
   const int t = threadIdx.x;
+  const int lane = t & 63;
   const int nb = (rows + RPB - 1) / RPB;
-  auto inner_sync = [&]() {
-    if constexpr (WAVE_ROWS) wave_sync();
-    else __syncthreads();
-  };
   for (int b = 0; b < nb; ++b) {            // uniform trip count
-    const int row = b * RPB + t / P;
-    const int p = t % P;
-    const bool act = (t < RPB * P) && row < rows;
+    const int row = b * RPB + (t >> 6) * RPW + lane / P;
+    const int p = lane % P;
+    const bool act = lane < RPW * P && row < rows;
     cplx<T> v[P];
     if (act) {
       cplx<T>* a = A + row * RS;
@@ -184,7 +183,7 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
         v[k] = cmul(v[k], w);
       }
     }
-    inner_sync();
+    wave_sync();
     // exchange Y[p][k] through LDS; element (p, k) is stored at p*P +
     // (k + p) mod P so that both the row-wise writes and the column-wise
     // reads of the P threads of a row fall on distinct banks
@@ -197,7 +196,7 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
         a[p * P + kk] = v[k];
       }
     }
-    inner_sync();
+    wave_sync();
     if (act) {
       cplx<T>* a = A + row * RS;
       const int c = p;
@@ -209,15 +208,15 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
       }
       dft_reg<T, P, INV>(v);
     }
-    inner_sync();
+    wave_sync();
     if (act) {
       cplx<T>* a = A + row * RS;
 #pragma unroll
       for (int k1 = 0; k1 < P; ++k1) a[p + P * k1] = v[k1];
     }
-    inner_sync();
+    wave_sync();
   }
-  if constexpr (WAVE_ROWS) __syncthreads();
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------- the kernel

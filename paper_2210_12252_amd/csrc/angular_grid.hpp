@@ -15,22 +15,26 @@ namespace helic {
 __host__ __device__ constexpr int grid_rs(int n2) { return n2 + 1; }
 
 // In-place length N2 = PA * PB DFT of rows 0..rows-1 of A (row stride RS),
-// TPR = max(PA, PB) threads per row.  x[p + PA q] -> PB-point DFT over q per
-// thread p -> twiddle exp(s 2 pi i p k1 / N2) -> exchange -> PA-point DFT over p
-// per thread k1 -> X[k1 + PB k2].  A must be synchronised on entry; it is on
-// exit.
+// TPR = max(PA, PB) threads per row, rows packed whole into waves (64 / TPR
+// rows per wave) so the exchange needs only wave-level ordering.  x[p + PA q]
+// -> PB-point DFT over q per thread p -> twiddle exp(s 2 pi i p k1 / N2) ->
+// exchange -> PA-point DFT over p per thread k1 -> X[k1 + PB k2].  A must be
+// synchronised on entry; it is on exit.
 template <typename T, int N2, int PA, int PB, int NTF, bool INV>
 __device__ __forceinline__ void row_dft2(cplx<T>* A, int rows, const cplx<T>* tw) {
   static_assert(PA * PB == N2, "row transform expects N2 = PA * PB");
   constexpr int RS = grid_rs(N2);
   constexpr int TPR = PA > PB ? PA : PB;
-  constexpr int RPB = NTF / TPR;
+  static_assert(TPR <= 64 && NTF % 64 == 0, "rows must fit in a wave");
+  constexpr int RPW = 64 / TPR;
+  constexpr int RPB = RPW * (NTF / 64);
   const int t = threadIdx.x;
+  const int lane = t & 63;
   const int nb = (rows + RPB - 1) / RPB;
-  for (int b = 0; b < nb; ++b) {            // uniform trip count, barriers outside divergent code
-    const int row = b * RPB + t / TPR;
-    const int p = t % TPR;
-    const bool in_row = (t < RPB * TPR) && row < rows;
+  for (int b = 0; b < nb; ++b) {            // uniform trip count
+    const int row = b * RPB + (t >> 6) * RPW + lane / TPR;
+    const int p = lane % TPR;
+    const bool in_row = lane < RPW * TPR && row < rows;
     const bool first = in_row && p < PA, second = in_row && p < PB;
     cplx<T>* a = A + (in_row ? row : 0) * RS;
     cplx<T> v[PB];
@@ -46,25 +50,26 @@ __device__ __forceinline__ void row_dft2(cplx<T>* A, int rows, const cplx<T>* tw
         v[k] = cmul(v[k], w);
       }
     }
-    __syncthreads();
+    wave_sync();
     if (first) {
 #pragma unroll
       for (int k = 0; k < PB; ++k) a[p * PB + (k + p) % PB] = v[k];   // Y[p][k], rotated by p
     }
-    __syncthreads();
+    wave_sync();
     cplx<T> u[PA];
     if (second) {
 #pragma unroll
       for (int q = 0; q < PA; ++q) u[q] = a[q * PB + (p + q) % PB];   // Y[q][k1 = p]
       dft_reg<T, PA, INV>(u);
     }
-    __syncthreads();
+    wave_sync();
     if (second) {
 #pragma unroll
       for (int k2 = 0; k2 < PA; ++k2) a[p + PB * k2] = u[k2];
     }
-    __syncthreads();
+    wave_sync();
   }
+  __syncthreads();
 }
 
 // GH[v][r][mode] holds G on entry and H on exit (complex T).  Vs[r][i1][i2]
