@@ -252,12 +252,12 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
 // with 4 register tiles per wave.  Staging: wave w moves radii
 // w * RC/4 ... of each chunk, lane l columns l + 64 b (b < CB), so colpad
 // <= 64 CB; at most FWD_PF_KT k tiles per group.
-template <typename T, int CB>
+template <typename T, int CB, int TM>
 __global__ void __launch_bounds__(NT)
 k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
                     int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* __restrict__ groups,
                     const DProb* __restrict__ probs, int add_kinetic) {
-  constexpr int RC = FWD_PF_RC, TM = 4, RW = FWD_PF_RC / (NT / 64), KTM = FWD_PF_KT;
+  constexpr int RC = FWD_PF_RC, RW = FWD_PF_RC / (NT / 64), KTM = FWD_PF_KT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Hs = reinterpret_cast<T*>(smem_raw);
   const int slot = xcd_slot(ngroups * nvec);
@@ -539,6 +539,16 @@ void launch_radial_inverse(int ks, int nwg, size_t lds, hipStream_t st, const do
                        groups, probs);
 }
 
+// Register tiles per wave of the pipelined radial forward kernel: measured
+// best 8 in FP64 (one pass over the slab for groups of up to 32 tiles) and
+// 4 in FP32 (occupancy); HELIC_FWD_PF_TILES = 4 or 8 overrides.
+template <typename T>
+int fwd_pf_tiles() {
+  const char* e = std::getenv("HELIC_FWD_PF_TILES");
+  if (e && (e[0] == '4' || e[0] == '8')) return e[0] - '0';
+  return sizeof(T) == 8 ? 8 : 4;
+}
+
 // One launch of the radial forward stage with the smallest register tile
 // count that covers every group in one pass.
 template <typename T>
@@ -546,13 +556,21 @@ void launch_radial_forward(int tmax, int nwg, size_t lds, hipStream_t st, const 
                            double* Y, int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* groups,
                            const DProb* probs, int mode) {
   switch (tmax) {
-    case 0:   // pipelined variants (columns staged per lane: 2 or 4 of 64)
-      hipLaunchKernelGGL((k_radial_forward_pf<T, 2>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
-                         ngroups, n_r, groups, probs, mode);
+    case 0:   // pipelined variants (columns staged per lane: 2 or 4 of 64; register tiles per wave)
+      if (fwd_pf_tiles<T>() == 8)
+        hipLaunchKernelGGL((k_radial_forward_pf<T, 2, 8>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+                           ngroups, n_r, groups, probs, mode);
+      else
+        hipLaunchKernelGGL((k_radial_forward_pf<T, 2, 4>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+                           ngroups, n_r, groups, probs, mode);
       break;
     case -1:
-      hipLaunchKernelGGL((k_radial_forward_pf<T, 4>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
-                         ngroups, n_r, groups, probs, mode);
+      if (fwd_pf_tiles<T>() == 8)
+        hipLaunchKernelGGL((k_radial_forward_pf<T, 4, 8>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+                           ngroups, n_r, groups, probs, mode);
+      else
+        hipLaunchKernelGGL((k_radial_forward_pf<T, 4, 4>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+                           ngroups, n_r, groups, probs, mode);
       break;
     case 4:
       hipLaunchKernelGGL((k_radial_forward<T, 4>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec, ngroups,
@@ -707,10 +725,14 @@ helic_status set_lds_limits() {
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T, 24>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              lim));
-  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 2, 4>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 4, 4>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 2, 8>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 4, 8>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 12>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
