@@ -261,7 +261,8 @@ helic_status helic_lpc_load(helic_lpc net, const char* path);
  * for the rest of a solve once the largest residual of the wanted pairs has
  * not reached a new minimum for three iterations in a row. */
 helic_status helic_lpc_attach(helic_basis h, helic_lpc net);
-/* V_ii per row in the compact order (host, L doubles); needs the potential. */
+/* V_ii per row in the compact order (host, L doubles), computed on the
+ * device by helic_set_potential; synchronises the device. */
 helic_status helic_lpc_vdiag(helic_basis h, double* vdiag);
 /* W = s * R for nvec columns with Ritz values lam (W may equal R). */
 helic_status helic_lpc_apply(helic_basis h, helic_lpc net, const double* R, int64_t ldr, const double* lam,

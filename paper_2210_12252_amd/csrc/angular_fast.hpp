@@ -132,6 +132,15 @@ __host__ __device__ constexpr int ang_rs(int n2) {
   return n2 == 16 ? 20 : n2 == 64 ? 72 : n2 + 1;
 }
 
+// Column swizzle of the block: element (m, j) sits at m * RS + (j ^ ang_swz(N2,
+// m)).  With the row strides above, 16 consecutive m of one column (how the
+// mode slab is laid out) then fall on 16 distinct 16-byte bank groups, while
+// the XOR by a per-row constant below 8 keeps every row-transform phase and
+// the column-wise convolution conflict-free.
+__host__ __device__ constexpr int ang_swz(int n2, int m) {
+  return n2 == 64 ? (m >> 1) & 7 : n2 == 16 ? (m >> 2) & 3 : 0;
+}
+
 template <typename T>
 __device__ __forceinline__ T fmac(T a, T b, T c) {
   if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
@@ -172,8 +181,9 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
     cplx<T> v[P];
     if (act) {
       cplx<T>* a = A + row * RS;
+      const int sw = ang_swz(N2, row);
 #pragma unroll
-      for (int q = 0; q < P; ++q) v[q] = a[p + P * q];
+      for (int q = 0; q < P; ++q) v[q] = a[(p + P * q) ^ sw];
       dft_reg<T, P, INV>(v);
       // twiddle exp(s 2 pi i p k / N2); tw[t] = exp(-2 pi i t / N2), p k < N2
 #pragma unroll
@@ -189,30 +199,33 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
     // reads of the P threads of a row fall on distinct banks
     if (act) {
       cplx<T>* a = A + row * RS;
+      const int sw = ang_swz(N2, row);
 #pragma unroll
       for (int k = 0; k < P; ++k) {
         int kk = k + p;
         kk -= (kk >= P) ? P : 0;
-        a[p * P + kk] = v[k];
+        a[(p * P + kk) ^ sw] = v[k];
       }
     }
     wave_sync();
     if (act) {
       cplx<T>* a = A + row * RS;
+      const int sw = ang_swz(N2, row);
       const int c = p;
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         int cc = c + q;
         cc -= (cc >= P) ? P : 0;
-        v[q] = a[q * P + cc];   // Y[q][c]
+        v[q] = a[(q * P + cc) ^ sw];   // Y[q][c]
       }
       dft_reg<T, P, INV>(v);
     }
     wave_sync();
     if (act) {
       cplx<T>* a = A + row * RS;
+      const int sw = ang_swz(N2, row);
 #pragma unroll
-      for (int k1 = 0; k1 < P; ++k1) a[p + P * k1] = v[k1];
+      for (int k1 = 0; k1 < P; ++k1) a[(p + P * k1) ^ sw] = v[k1];
     }
     wave_sync();
   }
@@ -222,8 +235,8 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
 // ---------------------------------------------------------------- the kernel
 // GH[v][r][mode] holds G on entry and H on exit (complex T).  Vh[r][j][d]
 // (complex T, d = 0..2 MPAD - 2 for m' - m = d - (MPAD - 1)).  mode_pos[i] =
-// (m_i - m_min) * ang_rs(N2) + (n_i mod N2).  Work: blockIdx -> (radius,
-// vector chunk).
+// (m_i - m_min) * ang_rs(N2) + ((n_i mod N2) ^ ang_swz(N2, m_i - m_min)).
+// Work: blockIdx -> (radius, vector chunk).
 template <typename T, int N2, int MPAD, int NTF>
 __global__ void __launch_bounds__(NTF)
 k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
@@ -298,7 +311,7 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
     if (conv_act) {
 #pragma unroll
       for (int m = 0; m < MPAD; ++m) {
-        const cplx<T> x = A[m * RS + j];
+        const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
 #pragma unroll
         for (int o = 0; o < OPT; ++o) {
           const cplx<T> wv = w[o - m + MPAD - 1];
@@ -313,7 +326,7 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
     if (conv_act) {
 #pragma unroll
       for (int o = 0; o < OPT; ++o)
-        if (a0 + o < MPAD) A[(a0 + o) * RS + j] = acc[o];
+        if (a0 + o < MPAD) A[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
     }
     __syncthreads();
     row_dft<T, N2, P, NTF, false>(A, MPAD, tw);

@@ -363,6 +363,46 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
   }
 }
 
+// Angular mean of the potential per radius: vbar[r] = sum_{i1,i2} Vs[r][i1][i2]
+// (Vs carries 1 / (n_t1 n_t2)); fixed-order block reduction.
+__global__ void __launch_bounds__(NT) k_angular_mean(const double* __restrict__ Vs, int nang, double* __restrict__ vbar) {
+  __shared__ double red[NT];
+  const int r = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nang; i += NT) acc += Vs[(int64_t)r * nang + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) vbar[r] = red[0];
+}
+
+// Diagonal of the potential term per row: the angular factors of a basis
+// function have unit modulus, so V_ii = sum_r (2 pi tau R^2 w_r xi(r)) xi(r)
+// vbar(r) depends on (|n|, k) only; one workgroup per |n| group reads both
+// packed radial tables (forward table = 2 pi tau R^2 w_r xi, inverse = xi).
+__global__ void __launch_bounds__(NT)
+k_potential_diagonal(const DGroup* __restrict__ groups, const int32_t* __restrict__ row_ck,
+                     const double* __restrict__ tinv, const double* __restrict__ tfwd,
+                     const double* __restrict__ vbar, int n_r, double* __restrict__ vdiag) {
+  __shared__ double per_k[4 * KS_MAX];
+  const DGroup g = groups[blockIdx.x];
+  const int nks = (g.Kmax + 3) / 4, nrs = (n_r + 3) / 4;
+  for (int k = threadIdx.x; k < g.Kmax; k += NT) {
+    double acc = 0.0;
+    for (int l = 0; l < n_r; ++l) {
+      const double xi = tinv[g.tinv_off + ((int64_t)(l / 16) * nks + k / 4) * FRAG + (l % 16) + 16 * (k % 4)];
+      const double wf = tfwd[g.tfwd_off + ((int64_t)(k / 16) * nrs + l / 4) * FRAG + (k % 16) + 16 * (l % 4)];
+      acc += wf * xi * vbar[l];
+    }
+    per_k[k] = acc;
+  }
+  __syncthreads();
+  for (int64_t row = g.row0 + threadIdx.x; row < g.row0 + g.nrows; row += NT) vdiag[row] = per_k[row_ck[row] & 0xffff];
+}
+
 // Vs[r][i1][i2] = scale * V[i1][i2][r] (and the single-precision copy)
 __global__ void __launch_bounds__(NT)
 k_relayout_potential(const double* __restrict__ V, double* __restrict__ Vs, float* __restrict__ Vsf,
@@ -849,7 +889,10 @@ helic_status ensure_device(helic_basis_s* h) {
     if ((s = set_fast_limits<double>()) || (s = set_fast_limits<float>())) return s;
     const int rs = ang_rs(h->n_t2);
     std::vector<int32_t> mp(h->modes.size());
-    for (size_t i = 0; i < h->modes.size(); ++i) mp[i] = (h->modes[i].m - mlo) * rs + h->modes[i].bin2;
+    for (size_t i = 0; i < h->modes.size(); ++i) {
+      const int mr = h->modes[i].m - mlo;
+      mp[i] = mr * rs + (h->modes[i].bin2 ^ ang_swz(h->n_t2, mr));
+    }
     if ((s = upload(mp, &d->mode_pos))) return s;
     const size_t nvh = (size_t)h->n_r * h->n_t2 * (2 * d->fast_mpad - 1) * 2;
     HIP_TRY(hipMalloc((void**)&d->Vh, nvh * sizeof(double)));
@@ -1067,8 +1110,14 @@ helic_status helic_set_potential(helic_basis h, const double* V, void* stream) {
                        h->n_r, d->fast_mpad);
     HIP_TRY(hipGetLastError());
   }
+  // the potential's diagonal in the basis (input of the learned preconditioner)
+  if (!d->vdiag) HIP_TRY(hipMalloc((void**)&d->vdiag, sizeof(double) * (h->L + h->n_r)));
+  double* vbar = d->vdiag + h->L;
+  hipLaunchKernelGGL(k_angular_mean, dim3(h->n_r), dim3(NT), 0, st, d->Vs, h->n_t1 * h->n_t2, vbar);
+  hipLaunchKernelGGL(k_potential_diagonal, dim3((int)h->groups.size()), dim3(NT), 0, st, d->groups, d->row_ck,
+                     d->tinv64, d->tfwd64, vbar, h->n_r, d->vdiag);
+  HIP_TRY(hipGetLastError());
   d->have_potential = true;
-  d->vdiag_valid = false;
   return HELIC_OK;
 }
 

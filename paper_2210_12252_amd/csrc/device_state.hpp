@@ -41,7 +41,7 @@ struct DeviceState {
   bool grid_var = false;          // the register-FFT angular kernel serves this grid
   int vchunk = 8;                 // vectors per workgroup of the specialised angular kernels
   int apply_chunk = APPLY_CHUNK;  // vectors per launch of the three stages
-  int32_t* mode_pos = nullptr;    // mode -> (m - m_min) * ang_rs(n_t2) + (n mod n_t2)
+  int32_t* mode_pos = nullptr;    // mode -> (m - m_min) * ang_rs(n_t2) + ((n mod n_t2) ^ ang_swz)
   double* Vh = nullptr;           // [n_r][n_t2][2 * fast_mpad - 1] complex
   float* Vhf = nullptr;
   DProb* probs64 = nullptr;       // one-entry problem tables of this handle
@@ -50,10 +50,10 @@ struct DeviceState {
   size_t part_bytes = 0;
   SolverState* solver = nullptr;
   // learned preconditioner: attached network, potential diagonal V_ii per
-  // row (recomputed after a new potential), per-call column workspace
+  // row (L values, then the n_r angular means; set with the potential),
+  // per-call column workspace
   helic_lpc_s* lpc = nullptr;
   double* vdiag = nullptr;
-  bool vdiag_valid = false;
   double* lpc_ws = nullptr;
   size_t lpc_ws_bytes = 0;
 };

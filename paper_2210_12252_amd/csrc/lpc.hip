@@ -451,39 +451,6 @@ helic_status check_net(const helic_lpc_s* net) {
   return HELIC_OK;
 }
 
-// V_ii = sum_r (2 pi tau R^2 w_r) xi_{|n|k}(r)^2 Vbar(r), Vbar the angular
-// mean of V: the angular factors of a basis function have unit modulus, so
-// the diagonal of the potential depends on (|n|, k) only.
-helic_status ensure_vdiag(helic_basis_s* h) {
-  DeviceState* d = h->dev;
-  if (d->vdiag_valid) return HELIC_OK;
-  const int nr = h->n_r;
-  const size_t nang = (size_t)h->n_t1 * h->n_t2;
-  std::vector<double> vs((size_t)nr * nang);
-  HIP_TRY_L(hipDeviceSynchronize());
-  HIP_TRY_L(hipMemcpy(vs.data(), d->Vs, vs.size() * sizeof(double), hipMemcpyDeviceToHost));
-  std::vector<double> vbar(nr, 0.0);   // Vs already carries 1 / (n_t1 n_t2)
-  for (int r = 0; r < nr; ++r)
-    for (size_t a = 0; a < nang; ++a) vbar[r] += vs[(size_t)r * nang + a];
-  const double pref = 2.0 * M_PI * h->p.tau * h->p.R * h->p.R;
-  std::vector<double> vd(h->L);
-  for (const Group& grp : h->groups) {
-    const int nks = (grp.Kmax + 3) / 4;
-    std::vector<double> per_k(grp.Kmax, 0.0);
-    for (int k = 0; k < grp.Kmax; ++k)
-      for (int l = 0; l < nr; ++l) {
-        const int t = l / 16, s = k / 4, ln = (l % 16) + 16 * (k % 4);
-        const double xi = h->tab_inv[grp.tinv_off + ((int64_t)t * nks + s) * FRAG + ln];
-        per_k[k] += pref * h->wq[l] * xi * xi * vbar[l];
-      }
-    for (int64_t row = grp.row0; row < grp.row0 + grp.nrows; ++row) vd[row] = per_k[h->row_ck[row] & 0xffff];
-  }
-  if (!d->vdiag) HIP_TRY_L(hipMalloc((void**)&d->vdiag, sizeof(double) * h->L));
-  HIP_TRY_L(hipMemcpy(d->vdiag, vd.data(), sizeof(double) * h->L, hipMemcpyHostToDevice));
-  d->vdiag_valid = true;
-  return HELIC_OK;
-}
-
 // Per-call column workspace of a basis: partial sums and records.
 helic_status column_ws(helic_basis_s* h, int ncol, int nb, double** part, ColRec** cols) {
   DeviceState* d = h->dev;
@@ -502,8 +469,8 @@ helic_status column_ws(helic_basis_s* h, int ncol, int nb, double** part, ColRec
 }
 
 helic_status ready(helic_basis_s* h) {
-  if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
-  return ensure_vdiag(h);
+  if (!h->dev || !h->dev->have_potential || !h->dev->vdiag) return fail(HELIC_ERR_STATE, "no potential set");
+  return HELIC_OK;
 }
 
 helic_status column_records(helic_basis_s* h, const double* R, int64_t ldr, const double* T, int64_t ldt,
@@ -734,6 +701,7 @@ helic_status helic_lpc_vdiag(helic_basis h, double* vdiag) {
   if (!h || !vdiag) return fail(HELIC_ERR_INVALID, "null argument");
   helic_status s = ready(h);
   if (s) return s;
+  HIP_TRY_L(hipDeviceSynchronize());   // the potential may have been set on any stream
   HIP_TRY_L(hipMemcpy(vdiag, h->dev->vdiag, sizeof(double) * h->L, hipMemcpyDeviceToHost));
   return HELIC_OK;
 }
