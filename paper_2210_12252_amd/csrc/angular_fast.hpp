@@ -156,22 +156,30 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // ---------------------------------------------------------------- row transform
-// In-place length N2 = P * P DFT of `rows` rows of A (row stride ang_rs(N2)) by
+// In-place length N2 = P * P DFT of `rows` rows of A = A0 + OFF (row stride
+// ang_rs(N2); OFF is a compile-time element offset, so blocks at different
+// offsets share the per-thread LDS addresses and differ in the immediate) by
 // P threads per row.  Thread p of a row loads x[p + P q], does the P-point
 // DFT over q, multiplies by exp(s 2 pi i p k / N2), exchanges through LDS so
 // that thread c gets Y[.][c], does the P-point DFT over p and stores
 // X[c + P k1] at its natural position.  Rows are packed whole into waves
 // (64 / P rows per wave, the remaining lanes idle), so the exchanges need only
 // wave-level ordering.  All threads of the block must call; A must be
-// synchronised on entry and is on exit.
-template <typename T, int N2, int P, int NTF, bool INV>
-__device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw) {
+// synchronised on entry, and the caller synchronises the block before other
+// waves read the result.
+template <typename T, int N2, int P, int NTF, bool INV, int OFF, bool PIN>
+__device__ __forceinline__ void row_dft(cplx<T>* A0, int rows, const cplx<T>* tw) {
   static_assert(P * P == N2, "row transform expects N2 = P * P");
   static_assert(P <= 64 && NTF % 64 == 0, "rows must fit in a wave");
   constexpr int RS = ang_rs(N2);
   constexpr int RPW = 64 / P;                 // rows per wave
   constexpr int RPB = RPW * (NTF / 64);       // rows per batch
-  const int t = threadIdx.x;
+  // With PIN, t passes through an empty asm so that the per-thread LDS
+  // addresses below are recomputed at each call instead of being hoisted out
+  // of the caller's vector loop, where they stay live throughout (faster
+  // while they fit in registers, spilled on the widest blocks)
+  int t = threadIdx.x;
+  if constexpr (PIN) asm volatile("" : "+v"(t));
   const int lane = t & 63;
   const int nb = (rows + RPB - 1) / RPB;
   for (int b = 0; b < nb; ++b) {            // uniform trip count
@@ -180,10 +188,10 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
     const bool act = lane < RPW * P && row < rows;
     cplx<T> v[P];
     if (act) {
-      cplx<T>* a = A + row * RS;
+      cplx<T>* a = A0 + row * RS;
       const int sw = ang_swz(N2, row);
 #pragma unroll
-      for (int q = 0; q < P; ++q) v[q] = a[(p + P * q) ^ sw];
+      for (int q = 0; q < P; ++q) v[q] = a[OFF + ((p + P * q) ^ sw)];
       dft_reg<T, P, INV>(v);
       // twiddle exp(s 2 pi i p k / N2); tw[t] = exp(-2 pi i t / N2), p k < N2
 #pragma unroll
@@ -198,38 +206,101 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
     // (k + p) mod P so that both the row-wise writes and the column-wise
     // reads of the P threads of a row fall on distinct banks
     if (act) {
-      cplx<T>* a = A + row * RS;
+      cplx<T>* a = A0 + row * RS;
       const int sw = ang_swz(N2, row);
 #pragma unroll
       for (int k = 0; k < P; ++k) {
         int kk = k + p;
         kk -= (kk >= P) ? P : 0;
-        a[(p * P + kk) ^ sw] = v[k];
+        a[OFF + ((p * P + kk) ^ sw)] = v[k];
       }
     }
     wave_sync();
     if (act) {
-      cplx<T>* a = A + row * RS;
+      cplx<T>* a = A0 + row * RS;
       const int sw = ang_swz(N2, row);
       const int c = p;
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         int cc = c + q;
         cc -= (cc >= P) ? P : 0;
-        v[q] = a[(q * P + cc) ^ sw];   // Y[q][c]
+        v[q] = a[OFF + ((q * P + cc) ^ sw)];   // Y[q][c]
       }
       dft_reg<T, P, INV>(v);
     }
     wave_sync();
     if (act) {
-      cplx<T>* a = A + row * RS;
+      cplx<T>* a = A0 + row * RS;
       const int sw = ang_swz(N2, row);
 #pragma unroll
-      for (int k1 = 0; k1 < P; ++k1) a[(p + P * k1) ^ sw] = v[k1];
+      for (int k1 = 0; k1 < P; ++k1) a[OFF + ((p + P * k1) ^ sw)] = v[k1];
     }
     wave_sync();
   }
-  __syncthreads();
+}
+
+// ---------------------------------------------------------------- convolution
+// The convolution proceeds in groups of CONV_MB rows: the accumulators pass
+// through an empty asm at each group boundary, which pins the multiply-adds
+// of a group between its loads and the next group's, so only CONV_MB column
+// values are in registers at a time (left alone, the compiler loads the whole
+// column first and runs the accumulator chains one after the other).
+#ifndef HELIC_CONV_MB
+#define HELIC_CONV_MB 8
+#endif
+constexpr int CONV_MB = HELIC_CONV_MB;
+
+template <typename T, int OPT>
+__device__ __forceinline__ void pin_acc(cplx<T>* acc) {
+#pragma unroll
+  for (int o = 0; o < OPT; ++o) asm volatile("" : "+v"(acc[o].x), "+v"(acc[o].y));
+}
+
+// Outputs m' = A0 .. A0 + OPT - 1 of column j: out[m'] = sum_m Vhat[m' - m]
+// in[m].  The potential is real, so Vhat[-d] = conj(Vhat[d]) and the thread
+// holds h[d] = Vhat[d] for d = 0 .. MPAD - 1 only; with A0 a compile-time
+// constant every (m', m) pair resolves to h or its conjugate at compile time.
+template <typename T, int N2, int MPAD, int OPT, int A0>
+__device__ __forceinline__ void conv_herm(const cplx<T>* A, cplx<T>* B, int j, const cplx<T>* h) {
+  constexpr int RS = ang_rs(N2);
+  cplx<T> acc[OPT];
+#pragma unroll
+  for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
+#pragma unroll
+  for (int m = 0; m < MPAD; ++m) {
+    if (m % CONV_MB == 0 && m > 0) pin_acc<T, OPT>(acc);
+    const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
+#pragma unroll
+    for (int o = 0; o < OPT; ++o) {
+      const int d = A0 + o - m;
+      if (A0 + o >= MPAD) continue;
+      if (d >= 0) {
+        const cplx<T> wv = h[d];
+        acc[o].x = fmac(wv.x, x.x, acc[o].x);
+        acc[o].x = fmac(-wv.y, x.y, acc[o].x);
+        acc[o].y = fmac(wv.x, x.y, acc[o].y);
+        acc[o].y = fmac(wv.y, x.x, acc[o].y);
+      } else {
+        const cplx<T> wv = h[-d];
+        acc[o].x = fmac(wv.x, x.x, acc[o].x);
+        acc[o].x = fmac(wv.y, x.y, acc[o].x);
+        acc[o].y = fmac(wv.x, x.y, acc[o].y);
+        acc[o].y = fmac(-wv.y, x.x, acc[o].y);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < OPT; ++o)
+    if (A0 + o < MPAD) B[(A0 + o) * RS + (j ^ ang_swz(N2, A0 + o))] = acc[o];
+}
+
+// Selects the compile-time output range of output group g (wave-uniform).
+template <typename T, int N2, int MPAD, int OPT, int G, int OG>
+__device__ __forceinline__ void conv_herm_group(int g, const cplx<T>* A, cplx<T>* B, int j, const cplx<T>* h) {
+  if constexpr (G < OG) {
+    if (g == G) conv_herm<T, N2, MPAD, OPT, G * OPT>(A, B, j, h);
+    else conv_herm_group<T, N2, MPAD, OPT, G + 1, OG>(g, A, B, j, h);
+  }
 }
 
 // ---------------------------------------------------------------- the kernel
@@ -237,8 +308,15 @@ __device__ __forceinline__ void row_dft(cplx<T>* A, int rows, const cplx<T>* tw)
 // (complex T, d = 0..2 MPAD - 2 for m' - m = d - (MPAD - 1)).  mode_pos[i] =
 // (m_i - m_min) * ang_rs(N2) + ((n_i mod N2) ^ ang_swz(N2, m_i - m_min)).
 // Work: blockIdx -> (radius, vector chunk).
+//
+// LDS holds two mode blocks: A receives the scattered slab and its theta2
+// inverse transform, the convolution writes into B, and B is transformed back
+// and gathered while A is cleared and filled with the next vector.  Per vector
+// the block then synchronises four times: after the scatter, after the
+// inverse row transforms, after the convolution and after the forward row
+// transforms.
 template <typename T, int N2, int MPAD, int NTF>
-__global__ void __launch_bounds__(NTF)
+__global__ void __launch_bounds__(NTF, 512 / NTF)
 k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
                const cplx<T>* __restrict__ tw2g, int vchunk) {
   constexpr int P = (N2 == 16) ? 4 : (N2 == 64) ? 8 : (N2 == 81) ? 9 : (N2 == 36) ? 6 : (N2 == 100) ? 10 : 0;
@@ -247,10 +325,13 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
   constexpr int OG = NTF / N2;                    // threads per column in the convolution
   constexpr int OPT = (MPAD + OG - 1) / OG;       // outputs per thread
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int RS = ang_rs(N2);                               // padded row stride of A
+  constexpr int RS = ang_rs(N2);                               // padded row stride of A and B
+  constexpr int BLK = MPAD * RS;
   constexpr int WN = OPT + MPAD - 1;                           // Vhat window of one thread
+  constexpr bool PIN_ROWS = MPAD >= 32 && sizeof(T) == 8;      // see row_dft
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);          // [MPAD][RS]
-  cplx<T>* tw = A + MPAD * RS;                                 // [N2]
+  cplx<T>* B = A + BLK;                                        // [MPAD][RS]
+  cplx<T>* tw = B + BLK;                                       // [N2]
   const int nchunks = (nvec + vchunk - 1) / vchunk;
   const int per = n_r * nchunks;
   const int slot = xcd_slot(nprob * per);
@@ -266,20 +347,24 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
   const int j = t % N2, og = t / N2;
   const bool conv_act = og < OG;
   const int a0 = og * OPT;
-  // Vhat_j[d] for d - (MPAD - 1) = m' - m over this thread's outputs m' in
-  // [a0, a0 + OPT) and all m: w[q] = Vhat[r][j][a0 + q], read once and kept
-  // in registers for every vector of the chunk
-  cplx<T> w[WN];
+  // With N2 = 64 the output group is the wave index, and the thread keeps
+  // h[d] = Vhat_j[d], d = 0 .. MPAD - 1 (the rest follows by conjugation).
+  // Otherwise it keeps the window w[q] = Vhat_j[a0 + q - (MPAD - 1)] that its
+  // outputs m' in [a0, a0 + OPT) need over all m.  Either is read once and
+  // kept in registers for every vector of the chunk.
+  constexpr bool HERM = (N2 == 64);
+  constexpr int NW = HERM ? MPAD : WN;
+  cplx<T> w[NW];
   {
     const cplx<T>* src = reinterpret_cast<const cplx<T>*>(Vh) + ((int64_t)r * N2 + j) * ND;
+    const int base = HERM ? MPAD - 1 : a0;
 #pragma unroll
-    for (int q = 0; q < WN; ++q)
-      w[q] = (conv_act && a0 + q < ND) ? src[a0 + q] : cplx<T>{(T)0, (T)0};
+    for (int q = 0; q < NW; ++q)
+      w[q] = (conv_act && base + q < ND) ? src[base + q] : cplx<T>{(T)0, (T)0};
   }
   // The mode slab of the next vector is fetched into registers while the
   // current one is transformed: thread t owns modes t + NTF q (coalesced
-  // global access) and writes them to their block positions mode_pos after
-  // the block has been cleared.
+  // global access) and writes them to their block positions mode_pos.
   constexpr int MS = (MPAD * N2 + NTF - 1) / NTF;   // every mode of a radius fits the block
   int mp[MS];
 #pragma unroll
@@ -294,23 +379,27 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
     for (int q = 0; q < MS; ++q) pre[q] = mp[q] >= 0 ? slab[t + NTF * q] : cplx<T>{(T)0, (T)0};
   };
   if (v0 < v1) fetch(v0);
+  for (int i = t; i < BLK; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
+  __syncthreads();
   for (int v = v0; v < v1; ++v) {
-    cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
-    for (int i = t; i < MPAD * RS; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
-    __syncthreads();
+    // A is clear here (and no thread still reads it); B is no longer read
 #pragma unroll
     for (int q = 0; q < MS; ++q)
       if (mp[q] >= 0) A[mp[q]] = pre[q];
     __syncthreads();
     if (v + 1 < v1) fetch(v + 1);
-    row_dft<T, N2, P, NTF, true>(A, MPAD, tw);
-    // theta1: Toeplitz convolution per column with the spectrum of V
-    cplx<T> acc[OPT];
+    row_dft<T, N2, P, NTF, true, 0, PIN_ROWS>(A, MPAD, tw);
+    __syncthreads();
+    // theta1: Toeplitz convolution per column with the spectrum of V, A -> B
+    if constexpr (HERM) {
+      conv_herm_group<T, N2, MPAD, OPT, 0, OG>(__builtin_amdgcn_readfirstlane(og), A, B, j, w);
+    } else if (conv_act) {
+      cplx<T> acc[OPT];
 #pragma unroll
-    for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
-    if (conv_act) {
+      for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
 #pragma unroll
       for (int m = 0; m < MPAD; ++m) {
+        if (m % CONV_MB == 0 && m > 0) pin_acc<T, OPT>(acc);
         const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
 #pragma unroll
         for (int o = 0; o < OPT; ++o) {
@@ -321,19 +410,18 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
           acc[o].y = fmac(wv.y, x.x, acc[o].y);
         }
       }
-    }
-    __syncthreads();
-    if (conv_act) {
 #pragma unroll
       for (int o = 0; o < OPT; ++o)
-        if (a0 + o < MPAD) A[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
+        if (a0 + o < MPAD) B[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
     }
     __syncthreads();
-    row_dft<T, N2, P, NTF, false>(A, MPAD, tw);
+    row_dft<T, N2, P, NTF, false, BLK, PIN_ROWS>(A, MPAD, tw);
+    for (int i = t; i < BLK; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
+    __syncthreads();
+    cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
 #pragma unroll
     for (int q = 0; q < MS; ++q)
-      if (mp[q] >= 0) slab[t + NTF * q] = A[mp[q]];
-    __syncthreads();
+      if (mp[q] >= 0) slab[t + NTF * q] = A[BLK + mp[q]];
   }
 }
 

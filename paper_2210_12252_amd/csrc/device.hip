@@ -643,12 +643,12 @@ size_t angular_lds_bytes(const helic_basis_s* h, size_t elem) {
 
 // Instantiated (n_t2, padded m count, block size) of the specialised angular kernel.
 struct FastVariant { int n2, mpad, ntf; };
-constexpr FastVariant FAST_VARIANTS[] = {{16, 12, 256}, {16, 16, 256}, {64, 24, 256}, {64, 32, 256},
-                                         {81, 24, 512}, {81, 32, 512}};
+constexpr FastVariant FAST_VARIANTS[] = {{16, 12, 256}, {16, 16, 256}, {64, 24, 256}, {64, 28, 256},
+                                         {64, 32, 256}, {81, 25, 512}, {81, 32, 512}};
 
 template <typename T>
 size_t fast_lds_bytes(int n2, int mpad) {
-  return ((size_t)mpad * ang_rs(n2) + n2) * sizeof(cplx<T>);
+  return ((size_t)2 * mpad * ang_rs(n2) + n2) * sizeof(cplx<T>);
 }
 
 // Tuning knobs (environment, read once per handle): vectors per angular
@@ -670,8 +670,9 @@ template <typename T>
 helic_status set_fast_limits() {
   helic_status s;
   if ((s = set_fast_limit<T, 16, 12, 256>()) || (s = set_fast_limit<T, 16, 16, 256>()) ||
-      (s = set_fast_limit<T, 64, 24, 256>()) || (s = set_fast_limit<T, 64, 32, 256>()) ||
-      (s = set_fast_limit<T, 81, 24, 512>()) || (s = set_fast_limit<T, 81, 32, 512>()))
+      (s = set_fast_limit<T, 64, 24, 256>()) || (s = set_fast_limit<T, 64, 28, 256>()) ||
+      (s = set_fast_limit<T, 64, 32, 256>()) || (s = set_fast_limit<T, 81, 25, 512>()) ||
+      (s = set_fast_limit<T, 81, 32, 512>()))
     return s;
   return HELIC_OK;
 }
@@ -694,8 +695,9 @@ helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
   HELIC_FAST_CASE(16, 12, 256)
   HELIC_FAST_CASE(16, 16, 256)
   HELIC_FAST_CASE(64, 24, 256)
+  HELIC_FAST_CASE(64, 28, 256)
   HELIC_FAST_CASE(64, 32, 256)
-  HELIC_FAST_CASE(81, 24, 512)
+  HELIC_FAST_CASE(81, 25, 512)
   HELIC_FAST_CASE(81, 32, 512)
 #undef HELIC_FAST_CASE
   return fail(HELIC_ERR_STATE, "no specialised angular kernel for this grid");
