@@ -181,7 +181,7 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
         rec = dict(structure=s, R=round(w0.R, 3), ecut=round(w0.ecut, 3), n_eta=len(probs),
                    grid=f"{n1}x{n2}x{nr}", L_min=int(Ls.min()), L_max=int(Ls.max()),
                    kernel=angular_kernel_name(n1, n2),
-                   setup_s=round(setup, 2), tuned_vectors_per_wg=chosen, ms_per_batched_apply=round(1e3 * dt, 3),
+                   setup_s=round(setup, 2), tuned_items_per_wg=chosen, ms_per_batched_apply=round(1e3 * dt, 3),
                    vec_applies_per_s=round(len(probs) * nvec / dt, 1))
         sub = bases[::eig_every]
         eb = helic.Batch(sub)

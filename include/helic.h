@@ -208,9 +208,10 @@ helic_status helic_batch_apply(helic_batch b, const double* X, double* Y, int32_
  * X and writes Y as captured. */
 helic_status helic_batch_capture(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec);
 helic_status helic_batch_replay(helic_batch b, void* stream);
-/* Tuner: times the batched apply for each candidate number of vectors per
- * workgroup of the angular stage and keeps the fastest (*chosen, *ms_best:
- * host, may be NULL).  Synchronises `stream`. */
+/* Tuner: times the batched apply for each candidate number of (problem,
+ * radius, vector) items per workgroup of the angular stage (0: spread evenly
+ * over the workgroups the device holds at once, the default) and keeps the
+ * fastest (*chosen, *ms_best: host, may be NULL).  Synchronises `stream`. */
 helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec,
                               void* stream, int32_t* chosen, double* ms_best);
 /* Lowest opts->nev eigenpairs of every problem, solved concurrently on

@@ -307,7 +307,7 @@ __device__ __forceinline__ void conv_herm_group(int g, const cplx<T>* A, cplx<T>
 // GH[v][r][mode] holds G on entry and H on exit (complex T).  Vh[r][j][d]
 // (complex T, d = 0..2 MPAD - 2 for m' - m = d - (MPAD - 1)).  mode_pos[i] =
 // (m_i - m_min) * ang_rs(N2) + ((n_i mod N2) ^ ang_swz(N2, m_i - m_min)).
-// Work: blockIdx -> (radius, vector chunk).
+// Work: blockIdx -> ipw consecutive (problem, radius, vector) items.
 //
 // LDS holds two mode blocks: A receives the scattered slab and its theta2
 // inverse transform, the convolution writes into B, and B is transformed back
@@ -318,7 +318,7 @@ __device__ __forceinline__ void conv_herm_group(int g, const cplx<T>* A, cplx<T>
 template <typename T, int N2, int MPAD, int NTF>
 __global__ void __launch_bounds__(NTF, 512 / NTF)
 k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
-               const cplx<T>* __restrict__ tw2g, int vchunk) {
+               const cplx<T>* __restrict__ tw2g, int ipw) {
   constexpr int P = (N2 == 16) ? 4 : (N2 == 64) ? 8 : (N2 == 81) ? 9 : (N2 == 36) ? 6 : (N2 == 100) ? 10 : 0;
   static_assert(P > 0, "unsupported N2");
   constexpr int ND = 2 * MPAD - 1;
@@ -332,96 +332,106 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);          // [MPAD][RS]
   cplx<T>* B = A + BLK;                                        // [MPAD][RS]
   cplx<T>* tw = B + BLK;                                       // [N2]
-  const int nchunks = (nvec + vchunk - 1) / vchunk;
-  const int per = n_r * nchunks;
-  const int slot = xcd_slot(nprob * per);
-  if (slot >= nprob * per) return;
-  const int pi = slot / per, rem = slot - pi * per;
-  const int r = rem / nchunks, ch = rem - r * nchunks;
-  const DProb& pb = probs[pi];
-  const int n_modes = pb.n_modes;
-  const T* Vh = reinterpret_cast<const T*>(pb.Vh);
-  const int v0 = ch * vchunk, v1 = min(nvec, v0 + vchunk);
+  // Work items are (problem, radius, vector) triples in that order; each
+  // workgroup takes ipw consecutive items, as segments of one radius each
+  // (the V-hat registers and mode positions are loaded once per segment).
+  const int64_t per_prob = (int64_t)n_r * nvec;
+  const int64_t total = per_prob * nprob;
+  const int nwg = (int)((total + ipw - 1) / ipw);
+  const int slot = xcd_slot(nwg);
+  if (slot >= nwg) return;
+  int64_t it = (int64_t)slot * ipw;
+  const int64_t it_end = total < it + ipw ? total : it + ipw;
   const int t = threadIdx.x;
   for (int i = t; i < N2; i += NTF) tw[i] = tw2g[i];
   const int j = t % N2, og = t / N2;
   const bool conv_act = og < OG;
   const int a0 = og * OPT;
-  // With N2 = 64 the output group is the wave index, and the thread keeps
-  // h[d] = Vhat_j[d], d = 0 .. MPAD - 1 (the rest follows by conjugation).
-  // Otherwise it keeps the window w[q] = Vhat_j[a0 + q - (MPAD - 1)] that its
-  // outputs m' in [a0, a0 + OPT) need over all m.  Either is read once and
-  // kept in registers for every vector of the chunk.
   constexpr bool HERM = (N2 == 64);
   constexpr int NW = HERM ? MPAD : WN;
-  cplx<T> w[NW];
-  {
-    const cplx<T>* src = reinterpret_cast<const cplx<T>*>(Vh) + ((int64_t)r * N2 + j) * ND;
-    const int base = HERM ? MPAD - 1 : a0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q)
-      w[q] = (conv_act && base + q < ND) ? src[base + q] : cplx<T>{(T)0, (T)0};
-  }
-  // The mode slab of the next vector is fetched into registers while the
-  // current one is transformed: thread t owns modes t + NTF q (coalesced
-  // global access) and writes them to their block positions mode_pos.
   constexpr int MS = (MPAD * N2 + NTF - 1) / NTF;   // every mode of a radius fits the block
-  int mp[MS];
-#pragma unroll
-  for (int q = 0; q < MS; ++q) {
-    const int i = t + NTF * q;
-    mp[q] = i < n_modes ? pb.mode_pos[i] : -1;
-  }
-  cplx<T> pre[MS];
-  auto fetch = [&](int v) {
-    const cplx<T>* slab = reinterpret_cast<const cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
-#pragma unroll
-    for (int q = 0; q < MS; ++q) pre[q] = mp[q] >= 0 ? slab[t + NTF * q] : cplx<T>{(T)0, (T)0};
-  };
-  if (v0 < v1) fetch(v0);
   for (int i = t; i < BLK; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
   __syncthreads();
-  for (int v = v0; v < v1; ++v) {
-    // A is clear here (and no thread still reads it); B is no longer read
+  while (it < it_end) {
+    const int pi = (int)(it / per_prob);
+    const int rem = (int)(it - pi * per_prob);
+    const int r = rem / nvec, v0 = rem - r * nvec;
+    const int v1 = (int)(nvec < v0 + (it_end - it) ? nvec : v0 + (it_end - it));
+    it += v1 - v0;
+    const DProb& pb = probs[pi];
+    const int n_modes = pb.n_modes;
+    const T* Vh = reinterpret_cast<const T*>(pb.Vh);
+    // With N2 = 64 the output group is the wave index, and the thread keeps
+    // h[d] = Vhat_j[d], d = 0 .. MPAD - 1 (the rest follows by conjugation).
+    // Otherwise it keeps the window w[q] = Vhat_j[a0 + q - (MPAD - 1)] that its
+    // outputs m' in [a0, a0 + OPT) need over all m.  Either is read once and
+    // kept in registers for every vector of the segment.
+    cplx<T> w[NW];
+    {
+      const cplx<T>* src = reinterpret_cast<const cplx<T>*>(Vh) + ((int64_t)r * N2 + j) * ND;
+      const int base = HERM ? MPAD - 1 : a0;
 #pragma unroll
-    for (int q = 0; q < MS; ++q)
-      if (mp[q] >= 0) A[mp[q]] = pre[q];
-    __syncthreads();
-    if (v + 1 < v1) fetch(v + 1);
-    row_dft<T, N2, P, NTF, true, 0, PIN_ROWS>(A, MPAD, tw);
-    __syncthreads();
-    // theta1: Toeplitz convolution per column with the spectrum of V, A -> B
-    if constexpr (HERM) {
-      conv_herm_group<T, N2, MPAD, OPT, 0, OG>(__builtin_amdgcn_readfirstlane(og), A, B, j, w);
-    } else if (conv_act) {
-      cplx<T> acc[OPT];
-#pragma unroll
-      for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
-#pragma unroll
-      for (int m = 0; m < MPAD; ++m) {
-        if (m % CONV_MB == 0 && m > 0) pin_acc<T, OPT>(acc);
-        const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
-#pragma unroll
-        for (int o = 0; o < OPT; ++o) {
-          const cplx<T> wv = w[o - m + MPAD - 1];
-          acc[o].x = fmac(wv.x, x.x, acc[o].x);
-          acc[o].x = fmac(-wv.y, x.y, acc[o].x);
-          acc[o].y = fmac(wv.x, x.y, acc[o].y);
-          acc[o].y = fmac(wv.y, x.x, acc[o].y);
-        }
-      }
-#pragma unroll
-      for (int o = 0; o < OPT; ++o)
-        if (a0 + o < MPAD) B[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
+      for (int q = 0; q < NW; ++q)
+        w[q] = (conv_act && base + q < ND) ? src[base + q] : cplx<T>{(T)0, (T)0};
     }
-    __syncthreads();
-    row_dft<T, N2, P, NTF, false, BLK, PIN_ROWS>(A, MPAD, tw);
-    for (int i = t; i < BLK; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
-    __syncthreads();
-    cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+    // The mode slab of the next vector is fetched into registers while the
+    // current one is transformed: thread t owns modes t + NTF q (coalesced
+    // global access) and writes them to their block positions mode_pos.
+    int mp[MS];
 #pragma unroll
-    for (int q = 0; q < MS; ++q)
-      if (mp[q] >= 0) slab[t + NTF * q] = A[BLK + mp[q]];
+    for (int q = 0; q < MS; ++q) {
+      const int i = t + NTF * q;
+      mp[q] = i < n_modes ? pb.mode_pos[i] : -1;
+    }
+    cplx<T> pre[MS];
+    auto fetch = [&](int v) {
+      const cplx<T>* slab = reinterpret_cast<const cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+#pragma unroll
+      for (int q = 0; q < MS; ++q) pre[q] = mp[q] >= 0 ? slab[t + NTF * q] : cplx<T>{(T)0, (T)0};
+    };
+    fetch(v0);
+    for (int v = v0; v < v1; ++v) {
+      // A is clear here (and no thread still reads it); B is no longer read
+#pragma unroll
+      for (int q = 0; q < MS; ++q)
+        if (mp[q] >= 0) A[mp[q]] = pre[q];
+      __syncthreads();
+      if (v + 1 < v1) fetch(v + 1);
+      row_dft<T, N2, P, NTF, true, 0, PIN_ROWS>(A, MPAD, tw);
+      __syncthreads();
+      // theta1: Toeplitz convolution per column with the spectrum of V, A -> B
+      if constexpr (HERM) {
+        conv_herm_group<T, N2, MPAD, OPT, 0, OG>(__builtin_amdgcn_readfirstlane(og), A, B, j, w);
+      } else if (conv_act) {
+        cplx<T> acc[OPT];
+#pragma unroll
+        for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
+#pragma unroll
+        for (int m = 0; m < MPAD; ++m) {
+          if (m % CONV_MB == 0 && m > 0) pin_acc<T, OPT>(acc);
+          const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
+#pragma unroll
+          for (int o = 0; o < OPT; ++o) {
+            const cplx<T> wv = w[o - m + MPAD - 1];
+            acc[o].x = fmac(wv.x, x.x, acc[o].x);
+            acc[o].x = fmac(-wv.y, x.y, acc[o].x);
+            acc[o].y = fmac(wv.x, x.y, acc[o].y);
+            acc[o].y = fmac(wv.y, x.x, acc[o].y);
+          }
+        }
+#pragma unroll
+        for (int o = 0; o < OPT; ++o)
+          if (a0 + o < MPAD) B[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
+      }
+      __syncthreads();
+      row_dft<T, N2, P, NTF, false, BLK, PIN_ROWS>(A, MPAD, tw);
+      for (int i = t; i < BLK; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
+      __syncthreads();
+      cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+#pragma unroll
+      for (int q = 0; q < MS; ++q)
+        if (mp[q] >= 0) slab[t + NTF * q] = A[BLK + mp[q]];
+    }
   }
 }
 

@@ -73,29 +73,33 @@ __device__ __forceinline__ void row_dft2(cplx<T>* A, int rows, const cplx<T>* tw
 }
 
 // GH[v][r][mode] holds G on entry and H on exit (complex T).  Vs[r][i1][i2]
-// is V / (N1 N2) (T).  Work: blockIdx -> (problem, radius, vector chunk).
+// is V / (N1 N2) (T).  Work: blockIdx -> ipw consecutive (problem, radius,
+// vector) items.
 template <typename T, int N1, int N2, int PA, int PB, int NTF>
 __global__ void __launch_bounds__(NTF)
 k_angular_grid(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
-               const cplx<T>* __restrict__ tw2g, int vchunk) {
+               const cplx<T>* __restrict__ tw2g, int ipw) {
   constexpr int RS = grid_rs(N2);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);   // [N1][RS]
   cplx<T>* tw = A + N1 * RS;                            // [N2]
-  const int nchunks = (nvec + vchunk - 1) / vchunk;
-  const int per = n_r * nchunks;
-  const int slot = xcd_slot(nprob * per);
-  if (slot >= nprob * per) return;
-  const int pi = slot / per, rem = slot - pi * per;
-  const int r = rem / nchunks, ch = rem - r * nchunks;
-  const DProb& pb = probs[pi];
-  const int n_modes = pb.n_modes;
-  const DMode* modes = pb.modes;
-  const T* vr = reinterpret_cast<const T*>(pb.Vs) + (int64_t)r * N1 * N2;
+  const int64_t per_prob = (int64_t)n_r * nvec;
+  const int64_t total = per_prob * nprob;
+  const int nwg = (int)((total + ipw - 1) / ipw);
+  const int slot = xcd_slot(nwg);
+  if (slot >= nwg) return;
   const int t = threadIdx.x;
   for (int i = t; i < N2; i += NTF) tw[i] = tw2g[i];
-  const int v0 = ch * vchunk, v1 = min(nvec, v0 + vchunk);
-  for (int v = v0; v < v1; ++v) {
+  const int64_t it0 = (int64_t)slot * ipw;
+  const int64_t it1 = total < it0 + ipw ? total : it0 + ipw;
+  for (int64_t it = it0; it < it1; ++it) {
+    const int pi = (int)(it / per_prob);
+    const int rem = (int)(it - pi * per_prob);
+    const int r = rem / nvec, v = rem - r * nvec;
+    const DProb& pb = probs[pi];
+    const int n_modes = pb.n_modes;
+    const DMode* modes = pb.modes;
+    const T* vr = reinterpret_cast<const T*>(pb.Vs) + (int64_t)r * N1 * N2;
     cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
     for (int i = t; i < N1 * RS; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
     __syncthreads();

@@ -111,6 +111,13 @@ helic_status build(helic_basis_s* h) {
     grp.nmodes = (int32_t)h->modes.size() - grp.mode0;
     grp.nrows = row - grp.row0;
     if (grp.nmodes == 0) continue;
+    // Storage order of the group's modes (the slab layout of the
+    // intermediates; rows keep the compact order through row0): K
+    // descending, so the 8 modes of a 16-column MFMA tile of the radial
+    // stages have similar K, and a tile's work ends at the K of its first
+    // mode (the radial kernels rely on this order).
+    std::stable_sort(h->modes.begin() + grp.mode0, h->modes.end(),
+                     [](const Mode& a, const Mode& b) { return a.K > b.K; });
     grp.zeros.assign(z.begin(), z.begin() + grp.Kmax);
     h->groups.push_back(grp);
   }

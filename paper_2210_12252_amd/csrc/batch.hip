@@ -241,7 +241,7 @@ helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t
   if (s != HELIC_OK) return s;
   if ((s = batch_workspace(b, nvec, prec == HELIC_FP64 ? 8 : 4))) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int cands[] = {1, 2, 4, 8, 16};
+  const int cands[] = {0, 2, 4, 8, 16};   // 0: even split over the resident workgroups
   hipEvent_t e0, e1;
   HIP_TRY_B(hipEventCreate(&e0));
   HIP_TRY_B(hipEventCreate(&e1));

@@ -25,6 +25,14 @@ namespace helic {
 // widest group; up to 16 steps the table fragments of the wave's next tile
 // are fetched into registers while the current tile's MFMAs run (beyond, the
 // doubled registers cost more occupancy than the prefetch gains).
+// Largest K among modes 8 c .. 8 c + 7 of a group (one 16-column MFMA tile),
+// for lane c < 64: output tiles beyond it are empty and contraction steps
+// beyond it multiply zeros.  The basis stores a group's modes by K
+// descending, so it is the K of the tile's first mode.
+__device__ __forceinline__ int tile_kmax(const DMode* gm, int nmodes, int lane) {
+  return 8 * lane < nmodes ? gm[8 * lane].K : 0;
+}
+
 template <typename T, int KS>
 __global__ void __launch_bounds__(NT)
 k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, int nvec, int ngroups, int n_r,
@@ -64,6 +72,10 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   }
   __syncthreads();
   T* gv = GH + (slab_off(pb, nvec, n_r, v, 0) + gr.mode0) * 2;
+  // k steps of column tile c: lane c holds the largest K of the tile's 8
+  // modes; groups of more than 64 tiles use the group's largest K throughout
+  const int ktile = tile_kmax(pb.modes + gr.mode0, gr.nmodes, lane);
+  auto tile_ks = [&](int c) { return nct <= 64 ? (__builtin_amdgcn_readlane(ktile, c) + 3) / 4 : nks; };
   typedef typename Mfma<T>::acc_t acc_t;
   const T* brow = Bs + (lane >> 4) * hs + (lane & 15);
   for (int rt = wave; rt < nrt; rt += NT / 64) {
@@ -75,16 +87,17 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
     } else {
       fetch(rt, a);
     }
-    // two column tiles at a time: independent accumulators interleave
+    // two column tiles at a time: independent accumulators interleave; rows
+    // beyond a mode's own K are zero in Bs
     for (int ct = 0; ct < nct; ct += 2) {
       const bool two = ct + 1 < nct;
+      const int ks0 = tile_ks(ct);
+      const int ks1 = two ? tile_ks(ct + 1) : 0;
       acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        if (s < nks) {
-          acc0 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct], acc0);
-          if (two) acc1 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct + 16], acc1);
-        }
+        if (s < ks0) acc0 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct], acc0);
+        if (s < ks1) acc1 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct + 16], acc1);
       }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -283,6 +296,7 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
   double* yv = Y + col_off(pb, ldy, nvec, v) * 2;
   typedef typename Mfma<T>::acc_t acc_t;
   const int nchunk = (n_r + RC - 1) / RC;
+  const int ktile = tile_kmax(modes + gr.mode0, gr.nmodes, lane);   // see k_radial_inverse
   T hreg[RW][CB], areg[KTM];
   auto fetch = [&](int r0) {
 #pragma unroll
@@ -316,6 +330,7 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
   for (int tbase = 0; tbase < ntiles; tbase += (NT / 64) * TM) {
     acc_t acc[TM];
     int aoff[TM], boff[TM];
+    bool live[TM];   // the tile has rows k < K for some of its modes
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       acc[i] = acc_t{0, 0, 0, 0};
@@ -323,6 +338,7 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
       const int kt = t / nct, ct = t - kt * nct;
       aoff[i] = kt * (RC / 4) * 64 + lane;
       boff[i] = (lane >> 4) * hs + 16 * ct + (lane & 15);
+      live[i] = t < ntiles && (nct > 64 || 16 * kt < __builtin_amdgcn_readlane(ktile, ct));
     }
     fetch(0);
     for (int c = 0; c < nchunk; ++c) {
@@ -333,7 +349,7 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
       const int steps = min(RC / 4, nrs - c * (RC / 4));
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        if (tbase + wave + (NT / 64) * i < ntiles) {
+        if (live[i]) {
 #pragma unroll
           for (int s = 0; s < RC / 4; ++s)
             if (s < steps) acc[i] = Mfma<T>::op(As[aoff[i] + s * 64], Hs[boff[i] + 4 * s * hs], acc[i]);
@@ -343,7 +359,7 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int t = tbase + wave + (NT / 64) * i;
-      if (t >= ntiles) continue;
+      if (!live[i]) continue;
       const int kt = t / nct, ct = t - kt * nct;
       const int col = 16 * ct + (lane & 15);
       const int c = col >> 1, ri = col & 1;
@@ -677,18 +693,53 @@ helic_status set_fast_limits() {
   return HELIC_OK;
 }
 
+// Resident workgroups of the chosen angular kernel on the whole device.
+template <typename T>
+int fast_slots(int n2, int mpad, int ncu) {
+  int nb = 0;
+  const size_t lds = fast_lds_bytes<T>(n2, mpad);
+#define HELIC_OCC_CASE(N2_, MP_, NTF_)                                                                 \
+  if (n2 == N2_ && mpad == MP_)                                                                       \
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_fast<T, N2_, MP_, NTF_>, NTF_, lds);
+  HELIC_OCC_CASE(16, 12, 256)
+  HELIC_OCC_CASE(16, 16, 256)
+  HELIC_OCC_CASE(64, 24, 256)
+  HELIC_OCC_CASE(64, 28, 256)
+  HELIC_OCC_CASE(64, 32, 256)
+  HELIC_OCC_CASE(81, 25, 512)
+  HELIC_OCC_CASE(81, 32, 512)
+#undef HELIC_OCC_CASE
+  return std::max(1, nb) * std::max(1, ncu);
+}
+
+// Work split of the specialised angular kernels: ls.vchunk items per
+// workgroup if set, else the fewest items per workgroup that let every
+// workgroup be resident at once (one wave of workgroups, no tail).
+template <typename T>
+int angular_items_per_wg(const LaunchSet& ls, int nvec) {
+  if (ls.vchunk > 0) return ls.vchunk;
+  const int64_t total = (int64_t)ls.nprob * ls.n_r * nvec;
+  const int64_t slots = std::max(1, std::is_same<T, double>::value ? ls.ang_slots64 : ls.ang_slots32);
+  return (int)std::max<int64_t>(1, (total + slots - 1) / slots);
+}
+
+inline unsigned angular_grid_size(const LaunchSet& ls, int nvec, int ipw) {
+  const int64_t total = (int64_t)ls.nprob * ls.n_r * nvec;
+  const int64_t nwg = (total + ipw - 1) / ipw;
+  return (unsigned)(8 * ((nwg + 7) / 8));
+}
+
 template <typename T>
 helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
   const DProb* probs = std::is_same<T, double>::value ? ls.probs64 : ls.probs32;
   const cplx<T>* tw2 = (const cplx<T>*)(std::is_same<T, double>::value ? ls.tw2_64 : ls.tw2_32);
-  const int vchunk = ls.vchunk;
-  const int work = ls.nprob * ls.n_r * ((nvec + vchunk - 1) / vchunk);
-  const dim3 grid(8 * ((work + 7) / 8));
+  const int ipw = angular_items_per_wg<T>(ls, nvec);
+  const dim3 grid(angular_grid_size(ls, nvec, ipw));
   const size_t lds = fast_lds_bytes<T>(ls.n_t2, ls.fast_mpad);
 #define HELIC_FAST_CASE(N2_, MP_, NTF_)                                                                   \
   if (ls.n_t2 == N2_ && ls.fast_mpad == MP_) {                                                          \
     hipLaunchKernelGGL((k_angular_fast<T, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, gh, ls.nprob, nvec, \
-                       ls.n_r, probs, tw2, vchunk);                                                     \
+                       ls.n_r, probs, tw2, ipw);                                                        \
     HIP_TRY(hipGetLastError());                                                                         \
     return HELIC_OK;                                                                                    \
   }
@@ -736,17 +787,34 @@ helic_status set_grid_limits() {
 }
 
 template <typename T>
+int grid_slots(int n1, int n2, int ncu) {
+  int nb = 0;
+  const size_t lds = grid_lds_bytes<T>(n1, n2);
+#define HELIC_OCC_CASE(N1_, N2_, PA_, PB_)                                                             \
+  if (n1 == N1_ && n2 == N2_)                                                                         \
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_grid<T, N1_, N2_, PA_, PB_, GRID_NTF>, \
+                                                       GRID_NTF, lds);
+  HELIC_OCC_CASE(20, 96, 8, 12)
+  HELIC_OCC_CASE(20, 120, 8, 15)
+  HELIC_OCC_CASE(24, 120, 8, 15)
+  HELIC_OCC_CASE(24, 135, 9, 15)
+  HELIC_OCC_CASE(27, 144, 12, 12)
+  HELIC_OCC_CASE(27, 180, 12, 15)
+#undef HELIC_OCC_CASE
+  return std::max(1, nb) * std::max(1, ncu);
+}
+
+template <typename T>
 helic_status launch_grid(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
   const DProb* probs = std::is_same<T, double>::value ? ls.probs64 : ls.probs32;
   const cplx<T>* tw2 = (const cplx<T>*)(std::is_same<T, double>::value ? ls.tw2_64 : ls.tw2_32);
-  const int vchunk = ls.vchunk;
-  const int work = ls.nprob * ls.n_r * ((nvec + vchunk - 1) / vchunk);
-  const dim3 grid(8 * ((work + 7) / 8));
+  const int ipw = angular_items_per_wg<T>(ls, nvec);
+  const dim3 grid(angular_grid_size(ls, nvec, ipw));
   const size_t lds = grid_lds_bytes<T>(ls.n_t1, ls.n_t2);
 #define HELIC_GRID_CASE(N1_, N2_, PA_, PB_)                                                              \
   if (ls.n_t1 == N1_ && ls.n_t2 == N2_) {                                                               \
     hipLaunchKernelGGL((k_angular_grid<T, N1_, N2_, PA_, PB_, GRID_NTF>), grid, dim3(GRID_NTF), lds, st, gh, \
-                       ls.nprob, nvec, ls.n_r, probs, tw2, vchunk);                                     \
+                       ls.nprob, nvec, ls.n_r, probs, tw2, ipw);                                        \
     HIP_TRY(hipGetLastError());                                                                         \
     return HELIC_OK;                                                                                    \
   }
@@ -856,12 +924,9 @@ helic_status ensure_device(helic_basis_s* h) {
       (s = upload(tw1, &d->tw1)) || (s = upload(tw2, &d->tw2)) || (s = upload(tw1f, &d->tw1f)) ||
       (s = upload(tw2f, &d->tw2f)))
     return s;
-  // vectors per angular workgroup: the largest power of two (<= 16) that
-  // still gives >= 1024 workgroups for a 64-vector launch (measured best on
-  // the nanotube and nanowire grids); HELIC_VCHUNK overrides
-  int vc = 16;
-  while (vc > 1 && (int64_t)h->n_r * 64 / vc < 1024) vc /= 2;
-  d->vchunk = env_int("HELIC_VCHUNK", vc, 1, 64);
+  // items per angular workgroup: 0 spreads a launch evenly over the
+  // resident workgroups; HELIC_VCHUNK fixes it
+  d->vchunk = env_int("HELIC_VCHUNK", 0, 0, 64);
   d->apply_chunk = env_int("HELIC_APPLY_CHUNK", APPLY_CHUNK, 1, APPLY_CHUNK);
   d->plan1 = make_plan(h->n_t1, h->fac1);
   d->plan2 = make_plan(h->n_t2, h->fac2);
@@ -887,8 +952,16 @@ helic_status ensure_device(helic_basis_s* h) {
         d->grid_var = true;
     if (d->grid_var && ((s = set_grid_limits<double>()) || (s = set_grid_limits<float>()))) return s;
   }
+  int ncu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d->device));
+  if (d->grid_var) {
+    d->ang_slots64 = grid_slots<double>(h->n_t1, h->n_t2, ncu);
+    d->ang_slots32 = grid_slots<float>(h->n_t1, h->n_t2, ncu);
+  }
   if (d->fast_mpad) {
     if ((s = set_fast_limits<double>()) || (s = set_fast_limits<float>())) return s;
+    d->ang_slots64 = fast_slots<double>(h->n_t2, d->fast_mpad, ncu);
+    d->ang_slots32 = fast_slots<float>(h->n_t2, d->fast_mpad, ncu);
     const int rs = ang_rs(h->n_t2);
     std::vector<int32_t> mp(h->modes.size());
     for (size_t i = 0; i < h->modes.size(); ++i) {
@@ -953,6 +1026,8 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.fast_mpad = d->fast_mpad;
   ls.grid_var = d->grid_var;
   ls.vchunk = d->vchunk;
+  ls.ang_slots64 = d->ang_slots64;
+  ls.ang_slots32 = d->ang_slots32;
   ls.rows1 = d->rows1;
   ls.nrows1 = (int)h->rows1.size();
   ls.plan1 = d->plan1;

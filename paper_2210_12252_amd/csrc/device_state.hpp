@@ -39,7 +39,9 @@ struct DeviceState {
   int fast_ntf = 256;
   int m_min = 0, m_count = 0;
   bool grid_var = false;          // the register-FFT angular kernel serves this grid
-  int vchunk = 8;                 // vectors per workgroup of the specialised angular kernels
+  int vchunk = 0;                 // (problem, radius, vector) items per workgroup of the specialised
+                                  // angular kernels; 0: spread evenly over the resident workgroups
+  int ang_slots64 = 1, ang_slots32 = 1;   // resident workgroups of that kernel on the device
   int apply_chunk = APPLY_CHUNK;  // vectors per launch of the three stages
   int32_t* mode_pos = nullptr;    // mode -> (m - m_min) * ang_rs(n_t2) + ((n mod n_t2) ^ ang_swz)
   double* Vh = nullptr;           // [n_r][n_t2][2 * fast_mpad - 1] complex
@@ -70,7 +72,8 @@ struct LaunchSet {
   int nprob = 1;
   int n_r = 0, n_t1 = 0, n_t2 = 0;
   size_t lds_inv64 = 0, lds_fwd64 = 0, lds_ang64 = 0, lds_fast64 = 0;   // FP32 uses half
-  int fast_mpad = 0, vchunk = 8;
+  int fast_mpad = 0, vchunk = 0;
+  int ang_slots64 = 1, ang_slots32 = 1;
   bool grid_var = false;
   int inv_ks = 24;                  // register k steps of the radial inverse stage
   int fwd_tmax = 4;                 // radial forward variant: register tiles per wave; 0, -1 = pipelined
