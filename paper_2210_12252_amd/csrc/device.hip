@@ -34,7 +34,7 @@ __device__ __forceinline__ int tile_kmax(const DMode* gm, int nmodes, int lane) 
 }
 
 template <typename T, int KS>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, KS <= 12 ? 4 : 3)
 k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, int nvec, int ngroups, int n_r,
                  const DGroup* __restrict__ groups, const DProb* __restrict__ probs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -271,6 +271,8 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
                     int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* __restrict__ groups,
                     const DProb* __restrict__ probs, int add_kinetic) {
   constexpr int RC = FWD_PF_RC, RW = FWD_PF_RC / (NT / 64), KTM = FWD_PF_KT;
+  constexpr int SPW = (RC / 4) / (NT / 64);   // table steps (of 4 radii) each wave stages per chunk
+  static_assert(SPW >= 1 && SPW * (NT / 64) * 4 == RC, "chunk must split evenly over the waves");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Hs = reinterpret_cast<T*>(smem_raw);
   const int slot = xcd_slot(ngroups * nvec);
@@ -297,7 +299,7 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
   typedef typename Mfma<T>::acc_t acc_t;
   const int nchunk = (n_r + RC - 1) / RC;
   const int ktile = tile_kmax(modes + gr.mode0, gr.nmodes, lane);   // see k_radial_inverse
-  T hreg[RW][CB], areg[KTM];
+  T hreg[RW][CB], areg[KTM][SPW];
   auto fetch = [&](int r0) {
 #pragma unroll
     for (int a = 0; a < RW; ++a) {
@@ -309,11 +311,14 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
         hreg[a][b] = (r < n_r && col < ncol) ? src[col] : (T)0;
       }
     }
-    // table fragments: thread (wave, lane) takes step `wave` of every k tile
-    const int rs = r0 / 4 + wave;
+    // table fragments: thread (wave, lane) takes steps wave * SPW + e of
+    // every k tile
+    const int rs0 = r0 / 4 + wave * SPW;
 #pragma unroll
     for (int kt = 0; kt < KTM; ++kt)
-      areg[kt] = (kt < nkt && rs < nrs) ? tg[((int64_t)kt * nrs + rs) * 64 + lane] : (T)0;
+#pragma unroll
+      for (int e = 0; e < SPW; ++e)
+        areg[kt][e] = (kt < nkt && rs0 + e < nrs) ? tg[((int64_t)kt * nrs + rs0 + e) * 64 + lane] : (T)0;
   };
   auto store = [&]() {
 #pragma unroll
@@ -325,7 +330,10 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
       }
 #pragma unroll
     for (int kt = 0; kt < KTM; ++kt)
-      if (kt < nkt) As[(kt * (RC / 4) + wave) * 64 + lane] = areg[kt];
+      if (kt < nkt) {
+#pragma unroll
+        for (int e = 0; e < SPW; ++e) As[(kt * (RC / 4) + wave * SPW + e) * 64 + lane] = areg[kt][e];
+      }
   };
   for (int tbase = 0; tbase < ntiles; tbase += (NT / 64) * TM) {
     acc_t acc[TM];
@@ -574,11 +582,11 @@ size_t fwd_pf_lds_bytes(const helic_basis_s* h, size_t elem) {
   return ((size_t)FWD_PF_RC * lds_stride(h->max_colpad) + (size_t)nkt_max * (FWD_PF_RC / 4) * 64) * elem;
 }
 
-// Register k steps of the inverse kernel: the smallest of 8, 16, 24 that
-// covers the widest group.
+// Register k steps of the inverse kernel: the smallest of 8, 12, 16, 24 that
+// covers the widest group (up to 12 the kernel fits four workgroups per CU).
 int inv_ks_for(const helic_basis_s* h) {
   const int nks = h->max_kpad / 4;
-  return nks <= 8 ? 8 : nks <= 16 ? 16 : 24;
+  return nks <= 8 ? 8 : nks <= 12 ? 12 : nks <= 16 ? 16 : 24;
 }
 
 template <typename T>
@@ -587,6 +595,9 @@ void launch_radial_inverse(int ks, int nwg, size_t lds, hipStream_t st, const do
   if (ks <= 8)
     hipLaunchKernelGGL((k_radial_inverse<T, 8>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r, groups,
                        probs);
+  else if (ks <= 12)
+    hipLaunchKernelGGL((k_radial_inverse<T, 12>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r,
+                       groups, probs);
   else if (ks <= 16)
     hipLaunchKernelGGL((k_radial_inverse<T, 16>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r,
                        groups, probs);
@@ -832,6 +843,7 @@ template <typename T>
 helic_status set_lds_limits() {
   const int lim = 160 * 1024;
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T, 12>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse<T, 24>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
