@@ -258,6 +258,14 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
   }
 }
 
+// LDS of the pipelined forward kernel: the chunk staging (RC slab rows of
+// stride hs, then kt_max x RC/4 table fragments), padded to 16 bytes, then
+// the per-group mode table and kappa x rows.
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+__host__ __device__ constexpr size_t fwd_pf_stage_bytes(int rc, int hs, int kt_max, size_t elem) {
+  return align16(((size_t)rc * hs + (size_t)kt_max * (rc / 4) * 64) * elem);
+}
+
 // Radial forward stage with software pipelining: the slab rows and table
 // fragments of the next FWD_PF_RC radii are fetched into registers while the
 // MFMAs run on the current ones from LDS, so global-memory latency overlaps
@@ -269,7 +277,9 @@ template <typename T, int CB, int TM>
 __global__ void __launch_bounds__(NT)
 k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
                     int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* __restrict__ groups,
-                    const DProb* __restrict__ probs, int add_kinetic) {
+                    const DProb* __restrict__ probs, int flags) {
+  // flags bit 0: add kappa x; bit 1: stage kappa x of the group's rows in LDS
+  const bool add_kinetic = flags & 1, kx_lds = (flags & 3) == 3;
   constexpr int RC = FWD_PF_RC, RW = FWD_PF_RC / (NT / 64), KTM = FWD_PF_KT;
   constexpr int SPW = (RC / 4) / (NT / 64);   // table steps (of 4 radii) each wave stages per chunk
   static_assert(SPW >= 1 && SPW * (NT / 64) * 4 == RC, "chunk must split evenly over the waves");
@@ -285,6 +295,11 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
   const int colpad = 16 * nct;
   const int hs = lds_stride(colpad);
   T* As = Hs + RC * hs;     // [k tile][step][64]
+  // the group's mode table (first row relative to the group, K) and, when
+  // LDS allows, kappa x of its rows, staged at the start so the epilogue
+  // does not wait on global memory after the contractions
+  int32_t* mtab = reinterpret_cast<int32_t*>(smem_raw + fwd_pf_stage_bytes(RC, hs, KTM, sizeof(T)));
+  double* kxs = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(mtab) + align16(8 * (size_t)gr.nmodes));
   const int nkt = (gr.Kmax + 15) / 16;
   const int ntiles = nkt * nct;
   const int nrs = (n_r + 3) / 4;
@@ -296,6 +311,13 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
   const double* kappa = pb.kappa;
   const double* xv = add_kinetic ? X + col_off(pb, ldx, nvec, v) * 2 : nullptr;
   double* yv = Y + col_off(pb, ldy, nvec, v) * 2;
+  for (int c = threadIdx.x; c < gr.nmodes; c += NT) {
+    const DMode md = modes[gr.mode0 + c];
+    mtab[2 * c] = (int32_t)(md.row0 - gr.row0);
+    mtab[2 * c + 1] = md.K;
+  }
+  if (kx_lds)
+    for (int i = threadIdx.x; i < 2 * gr.nrows; i += NT) kxs[i] = kappa[gr.row0 + (i >> 1)] * xv[2 * gr.row0 + i];
   typedef typename Mfma<T>::acc_t acc_t;
   const int nchunk = (n_r + RC - 1) / RC;
   const int ktile = tile_kmax(modes + gr.mode0, gr.nmodes, lane);   // see k_radial_inverse
@@ -372,15 +394,16 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
       const int col = 16 * ct + (lane & 15);
       const int c = col >> 1, ri = col & 1;
       if (c >= gr.nmodes) continue;
-      const DMode md = modes[gr.mode0 + c];
+      const int roff = mtab[2 * c], K = mtab[2 * c + 1];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 16 * kt + Mfma<T>::row(lane, j);
-        if (k < md.K) {
-          const int64_t row = md.row0 + k;
+        if (k < K) {
+          const int lr = roff + k;
           double y = (double)acc[i][j];
-          if (add_kinetic) y += kappa[row] * xv[2 * row + ri];
-          yv[2 * row + ri] = y;
+          if (kx_lds) y += kxs[2 * lr + ri];
+          else if (add_kinetic) y += kappa[gr.row0 + lr] * xv[2 * (gr.row0 + lr) + ri];
+          yv[2 * (gr.row0 + lr) + ri] = y;
         }
       }
     }
@@ -571,16 +594,26 @@ int fwd_tmax_for(int tiles) {
 
 // The pipelined radial forward kernel (variant 0) when the basis fits its
 // register staging; HELIC_FWD_PF=0 keeps the plain one.
+size_t fwd_pf_lds_bytes(const helic_basis_s* h, size_t elem, bool kx_lds) {
+  size_t tail = 0;   // mode table (and kappa x rows) of the largest group
+  for (const Group& g : h->groups)
+    tail = std::max(tail, align16(8 * (size_t)g.nmodes) + (kx_lds ? 16 * (size_t)g.nrows : 0));
+  return fwd_pf_stage_bytes(FWD_PF_RC, lds_stride(h->max_colpad), FWD_PF_KT, elem) + tail;
+}
+
+// kappa x is staged in LDS when that still leaves room for the workgroups
+// per CU the kernel's registers allow (two in FP64, three in FP32).
+bool fwd_pf_kx_lds(const helic_basis_s* h, size_t elem) {
+  return fwd_pf_lds_bytes(h, elem, true) <= (size_t)160 * 1024 / (elem == 8 ? 2 : 3);
+}
+
 bool fwd_pf_ok(const helic_basis_s* h) {
   if (const char* e = std::getenv("HELIC_FWD_PF"))
     if (e[0] == '0') return false;
-  return h->max_colpad <= FWD_PF_COLS && (h->max_kpad + 15) / 16 <= FWD_PF_KT;
+  return h->max_colpad <= FWD_PF_COLS && (h->max_kpad + 15) / 16 <= FWD_PF_KT &&
+         fwd_pf_lds_bytes(h, sizeof(double), false) <= 160 * 1024;
 }
 
-size_t fwd_pf_lds_bytes(const helic_basis_s* h, size_t elem) {
-  const int nkt_max = (h->max_kpad + 15) / 16;
-  return ((size_t)FWD_PF_RC * lds_stride(h->max_colpad) + (size_t)nkt_max * (FWD_PF_RC / 4) * 64) * elem;
-}
 
 // Register k steps of the inverse kernel: the smallest of 8, 12, 16, 24 that
 // covers the widest group (up to 12 the kernel fits four workgroups per CU).
@@ -1030,9 +1063,13 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.fwd_tmax = fwd_tmax_for(fwd_tiles_max(h));
   ls.fwd_tmax_plain = ls.fwd_tmax;
   ls.lds_fwd_plain64 = ls.lds_fwd64;
+  ls.lds_fwd32 = ls.lds_fwd64 / 2;
   if (ls.fwd_tmax == 4 && fwd_pf_ok(h)) {
     ls.fwd_tmax = h->max_colpad <= 128 ? 0 : -1;
-    ls.lds_fwd64 = fwd_pf_lds_bytes(h, sizeof(double));
+    ls.kx_lds64 = fwd_pf_kx_lds(h, sizeof(double));
+    ls.kx_lds32 = fwd_pf_kx_lds(h, sizeof(float));
+    ls.lds_fwd64 = fwd_pf_lds_bytes(h, sizeof(double), ls.kx_lds64);
+    ls.lds_fwd32 = fwd_pf_lds_bytes(h, sizeof(float), ls.kx_lds32);
   }
   ls.lds_ang64 = angular_lds_bytes(h, sizeof(double));
   ls.fast_mpad = d->fast_mpad;
@@ -1117,8 +1154,9 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
     HIP_TRY(hipGetLastError());
   }
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-  launch_radial_forward<T>(ls.fwd_tmax, wg_rad, ls.lds_fwd64 / sc, st, gh, X, ldx, Y, ldy, nvec, ls.ngroups, ls.n_r,
-                           ls.groups, probs, mode);
+  const bool kx_lds = ls.fwd_tmax <= 0 && mode && (f64 ? ls.kx_lds64 : ls.kx_lds32);
+  launch_radial_forward<T>(ls.fwd_tmax, wg_rad, f64 ? ls.lds_fwd64 : ls.lds_fwd32, st, gh, X, ldx, Y, ldy, nvec,
+                           ls.ngroups, ls.n_r, ls.groups, probs, mode | (kx_lds ? 2 : 0));
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   return HELIC_OK;

@@ -80,6 +80,8 @@ struct LaunchSet {
                                     // with 2 or 4 staged columns per lane
   int fwd_tmax_plain = 4;           // the non-pipelined variant and its LDS bytes (FP64)
   size_t lds_fwd_plain64 = 0;
+  size_t lds_fwd32 = 0;             // LDS bytes of the chosen forward variant in FP32
+  bool kx_lds64 = false, kx_lds32 = false;   // pipelined forward stages kappa x in LDS
   const int32_t* rows1 = nullptr;
   int nrows1 = 0;
   FftPlan plan1{}, plan2{};
