@@ -304,6 +304,14 @@ __device__ __forceinline__ void conv_herm_group(int g, const cplx<T>* A, cplx<T>
 }
 
 // ---------------------------------------------------------------- the kernel
+// Workgroups per CU the register allocation is held to: 16 waves per CU in
+// FP32 where the block fits 128 registers without spilling (row addresses
+// then recomputed per call, see row_dft), else 8.
+template <typename T, int N2, int MPAD, int NTF>
+constexpr int ang_min_wgs() {
+  return (sizeof(T) == 4 && !(N2 == 64 && MPAD > 24) ? 1024 : 512) / NTF;
+}
+
 // GH[v][r][mode] holds G on entry and H on exit (complex T).  Vh[r][j][d]
 // (complex T, d = 0..2 MPAD - 2 for m' - m = d - (MPAD - 1)).  mode_pos[i] =
 // (m_i - m_min) * ang_rs(N2) + ((n_i mod N2) ^ ang_swz(N2, m_i - m_min)).
@@ -316,7 +324,7 @@ __device__ __forceinline__ void conv_herm_group(int g, const cplx<T>* A, cplx<T>
 // inverse row transforms, after the convolution and after the forward row
 // transforms.
 template <typename T, int N2, int MPAD, int NTF>
-__global__ void __launch_bounds__(NTF, 512 / NTF)
+__global__ void __launch_bounds__(NTF, (ang_min_wgs<T, N2, MPAD, NTF>()))
 k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
                const cplx<T>* __restrict__ tw2g, int ipw) {
   constexpr int P = (N2 == 16) ? 4 : (N2 == 64) ? 8 : (N2 == 81) ? 9 : (N2 == 36) ? 6 : (N2 == 100) ? 10 : 0;
@@ -328,7 +336,7 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
   constexpr int RS = ang_rs(N2);                               // padded row stride of A and B
   constexpr int BLK = MPAD * RS;
   constexpr int WN = OPT + MPAD - 1;                           // Vhat window of one thread
-  constexpr bool PIN_ROWS = MPAD >= 32 && sizeof(T) == 8;      // see row_dft
+  constexpr bool PIN_ROWS = sizeof(T) == 4 || MPAD >= 32;       // see row_dft and ang_min_wgs
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);          // [MPAD][RS]
   cplx<T>* B = A + BLK;                                        // [MPAD][RS]
   cplx<T>* tw = B + BLK;                                       // [N2]

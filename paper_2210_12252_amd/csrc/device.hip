@@ -274,7 +274,7 @@ __host__ __device__ constexpr size_t fwd_pf_stage_bytes(int rc, int hs, int kt_m
 // w * RC/4 ... of each chunk, lane l columns l + 64 b (b < CB), so colpad
 // <= 64 CB; at most FWD_PF_KT k tiles per group.
 template <typename T, int CB, int TM>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 2 : 1)
 k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
                     int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* __restrict__ groups,
                     const DProb* __restrict__ probs, int flags) {
