@@ -25,6 +25,16 @@ namespace helic {
 // widest group; up to 16 steps the table fragments of the wave's next tile
 // are fetched into registers while the current tile's MFMAs run (beyond, the
 // doubled registers cost more occupancy than the prefetch gains).
+// Value of lane l ^ 1 (DPP quad permutation 1, 0, 3, 2; all lanes active).
+__device__ __forceinline__ double swap_lane_pairs(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float swap_lane_pairs(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
 // Largest K among modes 8 c .. 8 c + 7 of a group (one 16-column MFMA tile),
 // for lane c < 64: output tiles beyond it are empty and contraction steps
 // beyond it multiply zeros.  The basis stores a group's modes by K
@@ -62,13 +72,14 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   if constexpr (PF) fetch(wave, anext);   // in flight while the coefficients are staged
   for (int i = threadIdx.x; i < kpad * hs; i += NT) Bs[i] = (T)0;
   __syncthreads();
-  const double* xv = X + col_off(pb, ldx, nvec, v) * 2 + gr.row0 * 2;
+  // one row (re, im) per thread and access
+  const double2* xv = reinterpret_cast<const double2*>(X + col_off(pb, ldx, nvec, v) * 2) + gr.row0;
   const int32_t* row_ck = pb.row_ck;
-  const int nvals = (int)(2 * gr.nrows);
-  for (int i = threadIdx.x; i < nvals; i += NT) {
-    const int ck = row_ck[gr.row0 + (i >> 1)];
+  for (int i = threadIdx.x; i < (int)gr.nrows; i += NT) {
+    const int ck = row_ck[gr.row0 + i];
     const int c = ck >> 16, k = ck & 0xffff;
-    Bs[k * hs + 2 * c + (i & 1)] = (T)xv[i];
+    const double2 x = xv[i];
+    *reinterpret_cast<typename Vec2<T>::type*>(Bs + k * hs + 2 * c) = {(T)x.x, (T)x.y};
   }
   __syncthreads();
   T* gv = GH + (slab_off(pb, nvec, n_r, v, 0) + gr.mode0) * 2;
@@ -99,14 +110,24 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
         if (s < ks0) acc0 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct], acc0);
         if (s < ks1) acc1 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct + 16], acc1);
       }
+      // lanes 2j and 2j + 1 hold re and im of one mode for the same four rows;
+      // after a swap across the pair each lane stores two (re, im) pairs
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
+        const acc_t& ac = q == 0 ? acc0 : acc1;
+        T sw[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sw[i] = swap_lane_pairs(ac[i]);
         const int col = 16 * (ct + q) + (lane & 15);
         if (col < ncol && (q == 0 || two)) {
+          const bool odd = lane & 1;
+          T* dst = gv + (col & ~1);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = 16 * rt + Mfma<T>::row(lane, i);
-            if (r < n_r) gv[(int64_t)r * pb.n_modes * 2 + col] = q == 0 ? acc0[i] : acc1[i];
+          for (int h = 0; h < 2; ++h) {
+            const int r = 16 * rt + Mfma<T>::row(lane, odd ? 2 * h + 1 : 2 * h);
+            const T re = odd ? sw[2 * h + 1] : ac[2 * h];
+            const T im = odd ? ac[2 * h + 1] : sw[2 * h];
+            if (r < n_r) *reinterpret_cast<typename Vec2<T>::type*>(dst + (int64_t)r * pb.n_modes * 2) = {re, im};
           }
         }
       }
@@ -271,10 +292,17 @@ __host__ __device__ constexpr size_t fwd_pf_stage_bytes(int rc, int hs, int kt_m
 // MFMAs run on the current ones from LDS, so global-memory latency overlaps
 // the contractions.  Same tiles, layout and epilogue as k_radial_forward
 // with 4 register tiles per wave.  Staging: wave w moves radii
-// w * RC/4 ... of each chunk, lane l columns l + 64 b (b < CB), so colpad
-// <= 64 CB; at most FWD_PF_KT k tiles per group.
+// w * RC/4 ... of each chunk, lane l column pairs 2 (l + 64 b) + {0, 1}
+// (b < CB / 2), so colpad <= 64 CB; at most FWD_PF_KT k tiles per group.
+// Workgroups per CU its registers are held to: FP32 with 4 tiles and 2
+// staged columns fits four, other FP32 forms two (fewer spill otherwise).
 template <typename T, int CB, int TM>
-__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 2 : 1)
+constexpr int fwd_pf_min_wgs() {
+  return sizeof(T) == 8 ? 1 : (TM == 4 && CB == 2 ? 4 : 2);
+}
+
+template <typename T, int CB, int TM>
+__global__ void __launch_bounds__(NT, (fwd_pf_min_wgs<T, CB, TM>()))
 k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
                     int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* __restrict__ groups,
                     const DProb* __restrict__ probs, int flags) {
@@ -322,15 +350,21 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
   const int nchunk = (n_r + RC - 1) / RC;
   const int ktile = tile_kmax(modes + gr.mode0, gr.nmodes, lane);   // see k_radial_inverse
   T hreg[RW][CB], areg[KTM][SPW];
+  // lane l moves column pairs 2 (l + 64 b) + {0, 1} (re, im of one mode) as
+  // one 2-element access
+  typedef typename Vec2<T>::type T2;
   auto fetch = [&](int r0) {
 #pragma unroll
     for (int a = 0; a < RW; ++a) {
       const int r = r0 + wave * RW + a;
       const T* src = hv + (int64_t)r * rstride;
 #pragma unroll
-      for (int b = 0; b < CB; ++b) {
-        const int col = lane + 64 * b;
-        hreg[a][b] = (r < n_r && col < ncol) ? src[col] : (T)0;
+      for (int b = 0; b < CB / 2; ++b) {
+        const int col = 2 * (lane + 64 * b);
+        T2 pr = {(T)0, (T)0};
+        if (r < n_r && col < ncol) pr = *reinterpret_cast<const T2*>(src + col);
+        hreg[a][2 * b] = pr.x;
+        hreg[a][2 * b + 1] = pr.y;
       }
     }
     // table fragments: thread (wave, lane) takes steps wave * SPW + e of
@@ -346,9 +380,9 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
 #pragma unroll
     for (int a = 0; a < RW; ++a)
 #pragma unroll
-      for (int b = 0; b < CB; ++b) {
-        const int col = lane + 64 * b;
-        if (col < colpad) Hs[(wave * RW + a) * hs + col] = hreg[a][b];
+      for (int b = 0; b < CB / 2; ++b) {
+        const int col = 2 * (lane + 64 * b);
+        if (col < colpad) *reinterpret_cast<T2*>(Hs + (wave * RW + a) * hs + col) = T2{hreg[a][2 * b], hreg[a][2 * b + 1]};
       }
 #pragma unroll
     for (int kt = 0; kt < KTM; ++kt)
@@ -386,24 +420,37 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
         }
       }
     }
+    // lanes 2j and 2j + 1 hold re and im of one mode for the same rows k;
+    // after a swap across the pair each lane writes two complex rows of Y
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int t = tbase + wave + (NT / 64) * i;
-      if (!live[i]) continue;
+      if (!live[i]) continue;   // uniform over the wave
+      T sw[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sw[j] = swap_lane_pairs(acc[i][j]);
       const int kt = t / nct, ct = t - kt * nct;
       const int col = 16 * ct + (lane & 15);
-      const int c = col >> 1, ri = col & 1;
+      const int c = col >> 1;
+      const bool odd = lane & 1;
       if (c >= gr.nmodes) continue;
       const int roff = mtab[2 * c], K = mtab[2 * c + 1];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = 16 * kt + Mfma<T>::row(lane, j);
+      for (int h = 0; h < 2; ++h) {
+        const int k = 16 * kt + Mfma<T>::row(lane, odd ? 2 * h + 1 : 2 * h);
         if (k < K) {
           const int lr = roff + k;
-          double y = (double)acc[i][j];
-          if (kx_lds) y += kxs[2 * lr + ri];
-          else if (add_kinetic) y += kappa[gr.row0 + lr] * xv[2 * (gr.row0 + lr) + ri];
-          yv[2 * (gr.row0 + lr) + ri] = y;
+          double2 y = {(double)(odd ? sw[2 * h + 1] : acc[i][2 * h]), (double)(odd ? acc[i][2 * h + 1] : sw[2 * h])};
+          if (kx_lds) {
+            y.x += kxs[2 * lr];
+            y.y += kxs[2 * lr + 1];
+          } else if (add_kinetic) {
+            const double kp = kappa[gr.row0 + lr];
+            const double2 x = reinterpret_cast<const double2*>(xv)[gr.row0 + lr];
+            y.x += kp * x.x;
+            y.y += kp * x.y;
+          }
+          reinterpret_cast<double2*>(yv)[gr.row0 + lr] = y;
         }
       }
     }

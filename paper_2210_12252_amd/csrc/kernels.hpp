@@ -107,6 +107,11 @@ __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.
 template <typename T>
 __device__ __forceinline__ cplx<T> cmuli(cplx<T> a, T s) { return {-s * a.y, s * a.x}; }
 
+// Two consecutive elements moved by one memory instruction (16 bytes in FP64).
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { typedef double2 type; };
+template <> struct Vec2<float> { typedef float2 type; };
+
 template <typename T> struct Mfma;
 // 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
 // accumulator element i of lane l is D[row(l, i)][l % 16].  The row map
