@@ -113,8 +113,8 @@ def test_tuner_keeps_results_exact():
     Y0 = torch.zeros_like(X)
     batch.apply(X, Y0, nvec)
     chosen, ms = batch.tune(X, torch.zeros_like(X), nvec)
-    print(f"[tune] vectors per angular workgroup {chosen}, {ms:.3f} ms", flush=True)
-    assert chosen in (1, 2, 4, 8, 16) and ms > 0
+    print(f"[tune] items per angular workgroup {chosen} (0: even split), {ms:.3f} ms", flush=True)
+    assert chosen in (0, 2, 4, 8, 16) and ms > 0
     Y1 = torch.zeros_like(X)
     batch.apply(X, Y1, nvec)
     torch.cuda.synchronize()
