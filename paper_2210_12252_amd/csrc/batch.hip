@@ -131,6 +131,7 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
   int64_t mpre = 0;
   size_t lds_inv = 0, lds_fwd = 0, lds_ang = 0, lds_fwd_plain = 0, lds_fwd32 = 0;
   bool kx64 = true, kx32 = true;
+  int tm64 = 4, tm32 = 4;
   int fwd_tmax_plain = 4, inv_ks = 8;
   bool all_pf = true, pf_wide = false;
   for (int p = 0; p < nprob; ++p) {
@@ -148,6 +149,8 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
     lds_fwd32 = std::max(lds_fwd32, one.lds_fwd32);
     kx64 = kx64 && one.kx_lds64;
     kx32 = kx32 && one.kx_lds32;
+    tm64 = std::max(tm64, one.fwd_tm64);
+    tm32 = std::max(tm32, one.fwd_tm32);
     lds_fwd_plain = std::max(lds_fwd_plain, one.lds_fwd_plain64);
     lds_ang = std::max(lds_ang, one.lds_ang64);
     fwd_tmax_plain = std::max(fwd_tmax_plain, one.fwd_tmax_plain);
@@ -179,6 +182,8 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
   b->ls.lds_fwd32 = all_pf ? lds_fwd32 : lds_fwd_plain / 2;
   b->ls.kx_lds64 = all_pf && kx64;
   b->ls.kx_lds32 = all_pf && kx32;
+  b->ls.fwd_tm64 = tm64;
+  b->ls.fwd_tm32 = tm32;
   b->ls.lds_ang64 = lds_ang + rows1.size() * sizeof(int32_t);
   b->ls.rows1 = b->rows1;
   b->ls.nrows1 = (int)rows1.size();

@@ -686,14 +686,15 @@ void launch_radial_inverse(int ks, int nwg, size_t lds, hipStream_t st, const do
                        groups, probs);
 }
 
-// Register tiles per wave of the pipelined radial forward kernel: measured
-// best 8 in FP64 (one pass over the slab for groups of up to 32 tiles) and
-// 4 in FP32 (occupancy); HELIC_FWD_PF_TILES = 4 or 8 overrides.
-template <typename T>
-int fwd_pf_tiles() {
+// Register tiles per wave of the pipelined radial forward kernel: 8 in FP64
+// (one pass over the slab for groups of up to 32 tiles); in FP32 4 (four
+// workgroups per CU) unless the widest group then needs a second pass over
+// the slab (more than 16 tiles).  Measured best on the nanotube and nanowire
+// workloads; HELIC_FWD_PF_TILES = 4 or 8 overrides.
+int fwd_pf_tiles(bool fp64, int tiles_max) {
   const char* e = std::getenv("HELIC_FWD_PF_TILES");
   if (e && (e[0] == '4' || e[0] == '8')) return e[0] - '0';
-  return sizeof(T) == 8 ? 8 : 4;
+  return fp64 || tiles_max > 4 * (NT / 64) ? 8 : 4;
 }
 
 // One launch of the radial forward stage with the smallest register tile
@@ -701,10 +702,10 @@ int fwd_pf_tiles() {
 template <typename T>
 void launch_radial_forward(int tmax, int nwg, size_t lds, hipStream_t st, const T* gh, const double* X, int64_t ldx,
                            double* Y, int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* groups,
-                           const DProb* probs, int mode) {
+                           const DProb* probs, int mode, int tm = 8) {
   switch (tmax) {
     case 0:   // pipelined variants (columns staged per lane: 2 or 4 of 64; register tiles per wave)
-      if (fwd_pf_tiles<T>() == 8)
+      if (tm == 8)
         hipLaunchKernelGGL((k_radial_forward_pf<T, 2, 8>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
                            ngroups, n_r, groups, probs, mode);
       else
@@ -712,7 +713,7 @@ void launch_radial_forward(int tmax, int nwg, size_t lds, hipStream_t st, const 
                            ngroups, n_r, groups, probs, mode);
       break;
     case -1:
-      if (fwd_pf_tiles<T>() == 8)
+      if (tm == 8)
         hipLaunchKernelGGL((k_radial_forward_pf<T, 4, 8>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
                            ngroups, n_r, groups, probs, mode);
       else
@@ -1108,6 +1109,8 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.lds_fwd64 = fwd_lds_bytes(h, sizeof(double));
   ls.inv_ks = inv_ks_for(h);
   ls.fwd_tmax = fwd_tmax_for(fwd_tiles_max(h));
+  ls.fwd_tm64 = fwd_pf_tiles(true, fwd_tiles_max(h));
+  ls.fwd_tm32 = fwd_pf_tiles(false, fwd_tiles_max(h));
   ls.fwd_tmax_plain = ls.fwd_tmax;
   ls.lds_fwd_plain64 = ls.lds_fwd64;
   ls.lds_fwd32 = ls.lds_fwd64 / 2;
@@ -1203,7 +1206,8 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
   const bool kx_lds = ls.fwd_tmax <= 0 && mode && (f64 ? ls.kx_lds64 : ls.kx_lds32);
   launch_radial_forward<T>(ls.fwd_tmax, wg_rad, f64 ? ls.lds_fwd64 : ls.lds_fwd32, st, gh, X, ldx, Y, ldy, nvec,
-                           ls.ngroups, ls.n_r, ls.groups, probs, mode | (kx_lds ? 2 : 0));
+                           ls.ngroups, ls.n_r, ls.groups, probs, mode | (kx_lds ? 2 : 0),
+                           f64 ? ls.fwd_tm64 : ls.fwd_tm32);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   return HELIC_OK;

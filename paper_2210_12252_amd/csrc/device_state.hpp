@@ -82,6 +82,7 @@ struct LaunchSet {
   size_t lds_fwd_plain64 = 0;
   size_t lds_fwd32 = 0;             // LDS bytes of the chosen forward variant in FP32
   bool kx_lds64 = false, kx_lds32 = false;   // pipelined forward stages kappa x in LDS
+  int fwd_tm64 = 8, fwd_tm32 = 4;            // its register tiles per wave
   const int32_t* rows1 = nullptr;
   int nrows1 = 0;
   FftPlan plan1{}, plan2{};
