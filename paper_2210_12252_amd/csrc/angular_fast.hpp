@@ -239,6 +239,102 @@ __device__ __forceinline__ void row_dft(cplx<T>* A0, int rows, const cplx<T>* tw
   }
 }
 
+// Row transforms whose input (inverse) or output (forward) stays in the
+// registers of the row's P threads: lane (row, p) holds the elements at
+// columns p + P q.  The LDS row is used as the exchange buffer (and, for the
+// inverse, receives the transformed row).
+template <typename T, int N2, int P, int NTF, int ROWS, int OFF, bool PIN>
+__device__ __forceinline__ void row_idft_from_regs(cplx<T>* A0, const cplx<T>* tw, const cplx<T>* xin) {
+  constexpr int RS = ang_rs(N2);
+  constexpr int RPW = 64 / P;
+  static_assert(ROWS <= RPW * (NTF / 64), "one batch of rows");
+  int t = threadIdx.x;
+  if constexpr (PIN) asm volatile("" : "+v"(t));
+  const int lane = t & 63;
+  const int row = (t >> 6) * RPW + lane / P;
+  const int p = lane % P;
+  const bool act = lane < RPW * P && row < ROWS;
+  cplx<T> v[P];
+  cplx<T>* a = A0 + (act ? row : 0) * RS;
+  const int sw = ang_swz(N2, act ? row : 0);
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = xin[q];
+    dft_reg<T, P, true>(v);
+#pragma unroll
+    for (int k = 1; k < P; ++k) {
+      cplx<T> w = tw[p * k];
+      w.y = -w.y;
+      v[k] = cmul(v[k], w);
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      int kk = k + p;
+      kk -= (kk >= P) ? P : 0;
+      a[OFF + ((p * P + kk) ^ sw)] = v[k];
+    }
+  }
+  wave_sync();
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      int cc = p + q;
+      cc -= (cc >= P) ? P : 0;
+      v[q] = a[OFF + ((q * P + cc) ^ sw)];
+    }
+    dft_reg<T, P, true>(v);
+  }
+  wave_sync();
+  if (act) {
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) a[OFF + ((p + P * k1) ^ sw)] = v[k1];
+  }
+}
+
+template <typename T, int N2, int P, int NTF, int ROWS, int OFF, bool PIN>
+__device__ __forceinline__ void row_dft_to_regs(cplx<T>* A0, const cplx<T>* tw, cplx<T>* xout) {
+  constexpr int RS = ang_rs(N2);
+  constexpr int RPW = 64 / P;
+  static_assert(ROWS <= RPW * (NTF / 64), "one batch of rows");
+  int t = threadIdx.x;
+  if constexpr (PIN) asm volatile("" : "+v"(t));
+  const int lane = t & 63;
+  const int row = (t >> 6) * RPW + lane / P;
+  const int p = lane % P;
+  const bool act = lane < RPW * P && row < ROWS;
+  cplx<T> v[P];
+  cplx<T>* a = A0 + (act ? row : 0) * RS;
+  const int sw = ang_swz(N2, act ? row : 0);
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = a[OFF + ((p + P * q) ^ sw)];
+    dft_reg<T, P, false>(v);
+#pragma unroll
+    for (int k = 1; k < P; ++k) v[k] = cmul(v[k], tw[p * k]);
+  }
+  wave_sync();
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      int kk = k + p;
+      kk -= (kk >= P) ? P : 0;
+      a[OFF + ((p * P + kk) ^ sw)] = v[k];
+    }
+  }
+  wave_sync();
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      int cc = p + q;
+      cc -= (cc >= P) ? P : 0;
+      v[q] = a[OFF + ((q * P + cc) ^ sw)];
+    }
+    dft_reg<T, P, false>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) xout[k1] = v[k1];
+  }
+}
+
 // ---------------------------------------------------------------- convolution
 // The convolution proceeds in groups of CONV_MB rows: the accumulators pass
 // through an empty asm at each group boundary, which pins the multiply-adds
@@ -307,6 +403,16 @@ __device__ __forceinline__ void conv_herm_group(int g, const cplx<T>* A, cplx<T>
 // Workgroups per CU the register allocation is held to: 16 waves per CU in
 // FP32 where the block fits 128 registers without spilling (row addresses
 // then recomputed per call, see row_dft), else 8.
+// FP64 blocks of 64 columns and up to 24 rows move the mode slab straight
+// between global memory and the registers of the row transforms (the block
+// positions without a mode load zeros and store nothing): no clearing pass,
+// no LDS scatter and gather, two block barriers per vector.  Elsewhere the
+// extra registers spill, and the slab goes through LDS.
+template <typename T, int N2, int MPAD>
+constexpr bool ang_direct() {
+  return sizeof(T) == 8 && N2 == 64 && MPAD <= 24;
+}
+
 template <typename T, int N2, int MPAD, int NTF>
 constexpr int ang_min_wgs() {
   return (sizeof(T) == 4 && !(N2 == 64 && MPAD > 24) ? 1024 : 512) / NTF;
@@ -314,7 +420,8 @@ constexpr int ang_min_wgs() {
 
 // GH[v][r][mode] holds G on entry and H on exit (complex T).  Vh[r][j][d]
 // (complex T, d = 0..2 MPAD - 2 for m' - m = d - (MPAD - 1)).  mode_pos[i] =
-// (m_i - m_min) * ang_rs(N2) + ((n_i mod N2) ^ ang_swz(N2, m_i - m_min)).
+// (m_i - m_min) * ang_rs(N2) + ((n_i mod N2) ^ ang_swz(N2, m_i - m_min));
+// blk_mode is its inverse on the unswizzled block (see ang_direct).
 // Work: blockIdx -> ipw consecutive (problem, radius, vector) items.
 //
 // LDS holds two mode blocks: A receives the scattered slab and its theta2
@@ -382,63 +489,122 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
       for (int q = 0; q < NW; ++q)
         w[q] = (conv_act && base + q < ND) ? src[base + q] : cplx<T>{(T)0, (T)0};
     }
-    // The mode slab of the next vector is fetched into registers while the
-    // current one is transformed: thread t owns modes t + NTF q (coalesced
-    // global access) and writes them to their block positions mode_pos.
-    int mp[MS];
+    if constexpr (ang_direct<T, N2, MPAD>()) {
+      // Lane (row, p) of the row transforms moves the elements at columns
+      // p + P q of its row straight between the slab and its registers:
+      // idx[q] = mode index of that block position (blk_mode[row * N2 + col]),
+      // -1 where no mode is kept.  The next vector's elements are fetched while
+      // the current one is transformed.
+      constexpr int RPW_ = 64 / P;
+      const int rrow = (t >> 6) * RPW_ + (t & 63) / P, rp = (t & 63) % P;
+      const bool ract = (t & 63) < RPW_ * P && rrow < MPAD;
+      int idx[P];
 #pragma unroll
-    for (int q = 0; q < MS; ++q) {
-      const int i = t + NTF * q;
-      mp[q] = i < n_modes ? pb.mode_pos[i] : -1;
-    }
-    cplx<T> pre[MS];
-    auto fetch = [&](int v) {
-      const cplx<T>* slab = reinterpret_cast<const cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+      for (int q = 0; q < P; ++q) idx[q] = ract ? pb.blk_mode[rrow * N2 + rp + P * q] : -1;
+      cplx<T> xin[P];
+      auto fetch = [&](int v) {
+        const cplx<T>* slab = reinterpret_cast<const cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
 #pragma unroll
-      for (int q = 0; q < MS; ++q) pre[q] = mp[q] >= 0 ? slab[t + NTF * q] : cplx<T>{(T)0, (T)0};
-    };
-    fetch(v0);
-    for (int v = v0; v < v1; ++v) {
-      // A is clear here (and no thread still reads it); B is no longer read
+        for (int q = 0; q < P; ++q) xin[q] = idx[q] >= 0 ? slab[idx[q]] : cplx<T>{(T)0, (T)0};
+      };
+      fetch(v0);
+      for (int v = v0; v < v1; ++v) {
+        row_idft_from_regs<T, N2, P, NTF, MPAD, 0, PIN_ROWS>(A, tw, xin);
+        if (v + 1 < v1) fetch(v + 1);
+        __syncthreads();
+        // theta1: Toeplitz convolution per column with the spectrum of V, A -> B
+        if constexpr (HERM) {
+          conv_herm_group<T, N2, MPAD, OPT, 0, OG>(__builtin_amdgcn_readfirstlane(og), A, B, j, w);
+        } else if (conv_act) {
+          cplx<T> acc[OPT];
 #pragma unroll
-      for (int q = 0; q < MS; ++q)
-        if (mp[q] >= 0) A[mp[q]] = pre[q];
-      __syncthreads();
-      if (v + 1 < v1) fetch(v + 1);
-      row_dft<T, N2, P, NTF, true, 0, PIN_ROWS>(A, MPAD, tw);
-      __syncthreads();
-      // theta1: Toeplitz convolution per column with the spectrum of V, A -> B
-      if constexpr (HERM) {
-        conv_herm_group<T, N2, MPAD, OPT, 0, OG>(__builtin_amdgcn_readfirstlane(og), A, B, j, w);
-      } else if (conv_act) {
-        cplx<T> acc[OPT];
+          for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
 #pragma unroll
-        for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
+          for (int m = 0; m < MPAD; ++m) {
+            if (m % CONV_MB == 0 && m > 0) pin_acc<T, OPT>(acc);
+            const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
 #pragma unroll
-        for (int m = 0; m < MPAD; ++m) {
-          if (m % CONV_MB == 0 && m > 0) pin_acc<T, OPT>(acc);
-          const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
-#pragma unroll
-          for (int o = 0; o < OPT; ++o) {
-            const cplx<T> wv = w[o - m + MPAD - 1];
-            acc[o].x = fmac(wv.x, x.x, acc[o].x);
-            acc[o].x = fmac(-wv.y, x.y, acc[o].x);
-            acc[o].y = fmac(wv.x, x.y, acc[o].y);
-            acc[o].y = fmac(wv.y, x.x, acc[o].y);
+            for (int o = 0; o < OPT; ++o) {
+              const cplx<T> wv = w[o - m + MPAD - 1];
+              acc[o].x = fmac(wv.x, x.x, acc[o].x);
+              acc[o].x = fmac(-wv.y, x.y, acc[o].x);
+              acc[o].y = fmac(wv.x, x.y, acc[o].y);
+              acc[o].y = fmac(wv.y, x.x, acc[o].y);
+            }
           }
+#pragma unroll
+          for (int o = 0; o < OPT; ++o)
+            if (a0 + o < MPAD) B[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
         }
+        __syncthreads();
+        cplx<T> xout[P];
+        row_dft_to_regs<T, N2, P, NTF, MPAD, BLK, PIN_ROWS>(A, tw, xout);
+        cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+        if (ract) {
 #pragma unroll
-        for (int o = 0; o < OPT; ++o)
-          if (a0 + o < MPAD) B[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
+          for (int q = 0; q < P; ++q)
+            if (idx[q] >= 0) slab[idx[q]] = xout[q];
+        }
       }
-      __syncthreads();
-      row_dft<T, N2, P, NTF, false, BLK, PIN_ROWS>(A, MPAD, tw);
-      for (int i = t; i < BLK; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
-      __syncthreads();
-      cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+    } else {
+      // The mode slab of the next vector is fetched into registers while the
+      // current one is transformed: thread t owns modes t + NTF q (coalesced
+      // global access) and writes them to their block positions mode_pos.
+      int mp[MS];
 #pragma unroll
-      for (int q = 0; q < MS; ++q)
-        if (mp[q] >= 0) slab[t + NTF * q] = A[BLK + mp[q]];
+      for (int q = 0; q < MS; ++q) {
+        const int i = t + NTF * q;
+        mp[q] = i < n_modes ? pb.mode_pos[i] : -1;
+      }
+      cplx<T> pre[MS];
+      auto fetch = [&](int v) {
+        const cplx<T>* slab = reinterpret_cast<const cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+#pragma unroll
+        for (int q = 0; q < MS; ++q) pre[q] = mp[q] >= 0 ? slab[t + NTF * q] : cplx<T>{(T)0, (T)0};
+      };
+      fetch(v0);
+      for (int v = v0; v < v1; ++v) {
+        // A is clear here (and no thread still reads it); B is no longer read
+#pragma unroll
+        for (int q = 0; q < MS; ++q)
+          if (mp[q] >= 0) A[mp[q]] = pre[q];
+        __syncthreads();
+        if (v + 1 < v1) fetch(v + 1);
+        row_dft<T, N2, P, NTF, true, 0, PIN_ROWS>(A, MPAD, tw);
+        __syncthreads();
+        // theta1: Toeplitz convolution per column with the spectrum of V, A -> B
+        if constexpr (HERM) {
+          conv_herm_group<T, N2, MPAD, OPT, 0, OG>(__builtin_amdgcn_readfirstlane(og), A, B, j, w);
+        } else if (conv_act) {
+          cplx<T> acc[OPT];
+#pragma unroll
+          for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
+#pragma unroll
+          for (int m = 0; m < MPAD; ++m) {
+            if (m % CONV_MB == 0 && m > 0) pin_acc<T, OPT>(acc);
+            const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
+#pragma unroll
+            for (int o = 0; o < OPT; ++o) {
+              const cplx<T> wv = w[o - m + MPAD - 1];
+              acc[o].x = fmac(wv.x, x.x, acc[o].x);
+              acc[o].x = fmac(-wv.y, x.y, acc[o].x);
+              acc[o].y = fmac(wv.x, x.y, acc[o].y);
+              acc[o].y = fmac(wv.y, x.x, acc[o].y);
+            }
+          }
+#pragma unroll
+          for (int o = 0; o < OPT; ++o)
+            if (a0 + o < MPAD) B[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
+        }
+        __syncthreads();
+        row_dft<T, N2, P, NTF, false, BLK, PIN_ROWS>(A, MPAD, tw);
+        for (int i = t; i < BLK; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
+        __syncthreads();
+        cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+#pragma unroll
+        for (int q = 0; q < MS; ++q)
+          if (mp[q] >= 0) slab[t + NTF * q] = A[BLK + mp[q]];
+      }
     }
   }
 }

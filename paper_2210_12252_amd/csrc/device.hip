@@ -1062,6 +1062,10 @@ helic_status ensure_device(helic_basis_s* h) {
       mp[i] = mr * rs + (h->modes[i].bin2 ^ ang_swz(h->n_t2, mr));
     }
     if ((s = upload(mp, &d->mode_pos))) return s;
+    std::vector<int32_t> bm((size_t)d->fast_mpad * h->n_t2, -1);
+    for (size_t i = 0; i < h->modes.size(); ++i)
+      bm[(size_t)(h->modes[i].m - mlo) * h->n_t2 + h->modes[i].bin2] = (int32_t)i;
+    if ((s = upload(bm, &d->blk_mode))) return s;
     const size_t nvh = (size_t)h->n_r * h->n_t2 * (2 * d->fast_mpad - 1) * 2;
     HIP_TRY(hipMalloc((void**)&d->Vh, nvh * sizeof(double)));
     HIP_TRY(hipMalloc((void**)&d->Vhf, nvh * sizeof(float)));
@@ -1087,6 +1091,7 @@ DProb problem_entry(const helic_basis_s* h, bool fp64, int64_t Lpre, int64_t mpr
   p.Vs = fp64 ? (const void*)d->Vs : (const void*)d->Vsf;
   p.Vh = fp64 ? (const void*)d->Vh : (const void*)d->Vhf;
   p.mode_pos = d->mode_pos;
+  p.blk_mode = d->blk_mode;
   p.Lpre = Lpre;
   p.L = h->L;
   p.mpre = mpre;
@@ -1166,7 +1171,7 @@ void device_release(helic_basis_s* h) {
   if (!d) return;
   void* ptrs[] = {d->groups, d->modes, d->row_ck, d->kappa, d->rows1, d->tinv64, d->tfwd64,
                   d->tinv32, d->tfwd32, d->tw1, d->tw2, d->tw1f, d->tw2f, d->Vs, d->Vsf,
-                  d->gh, d->part, d->mode_pos, d->Vh, d->Vhf, d->probs64, d->probs32, d->vdiag, d->lpc_ws};
+                  d->gh, d->part, d->mode_pos, d->blk_mode, d->Vh, d->Vhf, d->probs64, d->probs32, d->vdiag, d->lpc_ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   release_solver_state(d);

@@ -44,6 +44,7 @@ struct DeviceState {
   int ang_slots64 = 1, ang_slots32 = 1;   // resident workgroups of that kernel on the device
   int apply_chunk = APPLY_CHUNK;  // vectors per launch of the three stages
   int32_t* mode_pos = nullptr;    // mode -> (m - m_min) * ang_rs(n_t2) + ((n mod n_t2) ^ ang_swz)
+  int32_t* blk_mode = nullptr;    // (m - m_min) * n_t2 + (n mod n_t2) -> mode, -1 if none
   double* Vh = nullptr;           // [n_r][n_t2][2 * fast_mpad - 1] complex
   float* Vhf = nullptr;
   DProb* probs64 = nullptr;       // one-entry problem tables of this handle

@@ -72,6 +72,7 @@ struct DProb {
   const void* Vs;
   const void* Vh;
   const int32_t* mode_pos;    // mode -> LDS position in the angular block (specialised kernel)
+  const int32_t* blk_mode;    // block position (m - m_min) * n_t2 + (n mod n_t2) -> mode, -1 if none
   int64_t Lpre, L, mpre;
   int32_t n_modes, pad;
 };
