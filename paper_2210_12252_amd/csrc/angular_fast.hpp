@@ -513,29 +513,8 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
         if (v + 1 < v1) fetch(v + 1);
         __syncthreads();
         // theta1: Toeplitz convolution per column with the spectrum of V, A -> B
-        if constexpr (HERM) {
-          conv_herm_group<T, N2, MPAD, OPT, 0, OG>(__builtin_amdgcn_readfirstlane(og), A, B, j, w);
-        } else if (conv_act) {
-          cplx<T> acc[OPT];
-#pragma unroll
-          for (int o = 0; o < OPT; ++o) acc[o] = cplx<T>{(T)0, (T)0};
-#pragma unroll
-          for (int m = 0; m < MPAD; ++m) {
-            if (m % CONV_MB == 0 && m > 0) pin_acc<T, OPT>(acc);
-            const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
-#pragma unroll
-            for (int o = 0; o < OPT; ++o) {
-              const cplx<T> wv = w[o - m + MPAD - 1];
-              acc[o].x = fmac(wv.x, x.x, acc[o].x);
-              acc[o].x = fmac(-wv.y, x.y, acc[o].x);
-              acc[o].y = fmac(wv.x, x.y, acc[o].y);
-              acc[o].y = fmac(wv.y, x.x, acc[o].y);
-            }
-          }
-#pragma unroll
-          for (int o = 0; o < OPT; ++o)
-            if (a0 + o < MPAD) B[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
-        }
+        static_assert(HERM, "the direct path serves 64-column blocks");
+        conv_herm_group<T, N2, MPAD, OPT, 0, OG>(__builtin_amdgcn_readfirstlane(og), A, B, j, w);
         __syncthreads();
         cplx<T> xout[P];
         row_dft_to_regs<T, N2, P, NTF, MPAD, BLK, PIN_ROWS>(A, tw, xout);
