@@ -208,6 +208,26 @@ def test_apply_H_full_size_sampled(name):
         assert herm < (1e-12 if prec == "fp64" else 1e-5)
 
 
+def test_apply_H_parity_64_column_block():
+    """Nanotube geometry at a reduced cutoff on the 48 x 64 grid with 40
+    radii: the specialised angular kernel on 64-column blocks (FP64 moves the
+    slab straight between global memory and the row transforms' registers,
+    FP32 through LDS), a ragged block of 37 vectors spread evenly over the
+    resident workgroups (work segments start and end inside radii); every
+    output element against the oracle."""
+    w = synth.workload("nanotube-ecut25").with_(name="nanotube-ecut10", ecut=10.0, n_t1=48, n_t2=64, n_r=40)
+    c = Case(w)
+    c.upload_V()
+    X = synth.random_block(c.o.mnk, 37, 4242)
+    ref = oh.apply(c.o, c.V, X)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        Yg = torch.zeros((37, c.o.L), dtype=torch.complex128, device=_dev())
+        c.g.apply_H(c.to_gpu_block(X), Yg, prec=prec)
+        err = _rel(c.from_gpu_block(Yg), ref)
+        print(f"[64-column block {prec}] rel err {err:.2e}", flush=True)
+        assert err < tol
+
+
 def test_general_and_specialised_angular_kernels_agree(tiny, monkeypatch):
     """The general LDS-FFT angular kernel and the specialised convolution
     kernel compute the same operator (both are checked against the oracle
