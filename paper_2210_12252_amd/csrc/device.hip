@@ -43,6 +43,17 @@ __device__ __forceinline__ int tile_kmax(const DMode* gm, int nmodes, int lane) 
   return 8 * lane < nmodes ? gm[8 * lane].K : 0;
 }
 
+// Column swizzle of the inverse kernel's coefficient block: row k stores
+// column pair c at pair c ^ ((k / 2 in FP64, k / 4 in FP32) mod 8), inside
+// its 16-column tile.  Rows are hs apart, an odd multiple of 16 elements, so
+// without it the staging writes of consecutive k of one mode (consecutive
+// threads) pile onto the same LDS banks; the MFMA B reads of a tile row stay
+// a permutation of that row.
+template <typename T>
+__device__ __forceinline__ int inv_swz(int k) {
+  return 2 * ((k >> (sizeof(T) == 8 ? 1 : 2)) & 7);
+}
+
 template <typename T, int KS>
 __global__ void __launch_bounds__(NT, KS <= 12 ? 4 : 3)
 k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, int nvec, int ngroups, int n_r,
@@ -79,7 +90,7 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
     const int ck = row_ck[gr.row0 + i];
     const int c = ck >> 16, k = ck & 0xffff;
     const double2 x = xv[i];
-    *reinterpret_cast<typename Vec2<T>::type*>(Bs + k * hs + 2 * c) = {(T)x.x, (T)x.y};
+    *reinterpret_cast<typename Vec2<T>::type*>(Bs + k * hs + ((2 * c) ^ inv_swz<T>(k))) = {(T)x.x, (T)x.y};
   }
   __syncthreads();
   T* gv = GH + (slab_off(pb, nvec, n_r, v, 0) + gr.mode0) * 2;
@@ -88,7 +99,12 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   const int ktile = tile_kmax(pb.modes + gr.mode0, gr.nmodes, lane);
   auto tile_ks = [&](int c) { return nct <= 64 ? (__builtin_amdgcn_readlane(ktile, c) + 3) / 4 : nks; };
   typedef typename Mfma<T>::acc_t acc_t;
-  const T* brow = Bs + (lane >> 4) * hs + (lane & 15);
+  // lane l reads B row 4 s + l / 16, column l % 16 of each tile, at its
+  // swizzled position; the XOR repeats every BP k steps
+  constexpr int BP = sizeof(T) == 8 ? 4 : 8;
+  const T* bcol[BP];
+#pragma unroll
+  for (int s = 0; s < BP; ++s) bcol[s] = Bs + (lane >> 4) * hs + ((lane & 15) ^ inv_swz<T>((lane >> 4) + 4 * s));
   for (int rt = wave; rt < nrt; rt += NT / 64) {
     T a[KS];
     if constexpr (PF) {
@@ -107,8 +123,8 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
       acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        if (s < ks0) acc0 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct], acc0);
-        if (s < ks1) acc1 = Mfma<T>::op(a[s], brow[4 * s * hs + 16 * ct + 16], acc1);
+        if (s < ks0) acc0 = Mfma<T>::op(a[s], bcol[s % BP][4 * s * hs + 16 * ct], acc0);
+        if (s < ks1) acc1 = Mfma<T>::op(a[s], bcol[s % BP][4 * s * hs + 16 * ct + 16], acc1);
       }
       // lanes 2j and 2j + 1 hold re and im of one mode for the same four rows;
       // after a swap across the pair each lane stores two (re, im) pairs
