@@ -60,9 +60,12 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
                  const DGroup* __restrict__ groups, const DProb* __restrict__ probs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Bs = reinterpret_cast<T*>(smem_raw);
+  // work in vector-major order: the slots of one XCD run every group of a few
+  // vectors, so the workgroups resident together cover adjacent rows of one
+  // vector's slab (and each XCD gets an even share of the work)
   const int slot = xcd_slot(ngroups * nvec);
   if (slot >= ngroups * nvec) return;
-  const int gi = slot / nvec, v = slot - gi * nvec;
+  const int v = slot / ngroups, gi = slot - v * ngroups;
   const DGroup gr = groups[gi];
   const DProb& pb = probs[gr.prob];
   const int nks = (gr.Kmax + 3) / 4;
@@ -216,7 +219,7 @@ k_radial_forward(const T* __restrict__ GH, const double* __restrict__ X, int64_t
   T* Hs = reinterpret_cast<T*>(smem_raw);
   const int slot = xcd_slot(ngroups * nvec);
   if (slot >= ngroups * nvec) return;
-  const int gi = slot / nvec, v = slot - gi * nvec;
+  const int v = slot / ngroups, gi = slot - v * ngroups;   // vector-major, see k_radial_inverse
   const DGroup gr = groups[gi];
   const DProb& pb = probs[gr.prob];
   const int ncol = 2 * gr.nmodes;
@@ -331,7 +334,7 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
   T* Hs = reinterpret_cast<T*>(smem_raw);
   const int slot = xcd_slot(ngroups * nvec);
   if (slot >= ngroups * nvec) return;
-  const int gi = slot / nvec, v = slot - gi * nvec;
+  const int v = slot / ngroups, gi = slot - v * ngroups;   // vector-major, see k_radial_inverse
   const DGroup gr = groups[gi];
   const DProb& pb = probs[gr.prob];
   const int ncol = 2 * gr.nmodes;
