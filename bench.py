@@ -89,20 +89,27 @@ def cpu_baseline(w, nsample: int):
 
 def time_to_eigenpairs(b, w, torch, tol=1e-8):
     """Lowest w.nev eigenpairs to ||H x - lambda x|| <= tol from the same
-    seeded random start, FP64 H*X and mixed (FP32 H*X, FP64 refinement); both
-    keep the FP64 Rayleigh-Ritz.  Reports wall time, iterations, the H*X and
-    Rayleigh-Ritz shares and the per-eigenvalue difference of mixed vs FP64."""
+    seeded random start, FP64 H*X and mixed (FP32 H*X, FP64 refinement); all
+    keep the FP64 Rayleigh-Ritz.  Two solvers: LOBPCG with the TPA
+    preconditioner and Chebyshev-filtered subspace iteration (automatic degree
+    and guard).  Reports wall time, iterations (outer filter steps for the
+    latter), the H*X and Rayleigh-Ritz shares and the largest eigenvalue
+    difference against LOBPCG in FP64."""
     import numpy as np
     out = {"nev": w.nev, "tol_Ha": tol}
     evs = {}
-    for prec in ("fp64", "fp32"):
+    # warm-up: library handles and kernels of both solvers loaded before timing
+    b.eigensolve_ex(4, tol=1e-3, maxit=2)
+    b.eigensolve_ex(4, tol=1e-3, maxit=1, cheb_degree=2)
+    runs = (("fp64", None, "fp64"), ("fp32", None, "mixed_fp32_fp64"),
+            ("fp64", 0, "chefsi_fp64"), ("fp32", 0, "chefsi_mixed_fp32_fp64"))
+    for prec, deg, key in runs:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ev, res, st, status = b.eigensolve_ex(w.nev, block=64, tol=tol, maxit=1000, prec=prec, seed=7,
-                                              log_every=LOG_EVERY)
+        ev, res, st, status = b.eigensolve_ex(w.nev, block=64, tol=tol, maxit=1000 if deg is None else 200,
+                                              prec=prec, seed=7, log_every=LOG_EVERY, cheb_degree=deg)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        key = "fp64" if prec == "fp64" else "mixed_fp32_fp64"
         out[key] = dict(seconds=round(wall, 3), converged=bool(status == 0), iters=st["iters"],
                         iters_fp32=st["iters_low"], hx_columns=st["n_apply"], hx_s=round(st["t_apply_ms"] / 1e3, 3),
                         rayleigh_ritz_s=round(st["t_rr_ms"] / 1e3, 3), max_resid=float(np.max(res)))
@@ -112,6 +119,10 @@ def time_to_eigenpairs(b, w, torch, tol=1e-8):
     d = np.abs(evs["mixed_fp32_fp64"] - evs["fp64"])
     out["mixed_vs_fp64_max_abs_Ha"] = float(d.max())
     out["speedup_mixed"] = round(out["fp64"]["seconds"] / out["mixed_fp32_fp64"]["seconds"], 3)
+    out["chefsi_vs_lobpcg_max_abs_Ha"] = float(max(np.abs(evs["chefsi_fp64"] - evs["fp64"]).max(),
+                                                   np.abs(evs["chefsi_mixed_fp32_fp64"] - evs["fp64"]).max()))
+    out["speedup_chefsi"] = round(out["fp64"]["seconds"] / out["chefsi_fp64"]["seconds"], 3)
+    out["speedup_chefsi_mixed"] = round(out["fp64"]["seconds"] / out["chefsi_mixed_fp32_fp64"]["seconds"], 3)
     return out
 
 

@@ -188,6 +188,23 @@ helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* opts, do
                                  double* resid, double* evecs, int64_t ldv, helic_solve_stats* stats,
                                  void* stream);
 
+/* Lowest nev eigenpairs by Chebyshev-filtered subspace iteration, the kind
+ * of eigensolver Sec. 3.5 names as the more efficient choice for later work.
+ * Each outer step filters the nev + guard columns with a degree-`degree`
+ * Chebyshev polynomial of H (scaled three-term recurrence; damped interval
+ * from the block's largest Ritz value to an upper bound of the spectrum
+ * taken from a 12-step FP64 Lanczos run), orthonormalises them (Cholesky QR,
+ * SVQB fallback, random refill of collapsed directions) and rotates them by
+ * FP64 Rayleigh-Ritz; degree * (nev + guard) column applications per step.
+ * degree 0 picks 32; 1..200 accepted.  guard -1 picks max(8, nev / 3).  opts, outputs, convergence test,
+ * FP32 ladder (prec, switch_tol), stats and errors as helic_eigensolve_ex;
+ * opts->precond is not used (the filter takes the preconditioner's place);
+ * stats->iters counts outer steps and t_precond_ms the residual and filter
+ * arithmetic. */
+helic_status helic_eigensolve_chefsi(helic_basis h, const helic_solve_opts* opts, int32_t degree,
+                                     double* evals, double* resid, double* evecs, int64_t ldv,
+                                     helic_solve_stats* stats, void* stream);
+
 /* ---- batches of Bloch parameters / structures (Sec. 3.3) ----------------
  * A batch groups problems (basis handles, each with its potential set) that
  * share the grid (n_t1, n_t2, n_r) and the angular kernel variant -- e.g. the

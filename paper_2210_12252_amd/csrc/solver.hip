@@ -62,6 +62,7 @@ namespace {
 
 typedef rocblas_double_complex zc;
 constexpr int NTS = 256;
+constexpr int CHEB_DEGREE_AUTO = 32;   // filter degree when the caller passes 0
 
 #define HIP_TRY_S(call)                                                               \
   do {                                                                                \
@@ -205,6 +206,47 @@ __global__ void k_diag_block(double* __restrict__ Cm, int ldc, const double* __r
   Cm[((size_t)j * ldc + i) * 2 + 1] = 0.0;
 }
 
+// One step of the scaled Chebyshev recurrence, elementwise over n doubles:
+// Out = alpha (AY - c Y) + beta Xp (Xp is not read when beta = 0).  Out may
+// be Xp: each element is read before it is written, by the same thread.
+__global__ void __launch_bounds__(NTS)
+k_cheb_step(const double* __restrict__ AY, const double* __restrict__ Y, const double* Xp, double* Out, int64_t n,
+            double alpha, double c, double beta) {
+  for (int64_t i = blockIdx.x * (int64_t)NTS + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTS) {
+    const double f = alpha * (AY[i] - c * Y[i]);
+    Out[i] = beta != 0.0 ? f + beta * Xp[i] : f;
+  }
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal d and off-diagonal e (Sturm sequence of the LDL^T pivots).
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    q = d[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Largest eigenvalue of that matrix by bisection inside its Gershgorin interval.
+double tridiag_max_eig(const std::vector<double>& d, const std::vector<double>& e) {
+  double lo = HUGE_VAL, hi = -HUGE_VAL;
+  for (size_t i = 0; i < d.size(); ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < d.size() ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  const int n = (int)d.size();
+  for (int k = 0; k < 200 && hi - lo > 1e-14 * std::max(1.0, std::fabs(hi)); ++k) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_count(d, e, mid) >= n) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
 struct Bufs {
   std::vector<void*> owned;
   ~Bufs() {
@@ -227,13 +269,16 @@ struct Timer {
 }  // namespace
 
 helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double* evals, double* resid,
-                             double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st, Harvest* hv) {
+                             double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st, Harvest* hv,
+                             int cheb_degree) {
   Timer total;
   helic_solve_stats S_;
   std::memset(&S_, 0, sizeof(S_));
   const int64_t L = h->L;
   const int nev = o.nev;
-  const int guard = o.guard >= 0 ? o.guard : std::max(4, nev / 8);
+  // automatic guard: a wider block speeds the filter's convergence (the
+  // damped interval starts further above the wanted eigenvalues)
+  const int guard = o.guard >= 0 ? o.guard : cheb_degree > 0 ? std::max(8, nev / 3) : std::max(4, nev / 8);
   const int n = (int)std::min<int64_t>(L, (int64_t)nev + guard);
   const int chunk = std::max(1, std::min(o.block, 64));
   const int kmax = 3 * n;
@@ -259,6 +304,8 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   const int64_t slice = L / nsplit;   // the last slice also takes L - nsplit * slice rows
   double* gpart = nullptr;
   if ((s = B.get(&gpart, (size_t)(nsplit + 1) * kmax * kmax * 2))) return s;
+  double* lz = nullptr;   // Lanczos columns of the Chebyshev-filtered solver
+  if (cheb_degree > 0 && (s = B.get(&lz, Lc * 3))) return s;
   int32_t *d_idx = nullptr, *d_info = nullptr, *d_sweeps = nullptr;
   HIP_TRY_S(hipMalloc((void**)&d_idx, sizeof(int32_t) * n));
   B.owned.push_back(d_idx);
@@ -534,130 +581,284 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   };
   bool converged = false;
   int it = 0;
-  for (it = 0; it < o.maxit; ++it) {
-    if ((s = residuals(nrm))) return s;
-    for (int j = 0; j < n; ++j)
-      if (!std::isfinite(nrm[j]))
-        return fail(HELIC_ERR_NOCONV, "residual of column " + std::to_string(j) + " is not finite at iteration " +
-                                          std::to_string(it));
-    // the nev lowest by value (the locked prefix and the rest may interleave)
-    bool all = true;
-    double worst = 0.0;
+  if (cheb_degree > 0) {
+    // ---- Chebyshev-filtered subspace iteration: per outer step the block
+    // is filtered by a degree-m Chebyshev polynomial of H that damps the
+    // interval [a, b] (a = the block's largest Ritz value, b = an upper bound
+    // of the spectrum) and grows what lies below a, then orthonormalised and
+    // rotated by FP64 Rayleigh-Ritz.  Scaled three-term recurrence (Zhou and
+    // Saad, 2007), applied to all n columns.
+    const int m = cheb_degree;
+    double b_up = 0.0;
     {
-      const std::vector<int> ord = lowest_order();
-      for (int q = 0; q < nev; ++q) {
-        all = all && nrm[ord[q]] <= o.tol;
-        worst = std::max(worst, nrm[ord[q]]);
-      }
-    }
-    if (all && prec == HELIC_FP64) {
-      converged = true;
-      break;
-    }
-    if (prec != HELIC_FP64 && worst <= switch_tol) {
-      // precision ladder: recompute H X and H P in FP64 and go on in FP64
-      prec = HELIC_FP64;
-      exact_x = false;   // H X recomputed: X^H H X is no longer exactly diagonal
-      if ((s = apply(S, AS, n))) return s;
-      if ((s = apply(Pb, APb, np))) return s;
-      --it;
-      continue;
-    }
-    if (o.log_every > 0 && it % o.log_every == 0) {
-      std::fprintf(stderr, "[helic] iteration %d: worst wanted residual %.3e, %s H*X, %.1f s\n", it, worst,
-                   prec == HELIC_FP64 ? "FP64" : "FP32", total.ms() / 1e3);
-      std::fflush(stderr);
-    }
-    if (learned) {
-      if (worst < best_worst) {
-        best_worst = worst;
-        stall = 0;
-      } else if (++stall >= 3) {
-        learned = false;
-      }
-    }
-    if (prec != HELIC_FP64) ++S_.iters_low;
-    // In the FP32 phase columns are locked at switch_tol: iterating a column
-    // whose residual is at the FP32 noise floor makes its normalised update
-    // directions amplify the rounding inconsistency between S and H S.
-    const double lock_tol = prec == HELIC_FP64 ? o.tol : std::max(o.tol, switch_tol);
-    if (prec == HELIC_FP64)
-      while (nl < n - 1 && nrm[nl] <= o.tol) ++nl;
-    active.clear();
-    for (int j = nl; j < n; ++j)
-      if (nrm[j] > lock_tol) active.push_back(j);
-    const int na = (int)active.size();
-    if (na == 0) return fail(HELIC_ERR_NOCONV, "no active column left below the target");
-    // W = T(R_active) into S columns [n, n + na)
-    Timer tp;
-    HIP_TRY_S(hipMemcpyAsync(d_idx, active.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
-    double* W = col(S, n);
-    hipLaunchKernelGGL(k_gather_cols, dim3(64, na), dim3(NTS), 0, st, R, W, d_idx, L, na);
-    HIP_TRY_S(hipGetLastError());
-    if (hv && it >= hv->next_iter && hv->ncol < hv->max_cols && (int)hv->snaps.size() < hv->n_snap) {
-      if ((s = snapshot(it, active, W, na))) return s;
-    }
-    if (o.precond == 0 || (o.precond == 2 && !learned)) {
-      if ((s = precondition_impl(h, W, L, W, L, na, st))) return s;
-      if (o.precond == 2) ++S_.n_fallback;
-    } else if (o.precond == 2) {
-      std::vector<double> lam_a(na);
-      for (int c = 0; c < na; ++c) lam_a[c] = lam_h[active[c]];
-      HIP_TRY_S(hipMemcpyAsync(d, lam_a.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
-      if ((s = lpc_precondition(h, W, L, d, W, L, na, st))) return s;
-      if ((s = sync())) return s;   // lam_a is read by the copy above
-    }
-    if ((s = sync())) return s;
-    S_.t_precond_ms += tp.ms();
-    // W: project against X twice, orthonormalise, then apply H
-    int nw = 0;
-    {
-      Timer t;
-      for (int rep = 0; rep < 2; ++rep)
-        if ((s = project(S, nullptr, n, W, nullptr, na))) return s;
-      if ((s = ortho_block(W, nullptr, na, &nw))) return s;
-      if ((s = sync())) return s;
-      S_.t_rr_ms += t.ms();
-    }
-    if ((s = apply(W, col(AS, n), nw))) return s;
-    // P after W: project against X and W twice, orthonormalise with H P
-    int npk = 0;
-    if (np > 0) {
-      Timer t;
-      double* P = col(S, n + nw);
-      double* AP = col(AS, n + nw);
-      HIP_TRY_S(hipMemcpyAsync(P, Pb, sizeof(double) * Lc * np, hipMemcpyDeviceToDevice, st));
-      HIP_TRY_S(hipMemcpyAsync(AP, APb, sizeof(double) * Lc * np, hipMemcpyDeviceToDevice, st));
-      // [X W] is orthonormal (W was projected against X and orthonormalised):
-      // one projection against the joint block, twice
-      for (int rep = 0; rep < 2; ++rep)
-        if ((s = project(S, AS, n + nw, P, AP, np))) return s;
-      if ((s = ortho_block(P, AP, np, &npk))) return s;
-      if ((s = sync())) return s;
-      S_.t_rr_ms += t.ms();
-    }
-    const int nx = n - nl;            // unlocked Ritz vectors
-    const int k = nx + nw + npk;
-    if ((s = rayleigh_ritz(nl, k, nx, exact_x ? nx : 0))) return s;
-    exact_x = true;
-    {
-      Timer t;
-      // new P = [W P] C[nx:k, active - nl], H P likewise
-      rel.resize(na);
-      for (int c = 0; c < na; ++c) rel[c] = active[c] - nl;
-      HIP_TRY_S(hipMemcpyAsync(d_idx, rel.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_gather_sub, dim3((k - nx + 63) / 64, na), dim3(64), 0, st, C, kmax, nx, k - nx, d_idx,
-                         na, T1, kmax);
+      // K-step Lanczos from one random column in FP64: the largest Ritz
+      // value plus the last off-diagonal bounds the spectrum from above
+      // (Zhou and Li, 2011)
+      const int K = (int)std::min<int64_t>(12, L);
+      double *v = lz, *vp = lz + Lc, *w = lz + 2 * Lc;
+      hipLaunchKernelGGL(k_random_normal, dim3(64), dim3(NTS), 0, st, v, (int64_t)Lc, o.seed ^ 0x243f6a8885a308d3ull);
       HIP_TRY_S(hipGetLastError());
-      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - nx, &one,
-                           (const zc*)col(S, n), (int)L, (const zc*)T1, kmax, &zero, (zc*)Pb, (int)L));
-      RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - nx, &one,
-                           (const zc*)col(AS, n), (int)L, (const zc*)T1, kmax, &zero, (zc*)APb, (int)L));
-      np = na;
-      HIP_TRY_S(hipMemcpyAsync(col(S, nl), col(Xn, nl), sizeof(double) * Lc * nx, hipMemcpyDeviceToDevice, st));
-      HIP_TRY_S(hipMemcpyAsync(col(AS, nl), col(AXn, nl), sizeof(double) * Lc * nx, hipMemcpyDeviceToDevice, st));
-      if ((s = sync())) return s;   // rel is read by the copy above
+      double nv = 0.0;
+      RB_TRY(rocblas_dznrm2(rb, (int)L, (const zc*)v, 1, &nv));
+      if (!(nv > 0.0)) return fail(HELIC_ERR_NOCONV, "Lanczos start vector vanished");
+      double inv = 1.0 / nv;
+      RB_TRY(rocblas_zdscal(rb, (int)L, &inv, (zc*)v, 1));
+      std::vector<double> al, be;
+      for (int j = 0; j < K; ++j) {
+        Timer t;
+        if ((s = apply_H_impl(h, v, L, w, L, 1, HELIC_FP64, st, chunk))) return s;
+        S_.n_apply += 1;
+        zc dot;
+        RB_TRY(rocblas_zdotc(rb, (int)L, (const zc*)v, 1, (const zc*)w, 1, &dot));
+        S_.t_apply_ms += t.ms();
+        const double a = reinterpret_cast<const double*>(&dot)[0];
+        const zc ma{-a, 0.0};
+        RB_TRY(rocblas_zaxpy(rb, (int)L, &ma, (const zc*)v, 1, (zc*)w, 1));
+        if (j > 0) {
+          const zc mb{-be.back(), 0.0};
+          RB_TRY(rocblas_zaxpy(rb, (int)L, &mb, (const zc*)vp, 1, (zc*)w, 1));
+        }
+        double bn = 0.0;
+        RB_TRY(rocblas_dznrm2(rb, (int)L, (const zc*)w, 1, &bn));
+        al.push_back(a);
+        be.push_back(bn);
+        if (!(bn > 1e-12 * std::max(1.0, std::fabs(a)))) break;   // invariant subspace found
+        double* t0 = vp;
+        vp = v;
+        v = w;
+        w = t0;
+        double ib = 1.0 / bn;
+        RB_TRY(rocblas_zdscal(rb, (int)L, &ib, (zc*)v, 1));
+      }
+      const std::vector<double> off(be.begin(), be.end() - 1);
+      b_up = tridiag_max_eig(al, off) + be.back();
+    }
+    // Hard locking in the FP64 phase: the leading nl columns, converged to
+    // tol, are no longer filtered; the filtered rest is projected against
+    // them and Rayleigh-Ritz runs on the rest only (nl as in LOBPCG below).
+    for (it = 0; it < o.maxit; ++it) {
+      if ((s = residuals(nrm))) return s;
+      for (int j = 0; j < n; ++j)
+        if (!std::isfinite(nrm[j]))
+          return fail(HELIC_ERR_NOCONV, "residual of column " + std::to_string(j) + " is not finite at iteration " +
+                                            std::to_string(it));
+      // the nev lowest by value (the locked prefix and the rest may interleave)
+      double worst = 0.0;
+      {
+        const std::vector<int> ord = lowest_order();
+        for (int q = 0; q < nev; ++q) worst = std::max(worst, nrm[ord[q]]);
+      }
+      if (worst <= o.tol && prec == HELIC_FP64) {
+        converged = true;
+        break;
+      }
+      if (prec != HELIC_FP64 && worst <= switch_tol) {
+        // precision ladder: H X in FP64 and a fresh Rayleigh-Ritz, then FP64 filters
+        prec = HELIC_FP64;
+        if ((s = apply(S, AS, n))) return s;
+        if ((s = rayleigh_ritz(0, n, n, 0))) return s;
+        HIP_TRY_S(hipMemcpyAsync(S, Xn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
+        HIP_TRY_S(hipMemcpyAsync(AS, AXn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
+        --it;
+        continue;
+      }
+      if (o.log_every > 0 && it % o.log_every == 0) {
+        std::fprintf(stderr, "[helic] filter step %d: worst wanted residual %.3e, %d locked, %s H*X, %.1f s\n", it,
+                     worst, nl, prec == HELIC_FP64 ? "FP64" : "FP32", total.ms() / 1e3);
+        std::fflush(stderr);
+      }
+      if (prec != HELIC_FP64) ++S_.iters_low;
+      if (prec == HELIC_FP64)
+        while (nl < n - 1 && nrm[nl] <= o.tol) ++nl;
+      const int nu = n - nl;
+      const int64_t nd = (int64_t)Lc * nu;
+      const int gridc = (int)std::min<int64_t>(4096, (nd + NTS - 1) / NTS);
+      double a = -HUGE_VAL, a0 = HUGE_VAL;
+      for (int j = 0; j < n; ++j) {
+        a = std::max(a, lam_h[j]);
+        a0 = std::min(a0, lam_h[j]);
+      }
+      if (!(b_up > a)) return fail(HELIC_ERR_NOCONV, "spectrum bound does not exceed the Ritz values");
+      const double e = 0.5 * (b_up - a), c = 0.5 * (b_up + a);
+      double sigma = e / (a0 - c);
+      const double tau = 2.0 / sigma;
+      // Y1 = (H X - c X) sigma / e from the Rayleigh-Ritz block and its H X
+      double* const X0 = col(S, nl);
+      double* const AX0 = col(AS, nl);
+      double* prev = X0;
+      double* cur = col(S, n);
+      {
+        Timer t;
+        hipLaunchKernelGGL(k_cheb_step, dim3(gridc), dim3(NTS), 0, st, AX0, X0, (const double*)nullptr, cur, nd,
+                           sigma / e, c, 0.0);
+        HIP_TRY_S(hipGetLastError());
+        S_.t_precond_ms += t.ms();
+      }
+      for (int i = 2; i <= m; ++i) {
+        if ((s = apply(cur, AX0, nu))) return s;
+        const double sigma2 = 1.0 / (tau - sigma);
+        Timer t;
+        // Y_i = (H Y_{i-1} - c Y_{i-1}) 2 sigma2 / e - sigma sigma2 Y_{i-2}, over Y_{i-2}
+        hipLaunchKernelGGL(k_cheb_step, dim3(gridc), dim3(NTS), 0, st, AX0, cur, prev, prev, nd, 2.0 * sigma2 / e,
+                           c, -sigma * sigma2);
+        HIP_TRY_S(hipGetLastError());
+        S_.t_precond_ms += t.ms();
+        std::swap(prev, cur);
+        sigma = sigma2;
+      }
+      Timer t;
+      if (cur != X0) HIP_TRY_S(hipMemcpyAsync(X0, cur, sizeof(double) * nd, hipMemcpyDeviceToDevice, st));
+      for (int rep = 0; rep < 2 && nl > 0; ++rep)
+        if ((s = project(S, nullptr, nl, X0, nullptr, nu))) return s;
+      int kept = 0;
+      if ((s = ortho_block(X0, nullptr, nu, &kept))) return s;
+      if (kept < nu) {
+        // the filter collapsed directions: refill with random columns
+        // orthogonal to the kept ones and the locked ones
+        const int nk = nl + kept;
+        const int64_t nr_ = (int64_t)Lc * (n - nk);
+        hipLaunchKernelGGL(k_random_normal, dim3((int)std::min<int64_t>(4096, (nr_ + NTS - 1) / NTS)), dim3(NTS), 0,
+                           st, col(S, nk), nr_, o.seed + 0x9e37ull * (uint64_t)(it + 1));
+        HIP_TRY_S(hipGetLastError());
+        for (int rep = 0; rep < 2; ++rep)
+          if ((s = project(S, nullptr, nk, col(S, nk), nullptr, n - nk))) return s;
+        int k2 = 0;
+        if ((s = ortho_block(col(S, nk), nullptr, n - nk, &k2))) return s;
+        if (k2 < n - nk) return fail(HELIC_ERR_NOCONV, "filtered block is rank deficient");
+      }
+      if ((s = sync())) return s;
       S_.t_rr_ms += t.ms();
+      if ((s = apply(X0, AX0, nu))) return s;
+      if ((s = rayleigh_ritz(nl, nu, nu, 0))) return s;
+      HIP_TRY_S(hipMemcpyAsync(X0, col(Xn, nl), sizeof(double) * nd, hipMemcpyDeviceToDevice, st));
+      HIP_TRY_S(hipMemcpyAsync(AX0, col(AXn, nl), sizeof(double) * nd, hipMemcpyDeviceToDevice, st));
+    }
+  } else {
+    for (it = 0; it < o.maxit; ++it) {
+      if ((s = residuals(nrm))) return s;
+      for (int j = 0; j < n; ++j)
+        if (!std::isfinite(nrm[j]))
+          return fail(HELIC_ERR_NOCONV, "residual of column " + std::to_string(j) + " is not finite at iteration " +
+                                            std::to_string(it));
+      // the nev lowest by value (the locked prefix and the rest may interleave)
+      bool all = true;
+      double worst = 0.0;
+      {
+        const std::vector<int> ord = lowest_order();
+        for (int q = 0; q < nev; ++q) {
+          all = all && nrm[ord[q]] <= o.tol;
+          worst = std::max(worst, nrm[ord[q]]);
+        }
+      }
+      if (all && prec == HELIC_FP64) {
+        converged = true;
+        break;
+      }
+      if (prec != HELIC_FP64 && worst <= switch_tol) {
+        // precision ladder: recompute H X and H P in FP64 and go on in FP64
+        prec = HELIC_FP64;
+        exact_x = false;   // H X recomputed: X^H H X is no longer exactly diagonal
+        if ((s = apply(S, AS, n))) return s;
+        if ((s = apply(Pb, APb, np))) return s;
+        --it;
+        continue;
+      }
+      if (o.log_every > 0 && it % o.log_every == 0) {
+        std::fprintf(stderr, "[helic] iteration %d: worst wanted residual %.3e, %s H*X, %.1f s\n", it, worst,
+                     prec == HELIC_FP64 ? "FP64" : "FP32", total.ms() / 1e3);
+        std::fflush(stderr);
+      }
+      if (learned) {
+        if (worst < best_worst) {
+          best_worst = worst;
+          stall = 0;
+        } else if (++stall >= 3) {
+          learned = false;
+        }
+      }
+      if (prec != HELIC_FP64) ++S_.iters_low;
+      // In the FP32 phase columns are locked at switch_tol: iterating a column
+      // whose residual is at the FP32 noise floor makes its normalised update
+      // directions amplify the rounding inconsistency between S and H S.
+      const double lock_tol = prec == HELIC_FP64 ? o.tol : std::max(o.tol, switch_tol);
+      if (prec == HELIC_FP64)
+        while (nl < n - 1 && nrm[nl] <= o.tol) ++nl;
+      active.clear();
+      for (int j = nl; j < n; ++j)
+        if (nrm[j] > lock_tol) active.push_back(j);
+      const int na = (int)active.size();
+      if (na == 0) return fail(HELIC_ERR_NOCONV, "no active column left below the target");
+      // W = T(R_active) into S columns [n, n + na)
+      Timer tp;
+      HIP_TRY_S(hipMemcpyAsync(d_idx, active.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
+      double* W = col(S, n);
+      hipLaunchKernelGGL(k_gather_cols, dim3(64, na), dim3(NTS), 0, st, R, W, d_idx, L, na);
+      HIP_TRY_S(hipGetLastError());
+      if (hv && it >= hv->next_iter && hv->ncol < hv->max_cols && (int)hv->snaps.size() < hv->n_snap) {
+        if ((s = snapshot(it, active, W, na))) return s;
+      }
+      if (o.precond == 0 || (o.precond == 2 && !learned)) {
+        if ((s = precondition_impl(h, W, L, W, L, na, st))) return s;
+        if (o.precond == 2) ++S_.n_fallback;
+      } else if (o.precond == 2) {
+        std::vector<double> lam_a(na);
+        for (int c = 0; c < na; ++c) lam_a[c] = lam_h[active[c]];
+        HIP_TRY_S(hipMemcpyAsync(d, lam_a.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
+        if ((s = lpc_precondition(h, W, L, d, W, L, na, st))) return s;
+        if ((s = sync())) return s;   // lam_a is read by the copy above
+      }
+      if ((s = sync())) return s;
+      S_.t_precond_ms += tp.ms();
+      // W: project against X twice, orthonormalise, then apply H
+      int nw = 0;
+      {
+        Timer t;
+        for (int rep = 0; rep < 2; ++rep)
+          if ((s = project(S, nullptr, n, W, nullptr, na))) return s;
+        if ((s = ortho_block(W, nullptr, na, &nw))) return s;
+        if ((s = sync())) return s;
+        S_.t_rr_ms += t.ms();
+      }
+      if ((s = apply(W, col(AS, n), nw))) return s;
+      // P after W: project against X and W twice, orthonormalise with H P
+      int npk = 0;
+      if (np > 0) {
+        Timer t;
+        double* P = col(S, n + nw);
+        double* AP = col(AS, n + nw);
+        HIP_TRY_S(hipMemcpyAsync(P, Pb, sizeof(double) * Lc * np, hipMemcpyDeviceToDevice, st));
+        HIP_TRY_S(hipMemcpyAsync(AP, APb, sizeof(double) * Lc * np, hipMemcpyDeviceToDevice, st));
+        // [X W] is orthonormal (W was projected against X and orthonormalised):
+        // one projection against the joint block, twice
+        for (int rep = 0; rep < 2; ++rep)
+          if ((s = project(S, AS, n + nw, P, AP, np))) return s;
+        if ((s = ortho_block(P, AP, np, &npk))) return s;
+        if ((s = sync())) return s;
+        S_.t_rr_ms += t.ms();
+      }
+      const int nx = n - nl;            // unlocked Ritz vectors
+      const int k = nx + nw + npk;
+      if ((s = rayleigh_ritz(nl, k, nx, exact_x ? nx : 0))) return s;
+      exact_x = true;
+      {
+        Timer t;
+        // new P = [W P] C[nx:k, active - nl], H P likewise
+        rel.resize(na);
+        for (int c = 0; c < na; ++c) rel[c] = active[c] - nl;
+        HIP_TRY_S(hipMemcpyAsync(d_idx, rel.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_gather_sub, dim3((k - nx + 63) / 64, na), dim3(64), 0, st, C, kmax, nx, k - nx, d_idx,
+                           na, T1, kmax);
+        HIP_TRY_S(hipGetLastError());
+        RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - nx, &one,
+                             (const zc*)col(S, n), (int)L, (const zc*)T1, kmax, &zero, (zc*)Pb, (int)L));
+        RB_TRY(rocblas_zgemm(rb, rocblas_operation_none, rocblas_operation_none, (int)L, na, k - nx, &one,
+                             (const zc*)col(AS, n), (int)L, (const zc*)T1, kmax, &zero, (zc*)APb, (int)L));
+        np = na;
+        HIP_TRY_S(hipMemcpyAsync(col(S, nl), col(Xn, nl), sizeof(double) * Lc * nx, hipMemcpyDeviceToDevice, st));
+        HIP_TRY_S(hipMemcpyAsync(col(AS, nl), col(AXn, nl), sizeof(double) * Lc * nx, hipMemcpyDeviceToDevice, st));
+        if ((s = sync())) return s;   // rel is read by the copy above
+        S_.t_rr_ms += t.ms();
+      }
     }
   }
   if (!converged && (s = residuals(nrm))) return s;
@@ -717,7 +918,24 @@ helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* o, doubl
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
   if (o->precond == 2 && !lpc_attached(h)) return fail(HELIC_ERR_STATE, "no learned preconditioner attached");
   try {
-    return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream), nullptr);
+    return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream), nullptr, 0);
+  } catch (const std::bad_alloc&) {
+    return fail(HELIC_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+helic_status helic_eigensolve_chefsi(helic_basis h, const helic_solve_opts* o, int32_t degree, double* evals,
+                                     double* resid, double* evecs, int64_t ldv, helic_solve_stats* stats,
+                                     void* stream) {
+  if (!h || !o || !evals || !resid) return fail(HELIC_ERR_INVALID, "null argument");
+  if (o->nev < 1 || o->nev > h->L || o->block < 1 || !(o->tol > 0) || o->maxit < 0 ||
+      (evecs && ldv < h->L) || degree < 0 || degree > 200)
+    return fail(HELIC_ERR_INVALID, "bad solver options");
+  if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
+  try {
+    return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream), nullptr,
+                           degree > 0 ? degree : CHEB_DEGREE_AUTO);
   } catch (const std::bad_alloc&) {
     return fail(HELIC_ERR_NOMEM, "host allocation failed");
   }
@@ -744,7 +962,7 @@ helic_status helic_lpc_harvest(helic_basis h, const helic_solve_opts* o, int32_t
     hv.lam = lam;
     std::vector<double> ev(o->nev), rs(o->nev);
     helic_status s = eigensolve_impl(h, *o, ev.data(), rs.data(), nullptr, 0, stats,
-                                     reinterpret_cast<hipStream_t>(stream), &hv);
+                                     reinterpret_cast<hipStream_t>(stream), &hv, 0);
     if (s) return s;
     *ncol = hv.ncol;
     return HELIC_OK;

@@ -27,7 +27,7 @@ PREC = {"fp64": FP64, "fp32": FP32}
 EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "helic_basis_indices",
            "helic_grid", "helic_set_potential", "helic_apply_H", "helic_transform_inverse",
            "helic_transform_forward", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
-           "helic_eigensolve_ex", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
+           "helic_eigensolve_ex", "helic_eigensolve_chefsi", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
            "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
            "helic_batch_eigensolve",
            "helic_lpc_create", "helic_lpc_destroy", "helic_lpc_get_params", "helic_lpc_set_params",
@@ -104,6 +104,8 @@ def load() -> ctypes.CDLL:
         "helic_eigensolve": [_P, _I32, _I32, _D, _I32, _I32, ctypes.c_uint64, _PD, _PD, _P, _I64,
                              _PI32, _P],
         "helic_eigensolve_ex": [_P, ctypes.POINTER(SolveOpts), _PD, _PD, _P, _I64, ctypes.POINTER(SolveStats), _P],
+        "helic_eigensolve_chefsi": [_P, ctypes.POINTER(SolveOpts), _I32, _PD, _PD, _P, _I64,
+                                    ctypes.POINTER(SolveStats), _P],
         "helic_batch_create": [ctypes.POINTER(_P), _I32, ctypes.POINTER(_P)],
         "helic_batch_destroy": [_P],
         "helic_batch_info": [_P, _PI64],
@@ -307,9 +309,10 @@ def eigensolve(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, evecs
 
 
 def eigensolve_ex(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa", guard=-1,
-                  switch_tol=1e-4, evecs=None, log_every=0, stream=None):
+                  switch_tol=1e-4, evecs=None, log_every=0, stream=None, cheb_degree=None):
     """Returns (evals, resid, stats dict, status); raises on errors other
-    than non-convergence."""
+    than non-convergence.  cheb_degree (an int, 0 = automatic) selects the
+    Chebyshev-filtered subspace iteration instead of LOBPCG."""
     o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=PREC[prec], seed=seed,
                   precond=PRECOND[precond], guard=guard, switch_tol=switch_tol, log_every=log_every)
     evals = np.zeros(nev)
@@ -322,8 +325,14 @@ def eigensolve_ex(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, pr
         vptr = ctypes.c_void_p(evecs.data_ptr())
     else:
         ldv, vptr = 0, ctypes.c_void_p(0)
-    status = load().helic_eigensolve_ex(h, ctypes.byref(o), _ptr(evals, ctypes.c_double),
-                                        _ptr(resid, ctypes.c_double), vptr, ldv, ctypes.byref(st), _stream(stream))
+    if cheb_degree is None:
+        status = load().helic_eigensolve_ex(h, ctypes.byref(o), _ptr(evals, ctypes.c_double),
+                                            _ptr(resid, ctypes.c_double), vptr, ldv, ctypes.byref(st),
+                                            _stream(stream))
+    else:
+        status = load().helic_eigensolve_chefsi(h, ctypes.byref(o), int(cheb_degree), _ptr(evals, ctypes.c_double),
+                                                _ptr(resid, ctypes.c_double), vptr, ldv, ctypes.byref(st),
+                                                _stream(stream))
     if status not in (OK, ERR_NOCONV):
         _check(status)
     stats = st.as_dict()

@@ -157,3 +157,93 @@ def test_full_size_eigenpairs_certified_by_the_oracle():
         r = np.linalg.norm(HX[:, i] - ev[j] * x) / np.linalg.norm(x)
         print(f"[full size] pair {j}: lambda {ev[j]:.10f} oracle residual {r:.2e}", flush=True)
         assert r <= 1.05e-8
+
+
+# ---- Chebyshev-filtered subspace iteration (helic_eigensolve_chefsi): same
+# eigenvalue bound as the LOBPCG tests above (residual <= tol places an exact
+# eigenvalue within tol), against the same oracle.
+
+def test_chefsi_tiny_matches_lapack():
+    w = synth.workload("tiny-helix")
+    o, b, V = _setup(w)
+    ref, _ = oh.lowest(oh.dense_explicit(o, V), w.nev)
+    for deg in (0, 8):
+        ev, res, st, status = b.eigensolve_ex(w.nev, tol=1e-9, maxit=300, seed=7, cheb_degree=deg)
+        print(f"[tiny chefsi deg {deg}] steps {st['iters']} max|dlambda| {np.max(np.abs(ev - ref)):.2e} "
+              f"max res {res.max():.2e}", flush=True)
+        assert status == helic.OK, st["message"]
+        assert np.all(res <= 1e-9)
+        assert np.max(np.abs(ev - ref)) < EIG_TOL
+
+
+def test_chefsi_mixed_precision_refines_to_fp64_accuracy():
+    w = synth.workload("tiny-helix")
+    o, b, V = _setup(w)
+    ref, _ = oh.lowest(oh.dense_explicit(o, V), w.nev)
+    ev, res, st, status = b.eigensolve_ex(w.nev, tol=1e-9, maxit=300, prec="fp32", switch_tol=1e-4,
+                                          cheb_degree=16)
+    assert status == helic.OK, st["message"]
+    assert st["iters_low"] > 0
+    assert np.max(np.abs(ev - ref)) < EIG_TOL
+
+
+def test_chefsi_free_particle_closed_form():
+    w = synth.Workload(name="free", R=6.0, tau=5.0, alpha=0.2, ecut=10.0, eta=0.3, n_t1=24, n_t2=32, n_r=48,
+                       nev=12)
+    o, b, V = _setup(w, potential=False)
+    ev, res, st, status = b.eigensolve_ex(w.nev, tol=1e-9, maxit=300, cheb_degree=0)
+    assert status == helic.OK, st["message"]
+    np.testing.assert_allclose(ev, np.sort(o.kappa)[:w.nev], atol=EIG_TOL)
+
+
+def test_chefsi_midsize_nanotube_against_dense_oracle():
+    w = synth.workload("nanotube-ecut25").with_(name="nanotube-ecut6", ecut=6.0, n_t1=24, n_t2=32, n_r=64,
+                                                 nev=40)
+    o, b, V = _setup(w)
+    ref, _ = oh.lowest(oh.dense_dft(o, V), w.nev)
+    ev, res, st, status = b.eigensolve_ex(w.nev, tol=1e-9, maxit=300, cheb_degree=0)
+    print(f"[mid chefsi] steps {st['iters']} applications {st['n_apply']} max|dlambda| "
+          f"{np.max(np.abs(ev - ref)):.2e}", flush=True)
+    assert status == helic.OK, st["message"]
+    assert np.max(np.abs(ev - ref)) < EIG_TOL
+
+
+def test_chefsi_full_size_certified_by_the_oracle():
+    """nanotube-ecut25, 120 pairs (the benchmark's solve) by the filtered
+    solver: sampled pairs certified by the oracle's matrix-free H as in the
+    LOBPCG test; both solvers must agree on all 120 eigenvalues."""
+    w = synth.workload("nanotube-ecut25")
+    o, b, V = _setup(w)
+    evecs = torch.zeros((w.nev, b.L), dtype=torch.complex128, device=_dev())
+    ev, res, st, status = b.eigensolve_ex(w.nev, tol=1e-8, maxit=200, seed=5, evecs=evecs, cheb_degree=0)
+    assert status == helic.OK, st["message"]
+    evl, _, stl, sl = b.eigensolve_ex(w.nev, tol=1e-8, maxit=1000, seed=7)
+    assert sl == helic.OK
+    print(f"[full size chefsi] steps {st['iters']} applications {st['n_apply']} vs LOBPCG its {stl['iters']}: "
+          f"max|dlambda| {np.max(np.abs(ev - evl)):.2e}", flush=True)
+    assert np.max(np.abs(ev - evl)) < 2e-8
+    mnk, _ = b.indices()
+    pos = {tuple(t): i for i, t in enumerate(o.mnk.tolist())}
+    perm = np.array([pos[tuple(t)] for t in mnk.tolist()])
+    cols = [0, w.nev // 2, w.nev - 1]
+    Xg = evecs[cols].cpu().numpy().T
+    X = np.empty_like(Xg)
+    X[perm] = Xg
+    HX = oh.apply(o, V, X)
+    for i, j in enumerate(cols):
+        x = X[:, i]
+        r = np.linalg.norm(HX[:, i] - ev[j] * x) / np.linalg.norm(x)
+        print(f"[full size chefsi] pair {j}: lambda {ev[j]:.10f} oracle residual {r:.2e}", flush=True)
+        assert r <= 1.05e-8
+
+
+def test_chefsi_argument_errors():
+    w = synth.workload("tiny-helix")
+    o, b, V = _setup(w)
+    for deg in (-1, 201):
+        with pytest.raises(helic.HelicError) as e:
+            b.eigensolve_ex(4, cheb_degree=deg)
+        assert e.value.status == helic.ERR_INVALID
+    ev, res, st, status = b.eigensolve_ex(4, tol=1e-14, maxit=1, cheb_degree=4)
+    assert status == helic.ERR_NOCONV and st["iters"] == 1
+    assert np.all(np.isfinite(ev)) and np.all(res > 0)
