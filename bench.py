@@ -87,7 +87,7 @@ def cpu_baseline(w, nsample: int):
                 f"64 block vectors of {w.name}, {wall:.1f} s wall on {os.cpu_count()} host cores")
 
 
-def time_to_eigenpairs(b, w, torch, tol=1e-8):
+def time_to_eigenpairs(b, w, torch, tol=1e-8, solvers=("lobpcg", "chefsi")):
     """Lowest w.nev eigenpairs to ||H x - lambda x|| <= tol from the same
     seeded random start, FP64 H*X and mixed (FP32 H*X, FP64 refinement); all
     keep the FP64 Rayleigh-Ritz.  Two solvers: LOBPCG with the TPA
@@ -101,8 +101,8 @@ def time_to_eigenpairs(b, w, torch, tol=1e-8):
     # warm-up: library handles and kernels of both solvers loaded before timing
     b.eigensolve_ex(4, tol=1e-3, maxit=2)
     b.eigensolve_ex(4, tol=1e-3, maxit=1, cheb_degree=2)
-    runs = (("fp64", None, "fp64"), ("fp32", None, "mixed_fp32_fp64"),
-            ("fp64", 0, "chefsi_fp64"), ("fp32", 0, "chefsi_mixed_fp32_fp64"))
+    runs = ((("fp64", None, "fp64"), ("fp32", None, "mixed_fp32_fp64")) if "lobpcg" in solvers else ()) + \
+           ((("fp64", 0, "chefsi_fp64"), ("fp32", 0, "chefsi_mixed_fp32_fp64")) if "chefsi" in solvers else ())
     for prec, deg, key in runs:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -116,6 +116,8 @@ def time_to_eigenpairs(b, w, torch, tol=1e-8):
         evs[key] = ev
         print(f"[bench] eigensolve {key}: {wall:.2f} s, {st['iters']} iterations, converged {status == 0}",
               file=sys.stderr, flush=True)
+    if "lobpcg" not in solvers or "chefsi" not in solvers:
+        return out
     d = np.abs(evs["mixed_fp32_fp64"] - evs["fp64"])
     out["mixed_vs_fp64_max_abs_Ha"] = float(d.max())
     out["speedup_mixed"] = round(out["fp64"]["seconds"] / out["mixed_fp32_fp64"]["seconds"], 3)
@@ -313,6 +315,8 @@ def main(argv=None):
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"))
     ap.add_argument("--cpu-sample", type=int, default=64, help="vectors for the CPU oracle leg (0: skip)")
     ap.add_argument("--eig", type=int, default=1, help="also time the eigensolve (FP64 and mixed) (0: skip)")
+    ap.add_argument("--eig-solvers", default="lobpcg,chefsi",
+                    help="comma list of eigensolvers the eigensolve leg times (lobpcg, chefsi)")
     ap.add_argument("--batched", default="4",
                     help="structures (0..7, comma list, 'all' or 'none') for the batched Bloch-parameter leg")
     ap.add_argument("--learned", default="same",
@@ -423,7 +427,7 @@ def main(argv=None):
         "stages": stage_info,
     }
     if args.eig:
-        line["eigensolve"] = time_to_eigenpairs(b, w, torch)
+        line["eigensolve"] = time_to_eigenpairs(b, w, torch, solvers=tuple(args.eig_solvers.split(",")))
     if args.batched != "none":
         structs = list(range(8)) if args.batched == "all" else [int(x) for x in args.batched.split(",")]
         line["batched"] = batched_leg(torch, structs)

@@ -28,6 +28,7 @@ import sys
 
 
 def short_name(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     m = re.match(r"(?:void )?([\w:]+(?:<[^()]*>)?)\(", name)
     return m.group(1) if m else name[:80]
 
