@@ -25,6 +25,8 @@ transparency over speed:
                     as a dense matrix built two independent ways, as a
                     matrix-free apply, and its lowest eigenpairs by LAPACK.
 * ``precond``    -- the Teter-Payne-Allan diagonal preconditioner (Sec. 3.5).
+* ``density``    -- the electron density sum_j occ_j |phi_j|^2 on the grid
+                    (Sec. 4.2, the density equation, one (eta, nu) term).
 * ``mlp``        -- forward and backward pass of the small per-coefficient
                     network used as a learned preconditioner (no paper source;
                     it exists to check the GPU kernels' gradients).

@@ -372,3 +372,45 @@ def test_potential_diagonal_is_the_dense_diagonal():
     H = oh.dense_explicit(b, V)
     vd = oh.potential_diagonal(b, V)
     np.testing.assert_allclose(vd, np.real(np.diag(H)) - b.kappa, rtol=0, atol=1e-12 * np.abs(V).max())
+
+
+# ------------------------------------------------------------------ density
+def test_density_integral_is_the_weighted_norm_sum(tiny):
+    """Parseval on the grid: sum_g W_g rho_g = sum_j occ_j ||x_j||^2 (the
+    quadrature integrates |phi|^2 of band-limited functions exactly)."""
+    from oracle import density as od
+    w, b, V, B = tiny
+    X = synth.random_block(b.mnk, 5, 21)
+    occ = np.array([2.0, 2.0, 1.5, 0.5, 0.25])
+    rho = od.density(b, X, occ)
+    W = ot.grid_weights(b)
+    want = float(np.sum(occ * np.sum(np.abs(X) ** 2, axis=0)))
+    assert rho.min() >= 0.0
+    assert abs(np.sum(W * rho) - want) < 1e-12 * want
+
+
+def test_density_of_one_basis_function_is_its_radial_factor_squared(tiny):
+    """|F_mnk|^2 = xi_{n,k}(r)^2 at every angle (the angular factors have unit
+    modulus): the closed form of a one-state density."""
+    from oracle import density as od
+    w, b, V, B = tiny
+    for i in (0, b.L // 3, b.L - 1):
+        x = np.zeros(b.L, dtype=np.complex128)
+        x[i] = 1.0
+        rho = od.density(b, x, np.array([1.0]))
+        m, n, k = b.mnk[i]
+        xi = b.xi(int(n), np.array([k]))[:, 0]
+        want = np.broadcast_to(xi ** 2, rho.shape)
+        assert np.max(np.abs(rho - want)) < 1e-12 * np.max(want)
+
+
+def test_density_against_the_basis_matrix(tiny):
+    """The same density from the naive inverse transform (explicit basis
+    matrix, eq. Naive_Inverse_Transform)."""
+    from oracle import density as od
+    w, b, V, B = tiny
+    X = synth.random_block(b.mnk, 3, 22)
+    occ = np.array([1.0, 0.75, 0.5])
+    g = ot.inverse_naive(b, X, B)
+    want = np.einsum("ijlv,v->ijl", np.abs(g) ** 2, occ)
+    assert np.max(np.abs(od.density(b, X, occ) - want)) < 1e-12 * np.max(want)
