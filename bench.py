@@ -128,6 +128,35 @@ def time_to_eigenpairs(b, w, torch, tol=1e-8, solvers=("lobpcg", "chefsi")):
     return out
 
 
+def density_leg(b, w, torch, nstates=None, reps=5):
+    """Electron density (Sec. 4.2) of nstates (default: the solve's nev)
+    normalised synthetic states with occupation 2, resident in HBM: wall time
+    of helic_density (inverse transforms to the grid plus the weighted
+    |phi|^2 accumulation) and its integral against 2 * nstates."""
+    import numpy as np
+    import synth
+    n = nstates or w.nev
+    mnk, _ = b.indices()
+    X = torch.from_numpy(np.ascontiguousarray(synth.random_block(mnk, n, 41).T)).cuda()
+    X /= torch.linalg.vector_norm(X, dim=1, keepdim=True)
+    t1, t2, r, wts = b.grid()
+    rho = torch.empty(len(t1) * len(t2) * len(r), dtype=torch.float64, device="cuda")
+    occ = np.full(n, 2.0)
+    b.density(X, occ, rho)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.density(X, occ, rho)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    # weight of a grid point: 2 pi tau / (N_theta1 N_theta2) (cyclic order 1) times omega_r = R^2 w_r
+    cell = 2.0 * np.pi * w.tau / (len(t1) * len(t2)) * w.R ** 2 * wts
+    W = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(cell, (len(t1), len(t2), len(r))).reshape(-1))).cuda()
+    integral = float((W * rho).sum())
+    return dict(states=n, occupation=2.0, ms=round(1e3 * dt, 3), states_per_s=round(n / dt, 1),
+                integral=integral, integral_rel_err=abs(integral - 2.0 * n) / (2.0 * n))
+
+
 # Angular-stage kernel the library selects for a grid (its variant tables:
 # convolution kernel for theta2 sizes 16, 64, 81; register-FFT kernel for the
 # listed (theta1, theta2) grids; the general LDS FFT otherwise).
@@ -428,6 +457,7 @@ def main(argv=None):
     }
     if args.eig:
         line["eigensolve"] = time_to_eigenpairs(b, w, torch, solvers=tuple(args.eig_solvers.split(",")))
+        line["density"] = density_leg(b, w, torch)
     if args.batched != "none":
         structs = list(range(8)) if args.batched == "all" else [int(x) for x in args.batched.split(",")]
         line["batched"] = batched_leg(torch, structs)

@@ -129,6 +129,20 @@ helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx
 helic_status helic_transform_forward(helic_basis h, const double* g, double* X, int64_t ldx,
                                      int32_t nvec, void* stream);
 
+/* Electron density on the grid (Sec. 4.2, the density equation, one (eta_b,
+ * nu) term of its sums): rho = sum_j occ_j |phi_j|^2, phi_j the inverse
+ * transform (Alg. 1 and 2) of coefficient column j of X (device block, see
+ * conventions).  occ (host, nvec doubles) carries each state's whole weight,
+ * (2 / N) w_b s_j, so that the caller sums several calls over (eta_b, nu)
+ * with accumulate = 1.  rho (device, n_t1*n_t2*n_r doubles in the
+ * potential's order: theta1 outermost, r fastest) is overwritten
+ * (accumulate = 0) or added to (1); nvec = 0 with accumulate = 0 zeroes it.
+ * FP64; the states are summed in column order (deterministic).  The first
+ * call grows a real-space workspace of 16 grids (hipMalloc); no potential
+ * is needed.  Synchronises `stream` before returning. */
+helic_status helic_density(helic_basis h, const double* X, int64_t ldx, int32_t nvec,
+                           const double* occ, double* rho, int32_t accumulate, void* stream);
+
 /* Timing aid: run `nrep` applications of H to the same block exactly as
  * helic_apply_H does (nvec <= 64), recording HIP events on `stream` around
  * each of the three stage kernels (radial inverse, angular, radial forward).

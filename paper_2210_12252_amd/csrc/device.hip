@@ -516,6 +516,24 @@ k_potential_diagonal(const DGroup* __restrict__ groups, const int32_t* __restric
   for (int64_t row = g.row0 + threadIdx.x; row < g.row0 + g.nrows; row += NT) vdiag[row] = per_k[row_ck[row] & 0xffff];
 }
 
+// Electron density (Sec. 4.2): rho[p] (+)= sum_v occ[v] |g_v[p]|^2 over the
+// npts grid points, g holding nv real-space grids of complex values.  One
+// thread per point, states in order, so the sum is deterministic.  HBM-bound:
+// 16 bytes read per state and point.
+__global__ void __launch_bounds__(NT)
+k_density_accum(const double* __restrict__ g, int nv, int64_t npts, const double* __restrict__ occ,
+                double* __restrict__ rho, int accumulate) {
+  const double2* z = reinterpret_cast<const double2*>(g);
+  for (int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x; p < npts; p += (int64_t)gridDim.x * NT) {
+    double s = accumulate ? rho[p] : 0.0;
+    for (int v = 0; v < nv; ++v) {
+      const double2 c = z[(int64_t)v * npts + p];
+      s += occ[v] * (c.x * c.x + c.y * c.y);
+    }
+    rho[p] = s;
+  }
+}
+
 // Vs[r][i1][i2] = scale * V[i1][i2][r] (and the single-precision copy)
 __global__ void __launch_bounds__(NT)
 k_relayout_potential(const double* __restrict__ V, double* __restrict__ Vs, float* __restrict__ Vsf,
@@ -1190,7 +1208,8 @@ void device_release(helic_basis_s* h) {
   if (!d) return;
   void* ptrs[] = {d->groups, d->modes, d->row_ck, d->kappa, d->rows1, d->tinv64, d->tfwd64,
                   d->tinv32, d->tfwd32, d->tw1, d->tw2, d->tw1f, d->tw2f, d->Vs, d->Vsf,
-                  d->gh, d->part, d->mode_pos, d->blk_mode, d->Vh, d->Vhf, d->probs64, d->probs32, d->vdiag, d->lpc_ws};
+                  d->gh, d->part, d->mode_pos, d->blk_mode, d->Vh, d->Vhf, d->probs64, d->probs32, d->vdiag, d->lpc_ws,
+                  d->dens_ws, d->dens_occ};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   release_solver_state(d);
@@ -1437,6 +1456,53 @@ helic_status helic_transform_forward(helic_basis h, const double* g, double* X, 
                                   X + (int64_t)v0 * ldx * 2, ldx, nv, ng, h->n_r, d->groups, d->probs64, 0);
     HIP_TRY(hipGetLastError());
   }
+  return HELIC_OK;
+}
+
+helic_status helic_density(helic_basis h, const double* X, int64_t ldx, int32_t nvec, const double* occ,
+                           double* rho, int32_t accumulate, void* stream) {
+  if (!h) return fail(HELIC_ERR_INVALID, "null handle");
+  if (nvec < 0 || (nvec > 0 && (!X || !occ)) || !rho || ldx < h->L) return fail(HELIC_ERR_INVALID, "bad arguments");
+  helic_status s = ensure_device(h);
+  if (s != HELIC_OK) return s;
+  DeviceState* d = h->dev;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t npts = (int64_t)h->n_t1 * h->n_t2 * h->n_r;
+  const unsigned nb = (unsigned)std::min<int64_t>(4096, (npts + NT - 1) / NT);
+  if (nvec == 0) {
+    if (!accumulate) {
+      hipLaunchKernelGGL(k_density_accum, dim3(nb), dim3(NT), 0, st, (const double*)nullptr, 0, npts,
+                         (const double*)nullptr, rho, 0);
+      HIP_TRY(hipGetLastError());
+    }
+    return HELIC_OK;
+  }
+  const int chunk = std::min(nvec, DENSITY_CHUNK);
+  const size_t need = (size_t)chunk * npts * 2 * sizeof(double);
+  if (need > d->dens_ws_bytes) {
+    if (d->dens_ws) HIP_TRY(hipFree(d->dens_ws));
+    d->dens_ws = nullptr;
+    d->dens_ws_bytes = 0;
+    HIP_TRY(hipMalloc((void**)&d->dens_ws, need));
+    d->dens_ws_bytes = need;
+  }
+  if ((size_t)nvec > d->dens_occ_n) {
+    if (d->dens_occ) HIP_TRY(hipFree(d->dens_occ));
+    d->dens_occ = nullptr;
+    d->dens_occ_n = 0;
+    HIP_TRY(hipMalloc((void**)&d->dens_occ, sizeof(double) * nvec));
+    d->dens_occ_n = nvec;
+  }
+  HIP_TRY(hipMemcpyAsync(d->dens_occ, occ, sizeof(double) * nvec, hipMemcpyHostToDevice, st));
+  for (int v0 = 0; v0 < nvec; v0 += chunk) {
+    const int nv = std::min(chunk, nvec - v0);
+    if ((s = helic_transform_inverse(h, X + (int64_t)v0 * ldx * 2, ldx, d->dens_ws, nv, stream)) != HELIC_OK)
+      return s;
+    hipLaunchKernelGGL(k_density_accum, dim3(nb), dim3(NT), 0, st, d->dens_ws, nv, npts, d->dens_occ + v0, rho,
+                       (v0 > 0 || accumulate) ? 1 : 0);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(st));
   return HELIC_OK;
 }
 

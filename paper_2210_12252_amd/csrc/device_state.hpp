@@ -11,6 +11,9 @@ namespace helic {
 // Vectors per launch of the H*X stages; bounds the intermediate buffer to
 // APPLY_CHUNK * n_r * n_modes complex values.
 constexpr int APPLY_CHUNK = 64;
+// States per real-space workspace pass of the density (n_t1*n_t2*n_r complex
+// values each).
+constexpr int DENSITY_CHUNK = 16;
 
 struct SolverState;
 }  // namespace helic
@@ -51,6 +54,10 @@ struct DeviceState {
   DProb* probs32 = nullptr;
   double* part = nullptr;
   size_t part_bytes = 0;
+  double* dens_ws = nullptr;      // density: real-space grids of one chunk of states
+  size_t dens_ws_bytes = 0;
+  double* dens_occ = nullptr;     // density: per-state weights
+  size_t dens_occ_n = 0;
   SolverState* solver = nullptr;
   // learned preconditioner: attached network, potential diagonal V_ii per
   // row (L values, then the n_r angular means; set with the potential),

@@ -26,7 +26,7 @@ PREC = {"fp64": FP64, "fp32": FP32}
 # every function declared in include/helic.h
 EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "helic_basis_indices",
            "helic_grid", "helic_set_potential", "helic_apply_H", "helic_transform_inverse",
-           "helic_transform_forward", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
+           "helic_transform_forward", "helic_density", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
            "helic_eigensolve_ex", "helic_eigensolve_chefsi", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
            "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
            "helic_batch_eigensolve",
@@ -99,6 +99,7 @@ def load() -> ctypes.CDLL:
         "helic_apply_H": [_P, _P, _I64, _P, _I64, _I32, _I32, _P],
         "helic_transform_inverse": [_P, _P, _I64, _P, _I32, _P],
         "helic_transform_forward": [_P, _P, _P, _I64, _I32, _P],
+        "helic_density": [_P, _P, _I64, _I32, _PD, _P, _I32, _P],
         "helic_precondition": [_P, _P, _I64, _P, _I64, _I32, _P],
         "helic_profile_apply": [_P, _P, _I64, _P, _I64, _I32, _I32, _I32, _P, _PD, _PD],
         "helic_eigensolve": [_P, _I32, _I32, _D, _I32, _I32, ctypes.c_uint64, _PD, _PD, _P, _I64,
@@ -254,6 +255,21 @@ def transform_inverse(h, X, g, stream=None):
         raise ValueError("g too small or not contiguous")
     _check(load().helic_transform_inverse(h, ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(g.data_ptr()),
                                           nx, _stream(stream)))
+
+
+def density(h, X, occ, rho, accumulate=False, stream=None):
+    """rho (float64 HIP tensor, n_t1*n_t2*n_r values) = or += sum_j occ[j]
+    |inverse transform of X's column j|^2; occ: one weight per column."""
+    nx, ldx = _block(X, "X")
+    i = basis_info(h)
+    occ = np.ascontiguousarray(occ, dtype=np.float64)
+    if occ.size != nx:
+        raise ValueError("occ needs one weight per column of X")
+    if not (rho.is_cuda and rho.is_contiguous() and str(rho.dtype) == "torch.float64"
+            and rho.numel() >= i["n_t1"] * i["n_t2"] * i["n_r"]):
+        raise ValueError("rho must be a contiguous float64 HIP tensor of n_t1*n_t2*n_r values")
+    _check(load().helic_density(h, ctypes.c_void_p(X.data_ptr()), ldx, nx, _ptr(occ, ctypes.c_double),
+                                ctypes.c_void_p(rho.data_ptr()), 1 if accumulate else 0, _stream(stream)))
 
 
 def transform_forward(h, g, X, stream=None):
@@ -504,6 +520,9 @@ class Basis:
 
     def transform_forward(self, g, X, stream=None):
         transform_forward(self.h, g, X, stream)
+
+    def density(self, X, occ, rho, accumulate=False, stream=None):
+        density(self.h, X, occ, rho, accumulate, stream)
 
     def precondition(self, R, W, stream=None):
         precondition(self.h, R, W, stream)

@@ -1,0 +1,137 @@
+"""GPU electron density (helic_density, Sec. 4.2) against the CPU oracle.
+
+Tolerance: rho is a weighted sum of squared moduli of FP64 inverse
+transforms, which agree with the oracle's explicit sums to 1e-12 of the
+column maximum (the transform parity bound); squaring doubles the relative
+error and the positive weights do not cancel, so rho agrees to 4e-12 of its
+largest value.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import basis as ob
+from oracle import density as od
+from oracle import transforms as ot
+
+torch = pytest.importorskip("torch")
+helic = pytest.importorskip("paper_2210_12252_amd.helic")
+
+pytestmark = pytest.mark.gpu
+TOL = 4e-12
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+class Case:
+    def __init__(self, w):
+        self.o = ob.basis_for(w)
+        self.g = helic.Basis.from_workload(w)
+        mnk, _ = self.g.indices()
+        pos = {tuple(t): i for i, t in enumerate(self.o.mnk.tolist())}
+        self.perm = np.array([pos[tuple(t)] for t in mnk.tolist()])   # gpu row -> oracle row
+        self.npts = self.o.n_t1 * self.o.n_t2 * self.o.n_r
+        print(f"[density case] {w.name} L={self.o.L} grid={self.o.n_t1}x{self.o.n_t2}x{self.o.n_r}", flush=True)
+
+    def block(self, Xo):
+        return torch.from_numpy(np.ascontiguousarray(Xo[self.perm].T)).to(_dev())
+
+    def rho(self):
+        return torch.full((self.npts,), np.nan, dtype=torch.float64, device=_dev())
+
+    def host(self, rho):
+        return rho.cpu().numpy().reshape(self.o.n_t1, self.o.n_t2, self.o.n_r)
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    _dev()
+    return Case(synth.workload("tiny-helix"))
+
+
+def test_density_matches_oracle_ragged_chunks(tiny):
+    # 37 states: two full workspace passes of 16 and a ragged tail of 5
+    X = synth.random_block(tiny.o.mnk, 37, 31)
+    occ = np.random.default_rng(3).uniform(0.1, 2.0, 37)
+    rho = tiny.rho()
+    tiny.g.density(tiny.block(X), occ, rho)
+    ref = od.density(tiny.o, X, occ)
+    assert _rel(tiny.host(rho), ref) < TOL
+
+
+def test_density_accumulates_and_zeroes(tiny):
+    X = synth.random_block(tiny.o.mnk, 21, 32)
+    occ = np.linspace(0.5, 2.0, 21)
+    whole = tiny.rho()
+    tiny.g.density(tiny.block(X), occ, whole)
+    parts = tiny.rho()
+    tiny.g.density(tiny.block(X[:, :9]), occ[:9], parts)
+    tiny.g.density(tiny.block(X[:, 9:]), occ[9:], parts, accumulate=True)
+    assert _rel(tiny.host(parts), tiny.host(whole)) < 1e-15
+    # no states: accumulate leaves rho alone, overwrite zeroes it
+    empty = torch.zeros((0, tiny.o.L), dtype=torch.complex128, device=_dev())
+    before = parts.clone()
+    load = helic.load()
+    import ctypes
+    st = load.helic_density(tiny.g.h, None, tiny.o.L, 0, None, ctypes.c_void_p(parts.data_ptr()), 1, None)
+    assert st == helic.OK and torch.equal(parts, before)
+    st = load.helic_density(tiny.g.h, None, tiny.o.L, 0, None, ctypes.c_void_p(parts.data_ptr()), 0, None)
+    torch.cuda.synchronize()
+    assert st == helic.OK and float(parts.abs().max()) == 0.0
+    del empty
+
+
+def test_density_argument_errors(tiny):
+    import ctypes
+    rho = tiny.rho()
+    load = helic.load()
+    # states requested without coefficients, a short leading dimension, no output
+    assert load.helic_density(tiny.g.h, None, tiny.o.L, 3, None, ctypes.c_void_p(rho.data_ptr()), 0,
+                              None) == helic.ERR_INVALID
+    X = tiny.block(synth.random_block(tiny.o.mnk, 2, 33))
+    occ = np.ones(2)
+    occp = occ.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert load.helic_density(tiny.g.h, ctypes.c_void_p(X.data_ptr()), tiny.o.L - 1, 2, occp,
+                              ctypes.c_void_p(rho.data_ptr()), 0, None) == helic.ERR_INVALID
+    assert load.helic_density(tiny.g.h, ctypes.c_void_p(X.data_ptr()), tiny.o.L, 2, occp, None, 0,
+                              None) == helic.ERR_INVALID
+    with pytest.raises(ValueError):
+        tiny.g.density(X, np.ones(3), rho)
+
+
+def test_density_full_size_eigenstates():
+    """nanotube-ecut25: the density of the 120 lowest states (occupation 2)
+    integrates to 240 (normalised eigenvectors, exact quadrature of |phi|^2),
+    and the density of three of them matches the oracle point by point."""
+    _dev()
+    w = synth.workload("nanotube-ecut25")
+    c = Case(w)
+    atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
+    V = synth.potential_at(c.o.theta1, c.o.theta2, c.o.r, w.tau, w.alpha, atoms)
+    c.g.set_potential(torch.from_numpy(V).to(_dev()))
+    evecs = torch.zeros((w.nev, c.g.L), dtype=torch.complex128, device=_dev())
+    ev, res, st, status = c.g.eigensolve_ex(w.nev, tol=1e-8, maxit=200, evecs=evecs, cheb_degree=0)
+    assert status == helic.OK
+    rho = c.rho()
+    c.g.density(evecs, np.full(w.nev, 2.0), rho)
+    W = ot.grid_weights(c.o)
+    total = float(np.sum(W * c.host(rho)))
+    print(f"[density full size] integral {total:.12f} (want {2.0 * w.nev})", flush=True)
+    assert abs(total - 2.0 * w.nev) < 1e-9 * 2.0 * w.nev
+    cols = [0, w.nev // 2, w.nev - 1]
+    occ = np.array([2.0, 1.0, 0.5])
+    sub = torch.stack([evecs[j] for j in cols])
+    c.g.density(sub, occ, rho)
+    Xg = sub.cpu().numpy().T
+    Xo = np.empty_like(Xg)
+    Xo[c.perm] = Xg
+    ref = od.density(c.o, Xo, occ)
+    assert _rel(c.host(rho), ref) < TOL
