@@ -175,8 +175,9 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
     E_cut ~ U[15, 35]): per structure one batch with a common grid (the
     largest automatic grid over its eta), tuned, captured in a HIP graph and
     replayed; and the lowest `nev` eigenpairs of every `eig_every`-th eta,
-    solved concurrently on 8 streams, with the plain preconditioner and (if
-    `learned`) with a network trained on one other eta of the structure."""
+    solved concurrently on 8 streams, with the plain preconditioner, by
+    Chebyshev-filtered subspace iteration, and (if `learned`) with a network
+    trained on one other eta of the structure."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -233,6 +234,12 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
         te = time.perf_counter() - te
         rec.update(eig_problems=len(sub), eig_nev=nev, eig_seconds=round(te, 2),
                    eig_converged=int(np.sum(status == 0)), eig_iters_mean=float(np.mean([x["iters"] for x in st])))
+        te = time.perf_counter()
+        evc, resc, stc, statusc = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=200, cheb_degree=0)
+        te = time.perf_counter() - te
+        rec.update(chefsi_eig_seconds=round(te, 2), chefsi_converged=int(np.sum(statusc == 0)),
+                   chefsi_steps_mean=float(np.mean([x["iters"] for x in stc])),
+                   chefsi_max_abs_dlambda=float(np.max(np.abs(evc - ev))))
         if learned:
             # one network per structure, trained on pairs from the solve at an
             # eta outside the solved subset, attached to every solved problem

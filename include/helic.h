@@ -252,6 +252,11 @@ helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t
 helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* opts, int32_t nstreams,
                                     double* evals, double* resid, helic_solve_stats* stats,
                                     int32_t* status);
+/* As helic_batch_eigensolve, each problem by Chebyshev-filtered subspace
+ * iteration (helic_eigensolve_chefsi; degree 0 picks 32). */
+helic_status helic_batch_eigensolve_chefsi(helic_batch b, const helic_solve_opts* opts, int32_t degree,
+                                           int32_t nstreams, double* evals, double* resid,
+                                           helic_solve_stats* stats, int32_t* status);
 
 /* ---- learned diagonal preconditioner -----------------------------------
  * Not in the paper, which only remarks (Sec. 5) that the method lends itself

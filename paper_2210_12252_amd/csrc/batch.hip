@@ -285,8 +285,8 @@ helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t
   return s;
 }
 
-helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* o, int32_t nstreams, double* evals,
-                                    double* resid, helic_solve_stats* stats, int32_t* status) {
+static helic_status batch_eigensolve(helic_batch b, const helic_solve_opts* o, int cheb_degree, int32_t nstreams,
+                                     double* evals, double* resid, helic_solve_stats* stats, int32_t* status) {
   if (!b || !o || !evals || !resid || nstreams < 1) return fail(HELIC_ERR_INVALID, "bad arguments");
   const int nprob = (int)b->bases.size();
   for (helic_basis h : b->bases)
@@ -304,7 +304,7 @@ helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* o, in
       helic_solve_stats ss;
       std::memset(&ss, 0, sizeof(ss));
       st[p] = s ? eigensolve_impl(b->bases[p], *o, evals + (size_t)p * o->nev, resid + (size_t)p * o->nev, nullptr, 0,
-                                  &ss, s, nullptr, 0)
+                                  &ss, s, nullptr, cheb_degree)
                 : HELIC_ERR_HIP;
       if (st[p] != HELIC_OK) msg[p] = helic_last_error();
       if (stats) stats[p] = ss;
@@ -329,6 +329,18 @@ helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* o, in
     for (int p = 0; p < nprob; ++p)
       if (st[p] == HELIC_ERR_NOCONV) return fail(HELIC_ERR_NOCONV, "problem " + std::to_string(p) + " did not converge");
   return ret;
+}
+
+helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* o, int32_t nstreams, double* evals,
+                                    double* resid, helic_solve_stats* stats, int32_t* status) {
+  return batch_eigensolve(b, o, 0, nstreams, evals, resid, stats, status);
+}
+
+helic_status helic_batch_eigensolve_chefsi(helic_batch b, const helic_solve_opts* o, int32_t degree,
+                                           int32_t nstreams, double* evals, double* resid,
+                                           helic_solve_stats* stats, int32_t* status) {
+  if (degree < 0 || degree > 200) return fail(HELIC_ERR_INVALID, "bad filter degree");
+  return batch_eigensolve(b, o, degree > 0 ? degree : CHEB_DEGREE_AUTO, nstreams, evals, resid, stats, status);
 }
 
 }  // extern "C"

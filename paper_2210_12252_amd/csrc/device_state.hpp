@@ -14,6 +14,8 @@ constexpr int APPLY_CHUNK = 64;
 // States per real-space workspace pass of the density (n_t1*n_t2*n_r complex
 // values each).
 constexpr int DENSITY_CHUNK = 16;
+// Chebyshev filter degree of the filtered eigensolver when the caller passes 0.
+constexpr int CHEB_DEGREE_AUTO = 32;
 
 struct SolverState;
 }  // namespace helic

@@ -62,7 +62,6 @@ namespace {
 
 typedef rocblas_double_complex zc;
 constexpr int NTS = 256;
-constexpr int CHEB_DEGREE_AUTO = 32;   // filter degree when the caller passes 0
 
 #define HIP_TRY_S(call)                                                               \
   do {                                                                                \

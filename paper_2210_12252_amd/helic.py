@@ -29,7 +29,7 @@ EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "hel
            "helic_transform_forward", "helic_density", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
            "helic_eigensolve_ex", "helic_eigensolve_chefsi", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
            "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
-           "helic_batch_eigensolve",
+           "helic_batch_eigensolve", "helic_batch_eigensolve_chefsi",
            "helic_lpc_create", "helic_lpc_destroy", "helic_lpc_get_params", "helic_lpc_set_params",
            "helic_lpc_save", "helic_lpc_load",
            "helic_lpc_attach", "helic_lpc_vdiag", "helic_lpc_apply", "helic_lpc_loss_grad", "helic_lpc_adam_step",
@@ -116,6 +116,8 @@ def load() -> ctypes.CDLL:
         "helic_batch_tune": [_P, _P, _P, _I32, _I32, _P, _PI32, _PD],
         "helic_batch_eigensolve": [_P, ctypes.POINTER(SolveOpts), _I32, _PD, _PD, ctypes.POINTER(SolveStats),
                                    _PI32],
+        "helic_batch_eigensolve_chefsi": [_P, ctypes.POINTER(SolveOpts), _I32, _I32, _PD, _PD, ctypes.POINTER(SolveStats),
+                                          _PI32],
         "helic_lpc_create": [ctypes.c_uint64, ctypes.POINTER(_P)],
         "helic_lpc_destroy": [_P],
         "helic_lpc_get_params": [_P, ctypes.POINTER(ctypes.c_float)],
@@ -461,7 +463,9 @@ class Batch:
         return chosen.value, ms.value
 
     def eigensolve(self, nev, nstreams=8, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa",
-                   guard=-1, switch_tol=1e-4, log_every=0):
+                   guard=-1, switch_tol=1e-4, log_every=0, cheb_degree=None):
+        """cheb_degree (an int, 0 = automatic) selects the Chebyshev-filtered
+        subspace iteration instead of LOBPCG."""
         n = len(self.bases)
         o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=PREC[prec], seed=seed,
                       precond=PRECOND[precond], guard=guard, switch_tol=switch_tol, log_every=log_every)
@@ -469,8 +473,13 @@ class Batch:
         resid = np.zeros((n, nev))
         stats = (SolveStats * n)()
         status = np.zeros(n, dtype=np.int32)
-        st = load().helic_batch_eigensolve(self.h, ctypes.byref(o), nstreams, _ptr(evals, ctypes.c_double),
-                                           _ptr(resid, ctypes.c_double), stats, _ptr(status, ctypes.c_int32))
+        if cheb_degree is None:
+            st = load().helic_batch_eigensolve(self.h, ctypes.byref(o), nstreams, _ptr(evals, ctypes.c_double),
+                                               _ptr(resid, ctypes.c_double), stats, _ptr(status, ctypes.c_int32))
+        else:
+            st = load().helic_batch_eigensolve_chefsi(self.h, ctypes.byref(o), int(cheb_degree), nstreams,
+                                                      _ptr(evals, ctypes.c_double), _ptr(resid, ctypes.c_double),
+                                                      stats, _ptr(status, ctypes.c_int32))
         if st not in (OK, ERR_NOCONV):
             _check(st)
         return evals, resid, [s.as_dict() for s in stats], status
