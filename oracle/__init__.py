@@ -27,6 +27,8 @@ transparency over speed:
 * ``precond``    -- the Teter-Payne-Allan diagonal preconditioner (Sec. 3.5).
 * ``density``    -- the electron density sum_j occ_j |phi_j|^2 on the grid
                     (Sec. 4.2, the density equation, one (eta, nu) term).
+* ``gradient``   -- derivatives of a field given by coefficients in helical
+                    and Cartesian coordinates (App. C).
 * ``mlp``        -- forward and backward pass of the small per-coefficient
                     network used as a learned preconditioner (no paper source;
                     it exists to check the GPU kernels' gradients).

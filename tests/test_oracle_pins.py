@@ -414,3 +414,64 @@ def test_density_against_the_basis_matrix(tiny):
     g = ot.inverse_naive(b, X, B)
     want = np.einsum("ijlv,v->ijl", np.abs(g) ** 2, occ)
     assert np.max(np.abs(od.density(b, X, occ) - want)) < 1e-12 * np.max(want)
+
+
+# ------------------------------------------------------------------ gradients (App. C)
+def test_gradient_of_one_function_closed_forms(tiny):
+    """F = exp(i 2 pi (m theta1 + n theta2)) xi_{n,k}(r): E_theta1 = i 2 pi m F,
+    E_theta2 = i 2 pi n F, and E_r = exp(...) d xi/dr, the latter against a
+    central difference of xi."""
+    from oracle import gradient as og
+    w, b, V, B = tiny
+    h = 1e-5 * b.R
+    for i in (0, b.L // 2, b.L - 1):
+        m, n, k = (int(t) for t in b.mnk[i])
+        x = np.zeros(b.L, dtype=np.complex128)
+        x[i] = 1.0
+        F = ot.inverse_naive(b, x, B)
+        e1, e2, er = og.helical_derivatives(b, x)
+        scale = np.max(np.abs(F)) * 2 * math.pi * max(1, abs(m), abs(n))
+        assert np.max(np.abs(e1 - 2j * math.pi * m * F)) < 1e-12 * scale
+        assert np.max(np.abs(e2 - 2j * math.pi * n * F)) < 1e-12 * scale
+        dxi = (b.xi(n, np.array([k]), b.r + h)[:, 0] - b.xi(n, np.array([k]), b.r - h)[:, 0]) / (2 * h)
+        ang = np.exp(2j * math.pi * (m * b.theta1[:, None] + n * b.theta2[None, :]))
+        want = ang[:, :, None] * dxi[None, None, :]
+        assert np.max(np.abs(er - want)) < 1e-7 * np.max(np.abs(want))
+
+
+def test_cartesian_gradient_against_finite_differences():
+    """The chain rule of eq. Cartesian_Derivatives against central differences
+    of the field evaluated at Cartesian points (x, y, z) mapped back to
+    helical coordinates: theta1 = z / tau, phi = atan2(y, x),
+    theta2 = phi / (2 pi) - alpha theta1, r = sqrt(x^2 + y^2)."""
+    from oracle import gradient as og
+    b = small_basis()
+    rng = np.random.default_rng(8)
+    idx = rng.choice(b.L, 6, replace=False)
+    coef = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    x = np.zeros(b.L, dtype=np.complex128)
+    x[idx] = coef
+
+    def field(px, py, pz):
+        t1 = pz / b.tau
+        t2 = math.atan2(py, px) / (2 * math.pi) - b.alpha * t1
+        rr = math.hypot(px, py)
+        s = 0.0
+        for i, c in zip(idx, coef):
+            m, n, k = (int(t) for t in b.mnk[i])
+            s += c * np.exp(2j * math.pi * (m * t1 + n * t2)) * b.xi(n, np.array([k]), np.array([rr]))[0, 0]
+        return s
+
+    ex, ey, ez = og.cartesian(b, *og.helical_derivatives(b, x))
+    h = 1e-5
+    for (i1, i2, l) in ((1, 3, 10), (5, 9, 20), (10, 14, 28), (7, 0, 5)):
+        t1, t2, rr = b.theta1[i1], b.theta2[i2], b.r[l]
+        phi = 2 * math.pi * (b.alpha * t1 + t2)
+        p = np.array([rr * math.cos(phi), rr * math.sin(phi), b.tau * t1])
+        fd = []
+        for d in range(3):
+            e = np.zeros(3)
+            e[d] = h
+            fd.append((field(*(p + e)) - field(*(p - e))) / (2 * h))
+        got = np.array([ex[i1, i2, l], ey[i1, i2, l], ez[i1, i2, l]])
+        assert np.max(np.abs(got - np.array(fd))) < 1e-6 * max(1.0, np.max(np.abs(fd))), (i1, i2, l, got, fd)
