@@ -129,6 +129,20 @@ helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx
 helic_status helic_transform_forward(helic_basis h, const double* g, double* X, int64_t ldx,
                                      int32_t nvec, void* stream);
 
+/* Derivatives of the fields given by nvec coefficient columns (App. C):
+ * grad (device) receives three blocks of nvec real-space arrays of complex
+ * doubles (n_t1*n_t2*n_r each, the inverse transform's layout): with
+ * cartesian = 0 the helical derivatives E_theta1 (transform of the
+ * coefficients times i 2 pi m), E_theta2 (times i 2 pi n) and E_r (the
+ * transform with d xi_{|n|,k} / dr as radial functions, eqs. E_r and B_r);
+ * with cartesian = 1 the Cartesian E_x, E_y, E_z from them by eq.
+ * Cartesian_Derivatives.  FP64.  The first call uploads the derivative
+ * tables and grows a coefficient workspace (hipMalloc).  Asynchronous on
+ * `stream`.  Errors: HELIC_ERR_INVALID for null pointers with nvec > 0,
+ * ldx < L or cartesian outside {0, 1}. */
+helic_status helic_gradient(helic_basis h, const double* X, int64_t ldx, int32_t nvec, double* grad,
+                            int32_t cartesian, void* stream);
+
 /* Electron density on the grid (Sec. 4.2, the density equation, one (eta_b,
  * nu) term of its sums): rho = sum_j occ_j |phi_j|^2, phi_j the inverse
  * transform (Alg. 1 and 2) of coefficient column j of X (device block, see

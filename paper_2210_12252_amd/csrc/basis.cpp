@@ -194,6 +194,7 @@ helic_status build(helic_basis_s* h) {
     h->max_colpad = std::max(h->max_colpad, 16 * ((2 * grp.nmodes + 15) / 16));
   }
   h->tab_inv.assign(inv_total, 0.0);
+  h->tab_dinv.assign(inv_total, 0.0);
   h->tab_fwd.assign(fwd_total, 0.0);
   const double norm0 = 1.0 / (std::sqrt(PI * tau) * R);
   std::vector<double> jv(2);
@@ -201,7 +202,8 @@ helic_status build(helic_basis_s* h) {
     const int nks = (grp.Kmax + 3) / 4;
     const int g = grp.g;
     std::vector<double> xi((size_t)nr * grp.Kmax);   // xi[l * Kmax + k]
-    std::vector<double> buf(g + 2);
+    std::vector<double> dxi((size_t)nr * grp.Kmax);  // d xi / dr
+    std::vector<double> buf(g + 2), buf2(g + 2);
     for (int k = 0; k < grp.Kmax; ++k) {
       const double b = grp.zeros[k];
       bessel_j_all(g + 1, b, buf.data());
@@ -209,14 +211,20 @@ helic_status build(helic_basis_s* h) {
       for (int l = 0; l < nr; ++l) {
         bessel_j_all(g, b * h->q[l], buf.data());
         xi[(size_t)l * grp.Kmax + k] = c * buf[g];
+        // J_g' = (J_{g-1} - J_{g+1}) / 2, with J_{-1} = -J_1
+        bessel_j_all(g + 1, b * h->q[l], buf2.data());
+        const double jm1 = g > 0 ? buf2[g - 1] : -buf2[1];
+        dxi[(size_t)l * grp.Kmax + k] = c * (b / R) * 0.5 * (jm1 - buf2[g + 1]);
       }
     }
     for (int t = 0; t < nrt; ++t)
       for (int s = 0; s < nks; ++s)
         for (int ln = 0; ln < FRAG; ++ln) {
           const int l = 16 * t + ln % 16, k = 4 * s + ln / 16;
-          if (l < nr && k < grp.Kmax)
+          if (l < nr && k < grp.Kmax) {
             h->tab_inv[grp.tinv_off + ((int64_t)t * nks + s) * FRAG + ln] = xi[(size_t)l * grp.Kmax + k];
+            h->tab_dinv[grp.tinv_off + ((int64_t)t * nks + s) * FRAG + ln] = dxi[(size_t)l * grp.Kmax + k];
+          }
         }
     const double pref = 2.0 * PI * tau;   // 2 pi tau / N with N = 1
     for (int t = 0; t < (grp.Kmax + 15) / 16; ++t)

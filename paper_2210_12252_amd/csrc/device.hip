@@ -516,6 +516,52 @@ k_potential_diagonal(const DGroup* __restrict__ groups, const int32_t* __restric
   for (int64_t row = g.row0 + threadIdx.x; row < g.row0 + g.nrows; row += NT) vdiag[row] = per_k[row_ck[row] & 0xffff];
 }
 
+constexpr double PI_D = 3.14159265358979323846;
+
+// Y_v = i f .* X_v for nv columns of L complex rows (App. C: the coefficients
+// of a theta derivative, f = 2 pi m or 2 pi n per row).
+__global__ void __launch_bounds__(NT)
+k_scale_imag(const double* __restrict__ X, int64_t ldx, double* __restrict__ Y, int64_t L, int nv,
+             const double* __restrict__ f) {
+  const int v = blockIdx.y;
+  const double2* x = reinterpret_cast<const double2*>(X) + (int64_t)v * ldx;
+  double2* y = reinterpret_cast<double2*>(Y) + (int64_t)v * L;
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < L; i += (int64_t)gridDim.x * NT) {
+    const double2 a = x[i];
+    y[i] = double2{-f[i] * a.y, f[i] * a.x};
+  }
+}
+
+// Helical to Cartesian derivatives at every grid point, in place (App. C, eq.
+// Cartesian_Derivatives): G holds three blocks of nv grids (E_theta1,
+// E_theta2, E_r), each grid n1 x n2 x n_r complex values with r fastest.
+// phi = 2 pi (alpha theta1 + theta2); E_x = -sin(phi) E_theta2 / (2 pi r) +
+// cos(phi) E_r, E_y = cos(phi) E_theta2 / (2 pi r) + sin(phi) E_r,
+// E_z = (E_theta1 - alpha E_theta2) / tau.
+__global__ void __launch_bounds__(NT)
+k_cartesian(double* __restrict__ G, int nv, int n1, int n2, int n_r, const double* __restrict__ rg, double alpha,
+            double tau) {
+  const int64_t npts = (int64_t)n1 * n2 * n_r;
+  double2* g = reinterpret_cast<double2*>(G);
+  const int v = blockIdx.y;
+  for (int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x; p < npts; p += (int64_t)gridDim.x * NT) {
+    const int l = (int)(p % n_r);
+    const int64_t a = p / n_r;
+    const int i2 = (int)(a % n2), i1 = (int)(a / n2);
+    const double phi = 2.0 * PI_D * (alpha * ((double)i1 / n1) + (double)i2 / n2);
+    double sn, cs;
+    sincos(phi, &sn, &cs);
+    const double ir = 1.0 / (2.0 * PI_D * rg[l]);
+    double2* e1 = g + (int64_t)v * npts + p;
+    double2* e2 = g + ((int64_t)nv + v) * npts + p;
+    double2* er = g + (2 * (int64_t)nv + v) * npts + p;
+    const double2 t1 = *e1, t2 = *e2, tr = *er;
+    *e1 = double2{-sn * ir * t2.x + cs * tr.x, -sn * ir * t2.y + cs * tr.y};
+    *e2 = double2{cs * ir * t2.x + sn * tr.x, cs * ir * t2.y + sn * tr.y};
+    *er = double2{(t1.x - alpha * t2.x) / tau, (t1.y - alpha * t2.y) / tau};
+  }
+}
+
 // Electron density (Sec. 4.2): rho[p] (+)= sum_v occ[v] |g_v[p]|^2 over the
 // npts grid points, g holding nv real-space grids of complex values.  One
 // thread per point, states in order, so the sum is deterministic.  HBM-bound:
@@ -1209,7 +1255,7 @@ void device_release(helic_basis_s* h) {
   void* ptrs[] = {d->groups, d->modes, d->row_ck, d->kappa, d->rows1, d->tinv64, d->tfwd64,
                   d->tinv32, d->tfwd32, d->tw1, d->tw2, d->tw1f, d->tw2f, d->Vs, d->Vsf,
                   d->gh, d->part, d->mode_pos, d->blk_mode, d->Vh, d->Vhf, d->probs64, d->probs32, d->vdiag, d->lpc_ws,
-                  d->dens_ws, d->dens_occ};
+                  d->dens_ws, d->dens_occ, d->tdinv64, d->probs_dr, d->grad_fac, d->rgrid, d->grad_ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   release_solver_state(d);
@@ -1404,15 +1450,12 @@ helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, do
   return HELIC_OK;
 }
 
-helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx, double* g, int32_t nvec,
-                                     void* stream) {
-  if (!h) return fail(HELIC_ERR_INVALID, "null handle");
-  if (nvec < 0 || (nvec > 0 && (!X || !g)) || ldx < h->L) return fail(HELIC_ERR_INVALID, "bad arguments");
-  if (nvec == 0) return HELIC_OK;
-  helic_status s = ensure_device(h);
-  if (s != HELIC_OK) return s;
+// Inverse transform of nvec columns onto nvec consecutive grids with the
+// radial tables of `probs` (the basis' own, or their r-derivatives).
+static helic_status inverse_transform(helic_basis_s* h, const double* X, int64_t ldx, double* g, int nvec,
+                                      hipStream_t st, const DProb* probs) {
   DeviceState* d = h->dev;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  helic_status s = HELIC_OK;
   const int ng = (int)h->groups.size();
   const int64_t grid_elems = (int64_t)h->n_t1 * h->n_t2 * h->n_r;
   for (int v0 = 0; v0 < nvec; v0 += APPLY_CHUNK) {
@@ -1421,11 +1464,78 @@ helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx
     double* gh = reinterpret_cast<double*>(d->gh);
     launch_radial_inverse<double>(inv_ks_for(h), 8 * ((ng * nv + 7) / 8),
                                   (size_t)h->max_kpad * lds_stride(h->max_colpad) * sizeof(double), st,
-                                  X + (int64_t)v0 * ldx * 2, ldx, gh, nv, ng, h->n_r, d->groups, d->probs64);
+                                  X + (int64_t)v0 * ldx * 2, ldx, gh, nv, ng, h->n_r, d->groups, probs);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_angular<double, 1>), dim3(8 * ((nv * h->n_r + 7) / 8)), dim3(NT),
                        angular_lds_bytes(h, sizeof(double)), st, gh, nullptr, g + v0 * grid_elems * 2, 1, nv,
-                       h->n_r, d->probs64, d->rows1, (int)h->rows1.size(), d->tw1, d->tw2, d->plan1, d->plan2, 1.0);
+                       h->n_r, probs, d->rows1, (int)h->rows1.size(), d->tw1, d->tw2, d->plan1, d->plan2, 1.0);
+    HIP_TRY(hipGetLastError());
+  }
+  return HELIC_OK;
+}
+
+helic_status helic_transform_inverse(helic_basis h, const double* X, int64_t ldx, double* g, int32_t nvec,
+                                     void* stream) {
+  if (!h) return fail(HELIC_ERR_INVALID, "null handle");
+  if (nvec < 0 || (nvec > 0 && (!X || !g)) || ldx < h->L) return fail(HELIC_ERR_INVALID, "bad arguments");
+  if (nvec == 0) return HELIC_OK;
+  helic_status s = ensure_device(h);
+  if (s != HELIC_OK) return s;
+  return inverse_transform(h, X, ldx, g, nvec, reinterpret_cast<hipStream_t>(stream), h->dev->probs64);
+}
+
+helic_status helic_gradient(helic_basis h, const double* X, int64_t ldx, int32_t nvec, double* grad,
+                            int32_t cartesian, void* stream) {
+  if (!h) return fail(HELIC_ERR_INVALID, "null handle");
+  if (nvec < 0 || (nvec > 0 && (!X || !grad)) || ldx < h->L || cartesian < 0 || cartesian > 1)
+    return fail(HELIC_ERR_INVALID, "bad arguments");
+  if (nvec == 0) return HELIC_OK;
+  helic_status s = ensure_device(h);
+  if (s != HELIC_OK) return s;
+  DeviceState* d = h->dev;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (!d->probs_dr) {
+    // first call: d xi / dr tables, a problem entry using them, 2 pi m and
+    // 2 pi n per row, the radii
+    std::vector<double> fac(2 * (size_t)h->L), rg(h->n_r);
+    for (int64_t i = 0; i < h->L; ++i) {
+      fac[i] = 2.0 * PI_D * h->mnk[3 * i];
+      fac[h->L + i] = 2.0 * PI_D * h->mnk[3 * i + 1];
+    }
+    for (int l = 0; l < h->n_r; ++l) rg[l] = h->p.R * h->q[l];
+    DProb p = problem_entry(h, true, 0, 0);
+    if ((s = upload(h->tab_dinv, &d->tdinv64)) || (s = upload(fac, &d->grad_fac)) || (s = upload(rg, &d->rgrid)))
+      return s;
+    p.tinv = d->tdinv64;
+    std::vector<DProb> pv(1, p);
+    if ((s = upload(pv, &d->probs_dr))) return s;
+  }
+  const int chunk = std::min<int>(nvec, APPLY_CHUNK);
+  const size_t need = (size_t)chunk * h->L * 2 * sizeof(double);
+  if (need > d->grad_ws_bytes) {
+    if (d->grad_ws) HIP_TRY(hipFree(d->grad_ws));
+    d->grad_ws = nullptr;
+    d->grad_ws_bytes = 0;
+    HIP_TRY(hipMalloc((void**)&d->grad_ws, need));
+    d->grad_ws_bytes = need;
+  }
+  const int64_t npts = (int64_t)h->n_t1 * h->n_t2 * h->n_r;
+  // E_theta1, E_theta2: transforms of (i 2 pi m) x and (i 2 pi n) x
+  for (int c = 0; c < 2; ++c)
+    for (int v0 = 0; v0 < nvec; v0 += chunk) {
+      const int nv = std::min(chunk, nvec - v0);
+      hipLaunchKernelGGL(k_scale_imag, dim3((unsigned)std::min<int64_t>(256, (h->L + NT - 1) / NT), nv), dim3(NT), 0,
+                         st, X + (int64_t)v0 * ldx * 2, ldx, d->grad_ws, h->L, nv, d->grad_fac + (size_t)c * h->L);
+      HIP_TRY(hipGetLastError());
+      if ((s = inverse_transform(h, d->grad_ws, h->L, grad + ((int64_t)c * nvec + v0) * npts * 2, nv, st,
+                                 d->probs64)))
+        return s;
+    }
+  // E_r: the transform with d xi / dr as the radial functions
+  if ((s = inverse_transform(h, X, ldx, grad + (int64_t)2 * nvec * npts * 2, nvec, st, d->probs_dr))) return s;
+  if (cartesian) {
+    hipLaunchKernelGGL(k_cartesian, dim3((unsigned)std::min<int64_t>(1024, (npts + NT - 1) / NT), nvec), dim3(NT), 0,
+                       st, grad, nvec, h->n_t1, h->n_t2, h->n_r, d->rgrid, h->p.alpha, h->p.tau);
     HIP_TRY(hipGetLastError());
   }
   return HELIC_OK;

@@ -60,6 +60,14 @@ struct DeviceState {
   size_t dens_ws_bytes = 0;
   double* dens_occ = nullptr;     // density: per-state weights
   size_t dens_occ_n = 0;
+  // field derivatives: d xi / dr tables, a problem entry that uses them,
+  // per-row factors 2 pi m and 2 pi n, radii, scaled-coefficient workspace
+  double* tdinv64 = nullptr;
+  DProb* probs_dr = nullptr;
+  double* grad_fac = nullptr;
+  double* rgrid = nullptr;
+  double* grad_ws = nullptr;
+  size_t grad_ws_bytes = 0;
   SolverState* solver = nullptr;
   // learned preconditioner: attached network, potential diagonal V_ii per
   // row (L values, then the n_r angular means; set with the potential),

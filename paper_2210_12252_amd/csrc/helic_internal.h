@@ -47,6 +47,7 @@ struct helic_basis_s {
   std::vector<int32_t> rows1;     // distinct theta1 bins that hold a mode
   // Packed radial tables (MFMA fragment order, see device.hip); doubles.
   std::vector<double> tab_inv, tab_fwd;
+  std::vector<double> tab_dinv;   // d xi / dr in tab_inv's layout (App. C, field derivatives)
   int32_t max_kpad = 0, max_colpad = 0;   // LDS tile bounds over the groups
   std::vector<int32_t> fac1, fac2;        // radix factorisations of n_t1, n_t2
   helic::DeviceState* dev = nullptr;

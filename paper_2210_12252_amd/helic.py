@@ -26,7 +26,7 @@ PREC = {"fp64": FP64, "fp32": FP32}
 # every function declared in include/helic.h
 EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "helic_basis_indices",
            "helic_grid", "helic_set_potential", "helic_apply_H", "helic_transform_inverse",
-           "helic_transform_forward", "helic_density", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
+           "helic_transform_forward", "helic_gradient", "helic_density", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
            "helic_eigensolve_ex", "helic_eigensolve_chefsi", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
            "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
            "helic_batch_eigensolve", "helic_batch_eigensolve_chefsi",
@@ -100,6 +100,7 @@ def load() -> ctypes.CDLL:
         "helic_transform_inverse": [_P, _P, _I64, _P, _I32, _P],
         "helic_transform_forward": [_P, _P, _P, _I64, _I32, _P],
         "helic_density": [_P, _P, _I64, _I32, _PD, _P, _I32, _P],
+        "helic_gradient": [_P, _P, _I64, _I32, _P, _I32, _P],
         "helic_precondition": [_P, _P, _I64, _P, _I64, _I32, _P],
         "helic_profile_apply": [_P, _P, _I64, _P, _I64, _I32, _I32, _I32, _P, _PD, _PD],
         "helic_eigensolve": [_P, _I32, _I32, _D, _I32, _I32, ctypes.c_uint64, _PD, _PD, _P, _I64,
@@ -257,6 +258,18 @@ def transform_inverse(h, X, g, stream=None):
         raise ValueError("g too small or not contiguous")
     _check(load().helic_transform_inverse(h, ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(g.data_ptr()),
                                           nx, _stream(stream)))
+
+
+def gradient(h, X, grad, cartesian=False, stream=None):
+    """grad (complex128 HIP tensor of shape (3, nvec, n_t1, n_t2, n_r) or as
+    many elements) receives (E_theta1, E_theta2, E_r), or (E_x, E_y, E_z)."""
+    nx, ldx = _block(X, "X")
+    i = basis_info(h)
+    if not (grad.is_cuda and grad.is_contiguous() and str(grad.dtype) == "torch.complex128"
+            and grad.numel() >= 3 * nx * i["n_t1"] * i["n_t2"] * i["n_r"]):
+        raise ValueError("grad must be a contiguous complex128 HIP tensor of 3 * nvec grids")
+    _check(load().helic_gradient(h, ctypes.c_void_p(X.data_ptr()), ldx, nx, ctypes.c_void_p(grad.data_ptr()),
+                                 1 if cartesian else 0, _stream(stream)))
 
 
 def density(h, X, occ, rho, accumulate=False, stream=None):
@@ -532,6 +545,9 @@ class Basis:
 
     def density(self, X, occ, rho, accumulate=False, stream=None):
         density(self.h, X, occ, rho, accumulate, stream)
+
+    def gradient(self, X, grad, cartesian=False, stream=None):
+        gradient(self.h, X, grad, cartesian, stream)
 
     def precondition(self, R, W, stream=None):
         precondition(self.h, R, W, stream)
