@@ -361,8 +361,8 @@ def main(argv=None):
                     help="also run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the helical-wave solve shards over Bloch "
-              "parameters without communication, which is not exercised here.", file=sys.stderr)
+        print("bench.py: the library and this benchmark run on one GPU; the helical-wave solve would shard "
+              "over Bloch parameters without communication, and no multi-GPU path is implemented.", file=sys.stderr)
         return 2
 
     import numpy as np
