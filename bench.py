@@ -176,8 +176,9 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
     largest automatic grid over its eta), tuned, captured in a HIP graph and
     replayed; and the lowest `nev` eigenpairs of every `eig_every`-th eta,
     solved concurrently on 8 streams, with the plain preconditioner, by
-    Chebyshev-filtered subspace iteration, and (if `learned`) with a network
-    trained on one other eta of the structure."""
+    Chebyshev-filtered subspace iteration (also with time-reversal halving of
+    the eta points), and (if `learned`) with a network trained on one other
+    eta of the structure."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -240,6 +241,15 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
         rec.update(chefsi_eig_seconds=round(te, 2), chefsi_converged=int(np.sum(statusc == 0)),
                    chefsi_steps_mean=float(np.mean([x["iters"] for x in stc])),
                    chefsi_max_abs_dlambda=float(np.max(np.abs(evc - ev))))
+        # time-reversal halving: eta and -eta of the subset share one solve
+        npairs = eb.time_reversal(True)
+        te = time.perf_counter()
+        evt, _, _, statust = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=200, cheb_degree=0)
+        te = time.perf_counter() - te
+        eb.time_reversal(False)
+        rec.update(time_reversal_pairs=npairs, chefsi_tr_eig_seconds=round(te, 2),
+                   chefsi_tr_converged=int(np.sum(statust == 0)),
+                   chefsi_tr_max_abs_dlambda=float(np.max(np.abs(evt - ev))))
         if learned:
             # one network per structure, trained on pairs from the solve at an
             # eta outside the solved subset, attached to every solved problem

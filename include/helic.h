@@ -266,6 +266,15 @@ helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t
 helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* opts, int32_t nstreams,
                                     double* evals, double* resid, helic_solve_stats* stats,
                                     int32_t* status);
+/* Time-reversal halving (Sec. 3.3): with enable = 1, a problem whose eta is
+ * the negative of an earlier problem's (0 < |eta| < 1/2) with the same
+ * geometry, cutoff, clamps, grid and potential (compared exactly) is not
+ * solved by the batched eigensolvers: it takes that problem's eigenvalues and
+ * residuals (lambda_j(eta) = lambda_j(-eta)), and its stats entry is zero.
+ * *npairs (host, may be NULL) receives the number of such problems.
+ * enable = 0 solves every problem again.  Reads the potentials back once
+ * (synchronous). */
+helic_status helic_batch_time_reversal(helic_batch b, int32_t enable, int32_t* npairs);
 /* As helic_batch_eigensolve, each problem by Chebyshev-filtered subspace
  * iteration (helic_eigensolve_chefsi; degree 0 picks 32). */
 helic_status helic_batch_eigensolve_chefsi(helic_batch b, const helic_solve_opts* opts, int32_t degree,

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -46,6 +47,7 @@ struct helic_batch_s {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::vector<int32_t> mirror;        // time reversal: partner solved in its place, or -1 (empty: none)
 };
 
 using namespace helic;
@@ -294,6 +296,7 @@ static helic_status batch_eigensolve(helic_batch b, const helic_solve_opts* o, i
   std::atomic<int> next(0);
   std::vector<helic_status> st(nprob, HELIC_OK);
   std::vector<std::string> msg(nprob);
+  const bool tr = !b->mirror.empty();
   auto worker = [&]() {
     (void)hipSetDevice(b->device);
     hipStream_t s = nullptr;
@@ -301,6 +304,7 @@ static helic_status batch_eigensolve(helic_batch b, const helic_solve_opts* o, i
     for (;;) {
       const int p = next.fetch_add(1);
       if (p >= nprob) break;
+      if (tr && b->mirror[p] >= 0) continue;   // takes its time-reversal partner's results below
       helic_solve_stats ss;
       std::memset(&ss, 0, sizeof(ss));
       st[p] = s ? eigensolve_impl(b->bases[p], *o, evals + (size_t)p * o->nev, resid + (size_t)p * o->nev, nullptr, 0,
@@ -318,6 +322,16 @@ static helic_status batch_eigensolve(helic_batch b, const helic_solve_opts* o, i
   const int nt = std::min(nstreams, nprob);
   for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
   for (auto& t : pool) t.join();
+  // time-reversal partners: lambda_j(eta) = lambda_j(-eta) (Sec. 3.3)
+  for (int p = 0; tr && p < nprob; ++p) {
+    const int q = b->mirror[p];
+    if (q < 0) continue;
+    std::copy(evals + (size_t)q * o->nev, evals + (size_t)(q + 1) * o->nev, evals + (size_t)p * o->nev);
+    std::copy(resid + (size_t)q * o->nev, resid + (size_t)(q + 1) * o->nev, resid + (size_t)p * o->nev);
+    st[p] = st[q];
+    msg[p] = msg[q];
+    if (stats) std::memset(&stats[p], 0, sizeof(helic_solve_stats));   // nothing was solved for p
+  }
   helic_status ret = HELIC_OK;
   for (int p = 0; p < nprob; ++p) {
     if (status) status[p] = st[p];
@@ -329,6 +343,49 @@ static helic_status batch_eigensolve(helic_batch b, const helic_solve_opts* o, i
     for (int p = 0; p < nprob; ++p)
       if (st[p] == HELIC_ERR_NOCONV) return fail(HELIC_ERR_NOCONV, "problem " + std::to_string(p) + " did not converge");
   return ret;
+}
+
+helic_status helic_batch_time_reversal(helic_batch b, int32_t enable, int32_t* npairs) {
+  if (!b) return fail(HELIC_ERR_INVALID, "null batch");
+  if (npairs) *npairs = 0;
+  b->mirror.clear();
+  if (!enable) return HELIC_OK;
+  const int nprob = (int)b->bases.size();
+  std::vector<int32_t> mirror(nprob, -1);
+  std::vector<std::vector<double>> V(nprob);
+  auto potential = [&](int p) -> helic_status {
+    if (!V[p].empty()) return HELIC_OK;
+    const helic_basis h = b->bases[p];
+    if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "a problem of the batch has no potential");
+    V[p].resize((size_t)h->n_t1 * h->n_t2 * h->n_r);
+    HIP_TRY_B(hipMemcpy(V[p].data(), h->dev->Vs, sizeof(double) * V[p].size(), hipMemcpyDeviceToHost));
+    return HELIC_OK;
+  };
+  int pairs = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const helic_params& a = b->bases[p]->p;
+    if (a.eta == 0.0 || std::fabs(a.eta) >= 0.5) continue;   // its own partner
+    for (int q = 0; q < p; ++q) {
+      const helic_params& c = b->bases[q]->p;
+      if (mirror[q] >= 0 || std::fabs(a.eta + c.eta) > 1e-12 || a.R != c.R || a.tau != c.tau ||
+          a.alpha != c.alpha || a.ecut != c.ecut || a.ncyc != c.ncyc || a.nu != c.nu || a.m_max != c.m_max ||
+          a.n_max != c.n_max || a.k_max != c.k_max || b->bases[p]->L != b->bases[q]->L ||
+          b->bases[p]->n_r != b->bases[q]->n_r)
+        continue;
+      bool taken = false;
+      for (int p2 = 0; p2 < p; ++p2) taken = taken || mirror[p2] == q;
+      if (taken) continue;
+      helic_status s;
+      if ((s = potential(p)) || (s = potential(q))) return s;
+      if (V[p] != V[q]) continue;   // the same structure only
+      mirror[p] = q;
+      ++pairs;
+      break;
+    }
+  }
+  b->mirror = mirror;
+  if (npairs) *npairs = pairs;
+  return HELIC_OK;
 }
 
 helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* o, int32_t nstreams, double* evals,

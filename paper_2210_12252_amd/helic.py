@@ -30,6 +30,7 @@ EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "hel
            "helic_eigensolve_ex", "helic_eigensolve_chefsi", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
            "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
            "helic_batch_eigensolve", "helic_batch_eigensolve_chefsi",
+           "helic_batch_time_reversal",
            "helic_lpc_create", "helic_lpc_destroy", "helic_lpc_get_params", "helic_lpc_set_params",
            "helic_lpc_save", "helic_lpc_load",
            "helic_lpc_attach", "helic_lpc_vdiag", "helic_lpc_apply", "helic_lpc_loss_grad", "helic_lpc_adam_step",
@@ -117,6 +118,7 @@ def load() -> ctypes.CDLL:
         "helic_batch_tune": [_P, _P, _P, _I32, _I32, _P, _PI32, _PD],
         "helic_batch_eigensolve": [_P, ctypes.POINTER(SolveOpts), _I32, _PD, _PD, ctypes.POINTER(SolveStats),
                                    _PI32],
+        "helic_batch_time_reversal": [_P, _I32, _PI32],
         "helic_batch_eigensolve_chefsi": [_P, ctypes.POINTER(SolveOpts), _I32, _I32, _PD, _PD, ctypes.POINTER(SolveStats),
                                           _PI32],
         "helic_lpc_create": [ctypes.c_uint64, ctypes.POINTER(_P)],
@@ -474,6 +476,13 @@ class Batch:
         _check(load().helic_batch_tune(self.h, self._flat(X, "X"), self._flat(Y, "Y"), nvec, PREC[prec],
                                        _stream(stream), ctypes.byref(chosen), ctypes.byref(ms)))
         return chosen.value, ms.value
+
+    def time_reversal(self, enable=True):
+        """Pair problems at eta and -eta (same structure) so that the batched
+        eigensolvers solve one of each pair; returns the number of pairs."""
+        n = ctypes.c_int32(0)
+        _check(load().helic_batch_time_reversal(self.h, 1 if enable else 0, ctypes.byref(n)))
+        return n.value
 
     def eigensolve(self, nev, nstreams=8, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa",
                    guard=-1, switch_tol=1e-4, log_every=0, cheb_degree=None):

@@ -148,6 +148,27 @@ def test_batched_filtered_eigensolve_matches_lapack_per_problem():
     batch.close()
 
 
+def test_time_reversal_halving_of_batched_eigensolves():
+    etas = (-0.25, 0.0, 0.25, 0.125)
+    probs, batch = make_batch(TINY, etas)
+    assert batch.time_reversal(True) == 1                  # eta = 0.25 takes eta = -0.25's results
+    for deg in (None, 0):
+        ev, res, stats, status = batch.eigensolve(TINY.nev, nstreams=2, tol=1e-9, maxit=400, cheb_degree=deg)
+        assert np.all(status == helic.OK), status
+        assert stats[2]["iters"] == 0 and stats[2]["n_apply"] == 0 and stats[0]["n_apply"] > 0
+        np.testing.assert_array_equal(ev[2], ev[0])
+        ref, _ = oh.lowest(oh.dense_explicit(probs[2].o, probs[2].V), TINY.nev)
+        assert np.max(np.abs(ev[2] - ref)) < 1e-8
+    assert batch.time_reversal(False) == 0
+    batch.close()
+    # same geometry and opposite eta but another potential: not paired
+    a = Problem(TINY.with_(eta=-0.25))
+    b = Problem(TINY.with_(eta=0.25), V=0.5 * a.V)
+    other = helic.Batch([a.g, b.g])
+    assert other.time_reversal(True) == 0
+    other.close()
+
+
 def test_incompatible_grids_are_rejected():
     a = Problem(TINY)
     b = Problem(TINY.with_(n_r=40))
