@@ -222,6 +222,12 @@ def test_chefsi_full_size_certified_by_the_oracle():
     print(f"[full size chefsi] steps {st['iters']} applications {st['n_apply']} vs LOBPCG its {stl['iters']}: "
           f"max|dlambda| {np.max(np.abs(ev - evl)):.2e}", flush=True)
     assert np.max(np.abs(ev - evl)) < 2e-8
+    # the FP32 ladder of the filtered solver reaches the same eigenvalues
+    ev32, res32, st32, s32 = b.eigensolve_ex(w.nev, tol=1e-8, maxit=200, seed=9, prec="fp32", cheb_degree=0)
+    assert s32 == helic.OK and st32["iters_low"] > 0
+    print(f"[full size chefsi] mixed steps {st32['iters']} (FP32 {st32['iters_low']}) max|dlambda| vs FP64 "
+          f"{np.max(np.abs(ev32 - ev)):.2e}", flush=True)
+    assert np.max(np.abs(ev32 - ev)) < 2e-8
     mnk, _ = b.indices()
     pos = {tuple(t): i for i, t in enumerate(o.mnk.tolist())}
     perm = np.array([pos[tuple(t)] for t in mnk.tolist()])

@@ -83,3 +83,21 @@ def test_gradient_argument_errors(tiny):
     assert load.helic_gradient(g.h, xp, o.L - 1, 2, gp, 0, None) == helic.ERR_INVALID
     assert load.helic_gradient(g.h, None, o.L, 2, gp, 0, None) == helic.ERR_INVALID
     assert load.helic_gradient(g.h, None, o.L, 0, None, 0, None) == helic.OK
+
+
+def test_cartesian_derivatives_full_size_nanotube():
+    """nanotube-ecut25 grid (48 x 64 x 160, L = 31,543): two columns against
+    the oracle at every grid point."""
+    _dev()
+    w = synth.workload("nanotube-ecut25")
+    o = ob.basis_for(w)
+    g = helic.Basis.from_workload(w)
+    mnk, _ = g.indices()
+    pos = {tuple(t): i for i, t in enumerate(o.mnk.tolist())}
+    perm = np.array([pos[tuple(t)] for t in mnk.tolist()])
+    X = synth.random_block(o.mnk, 2, 53)
+    got = _run(o, g, perm, X, cartesian=True)
+    ref = og.cartesian(o, *og.helical_derivatives(o, X))
+    for c in range(3):
+        print(f"[gradient full size] component {c}: rel err {_rel(got[c], ref[c]):.2e}", flush=True)
+        assert _rel(got[c], ref[c]) < TOL
