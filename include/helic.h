@@ -227,8 +227,9 @@ helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* opts, do
  * degree 0 picks 32; 1..200 accepted.  guard -1 picks max(8, nev / 3).  opts, outputs, convergence test,
  * FP32 ladder (prec, switch_tol), stats and errors as helic_eigensolve_ex;
  * opts->precond is not used (the filter takes the preconditioner's place);
- * stats->iters counts outer steps and t_precond_ms the residual and filter
- * arithmetic. */
+ * stats->iters counts outer steps, t_apply_ms the filter recurrence (H*X
+ * and its elementwise steps, queued without host synchronisation) and
+ * t_precond_ms the residuals. */
 helic_status helic_eigensolve_chefsi(helic_basis h, const helic_solve_opts* opts, int32_t degree,
                                      double* evals, double* resid, double* evecs, int64_t ldv,
                                      helic_solve_stats* stats, void* stream);
