@@ -586,7 +586,7 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     // interval [a, b] (a = the block's largest Ritz value, b = an upper bound
     // of the spectrum) and grows what lies below a, then orthonormalised and
     // rotated by FP64 Rayleigh-Ritz.  Scaled three-term recurrence (Zhou and
-    // Saad, 2007), applied to all n columns.
+    // Saad, 2007), applied to the columns not yet locked.
     const int m = cheb_degree;
     double b_up = 0.0;
     {
