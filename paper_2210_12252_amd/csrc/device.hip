@@ -1503,12 +1503,13 @@ helic_status helic_gradient(helic_basis h, const double* X, int64_t ldx, int32_t
       fac[h->L + i] = 2.0 * PI_D * h->mnk[3 * i + 1];
     }
     for (int l = 0; l < h->n_r; ++l) rg[l] = h->p.R * h->q[l];
+    if (!d->tdinv64 && (s = upload(h->tab_dinv, &d->tdinv64))) return s;
+    if (!d->grad_fac && (s = upload(fac, &d->grad_fac))) return s;
+    if (!d->rgrid && (s = upload(rg, &d->rgrid))) return s;
     DProb p = problem_entry(h, true, 0, 0);
-    if ((s = upload(h->tab_dinv, &d->tdinv64)) || (s = upload(fac, &d->grad_fac)) || (s = upload(rg, &d->rgrid)))
-      return s;
     p.tinv = d->tdinv64;
     std::vector<DProb> pv(1, p);
-    if ((s = upload(pv, &d->probs_dr))) return s;
+    if ((s = upload(pv, &d->probs_dr))) return s;   // set last: marks the set-up complete
   }
   const int chunk = std::min<int>(nvec, APPLY_CHUNK);
   const size_t need = (size_t)chunk * h->L * 2 * sizeof(double);
