@@ -274,7 +274,8 @@ helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* opts,
  * residuals (lambda_j(eta) = lambda_j(-eta)), and its stats entry is zero.
  * *npairs (host, may be NULL) receives the number of such problems.
  * enable = 0 solves every problem again.  Reads the potentials back once
- * (synchronous). */
+ * (synchronous); the pairing holds until the next call, so call again after
+ * changing a potential. */
 helic_status helic_batch_time_reversal(helic_batch b, int32_t enable, int32_t* npairs);
 /* As helic_batch_eigensolve, each problem by Chebyshev-filtered subspace
  * iteration (helic_eigensolve_chefsi; degree 0 picks 32). */
