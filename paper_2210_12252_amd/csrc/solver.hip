@@ -632,9 +632,10 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
       const std::vector<double> off(be.begin(), be.end() - 1);
       b_up = tridiag_max_eig(al, off) + be.back();
     }
-    // Hard locking in the FP64 phase: the leading nl columns, converged to
-    // tol, are no longer filtered; the filtered rest is projected against
-    // them and Rayleigh-Ritz runs on the rest only (nl as in LOBPCG below).
+    // Hard locking: the leading nl columns, converged to the phase's lock
+    // tolerance, are no longer filtered; the filtered rest is projected
+    // against them and Rayleigh-Ritz runs on the rest only (nl as in LOBPCG
+    // below).
     for (it = 0; it < o.maxit; ++it) {
       if ((s = residuals(nrm))) return s;
       for (int j = 0; j < n; ++j)
@@ -652,8 +653,10 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
         break;
       }
       if (prec != HELIC_FP64 && worst <= switch_tol) {
-        // precision ladder: H X in FP64 and a fresh Rayleigh-Ritz, then FP64 filters
+        // precision ladder: H X in FP64 and a fresh Rayleigh-Ritz over every
+        // column (the FP32 locks are released), then FP64 filters
         prec = HELIC_FP64;
+        nl = 0;
         if ((s = apply(S, AS, n))) return s;
         if ((s = rayleigh_ritz(0, n, n, 0))) return s;
         HIP_TRY_S(hipMemcpyAsync(S, Xn, sizeof(double) * Lc * n, hipMemcpyDeviceToDevice, st));
@@ -667,8 +670,10 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
         std::fflush(stderr);
       }
       if (prec != HELIC_FP64) ++S_.iters_low;
-      if (prec == HELIC_FP64)
-        while (nl < n - 1 && nrm[nl] <= o.tol) ++nl;
+      // in the FP32 phase a column is locked at switch_tol, where FP32
+      // filtering stops improving it; the FP64 phase starts unlocked
+      const double lock_tol = prec == HELIC_FP64 ? o.tol : std::max(o.tol, switch_tol);
+      while (nl < n - 1 && nrm[nl] <= lock_tol) ++nl;
       const int nu = n - nl;
       const int64_t nd = (int64_t)Lc * nu;
       const int gridc = (int)std::min<int64_t>(4096, (nd + NTS - 1) / NTS);
