@@ -1,6 +1,7 @@
 // Device side of the helical-wave Hamiltonian library: table upload, the
 // three kernels of H*X (see kernels.hpp), the transforms on their own, the
 // Teter-Payne-Allan preconditioner and their C ABI entry points.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +16,15 @@
 #include "kernels.hpp"
 #include "angular_fast.hpp"
 #include "angular_grid.hpp"
+
+// Stage launch; with timing events they ride on the kernel's own dispatch
+// packet (start and end timestamps of that kernel, no marker packets between
+// the stages).
+#define HELIC_LAUNCH(K, G, B, LDS, ST, E0, E1, ...)                                  \
+  do {                                                                             \
+    if (E0) hipExtLaunchKernelGGL(K, G, B, LDS, ST, E0, E1, 0, __VA_ARGS__);       \
+    else hipLaunchKernelGGL(K, G, B, LDS, ST, __VA_ARGS__);                         \
+  } while (0)
 
 namespace helic {
 
@@ -754,18 +764,19 @@ int inv_ks_for(const helic_basis_s* h) {
 
 template <typename T>
 void launch_radial_inverse(int ks, int nwg, size_t lds, hipStream_t st, const double* X, int64_t ldx, T* gh,
-                           int nvec, int ngroups, int n_r, const DGroup* groups, const DProb* probs) {
+                           int nvec, int ngroups, int n_r, const DGroup* groups, const DProb* probs,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (ks <= 8)
-    hipLaunchKernelGGL((k_radial_inverse<T, 8>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r, groups,
+    HELIC_LAUNCH((k_radial_inverse<T, 8>), dim3(nwg), dim3(NT), lds, st, e0, e1, X, ldx, gh, nvec, ngroups, n_r, groups,
                        probs);
   else if (ks <= 12)
-    hipLaunchKernelGGL((k_radial_inverse<T, 12>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r,
+    HELIC_LAUNCH((k_radial_inverse<T, 12>), dim3(nwg), dim3(NT), lds, st, e0, e1, X, ldx, gh, nvec, ngroups, n_r,
                        groups, probs);
   else if (ks <= 16)
-    hipLaunchKernelGGL((k_radial_inverse<T, 16>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r,
+    HELIC_LAUNCH((k_radial_inverse<T, 16>), dim3(nwg), dim3(NT), lds, st, e0, e1, X, ldx, gh, nvec, ngroups, n_r,
                        groups, probs);
   else
-    hipLaunchKernelGGL((k_radial_inverse<T, 24>), dim3(nwg), dim3(NT), lds, st, X, ldx, gh, nvec, ngroups, n_r,
+    HELIC_LAUNCH((k_radial_inverse<T, 24>), dim3(nwg), dim3(NT), lds, st, e0, e1, X, ldx, gh, nvec, ngroups, n_r,
                        groups, probs);
 }
 
@@ -785,38 +796,39 @@ int fwd_pf_tiles(bool fp64, int tiles_max) {
 template <typename T>
 void launch_radial_forward(int tmax, int nwg, size_t lds, hipStream_t st, const T* gh, const double* X, int64_t ldx,
                            double* Y, int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* groups,
-                           const DProb* probs, int mode, int tm = 8) {
+                           const DProb* probs, int mode, int tm = 8, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr) {
   switch (tmax) {
     case 0:   // pipelined variants (columns staged per lane: 2 or 4 of 64; register tiles per wave)
       if (tm == 8)
-        hipLaunchKernelGGL((k_radial_forward_pf<T, 2, 8>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+        HELIC_LAUNCH((k_radial_forward_pf<T, 2, 8>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
                            ngroups, n_r, groups, probs, mode);
       else
-        hipLaunchKernelGGL((k_radial_forward_pf<T, 2, 4>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+        HELIC_LAUNCH((k_radial_forward_pf<T, 2, 4>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
                            ngroups, n_r, groups, probs, mode);
       break;
     case -1:
       if (tm == 8)
-        hipLaunchKernelGGL((k_radial_forward_pf<T, 4, 8>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+        HELIC_LAUNCH((k_radial_forward_pf<T, 4, 8>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
                            ngroups, n_r, groups, probs, mode);
       else
-        hipLaunchKernelGGL((k_radial_forward_pf<T, 4, 4>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+        HELIC_LAUNCH((k_radial_forward_pf<T, 4, 4>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
                            ngroups, n_r, groups, probs, mode);
       break;
     case 4:
-      hipLaunchKernelGGL((k_radial_forward<T, 4>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec, ngroups,
+      HELIC_LAUNCH((k_radial_forward<T, 4>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec, ngroups,
                          n_r, groups, probs, mode);
       break;
     case 8:
-      hipLaunchKernelGGL((k_radial_forward<T, 8>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec, ngroups,
+      HELIC_LAUNCH((k_radial_forward<T, 8>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec, ngroups,
                          n_r, groups, probs, mode);
       break;
     case 12:
-      hipLaunchKernelGGL((k_radial_forward<T, 12>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+      HELIC_LAUNCH((k_radial_forward<T, 12>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
                          ngroups, n_r, groups, probs, mode);
       break;
     default:
-      hipLaunchKernelGGL((k_radial_forward<T, 16>), dim3(nwg), dim3(NT), lds, st, gh, X, ldx, Y, ldy, nvec,
+      HELIC_LAUNCH((k_radial_forward<T, 16>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
                          ngroups, n_r, groups, probs, mode);
       break;
   }
@@ -905,7 +917,8 @@ inline unsigned angular_grid_size(const LaunchSet& ls, int nvec, int ipw) {
 }
 
 template <typename T>
-helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
+helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr) {
   const DProb* probs = std::is_same<T, double>::value ? ls.probs64 : ls.probs32;
   const cplx<T>* tw2 = (const cplx<T>*)(std::is_same<T, double>::value ? ls.tw2_64 : ls.tw2_32);
   const int ipw = angular_items_per_wg<T>(ls, nvec);
@@ -913,8 +926,8 @@ helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
   const size_t lds = fast_lds_bytes<T>(ls.n_t2, ls.fast_mpad);
 #define HELIC_FAST_CASE(N2_, MP_, NTF_)                                                                   \
   if (ls.n_t2 == N2_ && ls.fast_mpad == MP_) {                                                          \
-    hipLaunchKernelGGL((k_angular_fast<T, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, gh, ls.nprob, nvec, \
-                       ls.n_r, probs, tw2, ipw);                                                        \
+    HELIC_LAUNCH((k_angular_fast<T, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, e0, e1, gh, ls.nprob, nvec, \
+                 ls.n_r, probs, tw2, ipw);                                                              \
     HIP_TRY(hipGetLastError());                                                                         \
     return HELIC_OK;                                                                                    \
   }
@@ -980,7 +993,8 @@ int grid_slots(int n1, int n2, int ncu) {
 }
 
 template <typename T>
-helic_status launch_grid(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
+helic_status launch_grid(const LaunchSet& ls, T* gh, int nvec, hipStream_t st, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr) {
   const DProb* probs = std::is_same<T, double>::value ? ls.probs64 : ls.probs32;
   const cplx<T>* tw2 = (const cplx<T>*)(std::is_same<T, double>::value ? ls.tw2_64 : ls.tw2_32);
   const int ipw = angular_items_per_wg<T>(ls, nvec);
@@ -988,8 +1002,8 @@ helic_status launch_grid(const LaunchSet& ls, T* gh, int nvec, hipStream_t st) {
   const size_t lds = grid_lds_bytes<T>(ls.n_t1, ls.n_t2);
 #define HELIC_GRID_CASE(N1_, N2_, PA_, PB_)                                                              \
   if (ls.n_t1 == N1_ && ls.n_t2 == N2_) {                                                               \
-    hipLaunchKernelGGL((k_angular_grid<T, N1_, N2_, PA_, PB_, GRID_NTF>), grid, dim3(GRID_NTF), lds, st, gh, \
-                       ls.nprob, nvec, ls.n_r, probs, tw2, ipw);                                        \
+    HELIC_LAUNCH((k_angular_grid<T, N1_, N2_, PA_, PB_, GRID_NTF>), grid, dim3(GRID_NTF), lds, st, e0, e1, gh, \
+                 ls.nprob, nvec, ls.n_r, probs, tw2, ipw);                                              \
     HIP_TRY(hipGetLastError());                                                                         \
     return HELIC_OK;                                                                                    \
   }
@@ -1273,32 +1287,30 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
   T* gh = reinterpret_cast<T*>(ls.gh);
   const size_t sc = f64 ? 1 : 2;
   const int wg_rad = 8 * ((ls.ngroups * nvec + 7) / 8);
-  if (ev) HIP_TRY(hipEventRecord(ev[0], st));
+  // ev (optional): start and end events of each of the three kernels
+  auto e = [&](int k) { return ev ? ev[k] : (hipEvent_t) nullptr; };
   launch_radial_inverse<T>(ls.inv_ks, wg_rad, ls.lds_inv64 / sc, st, X, ldx, gh, nvec, ls.ngroups, ls.n_r,
-                           ls.groups, probs);
+                           ls.groups, probs, e(0), e(1));
   HIP_TRY(hipGetLastError());
-  if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   if (ls.fast_mpad) {
-    helic_status s = launch_fast<T>(ls, gh, nvec, st);
+    helic_status s = launch_fast<T>(ls, gh, nvec, st, e(2), e(3));
     if (s != HELIC_OK) return s;
   } else if (ls.grid_var) {
-    helic_status s = launch_grid<T>(ls, gh, nvec, st);
+    helic_status s = launch_grid<T>(ls, gh, nvec, st, e(2), e(3));
     if (s != HELIC_OK) return s;
   } else {
     const int wg_ang = 8 * ((ls.nprob * nvec * ls.n_r + 7) / 8);
     const cplx<T>* tw1 = (const cplx<T>*)(f64 ? ls.tw1_64 : ls.tw1_32);
     const cplx<T>* tw2 = (const cplx<T>*)(f64 ? ls.tw2_64 : ls.tw2_32);
-    hipLaunchKernelGGL((k_angular<T, 0>), dim3(wg_ang), dim3(NT), ls.lds_ang64 / sc, st, gh, nullptr, nullptr,
-                       ls.nprob, nvec, ls.n_r, probs, ls.rows1, ls.nrows1, tw1, tw2, ls.plan1, ls.plan2, (T)1);
+    HELIC_LAUNCH((k_angular<T, 0>), dim3(wg_ang), dim3(NT), ls.lds_ang64 / sc, st, e(2), e(3), gh, nullptr, nullptr,
+                 ls.nprob, nvec, ls.n_r, probs, ls.rows1, ls.nrows1, tw1, tw2, ls.plan1, ls.plan2, (T)1);
     HIP_TRY(hipGetLastError());
   }
-  if (ev) HIP_TRY(hipEventRecord(ev[2], st));
   const bool kx_lds = ls.fwd_tmax <= 0 && mode && (f64 ? ls.kx_lds64 : ls.kx_lds32);
   launch_radial_forward<T>(ls.fwd_tmax, wg_rad, f64 ? ls.lds_fwd64 : ls.lds_fwd32, st, gh, X, ldx, Y, ldy, nvec,
                            ls.ngroups, ls.n_r, ls.groups, probs, mode | (kx_lds ? 2 : 0),
-                           f64 ? ls.fwd_tm64 : ls.fwd_tm32);
+                           f64 ? ls.fwd_tm64 : ls.fwd_tm32, e(4), e(5));
   HIP_TRY(hipGetLastError());
-  if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   return HELIC_OK;
 }
 
@@ -1416,15 +1428,19 @@ helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, do
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int chunk = h->dev->apply_chunk;
   const int nch = (nvec + chunk - 1) / chunk;
-  std::vector<hipEvent_t> ev(4 * (size_t)nrep * nch, nullptr);
-  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  // timing-only events: no system-scope fence (cache write-back and
+  // invalidation) at each record, which would otherwise sit between the stages
+  // start and end events of each stage kernel, carried by the kernels'
+  // dispatch packets (no marker packets, no cache fences between stages)
+  std::vector<hipEvent_t> ev(6 * (size_t)nrep * nch, nullptr);
+  for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   for (int i = 0; i < nrep && s == HELIC_OK; ++i)
     for (int c = 0; c < nch && s == HELIC_OK; ++c) {
       const int v0 = c * chunk, nv = std::min(chunk, nvec - v0);
-      hipEvent_t* e4 = &ev[4 * ((size_t)i * nch + c)];
+      hipEvent_t* e6 = &ev[6 * ((size_t)i * nch + c)];
       s = prec == HELIC_FP64
-              ? launch_apply<double>(h, X + (int64_t)v0 * ldx * 2, ldx, Y + (int64_t)v0 * ldy * 2, ldy, nv, st, 1, e4)
-              : launch_apply<float>(h, X + (int64_t)v0 * ldx * 2, ldx, Y + (int64_t)v0 * ldy * 2, ldy, nv, st, 1, e4);
+              ? launch_apply<double>(h, X + (int64_t)v0 * ldx * 2, ldx, Y + (int64_t)v0 * ldy * 2, ldy, nv, st, 1, e6)
+              : launch_apply<float>(h, X + (int64_t)v0 * ldx * 2, ldx, Y + (int64_t)v0 * ldy * 2, ldy, nv, st, 1, e6);
     }
   double acc[3] = {0, 0, 0}, tot = 0;
   if (s == HELIC_OK) {
@@ -1432,13 +1448,13 @@ helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, do
     for (size_t i = 0; i < (size_t)nrep * nch && e == hipSuccess; ++i) {
       float ms;
       for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-        e = hipEventElapsedTime(&ms, ev[4 * i + k], ev[4 * i + k + 1]);
+        e = hipEventElapsedTime(&ms, ev[6 * i + 2 * k], ev[6 * i + 2 * k + 1]);
         acc[k] += ms;
       }
     }
     for (int i = 0; i < nrep && e == hipSuccess; ++i) {
       float ms;
-      e = hipEventElapsedTime(&ms, ev[4 * (size_t)i * nch], ev[4 * ((size_t)i * nch + nch - 1) + 3]);
+      e = hipEventElapsedTime(&ms, ev[6 * (size_t)i * nch], ev[6 * ((size_t)i * nch + nch - 1) + 5]);
       tot += ms;
     }
     if (e != hipSuccess) s = fail(HELIC_ERR_HIP, std::string("event timing: ") + hipGetErrorString(e));

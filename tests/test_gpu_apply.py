@@ -319,3 +319,18 @@ def test_apply_H_widest_radial_groups_and_ragged_block():
         err = _rel(c.from_gpu_block(Yg), ref)
         print(f"[wide K {prec}] L={c.o.L} rel err {err:.2e}", flush=True)
         assert err < tol
+
+
+def test_profile_apply_matches_apply_and_times_each_stage(tiny):
+    """The timing path (start and end events carried by the three stage
+    kernels) computes the same block as helic_apply_H; the stage durations
+    are positive and fit inside the whole application's span."""
+    X = tiny.to_gpu_block(synth.random_block(tiny.o.mnk, 8, 61))
+    Y0 = torch.empty_like(X)
+    Y1 = torch.empty_like(X)
+    tiny.g.apply_H(X, Y0)
+    ms, tot = tiny.g.profile_apply(X, Y1, nrep=3)
+    torch.cuda.synchronize()
+    assert torch.equal(Y0, Y1)
+    assert all(m > 0 for m in ms) and tot > 0
+    assert sum(ms) <= tot * 1.001
