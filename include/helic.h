@@ -158,11 +158,12 @@ helic_status helic_density(helic_basis h, const double* X, int64_t ldx, int32_t 
                            const double* occ, double* rho, int32_t accumulate, void* stream);
 
 /* Timing aid: run `nrep` applications of H to the same block exactly as
- * helic_apply_H does (nvec <= 64), recording HIP events on `stream` around
- * each of the three stage kernels (radial inverse, angular, radial forward).
- * ms_stage (host, 3 doubles) receives each stage's mean duration in ms and
- * *ms_total (host, may be NULL) the mean time of one whole application.
- * Synchronises `stream` before returning. */
+ * helic_apply_H does (nvec <= 64), each of the three stage kernels (radial
+ * inverse, angular, radial forward) carrying start and end events on its own
+ * dispatch (timing-only events, no system-scope fence).  ms_stage (host, 3
+ * doubles) receives each kernel's mean duration in ms and *ms_total (host,
+ * may be NULL) the mean span of one whole application, first kernel start to
+ * last kernel end.  Synchronises `stream` before returning. */
 helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,
                                  int32_t nvec, helic_prec prec, int32_t nrep, void* stream,
                                  double* ms_stage, double* ms_total);
