@@ -135,13 +135,13 @@ def test_batched_eigensolve_matches_lapack_per_problem():
     batch.close()
 
 
-def test_batched_filtered_eigensolve_matches_lapack_per_problem():
-    etas = (-0.5, -0.25, 0.0, 0.25)
-    probs, batch = make_batch(TINY, etas)
-    ev, res, stats, status = batch.eigensolve(TINY.nev, nstreams=3, tol=1e-9, maxit=200, cheb_degree=0)
+@pytest.mark.parametrize("base,etas", [(TINY, (-0.5, -0.25, 0.0, 0.25)), (GENERAL, (-0.3, 0.0, 0.25))])
+def test_batched_filtered_eigensolve_matches_lapack_per_problem(base, etas):
+    probs, batch = make_batch(base, etas)
+    ev, res, stats, status = batch.eigensolve(base.nev, nstreams=3, tol=1e-9, maxit=200, cheb_degree=0)
     assert np.all(status == helic.OK), status
     for i, p in enumerate(probs):
-        ref, _ = oh.lowest(oh.dense_explicit(p.o, p.V), TINY.nev)
+        ref, _ = oh.lowest(oh.dense_explicit(p.o, p.V), base.nev)
         assert np.max(np.abs(ev[i] - ref)) < 1e-8, (i, ev[i] - ref)
     with pytest.raises(helic.HelicError):
         batch.eigensolve(TINY.nev, cheb_degree=-1)
