@@ -67,6 +67,16 @@ def test_density_matches_oracle_ragged_chunks(tiny):
     assert _rel(tiny.host(rho), ref) < TOL
 
 
+def test_density_with_a_padded_leading_dimension(tiny):
+    X = synth.random_block(tiny.o.mnk, 7, 34)
+    occ = np.linspace(0.25, 1.75, 7)
+    padded = torch.zeros((7, tiny.o.L + 13), dtype=torch.complex128, device=_dev())
+    padded[:, :tiny.o.L] = tiny.block(X)
+    rho = tiny.rho()
+    tiny.g.density(padded[:, :tiny.o.L], occ, rho)
+    assert _rel(tiny.host(rho), od.density(tiny.o, X, occ)) < TOL
+
+
 def test_density_accumulates_and_zeroes(tiny):
     X = synth.random_block(tiny.o.mnk, 21, 32)
     occ = np.linspace(0.5, 2.0, 21)

@@ -73,6 +73,19 @@ def test_cartesian_derivatives_match_oracle(tiny):
         assert _rel(got[c], ref[c]) < TOL
 
 
+def test_gradient_with_a_padded_leading_dimension(tiny):
+    o, g, perm = tiny
+    X = synth.random_block(o.mnk, 3, 54)
+    padded = torch.zeros((3, o.L + 9), dtype=torch.complex128, device=_dev())
+    padded[:, :o.L] = torch.from_numpy(np.ascontiguousarray(X[perm].T)).to(_dev())
+    out = torch.empty((3, 3, o.n_t1, o.n_t2, o.n_r), dtype=torch.complex128, device=_dev())
+    g.gradient(padded[:, :o.L], out)
+    torch.cuda.synchronize()
+    ref = og.helical_derivatives(o, X)
+    for c in range(3):
+        assert _rel(np.moveaxis(out[c].cpu().numpy(), 0, -1), ref[c]) < TOL
+
+
 def test_gradient_argument_errors(tiny):
     o, g, perm = tiny
     X = torch.zeros((2, o.L), dtype=torch.complex128, device=_dev())
