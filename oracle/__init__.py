@@ -22,18 +22,19 @@ transparency over speed:
                     with explicit exponential matrices (no FFT).
 * ``hamiltonian``-- the discrete operator H = kinetic diagonal + forward(V *
                     inverse(.)) (eqs. Simplify_2 and g_mnk, Alg. 5 at nu = 0)
-                    as a dense matrix built two independent ways, as a
-                    matrix-free apply, and its lowest eigenpairs by LAPACK.
+                    as a dense matrix built two independent ways (the second
+                    also one pair of angular modes at a time, for mid-size
+                    bases), as a matrix-free apply, and its lowest eigenpairs
+                    by LAPACK.
 * ``precond``    -- the Teter-Payne-Allan diagonal preconditioner (Sec. 3.5).
 * ``density``    -- the electron density sum_j occ_j |phi_j|^2 on the grid
                     (Sec. 4.2, the density equation, one (eta, nu) term).
 * ``gradient``   -- derivatives of a field given by coefficients in helical
                     and Cartesian coordinates (App. C).
 * ``mlp``        -- forward and backward pass of the small per-coefficient
-                    network used as a learned preconditioner (no paper source;
-                    it exists to check the GPU kernels' gradients).
-* ``solver``     -- a plain block eigensolver built on the dense oracle
-                    operator, for iteration-count comparisons.
+                    network used as a learned preconditioner and its Adam
+                    step (no paper source; it exists to check the GPU
+                    kernels' gradients and updates).
 
 Every function that is not pinned by a test against something other than
 itself says "parity unpinned" in its docstring.

@@ -3,7 +3,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <stdexcept>
 
 namespace helic {
 
@@ -113,51 +112,47 @@ void jacobi01(int n, double x, double* pn, double* pn1) {
   *pn1 = p0;
 }
 
-// Eigenvalues of the symmetric tridiagonal matrix (d diagonal, e[i] couples
-// i and i+1) by implicit QL with Wilkinson-type shifts.
-void tridiag_eigenvalues(std::vector<double>& d, std::vector<double> e) {
-  const int n = (int)d.size();
-  e.resize(n, 0.0);
-  for (int l = 0; l < n; ++l) {
-    int iter = 0, m;
-    do {
-      for (m = l; m < n - 1; ++m) {
-        double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-        if (std::fabs(e[m]) <= 1e-17 * dd) break;
-      }
-      if (m != l) {
-        if (++iter > 200) throw std::runtime_error("tridiagonal QL did not converge");
-        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-        double r = std::hypot(g, 1.0);
-        g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
-        double s = 1.0, c = 1.0, p = 0.0;
-        int i;
-        bool deflated = false;
-        for (i = m - 1; i >= l; --i) {
-          double f = s * e[i], b = c * e[i];
-          r = std::hypot(f, g);
-          e[i + 1] = r;
-          if (r == 0.0) {
-            d[i + 1] -= p;
-            e[m] = 0.0;
-            deflated = true;
-            break;
-          }
-          s = f / r;
-          c = g / r;
-          g = d[i + 1] - p;
-          r = (d[i] - g) * s + 2.0 * c * b;
-          p = s * r;
-          d[i + 1] = g + p;
-          g = c * r - b;
-        }
-        if (deflated) continue;
-        d[l] -= p;
-        e[l] = g;
-        e[m] = 0.0;
-      }
-    } while (m != l);
+// Number of eigenvalues below x of the symmetric tridiagonal matrix T with
+// diagonal d and off-diagonal e (e[i] couples i and i + 1): by Sylvester's
+// law of inertia, the number of negative pivots of the LDL^T factorisation of
+// T - x I, whose pivots obey p_0 = d_0 - x, p_i = d_i - x - e_{i-1}^2 / p_{i-1}
+// (the Sturm-sequence count of Barth, Martin and Wilkinson, 1967).  A zero
+// pivot is replaced by a tiny negative one.
+int count_below(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  int neg = 0;
+  double piv = 1.0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    piv = (d[i] - x) - (i > 0 ? e[i - 1] * e[i - 1] / piv : 0.0);
+    if (piv == 0.0) piv = -1e-300;
+    neg += piv < 0.0;
   }
+  return neg;
+}
+
+// All eigenvalues of that matrix, ascending, each by bisection on the count
+// above inside the Gershgorin interval, down to a few units in the last
+// place (the Newton step of the caller polishes them further).
+std::vector<double> tridiag_eigenvalues(const std::vector<double>& d, const std::vector<double>& e) {
+  const int n = (int)d.size();
+  double lo = d[0], hi = d[0];
+  for (int i = 0; i < n; ++i) {
+    const double rad = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - rad);
+    hi = std::max(hi, d[i] + rad);
+  }
+  std::vector<double> ev(n);
+  double floor_k = lo;   // eigenvalue k is >= eigenvalue k - 1
+  for (int k = 0; k < n; ++k) {
+    double a = floor_k, b = hi;   // count_below(a) <= k < count_below(b)
+    for (int it = 0; it < 200 && b - a > 4e-16 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+      const double mid = 0.5 * (a + b);
+      if (mid <= a || mid >= b) break;
+      if (count_below(d, e, mid) > k) b = mid; else a = mid;
+    }
+    ev[k] = 0.5 * (a + b);
+    floor_k = a;
+  }
+  return ev;
 }
 }  // namespace
 
@@ -167,10 +162,9 @@ void gauss_jacobi01(int n, double* q, double* w) {
   std::vector<double> d(n), e(n > 1 ? n - 1 : 0);
   for (int k = 0; k < n; ++k) d[k] = 1.0 / ((2.0 * k + 1) * (2.0 * k + 3));
   for (int k = 1; k < n; ++k) e[k - 1] = std::sqrt((double)k * (k + 1)) / (2.0 * k + 1);
-  tridiag_eigenvalues(d, e);
-  std::sort(d.begin(), d.end());
+  const std::vector<double> nodes = tridiag_eigenvalues(d, e);
   for (int i = 0; i < n; ++i) {
-    double x = d[i], pn, pn1, dp = 1.0;
+    double x = nodes[i], pn, pn1, dp = 1.0;
     for (int it = 0; it < 4; ++it) {
       jacobi01(n, x, &pn, &pn1);
       // (2n+1)(1-x^2) P_n' = n(-1 - (2n+1) x) P_n + 2 n (n+1) P_{n-1}

@@ -268,7 +268,8 @@ def test_apply_H_parity_radix2_grid(generic, monkeypatch):
     assert err < TOL64
 
 
-@pytest.mark.parametrize("grid", [(20, 96, 24), (27, 144, 24), (24, 135, 24)])
+@pytest.mark.parametrize("grid", [(20, 96, 24), (20, 120, 24), (24, 120, 24), (24, 135, 24), (27, 144, 24),
+                                  (27, 180, 24)])
 def test_register_fft_angular_kernel_parity(grid, monkeypatch):
     """Grids of the batched workload served by the register-FFT angular
     kernel (theta1 column DFTs in registers, non-square theta2 four-step):

@@ -204,6 +204,23 @@ def test_dense_modes_agree_and_are_hermitian(tiny):
     assert np.max(np.abs(oh.apply(b, V, X) - HA @ X)) < 1e-13
 
 
+def test_mode_pair_assembly_equals_the_basis_matrix_form(tiny):
+    """dense_dft_modes (mode B one pair of angular modes at a time, used for
+    mid-size golden eigenvalues) against the explicit basis-matrix form, on
+    the tiny workload and on a twisted, eta-shifted basis whose modes have
+    ragged radial lengths; its lowest eigenvalues against LAPACK on mode A."""
+    w, b, V, B = tiny
+    HA = oh.dense_explicit(b, V, B)
+    assert np.max(np.abs(oh.dense_dft_modes(b, V) - HA)) < 1e-13
+    lam = oh.lowest_values(oh.dense_dft_modes(b, V), 8)
+    assert np.max(np.abs(lam - oh.lowest(HA, 8)[0])) < 1e-12
+    b2 = small_basis()
+    V2 = synth.potential_at(b2.theta1, b2.theta2, b2.r, b2.tau, b2.alpha,
+                            synth.atoms_for("helix6", 4, b2.tau, b2.R))
+    assert len(set(b2.mnk[:, 2].tolist())) > 1
+    assert np.max(np.abs(oh.dense_dft_modes(b2, V2) - oh.dense_explicit(b2, V2))) < 1e-13
+
+
 def test_matrix_free_apply_is_hermitian():
     b = small_basis()
     atoms = synth.atoms_for("helix6", 9, b.tau, b.R)
@@ -360,6 +377,36 @@ def test_mlp_untrained_network_is_tpa_and_loss_invariances():
     sr = mlp.forward(theta, F, K)[0] * R
     l0, g0 = mlp.loss_and_grad(theta, F, K, R, sr)                  # target along s r: zero loss, zero gradient
     assert abs(l0) < 1e-14 and np.max(np.abs(g0)) < 1e-12
+
+
+def test_adam_step_against_the_published_algorithm():
+    """oracle.mlp.adam_step against Kingma & Ba (2015), Algorithm 1: moments
+    m_t = b1 m + (1 - b1) g, v_t = b2 v + (1 - b2) g^2, bias-corrected by
+    1 - b^t, step -lr m_hat / (sqrt(v_hat) + eps)."""
+    from oracle import mlp
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(50) * np.logspace(-3, 2, 50)
+    theta0 = rng.standard_normal(50)
+    # first step from zero moments: the bias corrections give m_hat = g and
+    # v_hat = g^2, so every coordinate moves by exactly lr * g / (|g| + eps)
+    th, m, v = mlp.adam_step(theta0, g, np.zeros(50), np.zeros(50), 1, 0.01)
+    np.testing.assert_allclose(th, theta0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=4e-15)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=4e-15)
+    # a constant gradient keeps m_hat = g and v_hat = g^2 at every step t
+    # (wrong powers of b1, b2 in the bias correction break this)
+    th, m, v = theta0.copy(), np.zeros(50), np.zeros(50)
+    for t in range(1, 31):
+        prev = th
+        th, m, v = mlp.adam_step(th, g, m, v, t, 0.01)
+        np.testing.assert_allclose(prev - th, 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-17)
+    # two steps worked by hand (40-digit decimal arithmetic): g = 1 then
+    # g = -1/2, lr = 0.1 from theta = 0: m = 0.04, v = 0.001249 after step 2
+    th, m, v = mlp.adam_step(np.zeros(1), np.ones(1), np.zeros(1), np.zeros(1), 1, 0.1)
+    assert abs(th[0] - (-0.0999999990000000099999999)) < 1e-16
+    th, m, v = mlp.adam_step(th, -0.5 * np.ones(1), m, v, 2, 0.1)
+    assert abs(m[0] - 0.04) < 1e-16 and abs(v[0] - 0.001249) < 1e-17
+    assert abs(th[0] - (-0.1266337026290970334541760)) < 1e-15
 
 
 def test_potential_diagonal_is_the_dense_diagonal():
