@@ -120,6 +120,28 @@ helic_status helic_set_potential(helic_basis h, const double* V, void* stream);
 helic_status helic_apply_H(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,
                            int32_t nvec, helic_prec prec, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): Y = H X
+ * exactly as helic_apply_H computes it, with the intermediate slabs in a
+ * fixed scratch array of HELIC_NOALLOC_SCRATCH_MIB MiB per GPU instead of
+ * the handle's growable buffer.  The array is part of the library's device
+ * code: each GPU the library runs on holds one copy from the first basis
+ * set-up on it until the process ends.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine); the caller passes X and
+ * Y as for helic_apply_H.  Vectors go through the stages in chunks of
+ * min(64, scratch / (n_r * n_modes * 16 bytes in FP64, 8 in FP32)).
+ * Requires a potential (helic_set_potential, which also completes the
+ * device set-up) on the current device.  All calls on one GPU share its
+ * array and leave their last chunk's slabs in it (nothing in it has to start
+ * at zero: every slab element is written before it is read); calls that
+ * overlap on one GPU (two streams or two host threads) race, so the caller
+ * serialises them.  Errors: as helic_apply_H; HELIC_ERR_STATE without a
+ * potential or on another device; HELIC_ERR_NOMEM when one vector's slabs
+ * (n_r * n_modes complex values) exceed the array. */
+#define HELIC_NOALLOC_SCRATCH_MIB 64
+helic_status helic_apply_H_noalloc(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                                   int32_t nvec, helic_prec prec, void* stream);
+
 /* Inverse basis transform (Alg. 1 and 2) of nvec coefficient columns onto the
  * grid: g (device) holds nvec consecutive real-space arrays of complex
  * doubles, n_t1*n_t2*n_r each.  Forward transform (Alg. 3 and 4):

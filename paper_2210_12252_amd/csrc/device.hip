@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1059,6 +1060,35 @@ FftPlan make_plan(int n, const std::vector<int32_t>& f) {
 
 }  // namespace
 
+// Scratch array of helic_apply_H_noalloc: the intermediate slabs of H*X for
+// callers that cannot allocate.  One copy per GPU, loaded with the code
+// object and held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the device
+// symbol): it uses the address hipGetSymbolAddress returns on each device,
+// taken once per device at the first handle set-up there (the device is
+// current then) and kept in scratch_dev.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)HELIC_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+helic_status scratch_setup(int dev) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(HELIC_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_dev[dev]) return HELIC_OK;
+  void* ptr = nullptr;
+  HIP_TRY(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(HELIC_ERR_HIP, "no device address for the scratch array");
+  scratch_dev[dev] = ptr;
+  return HELIC_OK;
+}
+
+void* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  return (dev >= 0 && dev < SCRATCH_MAX_DEVICES) ? scratch_dev[dev] : nullptr;
+}
+
 DProb problem_entry(const helic_basis_s* h, bool fp64, int64_t Lpre, int64_t mpre);
 
 helic_status ensure_device(helic_basis_s* h) {
@@ -1078,10 +1108,11 @@ helic_status ensure_device(helic_basis_s* h) {
   if ((size_t)h->max_kpad * lds_stride(h->max_colpad) * sizeof(double) > 160 * 1024 ||
       fwd_lds_bytes(h, sizeof(double)) > 160 * 1024)
     return fail(HELIC_ERR_GRID, "a radial tile of the widest |n| group does not fit in LDS");
+  helic_status s;
+  if ((s = scratch_setup(cur)) != HELIC_OK) return s;
   DeviceState* d = new DeviceState();
   d->device = cur;
   h->dev = d;
-  helic_status s;
   if ((s = set_lds_limits<double>()) != HELIC_OK) return s;
   if ((s = set_lds_limits<float>()) != HELIC_OK) return s;
   std::vector<DGroup> dg(h->groups.size());
@@ -1342,6 +1373,34 @@ helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double
   return HELIC_OK;
 }
 
+// helic_apply_H with the intermediate slabs in this device's scratch array:
+// as many vectors per launch as fit (at most the usual 64).  Allocates
+// nothing; the handle's own buffer is neither used nor grown.
+helic_status apply_H_noalloc_impl(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                                  int nvec, helic_prec prec, hipStream_t st) {
+  void* ws = scratch_ptr(h->dev->device);
+  if (!ws) return fail(HELIC_ERR_STATE, "scratch array not set up on this device");
+  const size_t elem = prec == HELIC_FP64 ? sizeof(double) : sizeof(float);
+  const size_t per_vec = (size_t)h->n_r * h->modes.size() * 2 * elem;
+  const size_t fit = NOALLOC_SCRATCH_BYTES / per_vec;
+  if (fit == 0)
+    return fail(HELIC_ERR_NOMEM, "one vector's intermediate slabs (" + std::to_string(per_vec) +
+                                     " bytes) exceed the " + std::to_string(HELIC_NOALLOC_SCRATCH_MIB) +
+                                     " MiB scratch array");
+  const int chunk = (int)std::min<size_t>(fit, (size_t)h->dev->apply_chunk);
+  LaunchSet ls = launch_set(h);
+  ls.gh = ws;
+  for (int v0 = 0; v0 < nvec; v0 += chunk) {
+    const int nv = std::min(chunk, nvec - v0);
+    const double* Xc = X + (int64_t)v0 * ldx * 2;
+    double* Yc = Y + (int64_t)v0 * ldy * 2;
+    const helic_status s = prec == HELIC_FP64 ? launch_stages<double>(ls, Xc, ldx, Yc, ldy, nv, st, 1, nullptr)
+                                              : launch_stages<float>(ls, Xc, ldx, Yc, ldy, nv, st, 1, nullptr);
+    if (s != HELIC_OK) return s;
+  }
+  return HELIC_OK;
+}
+
 helic_status precondition_impl(helic_basis_s* h, const double* Rr, int64_t ldr, double* W, int64_t ldw,
                                int nvec, hipStream_t st) {
   DeviceState* d = h->dev;
@@ -1411,6 +1470,21 @@ helic_status helic_apply_H(helic_basis h, const double* X, int64_t ldx, double* 
   helic_status s = ensure_device(h);
   if (s != HELIC_OK) return s;
   return apply_H_impl(h, X, ldx, Y, ldy, nvec, prec, reinterpret_cast<hipStream_t>(stream), APPLY_CHUNK);
+}
+
+helic_status helic_apply_H_noalloc(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                                   int32_t nvec, helic_prec prec, void* stream) {
+  if (!h) return fail(HELIC_ERR_INVALID, "null handle");
+  if (nvec < 0 || (nvec > 0 && (!X || !Y)) || ldx < h->L || ldy < h->L)
+    return fail(HELIC_ERR_INVALID, "bad block arguments");
+  if (prec != HELIC_FP64 && prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (nvec == 0) return HELIC_OK;
+  // the device state exists once a potential is set; no set-up happens here
+  if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != h->dev->device) return fail(HELIC_ERR_STATE, "handle was set up on another device");
+  return apply_H_noalloc_impl(h, X, ldx, Y, ldy, nvec, prec, reinterpret_cast<hipStream_t>(stream));
 }
 
 helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, double* Y, int64_t ldy,

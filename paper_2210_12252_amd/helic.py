@@ -25,7 +25,7 @@ PREC = {"fp64": FP64, "fp32": FP32}
 
 # every function declared in include/helic.h
 EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "helic_basis_indices",
-           "helic_grid", "helic_set_potential", "helic_apply_H", "helic_transform_inverse",
+           "helic_grid", "helic_set_potential", "helic_apply_H", "helic_apply_H_noalloc", "helic_transform_inverse",
            "helic_transform_forward", "helic_gradient", "helic_density", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
            "helic_eigensolve_ex", "helic_eigensolve_chefsi", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
            "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
@@ -98,6 +98,7 @@ def load() -> ctypes.CDLL:
         "helic_grid": [_P, _PD, _PD, _PD, _PD],
         "helic_set_potential": [_P, _P, _P],
         "helic_apply_H": [_P, _P, _I64, _P, _I64, _I32, _I32, _P],
+        "helic_apply_H_noalloc": [_P, _P, _I64, _P, _I64, _I32, _I32, _P],
         "helic_transform_inverse": [_P, _P, _I64, _P, _I32, _P],
         "helic_transform_forward": [_P, _P, _P, _I64, _I32, _P],
         "helic_density": [_P, _P, _I64, _I32, _PD, _P, _I32, _P],
@@ -251,6 +252,17 @@ def apply_H(h, X, Y, prec="fp64", stream=None):
         raise ValueError("Y has fewer columns than X")
     _check(load().helic_apply_H(h, ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(Y.data_ptr()), ldy,
                                 nx, PREC[prec], _stream(stream)))
+
+
+def apply_H_noalloc(h, X, Y, prec="fp64", stream=None):
+    """helic_apply_H with the intermediate slabs in the library's fixed
+    per-device scratch array (no device allocation in the call)."""
+    nx, ldx = _block(X, "X")
+    ny, ldy = _block(Y, "Y")
+    if ny < nx:
+        raise ValueError("Y has fewer columns than X")
+    _check(load().helic_apply_H_noalloc(h, ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(Y.data_ptr()),
+                                        ldy, nx, PREC[prec], _stream(stream)))
 
 
 def transform_inverse(h, X, g, stream=None):
@@ -545,6 +557,9 @@ class Basis:
 
     def apply_H(self, X, Y, prec="fp64", stream=None):
         apply_H(self.h, X, Y, prec, stream)
+
+    def apply_H_noalloc(self, X, Y, prec="fp64", stream=None):
+        apply_H_noalloc(self.h, X, Y, prec, stream)
 
     def transform_inverse(self, X, g, stream=None):
         transform_inverse(self.h, X, g, stream)
