@@ -359,7 +359,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="nanotube-ecut25")
-    ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"))
+    ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32", "bf16"))
     ap.add_argument("--cpu-sample", type=int, default=64, help="vectors for the CPU oracle leg (0: skip)")
     ap.add_argument("--eig", type=int, default=1, help="also time the eigensolve (FP64 and mixed) (0: skip)")
     ap.add_argument("--eig-solvers", default="lobpcg,chefsi",
@@ -440,7 +440,7 @@ def main(argv=None):
     print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (events {ms_total:.3f} ms), stages "
           + ", ".join(f"{s} {m:.3f} ms" for s, m in zip(STAGES, ms_stage)), file=sys.stderr, flush=True)
 
-    elem = 8 if args.prec == "fp64" else 4
+    elem = {"fp64": 8, "fp32": 4, "bf16": 2}[args.prec]
     counts = algorithmic_counts(b.L, b.n_modes, b.n_t1, b.n_t2, b.n_r, nvec, elem)
     stage_info = {}
     for s, ms in zip(STAGES, ms_stage):

@@ -60,10 +60,14 @@ typedef enum {
 } helic_status;
 
 /* Arithmetic of the transform stages of apply_H.  Inputs and outputs stay
- * complex double in every mode; FP32 runs the radial contractions, the
- * angular DFTs and the intermediates in single precision with FP32
- * accumulation. */
-typedef enum { HELIC_FP64 = 0, HELIC_FP32 = 1 } helic_prec;
+ * complex double in every mode, and the kinetic term kappa x is added in
+ * FP64.  FP32 runs the radial contractions (FP32 MFMA), the angular DFTs and
+ * the intermediates in single precision with FP32 accumulation.  BF16 runs
+ * the radial contractions on BF16 MFMA (tables and coefficients rounded to
+ * bfloat16, FP32 accumulation), keeps the intermediates as bfloat16 and does
+ * the angular DFTs and the potential product in FP32: unit roundoff 2^-8,
+ * a first rung for eigensolvers before FP32 and FP64. */
+typedef enum { HELIC_FP64 = 0, HELIC_FP32 = 1, HELIC_BF16 = 2 } helic_prec;
 
 typedef struct {
   double R;       /* cylinder radius, Bohr (> 0); Dirichlet wall at r = R        */
@@ -199,7 +203,8 @@ helic_status helic_precondition(helic_basis h, const double* Rres, int64_t ldr, 
 
 /* Lowest nev eigenpairs by block LOBPCG (Sec. 3.5) with the preconditioner
  * above, FP64 Rayleigh-Ritz, H applied in `prec` with a final FP64
- * refinement when prec != HELIC_FP64.  Converged when every
+ * refinement when prec != HELIC_FP64 (a precision ladder: BF16 until the
+ * worst wanted residual is below 3e-2, FP32 until 1e-4, then FP64).  Converged when every
  * ||H x - lambda x||_2 <= tol with ||x||_2 = 1.  evals, resid (host, nev):
  * eigenvalues ascending and residual norms; evecs (device, ld >= L, nev
  * columns) may be NULL; iters (host) may be NULL.  seed fixes the random
@@ -219,8 +224,11 @@ typedef struct {
   uint64_t seed;      /* random start                                                  */
   int32_t precond;    /* 0: Teter-Payne-Allan, 1: none, 2: learned (helic_lpc_*)       */
   int32_t guard;      /* extra iterated columns beyond nev (-1: automatic)             */
-  double switch_tol;  /* FP32 mode: residual below which FP64 applications take over  */
+  double switch_tol;  /* FP32/BF16: residual below which FP64 applications take over  */
   int32_t log_every;  /* > 0: one progress line on stderr every log_every iterations   */
+  double switch_tol_bf16; /* BF16 mode: residual below which FP32 takes over (0: 3e-2)  */
+  int32_t stop_low;   /* 1: stop at the first precision switch (results of the lower   */
+                      /* precision alone, for error studies); 0: refine to tol in FP64  */
 } helic_solve_opts;
 
 typedef struct {
@@ -232,6 +240,7 @@ typedef struct {
   double t_rr_ms;       /* time in orthogonalisation and Rayleigh-Ritz                */
   double t_precond_ms;  /* time in residuals and the preconditioner                   */
   double t_total_ms;    /* wall time of the call                                      */
+  int32_t iters_bf16;   /* of iters_low, iterations with BF16 H*X                     */
 } helic_solve_stats;
 
 /* As helic_eigensolve with all options; stats (host) may be NULL. */

@@ -418,7 +418,8 @@ constexpr int ang_min_wgs() {
   return (sizeof(T) == 4 && !(N2 == 64 && MPAD > 24) ? 1024 : 512) / NTF;
 }
 
-// GH[v][r][mode] holds G on entry and H on exit (complex T).  Vh[r][j][d]
+// GH[v][r][mode] holds G on entry and H on exit (elements E: complex T, or
+// bfloat16 pairs read and written in FP32 arithmetic).  Vh[r][j][d]
 // (complex T, d = 0..2 MPAD - 2 for m' - m = d - (MPAD - 1)).  mode_pos[i] =
 // (m_i - m_min) * ang_rs(N2) + ((n_i mod N2) ^ ang_swz(N2, m_i - m_min));
 // blk_mode is its inverse on the unswizzled block (see ang_direct).
@@ -430,9 +431,9 @@ constexpr int ang_min_wgs() {
 // the block then synchronises four times: after the scatter, after the
 // inverse row transforms, after the convolution and after the forward row
 // transforms.
-template <typename T, int N2, int MPAD, int NTF>
+template <typename T, typename E, int N2, int MPAD, int NTF>
 __global__ void __launch_bounds__(NTF, (ang_min_wgs<T, N2, MPAD, NTF>()))
-k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
+k_angular_fast(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
                const cplx<T>* __restrict__ tw2g, int ipw) {
   constexpr int P = (N2 == 16) ? 4 : (N2 == 64) ? 8 : (N2 == 81) ? 9 : (N2 == 36) ? 6 : (N2 == 100) ? 10 : 0;
   static_assert(P > 0, "unsupported N2");
@@ -503,9 +504,9 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
       for (int q = 0; q < P; ++q) idx[q] = ract ? pb.blk_mode[rrow * N2 + rp + P * q] : -1;
       cplx<T> xin[P];
       auto fetch = [&](int v) {
-        const cplx<T>* slab = reinterpret_cast<const cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+        const E* slab = GH + slab_off(pb, nvec, n_r, v, r);
 #pragma unroll
-        for (int q = 0; q < P; ++q) xin[q] = idx[q] >= 0 ? slab[idx[q]] : cplx<T>{(T)0, (T)0};
+        for (int q = 0; q < P; ++q) xin[q] = idx[q] >= 0 ? eload<T>(slab + idx[q]) : cplx<T>{(T)0, (T)0};
       };
       fetch(v0);
       for (int v = v0; v < v1; ++v) {
@@ -518,11 +519,11 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
         __syncthreads();
         cplx<T> xout[P];
         row_dft_to_regs<T, N2, P, NTF, MPAD, BLK, PIN_ROWS>(A, tw, xout);
-        cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+        E* slab = GH + slab_off(pb, nvec, n_r, v, r);
         if (ract) {
 #pragma unroll
           for (int q = 0; q < P; ++q)
-            if (idx[q] >= 0) slab[idx[q]] = xout[q];
+            if (idx[q] >= 0) estore(slab + idx[q], xout[q]);
         }
       }
     } else {
@@ -537,9 +538,9 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
       }
       cplx<T> pre[MS];
       auto fetch = [&](int v) {
-        const cplx<T>* slab = reinterpret_cast<const cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+        const E* slab = GH + slab_off(pb, nvec, n_r, v, r);
 #pragma unroll
-        for (int q = 0; q < MS; ++q) pre[q] = mp[q] >= 0 ? slab[t + NTF * q] : cplx<T>{(T)0, (T)0};
+        for (int q = 0; q < MS; ++q) pre[q] = mp[q] >= 0 ? eload<T>(slab + t + NTF * q) : cplx<T>{(T)0, (T)0};
       };
       fetch(v0);
       for (int v = v0; v < v1; ++v) {
@@ -579,10 +580,10 @@ k_angular_fast(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
         row_dft<T, N2, P, NTF, false, BLK, PIN_ROWS>(A, MPAD, tw);
         for (int i = t; i < BLK; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
         __syncthreads();
-        cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+        E* slab = GH + slab_off(pb, nvec, n_r, v, r);
 #pragma unroll
         for (int q = 0; q < MS; ++q)
-          if (mp[q] >= 0) slab[t + NTF * q] = A[BLK + mp[q]];
+          if (mp[q] >= 0) estore(slab + t + NTF * q, A[BLK + mp[q]]);
       }
     }
   }

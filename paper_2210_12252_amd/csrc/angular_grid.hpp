@@ -72,12 +72,13 @@ __device__ __forceinline__ void row_dft2(cplx<T>* A, int rows, const cplx<T>* tw
   __syncthreads();
 }
 
-// GH[v][r][mode] holds G on entry and H on exit (complex T).  Vs[r][i1][i2]
-// is V / (N1 N2) (T).  Work: blockIdx -> ipw consecutive (problem, radius,
+// GH[v][r][mode] holds G on entry and H on exit (elements E: complex T, or
+// bfloat16 pairs read and written in FP32 arithmetic).  Vs[r][i1][i2] is
+// V / (N1 N2) (T).  Work: blockIdx -> ipw consecutive (problem, radius,
 // vector) items.
-template <typename T, int N1, int N2, int PA, int PB, int NTF>
+template <typename T, typename E, int N1, int N2, int PA, int PB, int NTF>
 __global__ void __launch_bounds__(NTF)
-k_angular_grid(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
+k_angular_grid(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __restrict__ probs,
                const cplx<T>* __restrict__ tw2g, int ipw) {
   constexpr int RS = grid_rs(N2);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -100,12 +101,12 @@ k_angular_grid(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
     const int n_modes = pb.n_modes;
     const DMode* modes = pb.modes;
     const T* vr = reinterpret_cast<const T*>(pb.Vs) + (int64_t)r * N1 * N2;
-    cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+    E* slab = GH + slab_off(pb, nvec, n_r, v, r);
     for (int i = t; i < N1 * RS; i += NTF) A[i] = cplx<T>{(T)0, (T)0};
     __syncthreads();
     for (int i = t; i < n_modes; i += NTF) {
       const int bo = modes[i].boff;   // bin1 * N2 + bin2
-      A[(bo / N2) * RS + bo % N2] = slab[i];
+      A[(bo / N2) * RS + bo % N2] = eload<T>(slab + i);
     }
     __syncthreads();
     row_dft2<T, N2, PA, PB, NTF, true>(A, N1, tw);
@@ -128,7 +129,7 @@ k_angular_grid(T* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
     row_dft2<T, N2, PA, PB, NTF, false>(A, N1, tw);
     for (int i = t; i < n_modes; i += NTF) {
       const int bo = modes[i].boff;
-      slab[i] = A[(bo / N2) * RS + bo % N2];
+      estore(slab + i, A[(bo / N2) * RS + bo % N2]);
     }
     __syncthreads();
   }

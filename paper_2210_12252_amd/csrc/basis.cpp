@@ -33,6 +33,15 @@ namespace {
 constexpr double TIE_TOL = 1e-10;
 constexpr double PI = 3.14159265358979323846;
 
+// Nearest bfloat16 (ties to even) of a finite double, via its float value.
+uint16_t bf16_round(double v) {
+  const float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 std::vector<int32_t> radix_plan(int n) {
   std::vector<int32_t> f;
   while (n % 4 == 0) { f.push_back(4); n /= 4; }
@@ -184,18 +193,25 @@ helic_status build(helic_basis_s* h) {
   int64_t inv_total = 0, fwd_total = 0;
   h->max_kpad = 0;
   h->max_colpad = 0;
+  int64_t inv16_total = 0, fwd16_total = 0;
   for (Group& grp : h->groups) {
     const int nks = (grp.Kmax + 3) / 4, nkt = (grp.Kmax + 15) / 16;
     grp.tinv_off = inv_total;
     grp.tfwd_off = fwd_total;
     inv_total += (int64_t)nrt * nks * FRAG;
     fwd_total += (int64_t)nkt * nrs * FRAG;
+    grp.tinv16_off = inv16_total;
+    grp.tfwd16_off = fwd16_total;
+    inv16_total += (int64_t)nrt * nkt * FRAG;
+    fwd16_total += (int64_t)nkt * ((nr + 15) / 16) * FRAG;
     h->max_kpad = std::max(h->max_kpad, 4 * nks);
     h->max_colpad = std::max(h->max_colpad, 16 * ((2 * grp.nmodes + 15) / 16));
   }
   h->tab_inv.assign(inv_total, 0.0);
   h->tab_dinv.assign(inv_total, 0.0);
   h->tab_fwd.assign(fwd_total, 0.0);
+  h->tab_inv16.assign(inv16_total * 4, 0);
+  h->tab_fwd16.assign(fwd16_total * 4, 0);
   const double norm0 = 1.0 / (std::sqrt(PI * tau) * R);
   std::vector<double> jv(2);
   for (const Group& grp : h->groups) {
@@ -235,6 +251,27 @@ helic_status build(helic_basis_s* h) {
             h->tab_fwd[grp.tfwd_off + ((int64_t)t * nrs + s) * FRAG + ln] =
                 pref * R * R * h->wq[l] * xi[(size_t)l * grp.Kmax + k];
         }
+    // BF16 tables (16x16x16 fragments): inverse rows r, contraction k;
+    // forward rows k, contraction r
+    const int nk16 = (grp.Kmax + 15) / 16, nr16 = (nr + 15) / 16;
+    for (int t = 0; t < nrt; ++t)
+      for (int s = 0; s < nk16; ++s)
+        for (int ln = 0; ln < FRAG; ++ln)
+          for (int j = 0; j < 4; ++j) {
+            const int l = 16 * t + ln % 16, k = 16 * s + 4 * (ln / 16) + j;
+            if (l < nr && k < grp.Kmax)
+              h->tab_inv16[(grp.tinv16_off + ((int64_t)t * nk16 + s) * FRAG + ln) * 4 + j] =
+                  bf16_round(xi[(size_t)l * grp.Kmax + k]);
+          }
+    for (int t = 0; t < nk16; ++t)
+      for (int s = 0; s < nr16; ++s)
+        for (int ln = 0; ln < FRAG; ++ln)
+          for (int j = 0; j < 4; ++j) {
+            const int k = 16 * t + ln % 16, l = 16 * s + 4 * (ln / 16) + j;
+            if (l < nr && k < grp.Kmax)
+              h->tab_fwd16[(grp.tfwd16_off + ((int64_t)t * nr16 + s) * FRAG + ln) * 4 + j] =
+                  bf16_round(pref * R * R * h->wq[l] * xi[(size_t)l * grp.Kmax + k]);
+          }
   }
   return HELIC_OK;
 }

@@ -20,6 +20,7 @@ namespace helic {
 
 helic_status ensure_device(helic_basis_s* h);
 DProb problem_entry(const helic_basis_s* h, bool fp64, int64_t Lpre, int64_t mpre);
+DProb problem_entry16(const helic_basis_s* h, int64_t Lpre, int64_t mpre);
 LaunchSet launch_set(const helic_basis_s* h);
 template <typename T>
 helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, double* Y, int64_t ldy, int nvec,
@@ -29,6 +30,7 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
                              double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st, Harvest* hv,
                              int cheb_degree);
 void release_workspace(helic_basis_s* h);
+size_t slab_elem_bytes(helic_prec prec);
 
 }  // namespace helic
 
@@ -40,6 +42,7 @@ struct helic_batch_s {
   helic::DGroup* groups = nullptr;
   helic::DProb* probs64 = nullptr;
   helic::DProb* probs32 = nullptr;
+  helic::DProb* probs16 = nullptr;
   int32_t* rows1 = nullptr;
   helic::LaunchSet ls;
   void* gh = nullptr;
@@ -91,13 +94,15 @@ helic_status batch_workspace(helic_batch_s* b, int nvec, size_t elem) {
 
 helic_status batch_launch(helic_batch_s* b, const double* X, double* Y, int nvec, helic_prec prec, hipStream_t st,
                           hipEvent_t* ev) {
-  return prec == HELIC_FP64 ? launch_stages<double>(b->ls, X, -1, Y, -1, nvec, st, 1, ev)
-                            : launch_stages<float>(b->ls, X, -1, Y, -1, nvec, st, 1, ev);
+  return prec == HELIC_FP64   ? launch_stages<double>(b->ls, X, -1, Y, -1, nvec, st, 1, ev)
+         : prec == HELIC_FP32 ? launch_stages<float>(b->ls, X, -1, Y, -1, nvec, st, 1, ev)
+                              : launch_stages<bf16x2>(b->ls, X, -1, Y, -1, nvec, st, 1, ev);
 }
 
 helic_status check_block(helic_batch_s* b, const double* X, double* Y, int nvec, helic_prec prec) {
   if (!X || !Y || nvec < 1 || nvec > APPLY_CHUNK) return fail(HELIC_ERR_INVALID, "bad batch block (1 <= nvec <= 64)");
-  if (prec != HELIC_FP64 && prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (prec != HELIC_FP64 && prec != HELIC_FP32 && prec != HELIC_BF16)
+    return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
   const char* a = reinterpret_cast<const char*>(X);
   const char* c = reinterpret_cast<const char*>(Y);
   const size_t n = (size_t)nvec * b->Lpre.back() * 16;
@@ -129,10 +134,10 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
   b->device = h0->dev->device;
   b->Lpre.assign(nprob + 1, 0);
   std::vector<DGroup> groups;
-  std::vector<DProb> p64(nprob), p32(nprob);
+  std::vector<DProb> p64(nprob), p32(nprob), p16(nprob);
   std::vector<char> row_used(h0->n_t1, 0);
   int64_t mpre = 0;
-  size_t lds_inv = 0, lds_fwd = 0, lds_ang = 0, lds_fwd_plain = 0, lds_fwd32 = 0;
+  size_t lds_inv = 0, lds_fwd = 0, lds_ang = 0, lds_fwd_plain = 0, lds_fwd32 = 0, lds_inv16 = 0, lds_fwd16 = 0;
   bool kx64 = true, kx32 = true;
   int tm64 = 4, tm32 = 4;
   int fwd_tmax_plain = 4, inv_ks = 8;
@@ -142,12 +147,16 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
     b->Lpre[p + 1] = b->Lpre[p] + h->L;
     p64[p] = problem_entry(h, true, b->Lpre[p], mpre);
     p32[p] = problem_entry(h, false, b->Lpre[p], mpre);
+    p16[p] = problem_entry16(h, b->Lpre[p], mpre);
     for (const Group& g : h->groups)
-      groups.push_back(DGroup{g.mode0, g.nmodes, g.Kmax, p, g.row0, g.nrows, g.tinv_off, g.tfwd_off});
+      groups.push_back(DGroup{g.mode0, g.nmodes, g.Kmax, p, g.row0, g.nrows, g.tinv_off, g.tfwd_off,
+                              g.tinv16_off, g.tfwd16_off});
     for (int r : h->rows1) row_used[r] = 1;
     mpre += (int64_t)h->modes.size();
     const LaunchSet one = launch_set(h);
     lds_inv = std::max(lds_inv, one.lds_inv64);
+    lds_inv16 = std::max(lds_inv16, one.lds_inv16);
+    lds_fwd16 = std::max(lds_fwd16, one.lds_fwd16);
     lds_fwd = std::max(lds_fwd, one.lds_fwd64);
     lds_fwd32 = std::max(lds_fwd32, one.lds_fwd32);
     kx64 = kx64 && one.kx_lds64;
@@ -167,7 +176,8 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
     if (row_used[i]) rows1.push_back(i);
   helic_status s;
   if ((s = upload_vec(groups, &b->groups)) || (s = upload_vec(p64, &b->probs64)) ||
-      (s = upload_vec(p32, &b->probs32)) || (s = upload_vec(rows1, &b->rows1))) {
+      (s = upload_vec(p32, &b->probs32)) || (s = upload_vec(p16, &b->probs16)) ||
+      (s = upload_vec(rows1, &b->rows1))) {
     helic_batch_destroy(b);
     return s;
   }
@@ -176,7 +186,10 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
   b->ls.ngroups = (int)groups.size();
   b->ls.probs64 = b->probs64;
   b->ls.probs32 = b->probs32;
+  b->ls.probs16 = b->probs16;
   b->ls.nprob = nprob;
+  b->ls.lds_inv16 = lds_inv16;
+  b->ls.lds_fwd16 = lds_fwd16;
   b->ls.lds_inv64 = lds_inv;
   // the pipelined radial forward variant only if every problem fits it
   b->ls.inv_ks = inv_ks;
@@ -199,7 +212,7 @@ helic_status helic_batch_destroy(helic_batch b) {
   if (!b) return HELIC_OK;
   release_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  void* ptrs[] = {b->groups, b->probs64, b->probs32, b->rows1, b->gh};
+  void* ptrs[] = {b->groups, b->probs64, b->probs32, b->probs16, b->rows1, b->gh};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -217,7 +230,7 @@ helic_status helic_batch_apply(helic_batch b, const double* X, double* Y, int32_
   if (!b) return fail(HELIC_ERR_INVALID, "null batch");
   helic_status s = check_block(b, X, Y, nvec, prec);
   if (s != HELIC_OK) return s;
-  if ((s = batch_workspace(b, nvec, prec == HELIC_FP64 ? 8 : 4))) return s;
+  if ((s = batch_workspace(b, nvec, slab_elem_bytes(prec) / 2))) return s;
   return batch_launch(b, X, Y, nvec, prec, reinterpret_cast<hipStream_t>(stream), nullptr);
 }
 
@@ -225,7 +238,7 @@ helic_status helic_batch_capture(helic_batch b, const double* X, double* Y, int3
   if (!b) return fail(HELIC_ERR_INVALID, "null batch");
   helic_status s = check_block(b, X, Y, nvec, prec);
   if (s != HELIC_OK) return s;
-  if ((s = batch_workspace(b, nvec, prec == HELIC_FP64 ? 8 : 4))) return s;
+  if ((s = batch_workspace(b, nvec, slab_elem_bytes(prec) / 2))) return s;
   release_graph(b);
   if (!b->cap_stream) HIP_TRY_B(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   HIP_TRY_B(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -254,7 +267,7 @@ helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t
   if (!b) return fail(HELIC_ERR_INVALID, "null batch");
   helic_status s = check_block(b, X, Y, nvec, prec);
   if (s != HELIC_OK) return s;
-  if ((s = batch_workspace(b, nvec, prec == HELIC_FP64 ? 8 : 4))) return s;
+  if ((s = batch_workspace(b, nvec, slab_elem_bytes(prec) / 2))) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int cands[] = {0, 2, 4, 8, 16};   // 0: even split over the resident workgroups
   hipEvent_t e0, e1;

@@ -165,9 +165,10 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   }
 }
 
-template <typename T, int MODE>
+// GHv holds slab elements E (complex T, or bfloat16 pairs with T = float).
+template <typename T, int MODE, typename E = cplx<T>>
 __global__ void __launch_bounds__(NT)
-k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __restrict__ grid_out, int nprob, int nvec,
+k_angular(void* __restrict__ GHv, const double* __restrict__ grid_in, double* __restrict__ grid_out, int nprob, int nvec,
           int n_r, const DProb* __restrict__ probs, const int32_t* __restrict__ rows1, int nrows1,
           const cplx<T>* __restrict__ tw1g, const cplx<T>* __restrict__ tw2g, FftPlan p1, FftPlan p2, T out_scale) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -187,7 +188,7 @@ k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __rest
   for (int i = threadIdx.x; i < n1; i += NT) tw1[i] = tw1g[i];
   for (int i = threadIdx.x; i < n2; i += NT) tw2[i] = tw2g[i];
   for (int i = threadIdx.x; i < nrows1; i += NT) rws[i] = rows1[i];
-  cplx<T>* slab = reinterpret_cast<cplx<T>*>(GH) + slab_off(pb, nvec, n_r, v, r);
+  E* slab = reinterpret_cast<E*>(GHv) + slab_off(pb, nvec, n_r, v, r);
   if (MODE == 2) {
     const double* gi = grid_in + (int64_t)v * nn * n_r * 2;
     for (int i = threadIdx.x; i < nn; i += NT)
@@ -196,7 +197,7 @@ k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __rest
   } else {
     for (int i = threadIdx.x; i < nn; i += NT) buf[i] = cplx<T>{(T)0, (T)0};
     __syncthreads();
-    for (int i = threadIdx.x; i < n_modes; i += NT) buf[modes[i].boff] = slab[i];
+    for (int i = threadIdx.x; i < n_modes; i += NT) buf[modes[i].boff] = eload<T>(slab + i);
     __syncthreads();
     // inverse: theta2 lines on the occupied theta1 bins, then all theta1 lines
     fft_lines<T>(buf, nrows1, rws, n2, 1, p2, tw2, (T)1, nullptr);
@@ -217,7 +218,7 @@ k_angular(T* __restrict__ GH, const double* __restrict__ grid_in, double* __rest
   fft_lines<T>(buf, nrows1, rws, n2, 1, p2, tw2, (T)-1, nullptr);
   for (int i = threadIdx.x; i < n_modes; i += NT) {
     cplx<T> x = buf[modes[i].boff];
-    slab[i] = cplx<T>{x.x * out_scale, x.y * out_scale};
+    estore(slab + i, cplx<T>{x.x * out_scale, x.y * out_scale});
   }
 }
 
@@ -486,6 +487,10 @@ k_radial_forward_pf(const T* __restrict__ GH, const double* __restrict__ X, int6
     }
   }
 }
+
+}  // namespace helic
+#include "radial_bf16.hpp"
+namespace helic {
 
 // Angular mean of the potential per radius: vbar[r] = sum_{i1,i2} Vs[r][i1][i2]
 // (Vs carries 1 / (n_t1 n_t2)); fixed-order block reduction.
@@ -845,6 +850,14 @@ size_t angular_lds_bytes(const helic_basis_s* h, size_t elem) {
          (size_t)h->rows1.size() * sizeof(int32_t);
 }
 
+// Problem tables of a launch in its precision: FP64, FP32, or BF16 (BF16
+// radial tables, FP32 potential and twiddles).
+template <typename T, typename E>
+const DProb* launch_probs(const LaunchSet& ls) {
+  if constexpr (std::is_same<E, bf16x2>::value) return ls.probs16;
+  else return std::is_same<T, double>::value ? ls.probs64 : ls.probs32;
+}
+
 // Instantiated (n_t2, padded m count, block size) of the specialised angular kernel.
 struct FastVariant { int n2, mpad, ntf; };
 constexpr FastVariant FAST_VARIANTS[] = {{16, 12, 256}, {16, 16, 256}, {64, 24, 256}, {64, 28, 256},
@@ -863,32 +876,32 @@ int env_int(const char* name, int dflt, int lo, int hi) {
   return std::max(lo, std::min(hi, std::atoi(e)));
 }
 
-template <typename T, int N2, int MPAD, int NTF>
+template <typename T, typename E, int N2, int MPAD, int NTF>
 helic_status set_fast_limit() {
-  HIP_TRY(hipFuncSetAttribute((const void*)k_angular_fast<T, N2, MPAD, NTF>,
+  HIP_TRY(hipFuncSetAttribute((const void*)k_angular_fast<T, E, N2, MPAD, NTF>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   return HELIC_OK;
 }
 
-template <typename T>
+template <typename T, typename E>
 helic_status set_fast_limits() {
   helic_status s;
-  if ((s = set_fast_limit<T, 16, 12, 256>()) || (s = set_fast_limit<T, 16, 16, 256>()) ||
-      (s = set_fast_limit<T, 64, 24, 256>()) || (s = set_fast_limit<T, 64, 28, 256>()) ||
-      (s = set_fast_limit<T, 64, 32, 256>()) || (s = set_fast_limit<T, 81, 25, 512>()) ||
-      (s = set_fast_limit<T, 81, 32, 512>()))
+  if ((s = set_fast_limit<T, E, 16, 12, 256>()) || (s = set_fast_limit<T, E, 16, 16, 256>()) ||
+      (s = set_fast_limit<T, E, 64, 24, 256>()) || (s = set_fast_limit<T, E, 64, 28, 256>()) ||
+      (s = set_fast_limit<T, E, 64, 32, 256>()) || (s = set_fast_limit<T, E, 81, 25, 512>()) ||
+      (s = set_fast_limit<T, E, 81, 32, 512>()))
     return s;
   return HELIC_OK;
 }
 
 // Resident workgroups of the chosen angular kernel on the whole device.
-template <typename T>
+template <typename T, typename E>
 int fast_slots(int n2, int mpad, int ncu) {
   int nb = 0;
   const size_t lds = fast_lds_bytes<T>(n2, mpad);
 #define HELIC_OCC_CASE(N2_, MP_, NTF_)                                                                 \
   if (n2 == N2_ && mpad == MP_)                                                                       \
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_fast<T, N2_, MP_, NTF_>, NTF_, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_fast<T, E, N2_, MP_, NTF_>, NTF_, lds);
   HELIC_OCC_CASE(16, 12, 256)
   HELIC_OCC_CASE(16, 16, 256)
   HELIC_OCC_CASE(64, 24, 256)
@@ -903,11 +916,13 @@ int fast_slots(int n2, int mpad, int ncu) {
 // Work split of the specialised angular kernels: ls.vchunk items per
 // workgroup if set, else the fewest items per workgroup that let every
 // workgroup be resident at once (one wave of workgroups, no tail).
-template <typename T>
+template <typename T, typename E>
 int angular_items_per_wg(const LaunchSet& ls, int nvec) {
   if (ls.vchunk > 0) return ls.vchunk;
   const int64_t total = (int64_t)ls.nprob * ls.n_r * nvec;
-  const int64_t slots = std::max(1, std::is_same<T, double>::value ? ls.ang_slots64 : ls.ang_slots32);
+  const int64_t slots = std::max(1, std::is_same<E, bf16x2>::value   ? ls.ang_slots16
+                                    : std::is_same<T, double>::value ? ls.ang_slots64
+                                                                     : ls.ang_slots32);
   return (int)std::max<int64_t>(1, (total + slots - 1) / slots);
 }
 
@@ -917,17 +932,17 @@ inline unsigned angular_grid_size(const LaunchSet& ls, int nvec, int ipw) {
   return (unsigned)(8 * ((nwg + 7) / 8));
 }
 
-template <typename T>
-helic_status launch_fast(const LaunchSet& ls, T* gh, int nvec, hipStream_t st, hipEvent_t e0 = nullptr,
+template <typename T, typename E>
+helic_status launch_fast(const LaunchSet& ls, E* gh, int nvec, hipStream_t st, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr) {
-  const DProb* probs = std::is_same<T, double>::value ? ls.probs64 : ls.probs32;
+  const DProb* probs = launch_probs<T, E>(ls);
   const cplx<T>* tw2 = (const cplx<T>*)(std::is_same<T, double>::value ? ls.tw2_64 : ls.tw2_32);
-  const int ipw = angular_items_per_wg<T>(ls, nvec);
+  const int ipw = angular_items_per_wg<T, E>(ls, nvec);
   const dim3 grid(angular_grid_size(ls, nvec, ipw));
   const size_t lds = fast_lds_bytes<T>(ls.n_t2, ls.fast_mpad);
 #define HELIC_FAST_CASE(N2_, MP_, NTF_)                                                                   \
   if (ls.n_t2 == N2_ && ls.fast_mpad == MP_) {                                                          \
-    HELIC_LAUNCH((k_angular_fast<T, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, e0, e1, gh, ls.nprob, nvec, \
+    HELIC_LAUNCH((k_angular_fast<T, E, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, e0, e1, gh, ls.nprob, nvec, \
                  ls.n_r, probs, tw2, ipw);                                                              \
     HIP_TRY(hipGetLastError());                                                                         \
     return HELIC_OK;                                                                                    \
@@ -960,10 +975,10 @@ size_t grid_lds_bytes(int n1, int n2) {
   return ((size_t)n1 * grid_rs(n2) + n2) * sizeof(cplx<T>);
 }
 
-template <typename T>
+template <typename T, typename E>
 helic_status set_grid_limits() {
 #define HELIC_GRID_ATTR(N1_, N2_, PA_, PB_)                                                              \
-  HIP_TRY(hipFuncSetAttribute((const void*)k_angular_grid<T, N1_, N2_, PA_, PB_, GRID_NTF>,            \
+  HIP_TRY(hipFuncSetAttribute((const void*)k_angular_grid<T, E, N1_, N2_, PA_, PB_, GRID_NTF>,         \
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   HELIC_GRID_ATTR(20, 96, 8, 12)
   HELIC_GRID_ATTR(20, 120, 8, 15)
@@ -975,13 +990,13 @@ helic_status set_grid_limits() {
   return HELIC_OK;
 }
 
-template <typename T>
+template <typename T, typename E>
 int grid_slots(int n1, int n2, int ncu) {
   int nb = 0;
   const size_t lds = grid_lds_bytes<T>(n1, n2);
 #define HELIC_OCC_CASE(N1_, N2_, PA_, PB_)                                                             \
   if (n1 == N1_ && n2 == N2_)                                                                         \
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_grid<T, N1_, N2_, PA_, PB_, GRID_NTF>, \
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_grid<T, E, N1_, N2_, PA_, PB_, GRID_NTF>, \
                                                        GRID_NTF, lds);
   HELIC_OCC_CASE(20, 96, 8, 12)
   HELIC_OCC_CASE(20, 120, 8, 15)
@@ -993,17 +1008,17 @@ int grid_slots(int n1, int n2, int ncu) {
   return std::max(1, nb) * std::max(1, ncu);
 }
 
-template <typename T>
-helic_status launch_grid(const LaunchSet& ls, T* gh, int nvec, hipStream_t st, hipEvent_t e0 = nullptr,
+template <typename T, typename E>
+helic_status launch_grid(const LaunchSet& ls, E* gh, int nvec, hipStream_t st, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr) {
-  const DProb* probs = std::is_same<T, double>::value ? ls.probs64 : ls.probs32;
+  const DProb* probs = launch_probs<T, E>(ls);
   const cplx<T>* tw2 = (const cplx<T>*)(std::is_same<T, double>::value ? ls.tw2_64 : ls.tw2_32);
-  const int ipw = angular_items_per_wg<T>(ls, nvec);
+  const int ipw = angular_items_per_wg<T, E>(ls, nvec);
   const dim3 grid(angular_grid_size(ls, nvec, ipw));
   const size_t lds = grid_lds_bytes<T>(ls.n_t1, ls.n_t2);
 #define HELIC_GRID_CASE(N1_, N2_, PA_, PB_)                                                              \
   if (ls.n_t1 == N1_ && ls.n_t2 == N2_) {                                                               \
-    HELIC_LAUNCH((k_angular_grid<T, N1_, N2_, PA_, PB_, GRID_NTF>), grid, dim3(GRID_NTF), lds, st, e0, e1, gh, \
+    HELIC_LAUNCH((k_angular_grid<T, E, N1_, N2_, PA_, PB_, GRID_NTF>), grid, dim3(GRID_NTF), lds, st, e0, e1, gh, \
                  ls.nprob, nvec, ls.n_r, probs, tw2, ipw);                                              \
     HIP_TRY(hipGetLastError());                                                                         \
     return HELIC_OK;                                                                                    \
@@ -1040,6 +1055,49 @@ helic_status set_lds_limits() {
   HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_angular<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  return HELIC_OK;
+}
+
+// BF16 radial kernels: k steps (of 16) of the widest group, and LDS bytes of
+// the staged coefficient columns (inverse) and slab chunk (forward).
+int inv_kt16_for(int max_kpad) { return (max_kpad + 15) / 16 <= 2 ? 2 : (max_kpad + 15) / 16 <= 4 ? 4 : 6; }
+size_t lds_inv16_bytes(int max_kpad, int max_colpad) {
+  return (size_t)max_colpad * bf16_col_stride(16 * ((max_kpad + 15) / 16)) * sizeof(uint16_t);
+}
+size_t lds_fwd16_bytes(int max_colpad) {
+  return (size_t)max_colpad * bf16_col_stride(FWD16_RC) * sizeof(uint16_t);
+}
+
+void launch_radial_inverse_bf16(int kt16, int nwg, size_t lds, hipStream_t st, const double* X, int64_t ldx,
+                                bf16x2* gh, int nvec, int ngroups, int n_r, const DGroup* groups, const DProb* probs,
+                                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (kt16 <= 2)
+    HELIC_LAUNCH((k_radial_inverse_bf16<2>), dim3(nwg), dim3(NT), lds, st, e0, e1, X, ldx, gh, nvec, ngroups, n_r,
+                 groups, probs);
+  else if (kt16 <= 4)
+    HELIC_LAUNCH((k_radial_inverse_bf16<4>), dim3(nwg), dim3(NT), lds, st, e0, e1, X, ldx, gh, nvec, ngroups, n_r,
+                 groups, probs);
+  else
+    HELIC_LAUNCH((k_radial_inverse_bf16<6>), dim3(nwg), dim3(NT), lds, st, e0, e1, X, ldx, gh, nvec, ngroups, n_r,
+                 groups, probs);
+}
+
+void launch_radial_forward_bf16(int nwg, size_t lds, hipStream_t st, const bf16x2* gh, const double* X, int64_t ldx,
+                                double* Y, int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* groups,
+                                const DProb* probs, int mode, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  HELIC_LAUNCH((k_radial_forward_bf16<FWD16_TM>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
+               ngroups, n_r, groups, probs, mode);
+}
+
+helic_status set_bf16_limits() {
+  const int lim = 160 * 1024;
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse_bf16<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse_bf16<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse_bf16<6>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_bf16<FWD16_TM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_angular<float, 0, bf16x2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lim));
   return HELIC_OK;
 }
 
@@ -1090,6 +1148,7 @@ void* scratch_ptr(int dev) {
 }
 
 DProb problem_entry(const helic_basis_s* h, bool fp64, int64_t Lpre, int64_t mpre);
+DProb problem_entry16(const helic_basis_s* h, int64_t Lpre, int64_t mpre);
 
 helic_status ensure_device(helic_basis_s* h) {
   int cur = 0;
@@ -1115,10 +1174,12 @@ helic_status ensure_device(helic_basis_s* h) {
   h->dev = d;
   if ((s = set_lds_limits<double>()) != HELIC_OK) return s;
   if ((s = set_lds_limits<float>()) != HELIC_OK) return s;
+  if ((s = set_bf16_limits()) != HELIC_OK) return s;
   std::vector<DGroup> dg(h->groups.size());
   for (size_t i = 0; i < h->groups.size(); ++i) {
     const Group& g = h->groups[i];
-    dg[i] = DGroup{g.mode0, g.nmodes, g.Kmax, /*prob*/ 0, g.row0, g.nrows, g.tinv_off, g.tfwd_off};
+    dg[i] = DGroup{g.mode0, g.nmodes, g.Kmax, /*prob*/ 0, g.row0, g.nrows, g.tinv_off, g.tfwd_off,
+                   g.tinv16_off, g.tfwd16_off};
   }
   std::vector<DMode> dm(h->modes.size());
   for (size_t i = 0; i < h->modes.size(); ++i) {
@@ -1142,6 +1203,7 @@ helic_status ensure_device(helic_basis_s* h) {
       (s = upload(h->kappa, &d->kappa)) || (s = upload(h->rows1, &d->rows1)) ||
       (s = upload(h->tab_inv, &d->tinv64)) || (s = upload(h->tab_fwd, &d->tfwd64)) ||
       (s = upload(tinv32, &d->tinv32)) || (s = upload(tfwd32, &d->tfwd32)) ||
+      (s = upload(h->tab_inv16, &d->tinv16)) || (s = upload(h->tab_fwd16, &d->tfwd16)) ||
       (s = upload(tw1, &d->tw1)) || (s = upload(tw2, &d->tw2)) || (s = upload(tw1f, &d->tw1f)) ||
       (s = upload(tw2f, &d->tw2f)))
     return s;
@@ -1171,18 +1233,24 @@ helic_status ensure_device(helic_basis_s* h) {
     for (const GridVariant& gv : GRID_VARIANTS)
       if (gv.n1 == h->n_t1 && gv.n2 == h->n_t2 && grid_lds_bytes<double>(gv.n1, gv.n2) <= 160 * 1024)
         d->grid_var = true;
-    if (d->grid_var && ((s = set_grid_limits<double>()) || (s = set_grid_limits<float>()))) return s;
+    if (d->grid_var && ((s = set_grid_limits<double, cplx<double>>()) || (s = set_grid_limits<float, cplx<float>>()) ||
+                        (s = set_grid_limits<float, bf16x2>())))
+      return s;
   }
   int ncu = 0;
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d->device));
   if (d->grid_var) {
-    d->ang_slots64 = grid_slots<double>(h->n_t1, h->n_t2, ncu);
-    d->ang_slots32 = grid_slots<float>(h->n_t1, h->n_t2, ncu);
+    d->ang_slots64 = grid_slots<double, cplx<double>>(h->n_t1, h->n_t2, ncu);
+    d->ang_slots32 = grid_slots<float, cplx<float>>(h->n_t1, h->n_t2, ncu);
+    d->ang_slots16 = grid_slots<float, bf16x2>(h->n_t1, h->n_t2, ncu);
   }
   if (d->fast_mpad) {
-    if ((s = set_fast_limits<double>()) || (s = set_fast_limits<float>())) return s;
-    d->ang_slots64 = fast_slots<double>(h->n_t2, d->fast_mpad, ncu);
-    d->ang_slots32 = fast_slots<float>(h->n_t2, d->fast_mpad, ncu);
+    if ((s = set_fast_limits<double, cplx<double>>()) || (s = set_fast_limits<float, cplx<float>>()) ||
+        (s = set_fast_limits<float, bf16x2>()))
+      return s;
+    d->ang_slots64 = fast_slots<double, cplx<double>>(h->n_t2, d->fast_mpad, ncu);
+    d->ang_slots32 = fast_slots<float, cplx<float>>(h->n_t2, d->fast_mpad, ncu);
+    d->ang_slots16 = fast_slots<float, bf16x2>(h->n_t2, d->fast_mpad, ncu);
     const int rs = ang_rs(h->n_t2);
     std::vector<int32_t> mp(h->modes.size());
     for (size_t i = 0; i < h->modes.size(); ++i) {
@@ -1201,9 +1269,18 @@ helic_status ensure_device(helic_basis_s* h) {
   const size_t nv = (size_t)h->n_t1 * h->n_t2 * h->n_r;
   HIP_TRY(hipMalloc((void**)&d->Vs, nv * sizeof(double)));
   HIP_TRY(hipMalloc((void**)&d->Vsf, nv * sizeof(float)));
-  std::vector<DProb> p64{problem_entry(h, true, 0, 0)}, p32{problem_entry(h, false, 0, 0)};
-  if ((s = upload(p64, &d->probs64)) || (s = upload(p32, &d->probs32))) return s;
+  std::vector<DProb> p64{problem_entry(h, true, 0, 0)}, p32{problem_entry(h, false, 0, 0)},
+      p16{problem_entry16(h, 0, 0)};
+  if ((s = upload(p64, &d->probs64)) || (s = upload(p32, &d->probs32)) || (s = upload(p16, &d->probs16))) return s;
   return HELIC_OK;
+}
+
+// The BF16 mode's problem entry: BF16 radial tables, FP32 potential.
+DProb problem_entry16(const helic_basis_s* h, int64_t Lpre, int64_t mpre) {
+  DProb p = problem_entry(h, false, Lpre, mpre);
+  p.tinv = h->dev->tinv16;
+  p.tfwd = h->dev->tfwd16;
+  return p;
 }
 
 DProb problem_entry(const helic_basis_s* h, bool fp64, int64_t Lpre, int64_t mpre) {
@@ -1234,6 +1311,7 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.ngroups = (int)h->groups.size();
   ls.probs64 = d->probs64;
   ls.probs32 = d->probs32;
+  ls.probs16 = d->probs16;
   ls.nprob = 1;
   ls.n_r = h->n_r;
   ls.n_t1 = h->n_t1;
@@ -1260,6 +1338,9 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.vchunk = d->vchunk;
   ls.ang_slots64 = d->ang_slots64;
   ls.ang_slots32 = d->ang_slots32;
+  ls.ang_slots16 = d->ang_slots16;
+  ls.lds_inv16 = lds_inv16_bytes(h->max_kpad, h->max_colpad);
+  ls.lds_fwd16 = lds_fwd16_bytes(h->max_colpad);
   ls.rows1 = d->rows1;
   ls.nrows1 = (int)h->rows1.size();
   ls.plan1 = d->plan1;
@@ -1300,7 +1381,8 @@ void device_release(helic_basis_s* h) {
   void* ptrs[] = {d->groups, d->modes, d->row_ck, d->kappa, d->rows1, d->tinv64, d->tfwd64,
                   d->tinv32, d->tfwd32, d->tw1, d->tw2, d->tw1f, d->tw2f, d->Vs, d->Vsf,
                   d->gh, d->part, d->mode_pos, d->blk_mode, d->Vh, d->Vhf, d->probs64, d->probs32, d->vdiag, d->lpc_ws,
-                  d->dens_ws, d->dens_occ, d->tdinv64, d->probs_dr, d->grad_fac, d->rgrid, d->grad_ws};
+                  d->dens_ws, d->dens_occ, d->tdinv64, d->probs_dr, d->grad_fac, d->rgrid, d->grad_ws,
+                  d->tinv16, d->tfwd16, d->probs16};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   release_solver_state(d);
@@ -1309,38 +1391,53 @@ void device_release(helic_basis_s* h) {
 }
 
 // The three H*X stages over a launch set (one handle or a batch) for nvec
-// vectors; ldx / ldy < 0 selects the concatenated batch layout.
-template <typename T>
+// vectors; ldx / ldy < 0 selects the concatenated batch layout.  P names the
+// precision: double or float (slabs, tables and angular arithmetic in P), or
+// bf16x2 (BF16 radial contractions and slabs, FP32 angular arithmetic).
+template <typename P>
 helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, double* Y, int64_t ldy, int nvec,
                            hipStream_t st, int mode, hipEvent_t* ev) {
+  constexpr bool BF = std::is_same<P, bf16x2>::value;
+  typedef typename std::conditional<BF, float, P>::type T;        // angular arithmetic
+  typedef typename std::conditional<BF, bf16x2, cplx<T>>::type E;  // slab element
   const bool f64 = std::is_same<T, double>::value;
-  const DProb* probs = f64 ? ls.probs64 : ls.probs32;
-  T* gh = reinterpret_cast<T*>(ls.gh);
+  const DProb* probs = launch_probs<T, E>(ls);
+  E* gh = reinterpret_cast<E*>(ls.gh);
   const size_t sc = f64 ? 1 : 2;
   const int wg_rad = 8 * ((ls.ngroups * nvec + 7) / 8);
   // ev (optional): start and end events of each of the three kernels
   auto e = [&](int k) { return ev ? ev[k] : (hipEvent_t) nullptr; };
-  launch_radial_inverse<T>(ls.inv_ks, wg_rad, ls.lds_inv64 / sc, st, X, ldx, gh, nvec, ls.ngroups, ls.n_r,
-                           ls.groups, probs, e(0), e(1));
+  if constexpr (BF) {
+    launch_radial_inverse_bf16(inv_kt16_for(4 * ls.inv_ks), wg_rad, ls.lds_inv16, st, X, ldx, gh, nvec, ls.ngroups,
+                               ls.n_r, ls.groups, probs, e(0), e(1));
+  } else {
+    launch_radial_inverse<T>(ls.inv_ks, wg_rad, ls.lds_inv64 / sc, st, X, ldx, reinterpret_cast<T*>(gh), nvec,
+                             ls.ngroups, ls.n_r, ls.groups, probs, e(0), e(1));
+  }
   HIP_TRY(hipGetLastError());
   if (ls.fast_mpad) {
-    helic_status s = launch_fast<T>(ls, gh, nvec, st, e(2), e(3));
+    helic_status s = launch_fast<T, E>(ls, gh, nvec, st, e(2), e(3));
     if (s != HELIC_OK) return s;
   } else if (ls.grid_var) {
-    helic_status s = launch_grid<T>(ls, gh, nvec, st, e(2), e(3));
+    helic_status s = launch_grid<T, E>(ls, gh, nvec, st, e(2), e(3));
     if (s != HELIC_OK) return s;
   } else {
     const int wg_ang = 8 * ((ls.nprob * nvec * ls.n_r + 7) / 8);
     const cplx<T>* tw1 = (const cplx<T>*)(f64 ? ls.tw1_64 : ls.tw1_32);
     const cplx<T>* tw2 = (const cplx<T>*)(f64 ? ls.tw2_64 : ls.tw2_32);
-    HELIC_LAUNCH((k_angular<T, 0>), dim3(wg_ang), dim3(NT), ls.lds_ang64 / sc, st, e(2), e(3), gh, nullptr, nullptr,
-                 ls.nprob, nvec, ls.n_r, probs, ls.rows1, ls.nrows1, tw1, tw2, ls.plan1, ls.plan2, (T)1);
+    HELIC_LAUNCH((k_angular<T, 0, E>), dim3(wg_ang), dim3(NT), ls.lds_ang64 / sc, st, e(2), e(3), gh, nullptr,
+                 nullptr, ls.nprob, nvec, ls.n_r, probs, ls.rows1, ls.nrows1, tw1, tw2, ls.plan1, ls.plan2, (T)1);
     HIP_TRY(hipGetLastError());
   }
-  const bool kx_lds = ls.fwd_tmax <= 0 && mode && (f64 ? ls.kx_lds64 : ls.kx_lds32);
-  launch_radial_forward<T>(ls.fwd_tmax, wg_rad, f64 ? ls.lds_fwd64 : ls.lds_fwd32, st, gh, X, ldx, Y, ldy, nvec,
-                           ls.ngroups, ls.n_r, ls.groups, probs, mode | (kx_lds ? 2 : 0),
-                           f64 ? ls.fwd_tm64 : ls.fwd_tm32, e(4), e(5));
+  if constexpr (BF) {
+    launch_radial_forward_bf16(wg_rad, ls.lds_fwd16, st, gh, X, ldx, Y, ldy, nvec, ls.ngroups, ls.n_r, ls.groups,
+                               probs, mode, e(4), e(5));
+  } else {
+    const bool kx_lds = ls.fwd_tmax <= 0 && mode && (f64 ? ls.kx_lds64 : ls.kx_lds32);
+    launch_radial_forward<T>(ls.fwd_tmax, wg_rad, f64 ? ls.lds_fwd64 : ls.lds_fwd32, st, reinterpret_cast<T*>(gh),
+                             X, ldx, Y, ldy, nvec, ls.ngroups, ls.n_r, ls.groups, probs, mode | (kx_lds ? 2 : 0),
+                             f64 ? ls.fwd_tm64 : ls.fwd_tm32, e(4), e(5));
+  }
   HIP_TRY(hipGetLastError());
   return HELIC_OK;
 }
@@ -1349,25 +1446,32 @@ template helic_status launch_stages<double>(const LaunchSet&, const double*, int
                                             hipStream_t, int, hipEvent_t*);
 template helic_status launch_stages<float>(const LaunchSet&, const double*, int64_t, double*, int64_t, int,
                                            hipStream_t, int, hipEvent_t*);
+template helic_status launch_stages<bf16x2>(const LaunchSet&, const double*, int64_t, double*, int64_t, int,
+                                            hipStream_t, int, hipEvent_t*);
 
-template <typename T>
-helic_status launch_apply(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy, int nvec,
-                          hipStream_t st, int mode, hipEvent_t* ev = nullptr) {
-  return launch_stages<T>(launch_set(h), X, ldx, Y, ldy, nvec, st, mode, ev);
+// Bytes per complex slab element in precision prec.
+size_t slab_elem_bytes(helic_prec prec) {
+  return prec == HELIC_FP64 ? 16 : prec == HELIC_FP32 ? 8 : 4;
+}
+
+helic_status launch_apply(helic_basis_s* h, helic_prec prec, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                          int nvec, hipStream_t st, int mode, hipEvent_t* ev = nullptr) {
+  const LaunchSet ls = launch_set(h);
+  return prec == HELIC_FP64   ? launch_stages<double>(ls, X, ldx, Y, ldy, nvec, st, mode, ev)
+         : prec == HELIC_FP32 ? launch_stages<float>(ls, X, ldx, Y, ldy, nvec, st, mode, ev)
+                              : launch_stages<bf16x2>(ls, X, ldx, Y, ldy, nvec, st, mode, ev);
 }
 
 helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy,
                           int nvec, helic_prec prec, hipStream_t st, int chunk) {
   chunk = std::max(1, std::min(chunk, h->dev->apply_chunk));
-  const size_t elem = prec == HELIC_FP64 ? sizeof(double) : sizeof(float);
-  helic_status s = ensure_workspace(h, std::min(nvec, chunk), elem);
+  helic_status s = ensure_workspace(h, std::min(nvec, chunk), slab_elem_bytes(prec) / 2);
   if (s != HELIC_OK) return s;
   for (int v0 = 0; v0 < nvec; v0 += chunk) {
     const int nv = std::min(chunk, nvec - v0);
     const double* Xc = X + (int64_t)v0 * ldx * 2;
     double* Yc = Y + (int64_t)v0 * ldy * 2;
-    s = prec == HELIC_FP64 ? launch_apply<double>(h, Xc, ldx, Yc, ldy, nv, st, 1)
-                           : launch_apply<float>(h, Xc, ldx, Yc, ldy, nv, st, 1);
+    s = launch_apply(h, prec, Xc, ldx, Yc, ldy, nv, st, 1);
     if (s != HELIC_OK) return s;
   }
   return HELIC_OK;
@@ -1380,8 +1484,7 @@ helic_status apply_H_noalloc_impl(helic_basis_s* h, const double* X, int64_t ldx
                                   int nvec, helic_prec prec, hipStream_t st) {
   void* ws = scratch_ptr(h->dev->device);
   if (!ws) return fail(HELIC_ERR_STATE, "scratch array not set up on this device");
-  const size_t elem = prec == HELIC_FP64 ? sizeof(double) : sizeof(float);
-  const size_t per_vec = (size_t)h->n_r * h->modes.size() * 2 * elem;
+  const size_t per_vec = (size_t)h->n_r * h->modes.size() * slab_elem_bytes(prec);
   const size_t fit = NOALLOC_SCRATCH_BYTES / per_vec;
   if (fit == 0)
     return fail(HELIC_ERR_NOMEM, "one vector's intermediate slabs (" + std::to_string(per_vec) +
@@ -1394,8 +1497,9 @@ helic_status apply_H_noalloc_impl(helic_basis_s* h, const double* X, int64_t ldx
     const int nv = std::min(chunk, nvec - v0);
     const double* Xc = X + (int64_t)v0 * ldx * 2;
     double* Yc = Y + (int64_t)v0 * ldy * 2;
-    const helic_status s = prec == HELIC_FP64 ? launch_stages<double>(ls, Xc, ldx, Yc, ldy, nv, st, 1, nullptr)
-                                              : launch_stages<float>(ls, Xc, ldx, Yc, ldy, nv, st, 1, nullptr);
+    const helic_status s = prec == HELIC_FP64   ? launch_stages<double>(ls, Xc, ldx, Yc, ldy, nv, st, 1, nullptr)
+                           : prec == HELIC_FP32 ? launch_stages<float>(ls, Xc, ldx, Yc, ldy, nv, st, 1, nullptr)
+                                                : launch_stages<bf16x2>(ls, Xc, ldx, Yc, ldy, nv, st, 1, nullptr);
     if (s != HELIC_OK) return s;
   }
   return HELIC_OK;
@@ -1464,7 +1568,8 @@ helic_status helic_apply_H(helic_basis h, const double* X, int64_t ldx, double* 
   if (!h) return fail(HELIC_ERR_INVALID, "null handle");
   if (nvec < 0 || (nvec > 0 && (!X || !Y)) || ldx < h->L || ldy < h->L)
     return fail(HELIC_ERR_INVALID, "bad block arguments");
-  if (prec != HELIC_FP64 && prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (prec != HELIC_FP64 && prec != HELIC_FP32 && prec != HELIC_BF16)
+    return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
   if (nvec == 0) return HELIC_OK;
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
   helic_status s = ensure_device(h);
@@ -1477,7 +1582,8 @@ helic_status helic_apply_H_noalloc(helic_basis h, const double* X, int64_t ldx, 
   if (!h) return fail(HELIC_ERR_INVALID, "null handle");
   if (nvec < 0 || (nvec > 0 && (!X || !Y)) || ldx < h->L || ldy < h->L)
     return fail(HELIC_ERR_INVALID, "bad block arguments");
-  if (prec != HELIC_FP64 && prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (prec != HELIC_FP64 && prec != HELIC_FP32 && prec != HELIC_BF16)
+    return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
   if (nvec == 0) return HELIC_OK;
   // the device state exists once a potential is set; no set-up happens here
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
@@ -1493,12 +1599,12 @@ helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, do
   if (!h || !ms_stage) return fail(HELIC_ERR_INVALID, "null argument");
   if (nvec <= 0 || nvec > APPLY_CHUNK || !X || !Y || ldx < h->L || ldy < h->L || nrep <= 0)
     return fail(HELIC_ERR_INVALID, "bad block arguments (1 <= nvec <= 64, nrep >= 1)");
-  if (prec != HELIC_FP64 && prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (prec != HELIC_FP64 && prec != HELIC_FP32 && prec != HELIC_BF16)
+    return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
   helic_status s = ensure_device(h);
   if (s != HELIC_OK) return s;
-  const size_t elem = prec == HELIC_FP64 ? sizeof(double) : sizeof(float);
-  if ((s = ensure_workspace(h, nvec, elem)) != HELIC_OK) return s;
+  if ((s = ensure_workspace(h, nvec, slab_elem_bytes(prec) / 2)) != HELIC_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int chunk = h->dev->apply_chunk;
   const int nch = (nvec + chunk - 1) / chunk;
@@ -1512,9 +1618,7 @@ helic_status helic_profile_apply(helic_basis h, const double* X, int64_t ldx, do
     for (int c = 0; c < nch && s == HELIC_OK; ++c) {
       const int v0 = c * chunk, nv = std::min(chunk, nvec - v0);
       hipEvent_t* e6 = &ev[6 * ((size_t)i * nch + c)];
-      s = prec == HELIC_FP64
-              ? launch_apply<double>(h, X + (int64_t)v0 * ldx * 2, ldx, Y + (int64_t)v0 * ldy * 2, ldy, nv, st, 1, e6)
-              : launch_apply<float>(h, X + (int64_t)v0 * ldx * 2, ldx, Y + (int64_t)v0 * ldy * 2, ldy, nv, st, 1, e6);
+      s = launch_apply(h, prec, X + (int64_t)v0 * ldx * 2, ldx, Y + (int64_t)v0 * ldy * 2, ldy, nv, st, 1, e6);
     }
   double acc[3] = {0, 0, 0}, tot = 0;
   if (s == HELIC_OK) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 
 #include "kernels.hpp"
 
@@ -31,6 +32,7 @@ struct DeviceState {
   int32_t* rows1 = nullptr;
   double *tinv64 = nullptr, *tfwd64 = nullptr;
   float *tinv32 = nullptr, *tfwd32 = nullptr;
+  uint16_t *tinv16 = nullptr, *tfwd16 = nullptr;   // BF16 tables (16x16x16 fragments)
   cplx<double>*tw1 = nullptr, *tw2 = nullptr;
   cplx<float>*tw1f = nullptr, *tw2f = nullptr;
   FftPlan plan1{}, plan2{};
@@ -46,7 +48,7 @@ struct DeviceState {
   bool grid_var = false;          // the register-FFT angular kernel serves this grid
   int vchunk = 0;                 // (problem, radius, vector) items per workgroup of the specialised
                                   // angular kernels; 0: spread evenly over the resident workgroups
-  int ang_slots64 = 1, ang_slots32 = 1;   // resident workgroups of that kernel on the device
+  int ang_slots64 = 1, ang_slots32 = 1, ang_slots16 = 1;   // resident workgroups of that kernel on the device
   int apply_chunk = APPLY_CHUNK;  // vectors per launch of the three stages
   int32_t* mode_pos = nullptr;    // mode -> (m - m_min) * ang_rs(n_t2) + ((n mod n_t2) ^ ang_swz)
   int32_t* blk_mode = nullptr;    // (m - m_min) * n_t2 + (n mod n_t2) -> mode, -1 if none
@@ -54,6 +56,7 @@ struct DeviceState {
   float* Vhf = nullptr;
   DProb* probs64 = nullptr;       // one-entry problem tables of this handle
   DProb* probs32 = nullptr;
+  DProb* probs16 = nullptr;       // BF16 mode: BF16 tables, FP32 potential
   double* part = nullptr;
   size_t part_bytes = 0;
   double* dens_ws = nullptr;      // density: real-space grids of one chunk of states
@@ -87,12 +90,14 @@ struct LaunchSet {
   int ngroups = 0;
   const DProb* probs64 = nullptr;
   const DProb* probs32 = nullptr;
+  const DProb* probs16 = nullptr;
   int nprob = 1;
   int n_r = 0, n_t1 = 0, n_t2 = 0;
   size_t lds_inv64 = 0, lds_fwd64 = 0, lds_ang64 = 0, lds_fast64 = 0;   // FP32 uses half
   int fast_mpad = 0, vchunk = 0;
-  int ang_slots64 = 1, ang_slots32 = 1;
+  int ang_slots64 = 1, ang_slots32 = 1, ang_slots16 = 1;
   bool grid_var = false;
+  size_t lds_inv16 = 0, lds_fwd16 = 0;   // LDS bytes of the BF16 radial kernels
   int inv_ks = 24;                  // register k steps of the radial inverse stage
   int fwd_tmax = 4;                 // radial forward variant: register tiles per wave; 0, -1 = pipelined
                                     // with 2 or 4 staged columns per lane

@@ -27,6 +27,8 @@ struct Group {
   int64_t row0, nrows;      // rows [row0, row0 + nrows) of the group
   int64_t tinv_off;         // offset (elements) of the packed inverse table
   int64_t tfwd_off;         // offset (elements) of the packed forward table
+  int64_t tinv16_off;       // offsets (4-element fragments) of the BF16 tables
+  int64_t tfwd16_off;
   std::vector<double> zeros;  // b_k^{g}, k = 1..Kmax
 };
 
@@ -48,6 +50,10 @@ struct helic_basis_s {
   // Packed radial tables (MFMA fragment order, see device.hip); doubles.
   std::vector<double> tab_inv, tab_fwd;
   std::vector<double> tab_dinv;   // d xi / dr in tab_inv's layout (App. C, field derivatives)
+  // The same two tables in bfloat16 for the 16x16x16 BF16 MFMA: per group
+  // fragments of 16 rows x 16 contraction indices, lane l holding row l % 16
+  // and contraction indices 4 (l / 16) + 0..3 (four bfloat16 in 64 bits).
+  std::vector<uint16_t> tab_inv16, tab_fwd16;
   int32_t max_kpad = 0, max_colpad = 0;   // LDS tile bounds over the groups
   std::vector<int32_t> fac1, fac2;        // radix factorisations of n_t1, n_t2
   helic::DeviceState* dev = nullptr;

@@ -31,6 +31,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace helic {
 
@@ -49,6 +50,7 @@ __host__ __device__ constexpr int lds_stride(int colpad) { return (colpad & 16) 
 struct DGroup {
   int32_t mode0, nmodes, Kmax, prob;   // modes relative to the problem; prob indexes DProb
   int64_t row0, nrows, tinv_off, tfwd_off;
+  int64_t tinv16_off, tfwd16_off;      // offsets (4-element BF16 fragments) of the BF16 tables
 };
 
 struct DMode {
@@ -112,6 +114,53 @@ __device__ __forceinline__ cplx<T> cmuli(cplx<T> a, T s) { return {-s * a.y, s *
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { typedef double2 type; };
 template <> struct Vec2<float> { typedef float2 type; };
+
+// ---------------------------------------------------------------- BF16 storage
+// A complex value stored as two bfloat16 (re in the low half, im in the high
+// half of one 32-bit word): the intermediate slabs of the BF16 mode.
+struct bf16x2 {
+  uint32_t u;
+};
+// float -> bfloat16 bits, rounded to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+
+// Slab element E (cplx<double>, cplx<float> or bf16x2) read and written in
+// the arithmetic type T of the kernel that moves it.
+template <typename T, typename E>
+__device__ __forceinline__ cplx<T> eload(const E* p) {
+  if constexpr (std::is_same<E, bf16x2>::value) {
+    const uint32_t u = p->u;
+    return cplx<T>{(T)bf16_lo(u), (T)bf16_hi(u)};
+  } else {
+    const E e = *p;
+    return cplx<T>{(T)e.x, (T)e.y};
+  }
+}
+template <typename T, typename E>
+__device__ __forceinline__ void estore(E* p, cplx<T> v) {
+  if constexpr (std::is_same<E, bf16x2>::value) {
+    p->u = bf16_bits((float)v.x) | (bf16_bits((float)v.y) << 16);
+  } else {
+    *p = E{v.x, v.y};
+  }
+}
+
+// 16x16x16 BF16 MFMA with FP32 accumulation: lane l supplies A[l % 16][4 (l /
+// 16) + j] and B[4 (l / 16) + j][l % 16] (j = 0..3, four bfloat16 in 64 bits);
+// accumulator element i of lane l is D[4 (l / 16) + i][l % 16] (as the 32-bit
+// 16x16x4 form).
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4_t mfma_bf16(uint64_t a, uint64_t b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4_t, a), __builtin_bit_cast(bf16x4_t, b),
+                                                   c, 0, 0, 0);
+}
 
 template <typename T> struct Mfma;
 // 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];

@@ -1,0 +1,183 @@
+// Radial stages of H*X in the BF16 mode: the contractions of Alg. 1 and Alg. 3
+// (radial parts) on 16x16x16 BF16 MFMA with FP32 accumulation, reading and
+// writing the intermediate slabs as bfloat16 pairs (bf16x2).  Same work split
+// as the FP64/FP32 kernels (one |n| group x one vector per workgroup, vector-
+// major XCD mapping); the tables are the basis' BF16 copies, whose fragments
+// hold 16 rows x 16 contraction indices (lane l: row l % 16, contraction
+// indices 4 (l / 16) + 0..3).  Included by device.hip after the helpers it
+// shares with the other radial kernels (tile_kmax, swap_lane_pairs).
+#pragma once
+#include "kernels.hpp"
+
+namespace helic {
+
+// LDS stride (bfloat16 elements) of one staged column: 8 beyond a multiple of
+// 16, so the 16 columns an MFMA operand reads (8 bytes per lane) start on
+// distinct LDS banks.
+__host__ __device__ constexpr int bf16_col_stride(int len16) { return len16 + 8; }
+constexpr int FWD16_RC = 32;   // radii staged per chunk of the forward kernel
+constexpr int FWD16_TM = 12;   // output tiles (16 k x 16 columns) per wave and pass
+
+// G_{mn}(r_l) = sum_k xi_{|n|,k}(r_l) x_{mnk}: the group's coefficients are
+// staged in LDS as bfloat16 columns [2 modes][k] (re and im as separate real
+// columns, k contiguous, zero beyond each mode's K); each wave takes 16-radius
+// tiles; KT16 bounds the k steps (of 16) of the widest group.
+template <int KT16>
+__global__ void __launch_bounds__(NT)
+k_radial_inverse_bf16(const double* __restrict__ X, int64_t ldx, bf16x2* __restrict__ GH, int nvec, int ngroups,
+                      int n_r, const DGroup* __restrict__ groups, const DProb* __restrict__ probs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint16_t* Bs = reinterpret_cast<uint16_t*>(smem_raw);
+  const int slot = xcd_slot(ngroups * nvec);
+  if (slot >= ngroups * nvec) return;
+  const int v = slot / ngroups, gi = slot - v * ngroups;
+  const DGroup gr = groups[gi];
+  const DProb& pb = probs[gr.prob];
+  const int nk16 = (gr.Kmax + 15) / 16;
+  const int kst = bf16_col_stride(16 * nk16);
+  const int ncol = 2 * gr.nmodes;
+  const int nct = (ncol + 15) / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nrt = (n_r + 15) / 16;
+  uint32_t* Bw = reinterpret_cast<uint32_t*>(Bs);
+  for (int i = threadIdx.x; i < 16 * nct * kst / 2; i += NT) Bw[i] = 0u;
+  __syncthreads();
+  const double2* xv = reinterpret_cast<const double2*>(X + col_off(pb, ldx, nvec, v) * 2) + gr.row0;
+  for (int i = threadIdx.x; i < (int)gr.nrows; i += NT) {
+    const int ck = pb.row_ck[gr.row0 + i];
+    const int c = ck >> 16, k = ck & 0xffff;
+    const double2 x = xv[i];
+    Bs[(2 * c) * kst + k] = (uint16_t)bf16_bits((float)x.x);
+    Bs[(2 * c + 1) * kst + k] = (uint16_t)bf16_bits((float)x.y);
+  }
+  __syncthreads();
+  const uint64_t* tg = reinterpret_cast<const uint64_t*>(pb.tinv) + gr.tinv16_off;
+  bf16x2* gv = GH + slab_off(pb, nvec, n_r, v, 0) + gr.mode0;
+  // k steps of column tile c: lane c holds the largest K of the tile's modes
+  const int ktile = tile_kmax(pb.modes + gr.mode0, gr.nmodes, lane);
+  const int bpos = (lane & 15) * kst + 4 * (lane >> 4);
+  for (int rt = wave; rt < nrt; rt += NT / 64) {
+    uint64_t a[KT16];
+#pragma unroll
+    for (int s = 0; s < KT16; ++s) a[s] = s < nk16 ? tg[((int64_t)rt * nk16 + s) * 64 + lane] : 0ull;
+    for (int ct = 0; ct < nct; ++ct) {
+      const int ks = nct <= 64 ? (__builtin_amdgcn_readlane(ktile, ct) + 15) / 16 : nk16;
+      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+      const uint16_t* bt = Bs + 16 * ct * kst + bpos;
+#pragma unroll
+      for (int s = 0; s < KT16; ++s)
+        if (s < ks) acc = mfma_bf16(a[s], *reinterpret_cast<const uint64_t*>(bt + 16 * s), acc);
+      // lanes 2j and 2j + 1 hold re and im of one mode for the same radii;
+      // after a swap across the pair each lane stores two complex values
+      float sw[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sw[i] = swap_lane_pairs(acc[i]);
+      const int col = 16 * ct + (lane & 15);
+      if (col < ncol) {
+        const bool odd = lane & 1;
+        bf16x2* dst = gv + (col >> 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = odd ? 2 * h + 1 : 2 * h;
+          const int r = 16 * rt + 4 * (lane >> 4) + i;
+          const float re = odd ? sw[i] : acc[i];
+          const float im = odd ? acc[i] : sw[i];
+          if (r < n_r) estore<float>(dst + (int64_t)r * pb.n_modes, cplx<float>{re, im});
+        }
+      }
+    }
+  }
+}
+
+// y_{mnk} = kappa x_{mnk} + sum_l (2 pi tau omega_l xi_{|n|,k}(r_l)) H_{mn}(r_l):
+// chunks of FWD16_RC radii of the group's slab rows are staged in LDS as
+// bfloat16 columns [2 modes][r] (r contiguous); each wave accumulates up to TM
+// output tiles over all chunks, then adds kappa x in FP64 and writes rows
+// k <= K of each mode.
+template <int TM>
+__global__ void __launch_bounds__(NT)
+k_radial_forward_bf16(const bf16x2* __restrict__ GH, const double* __restrict__ X, int64_t ldx,
+                      double* __restrict__ Y, int64_t ldy, int nvec, int ngroups, int n_r,
+                      const DGroup* __restrict__ groups, const DProb* __restrict__ probs, int add_kinetic) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint16_t* Hs = reinterpret_cast<uint16_t*>(smem_raw);
+  constexpr int RST = bf16_col_stride(FWD16_RC);
+  const int slot = xcd_slot(ngroups * nvec);
+  if (slot >= ngroups * nvec) return;
+  const int v = slot / ngroups, gi = slot - v * ngroups;
+  const DGroup gr = groups[gi];
+  const DProb& pb = probs[gr.prob];
+  const int nmodes = gr.nmodes;
+  const int ncol = 2 * nmodes;
+  const int nct = (ncol + 15) / 16;
+  const int nkt = (gr.Kmax + 15) / 16;
+  const int ntiles = nkt * nct;
+  const int nr16 = (n_r + 15) / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t* tg = reinterpret_cast<const uint64_t*>(pb.tfwd) + gr.tfwd16_off;
+  const bf16x2* hv = GH + slab_off(pb, nvec, n_r, v, 0) + gr.mode0;
+  const DMode* modes = pb.modes;
+  const double* kappa = pb.kappa;
+  const double* xv = add_kinetic ? X + col_off(pb, ldx, nvec, v) * 2 : nullptr;
+  double* yv = Y + col_off(pb, ldy, nvec, v) * 2;
+  const int ktile = tile_kmax(modes + gr.mode0, nmodes, lane);
+  const int half = 8 * nct;   // staged (re, im) column pairs, padded to whole tiles
+  for (int tbase = 0; tbase < ntiles; tbase += (NT / 64) * TM) {
+    f32x4_t acc[TM];
+    int tk[TM], tc[TM];
+    bool live[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      acc[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      const int t = tbase + wave + (NT / 64) * i;
+      tk[i] = t / nct;
+      tc[i] = t - tk[i] * nct;
+      live[i] = t < ntiles && (nct > 64 || 16 * tk[i] < __builtin_amdgcn_readlane(ktile, tc[i]));
+    }
+    for (int r0 = 0; r0 < n_r; r0 += FWD16_RC) {
+      __syncthreads();
+      // (radius, mode) pairs, modes fastest: coalesced 4-byte reads
+      for (int idx = threadIdx.x; idx < FWD16_RC * half; idx += NT) {
+        const int rr = idx / half, c = idx - rr * half;
+        const int r = r0 + rr;
+        const uint32_t u = (c < nmodes && r < n_r) ? hv[(int64_t)r * pb.n_modes + c].u : 0u;
+        Hs[(2 * c) * RST + rr] = (uint16_t)(u & 0xffffu);
+        Hs[(2 * c + 1) * RST + rr] = (uint16_t)(u >> 16);
+      }
+      __syncthreads();
+      const int rs0 = r0 / 16;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        if (!live[i]) continue;
+        const uint16_t* bt = Hs + (16 * tc[i] + (lane & 15)) * RST + 4 * (lane >> 4);
+#pragma unroll
+        for (int s = 0; s < FWD16_RC / 16; ++s) {
+          if (rs0 + s < nr16) {
+            const uint64_t a = tg[((int64_t)tk[i] * nr16 + rs0 + s) * 64 + lane];
+            acc[i] = mfma_bf16(a, *reinterpret_cast<const uint64_t*>(bt + 16 * s), acc[i]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      if (!live[i]) continue;
+      const int col = 16 * tc[i] + (lane & 15);
+      const int c = col >> 1, ri = col & 1;
+      if (c >= nmodes) continue;
+      const DMode md = modes[gr.mode0 + c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * tk[i] + 4 * (lane >> 4) + j;
+        if (k < md.K) {
+          const int64_t row = md.row0 + k;
+          double y = (double)acc[i][j];
+          if (add_kinetic) y += kappa[row] * xv[2 * row + ri];
+          yv[2 * row + ri] = y;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace helic

@@ -283,6 +283,12 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   const int kmax = 3 * n;
   helic_prec prec = (helic_prec)o.prec;
   const double switch_tol = o.switch_tol > 0 ? o.switch_tol : 1e-4;
+  // BF16 start: FP32 takes over below switch_bf16, FP64 below switch_tol
+  const double switch_bf16 = std::max(switch_tol, o.switch_tol_bf16 > 0 ? o.switch_tol_bf16 : 3e-2);
+  auto prec_name = [&]() { return prec == HELIC_FP64 ? "FP64" : prec == HELIC_FP32 ? "FP32" : "BF16"; };
+  // lock tolerance of the low-precision phases: where their H*X stops improving a column
+  auto phase_tol = [&]() { return prec == HELIC_FP64 ? o.tol : std::max(o.tol, prec == HELIC_FP32 ? switch_tol : switch_bf16); };
+  bool stopped_low = false;   // o.stop_low: ended at the first precision switch
 
   Bufs B;
   double *S, *AS, *Pb, *APb, *Xn, *AXn, *R, *GA, *Z, *T1, *C, *theta, *E, *d, *lam, *part, *norms, *jres;
@@ -652,10 +658,17 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
         converged = true;
         break;
       }
-      if (prec != HELIC_FP64 && worst <= switch_tol) {
-        // precision ladder: H X in FP64 and a fresh Rayleigh-Ritz over every
-        // column (the FP32 locks are released), then FP64 filters
-        prec = HELIC_FP64;
+      const bool to64 = prec != HELIC_FP64 && worst <= switch_tol;
+      const bool to32 = !to64 && prec == HELIC_BF16 && worst <= switch_bf16;
+      if ((to64 || to32) && o.stop_low) {
+        stopped_low = true;
+        break;
+      }
+      if (to64 || to32) {
+        // precision ladder: H X in the next precision and a fresh
+        // Rayleigh-Ritz over every column (the locks of the lower phase are
+        // released), then filters in that precision
+        prec = to64 ? HELIC_FP64 : HELIC_FP32;
         nl = 0;
         if ((s = apply(S, AS, n))) return s;
         if ((s = rayleigh_ritz(0, n, n, 0))) return s;
@@ -666,13 +679,15 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
       }
       if (o.log_every > 0 && it % o.log_every == 0) {
         std::fprintf(stderr, "[helic] filter step %d: worst wanted residual %.3e, %d locked, %s H*X, %.1f s\n", it,
-                     worst, nl, prec == HELIC_FP64 ? "FP64" : "FP32", total.ms() / 1e3);
+                     worst, nl, prec_name(), total.ms() / 1e3);
         std::fflush(stderr);
       }
       if (prec != HELIC_FP64) ++S_.iters_low;
-      // in the FP32 phase a column is locked at switch_tol, where FP32
-      // filtering stops improving it; the FP64 phase starts unlocked
-      const double lock_tol = prec == HELIC_FP64 ? o.tol : std::max(o.tol, switch_tol);
+      if (prec == HELIC_BF16) ++S_.iters_bf16;
+      // in a low-precision phase a column is locked at its switch tolerance,
+      // where filtering in that precision stops improving it; the next phase
+      // starts unlocked
+      const double lock_tol = phase_tol();
       while (nl < n - 1 && nrm[nl] <= lock_tol) ++nl;
       const int nu = n - nl;
       const int64_t nd = (int64_t)Lc * nu;
@@ -758,9 +773,15 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
         converged = true;
         break;
       }
-      if (prec != HELIC_FP64 && worst <= switch_tol) {
-        // precision ladder: recompute H X and H P in FP64 and go on in FP64
-        prec = HELIC_FP64;
+      const bool to64 = prec != HELIC_FP64 && worst <= switch_tol;
+      const bool to32 = !to64 && prec == HELIC_BF16 && worst <= switch_bf16;
+      if ((to64 || to32) && o.stop_low) {
+        stopped_low = true;
+        break;
+      }
+      if (to64 || to32) {
+        // precision ladder: recompute H X and H P in the next precision and go on
+        prec = to64 ? HELIC_FP64 : HELIC_FP32;
         exact_x = false;   // H X recomputed: X^H H X is no longer exactly diagonal
         if ((s = apply(S, AS, n))) return s;
         if ((s = apply(Pb, APb, np))) return s;
@@ -769,7 +790,7 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
       }
       if (o.log_every > 0 && it % o.log_every == 0) {
         std::fprintf(stderr, "[helic] iteration %d: worst wanted residual %.3e, %s H*X, %.1f s\n", it, worst,
-                     prec == HELIC_FP64 ? "FP64" : "FP32", total.ms() / 1e3);
+                     prec_name(), total.ms() / 1e3);
         std::fflush(stderr);
       }
       if (learned) {
@@ -781,10 +802,12 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
         }
       }
       if (prec != HELIC_FP64) ++S_.iters_low;
-      // In the FP32 phase columns are locked at switch_tol: iterating a column
-      // whose residual is at the FP32 noise floor makes its normalised update
-      // directions amplify the rounding inconsistency between S and H S.
-      const double lock_tol = prec == HELIC_FP64 ? o.tol : std::max(o.tol, switch_tol);
+      if (prec == HELIC_BF16) ++S_.iters_bf16;
+      // In a low-precision phase columns are locked at its switch tolerance:
+      // iterating a column whose residual is at that precision's noise floor
+      // makes its normalised update directions amplify the rounding
+      // inconsistency between S and H S.
+      const double lock_tol = phase_tol();
       if (prec == HELIC_FP64)
         while (nl < n - 1 && nrm[nl] <= o.tol) ++nl;
       active.clear();
@@ -884,11 +907,12 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     lam_h.swap(l2);
     nrm.swap(r2);
   }
-  if (!converged) {
+  if (!converged && !stopped_low) {
     converged = prec == HELIC_FP64;
     for (int j = 0; j < nev; ++j) converged = converged && nrm[j] <= o.tol;
   }
-  if (hv && converged)
+  if (stopped_low) converged = true;
+  if (hv && converged && !stopped_low)
     if ((s = harvest_targets())) return s;
   if (evecs)
     HIP_TRY_S(hipMemcpy2DAsync(evecs, sizeof(double) * 2 * ldv, S, sizeof(double) * Lc, sizeof(double) * Lc, nev,
@@ -917,7 +941,8 @@ helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* o, doubl
   if (o->nev < 1 || o->nev > h->L || o->block < 1 || !(o->tol > 0) || o->maxit < 0 ||
       (evecs && ldv < h->L))
     return fail(HELIC_ERR_INVALID, "bad solver options");
-  if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32 && o->prec != HELIC_BF16)
+    return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
   if (o->precond < 0 || o->precond > 2) return fail(HELIC_ERR_UNSUPPORTED, "unknown preconditioner");
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
   if (o->precond == 2 && !lpc_attached(h)) return fail(HELIC_ERR_STATE, "no learned preconditioner attached");
@@ -935,7 +960,8 @@ helic_status helic_eigensolve_chefsi(helic_basis h, const helic_solve_opts* o, i
   if (o->nev < 1 || o->nev > h->L || o->block < 1 || !(o->tol > 0) || o->maxit < 0 ||
       (evecs && ldv < h->L) || degree < 0 || degree > 200)
     return fail(HELIC_ERR_INVALID, "bad solver options");
-  if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32 && o->prec != HELIC_BF16)
+    return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
   try {
     return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream), nullptr,
@@ -953,7 +979,8 @@ helic_status helic_lpc_harvest(helic_basis h, const helic_solve_opts* o, int32_t
   if (n_snap < 1 || max_cols < 1) return fail(HELIC_ERR_INVALID, "bad harvest sizes");
   if (o->nev < 1 || o->nev > h->L || o->block < 1 || !(o->tol > 0) || o->maxit < 0)
     return fail(HELIC_ERR_INVALID, "bad solver options");
-  if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32) return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
+  if (o->prec != HELIC_FP64 && o->prec != HELIC_FP32 && o->prec != HELIC_BF16)
+    return fail(HELIC_ERR_UNSUPPORTED, "unknown precision");
   if (o->precond < 0 || o->precond > 2) return fail(HELIC_ERR_UNSUPPORTED, "unknown preconditioner");
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
   if (o->precond == 2 && !lpc_attached(h)) return fail(HELIC_ERR_STATE, "no learned preconditioner attached");

@@ -19,9 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libhelic.so")
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_GRID, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_CUTOFF_TIE, ERR_STATE = range(9)
-FP64, FP32 = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
 LPC_NPARAM = 4801
-PREC = {"fp64": FP64, "fp32": FP32}
+PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
 # every function declared in include/helic.h
 EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "helic_basis_indices",
@@ -49,13 +49,13 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int32), ("block", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int32), ("prec", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("precond", ctypes.c_int32), ("guard", ctypes.c_int32), ("switch_tol", ctypes.c_double),
-                ("log_every", ctypes.c_int32)]
+                ("log_every", ctypes.c_int32), ("switch_tol_bf16", ctypes.c_double), ("stop_low", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("iters_low", ctypes.c_int32), ("n_apply", ctypes.c_int64),
                 ("n_fallback", ctypes.c_int32), ("t_apply_ms", ctypes.c_double), ("t_rr_ms", ctypes.c_double),
-                ("t_precond_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+                ("t_precond_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double), ("iters_bf16", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -354,12 +354,15 @@ def eigensolve(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, evecs
 
 
 def eigensolve_ex(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa", guard=-1,
-                  switch_tol=1e-4, evecs=None, log_every=0, stream=None, cheb_degree=None):
+                  switch_tol=1e-4, evecs=None, log_every=0, stream=None, cheb_degree=None, switch_tol_bf16=0.0,
+                  stop_low=False):
     """Returns (evals, resid, stats dict, status); raises on errors other
     than non-convergence.  cheb_degree (an int, 0 = automatic) selects the
-    Chebyshev-filtered subspace iteration instead of LOBPCG."""
+    Chebyshev-filtered subspace iteration instead of LOBPCG; stop_low ends a
+    low-precision solve at its first precision switch."""
     o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=PREC[prec], seed=seed,
-                  precond=PRECOND[precond], guard=guard, switch_tol=switch_tol, log_every=log_every)
+                  precond=PRECOND[precond], guard=guard, switch_tol=switch_tol, log_every=log_every,
+                  switch_tol_bf16=switch_tol_bf16, stop_low=int(bool(stop_low)))
     evals = np.zeros(nev)
     resid = np.zeros(nev)
     st = SolveStats()

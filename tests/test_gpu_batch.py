@@ -72,7 +72,7 @@ def test_batched_apply_matches_oracle_per_problem(base, etas):
     probs, batch = make_batch(base, etas)
     nvec = 7
     X, xs = pack(batch, probs, nvec, 300)
-    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32), ("bf16", 1e-2)):
         Y = torch.full_like(X, 3.0)
         batch.apply(X, Y, nvec, prec=prec)
         for i, p in enumerate(probs):

@@ -5,6 +5,8 @@ tol with ||x||_2 = 1, which for a Hermitian H places an exact eigenvalue
 within tol of each Ritz value; with tol = 1e-9 the eigenvalues are compared
 with LAPACK's to 1e-8 Ha (the bound stated for the FP64 path).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -23,6 +25,14 @@ def _dev():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch.device("cuda:0")
+
+
+def _golden(name, nev):
+    """Lowest eigenvalues of a workload written by tests/golden/make_lowest.py
+    (dense FP64 oracle, LAPACK)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        f"{name.replace('-', '_')}_lowest{nev}.txt")
+    return np.loadtxt(path, comments="#", usecols=1)
 
 
 def _setup(w, potential=True):
@@ -116,6 +126,32 @@ def test_time_reversal_on_gpu():
     np.testing.assert_allclose(ev1, ev2, atol=EIG_TOL)
 
 
+def test_bf16_ladder_and_low_precision_stops_tiny():
+    """Precision ladders against LAPACK: BF16 -> FP32 -> FP64 reaches the
+    FP64 bound with LOBPCG and the filtered solver; a solve stopped at its
+    first precision switch (stop_low) returns the low-precision Ritz values,
+    whose error is reported (and bounded by the switch tolerance: the
+    residual there places an exact eigenvalue within it)."""
+    w = synth.workload("tiny-helix")
+    o, b, V = _setup(w)
+    ref, _ = oh.lowest(oh.dense_explicit(o, V), w.nev)
+    for deg in (None, 0):
+        ev, res, st, status = b.eigensolve_ex(w.nev, tol=1e-9, maxit=400, prec="bf16", cheb_degree=deg)
+        print(f"[tiny bf16 ladder deg {deg}] iters {st['iters']} (BF16 {st['iters_bf16']}, low {st['iters_low']}) "
+              f"max|dlambda| {np.max(np.abs(ev - ref)):.2e}", flush=True)
+        assert status == helic.OK, st["message"]
+        assert st["iters_bf16"] > 0 and st["iters_low"] >= st["iters_bf16"]
+        assert np.max(np.abs(ev - ref)) < EIG_TOL
+        for prec, sw in (("fp32", 1e-4), ("bf16", 3e-2)):
+            ev0, res0, st0, s0 = b.eigensolve_ex(w.nev, tol=1e-9, maxit=400, prec=prec, cheb_degree=deg,
+                                                 stop_low=True)
+            err = np.max(np.abs(ev0 - ref))
+            print(f"[tiny {prec} before refinement deg {deg}] iters {st0['iters']} max res {res0.max():.2e} "
+                  f"max|dlambda| {err:.2e}", flush=True)
+            assert s0 == helic.OK
+            assert res0.max() <= sw and err <= sw
+
+
 def test_solver_argument_errors():
     w = synth.workload("tiny-helix")
     o, b, V = _setup(w)
@@ -136,14 +172,18 @@ def test_full_size_eigenpairs_certified_by_the_oracle():
     runs (different random starts) must agree on all 120 eigenvalues."""
     w = synth.workload("nanotube-ecut25")
     o, b, V = _setup(w)
+    gold = _golden(w.name, w.nev)
     evecs = torch.zeros((w.nev, b.L), dtype=torch.complex128, device=_dev())
     ev, res, st, status = b.eigensolve_ex(w.nev, tol=1e-8, maxit=1000, seed=7, evecs=evecs)
     assert status == helic.OK
     ev32, res32, st32, s32 = b.eigensolve_ex(w.nev, tol=1e-8, maxit=1000, seed=11, prec="fp32")
     assert s32 == helic.OK
     print(f"[full size] fp64 its {st['iters']} mixed its {st32['iters']} max|dlambda| "
-          f"{np.max(np.abs(ev - ev32)):.2e}", flush=True)
-    assert np.max(np.abs(ev - ev32)) < 2e-8
+          f"{np.max(np.abs(ev - ev32)):.2e}; vs the dense oracle: fp64 {np.max(np.abs(ev - gold)):.2e} "
+          f"mixed {np.max(np.abs(ev32 - gold)):.2e}", flush=True)
+    # all 120 against the dense oracle's lowest 120 (no eigenvalue skipped)
+    assert np.max(np.abs(ev - gold)) < EIG_TOL
+    assert np.max(np.abs(ev32 - gold)) < EIG_TOL
     mnk, _ = b.indices()
     pos = {tuple(t): i for i, t in enumerate(o.mnk.tolist())}
     perm = np.array([pos[tuple(t)] for t in mnk.tolist()])
@@ -217,17 +257,17 @@ def test_chefsi_full_size_certified_by_the_oracle():
     evecs = torch.zeros((w.nev, b.L), dtype=torch.complex128, device=_dev())
     ev, res, st, status = b.eigensolve_ex(w.nev, tol=1e-8, maxit=200, seed=5, evecs=evecs, cheb_degree=0)
     assert status == helic.OK, st["message"]
-    evl, _, stl, sl = b.eigensolve_ex(w.nev, tol=1e-8, maxit=1000, seed=7)
-    assert sl == helic.OK
-    print(f"[full size chefsi] steps {st['iters']} applications {st['n_apply']} vs LOBPCG its {stl['iters']}: "
-          f"max|dlambda| {np.max(np.abs(ev - evl)):.2e}", flush=True)
-    assert np.max(np.abs(ev - evl)) < 2e-8
-    # the FP32 ladder of the filtered solver reaches the same eigenvalues
-    ev32, res32, st32, s32 = b.eigensolve_ex(w.nev, tol=1e-8, maxit=200, seed=9, prec="fp32", cheb_degree=0)
-    assert s32 == helic.OK and st32["iters_low"] > 0
-    print(f"[full size chefsi] mixed steps {st32['iters']} (FP32 {st32['iters_low']}) max|dlambda| vs FP64 "
-          f"{np.max(np.abs(ev32 - ev)):.2e}", flush=True)
-    assert np.max(np.abs(ev32 - ev)) < 2e-8
+    gold = _golden(w.name, w.nev)
+    print(f"[full size chefsi] steps {st['iters']} applications {st['n_apply']}: max|dlambda| vs the dense oracle "
+          f"{np.max(np.abs(ev - gold)):.2e}", flush=True)
+    assert np.max(np.abs(ev - gold)) < EIG_TOL
+    # the FP32 and BF16 ladders of the filtered solver reach the same eigenvalues
+    for prec, seed in (("fp32", 9), ("bf16", 13)):
+        evl, resl, stl, sl = b.eigensolve_ex(w.nev, tol=1e-8, maxit=200, seed=seed, prec=prec, cheb_degree=0)
+        assert sl == helic.OK and stl["iters_low"] > 0
+        print(f"[full size chefsi] {prec} ladder steps {stl['iters']} (low {stl['iters_low']}, BF16 "
+              f"{stl['iters_bf16']}) max|dlambda| vs the dense oracle {np.max(np.abs(evl - gold)):.2e}", flush=True)
+        assert np.max(np.abs(evl - gold)) < EIG_TOL
     mnk, _ = b.indices()
     pos = {tuple(t): i for i, t in enumerate(o.mnk.tolist())}
     perm = np.array([pos[tuple(t)] for t in mnk.tolist()])
