@@ -1,14 +1,19 @@
 """Benchmark of the helical-wave Hamiltonian apply on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--workload nanotube-ecut25]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload nanowire-ecut30]
 
-One step applies H to a block of 64 coefficient vectors (the whole H*X path:
-radial inverse GEMMs, angular inverse DFT / potential / forward DFT per
-radius, radial forward GEMMs with the kinetic diagonal).  The block, the
-potential and every table are resident in HBM before timing starts.  Rank 0
-prints one JSON line with the throughput in vector applications per second,
-the roofline position of the dominant kernel and the CPU oracle's throughput
-on a bounded sample of the same workload.
+One step applies H to a block of 64 coefficient vectors of the largest
+single-GPU workload (the filled nanowire, 88,951 basis functions): the whole
+H*X path -- radial inverse GEMMs, angular inverse DFT / potential / forward
+DFT per radius, radial forward GEMMs with the kinetic diagonal.  The block,
+the potential and every table are resident in HBM before timing starts.
+Rank 0 prints one JSON line with the throughput in vector applications per
+second, the roofline position of the dominant kernel, the time to the lowest
+eigenpairs in FP64 and along the BF16 / FP32 -> FP64 ladders on the 40 Ha
+nanotube (200 pairs, per-eigenvalue errors before and after refinement), the
+learned preconditioner against the plain one on the nanowire (400 pairs),
+the batched Bloch-parameter solves of all eight seeded structures, and the
+CPU oracle's throughput on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -29,6 +34,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector and FP64 matrix (dense)
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X FP32 matrix (dense)
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published (packed FP32 counted; these kernels issue none)
+BF16_MFMA_PEAK_TFLOPS = 2500.0 # MI355X BF16 matrix (dense)
 STAGES = ("k_radial_inverse", "k_angular", "k_radial_forward")
 KERNEL_SOURCES = ("paper_2210_12252_amd/csrc/kernels.hpp", "paper_2210_12252_amd/csrc/angular_fast.hpp",
                   "paper_2210_12252_amd/csrc/device.hip")
@@ -66,66 +72,147 @@ def algorithmic_counts(L, n_modes, n1, n2, n_r, nvec, elem):
     return dict(zip(STAGES, (inv, ang, fwd)))
 
 
+_CPU = {}
+
+
+def _cpu_init(o, V):
+    _CPU["o"], _CPU["V"] = o, V
+
+
+def _cpu_apply(X):
+    """Oracle H*X of one column slice (runs in a worker process)."""
+    from oracle import hamiltonian as oh
+    return oh.apply(_CPU["o"], _CPU["V"], X)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def cpu_baseline(w, nsample: int):
-    """The CPU oracle's matrix-free H*X on `nsample` vectors of the same
-    workload, timed on the host."""
+    """The CPU oracle's matrix-free H*X (unchanged, FP64 NumPy) on `nsample`
+    vectors of the same workload, timed on the host: the columns are split
+    over one worker process per available host core (at most 16), each
+    running the oracle on its slice."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
     import numpy as np
 
     import synth
     from oracle import basis as ob
-    from oracle import hamiltonian as oh
     o = ob.basis_for(w)
     atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
     V = synth.potential_at(o.theta1, o.theta2, o.r, w.tau, w.alpha, atoms)
     X = synth.random_block(o.mnk, nsample, 1234)
-    c0, t0 = time.process_time(), time.perf_counter()
-    Y = oh.apply(o, V, X)
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
-    assert np.all(np.isfinite(Y))
-    return dict(value=nsample / wall, unit="vec-applies/s", cores=max(1, round(cpu / wall)),
-                kind="oracle", sample=f"matrix-free oracle H*X (explicit DFT sums, FP64) on {nsample} of the "
-                f"64 block vectors of {w.name}, {wall:.1f} s wall on {os.cpu_count()} host cores")
+    nw = min(host_cores(), nsample)
+    slices = [X[:, i::nw] for i in range(nw)]
+    with cf.ProcessPoolExecutor(nw, mp_context=mp.get_context("spawn"), initializer=_cpu_init,
+                                initargs=(o, V)) as ex:
+        list(ex.map(_cpu_apply, [s[:, :1] for s in slices]))   # workers started and warm
+        t0 = time.perf_counter()
+        Ys = list(ex.map(_cpu_apply, slices))
+        wall = time.perf_counter() - t0
+    assert all(np.all(np.isfinite(Y)) for Y in Ys)
+    return dict(value=nsample / wall, unit="vec-applies/s", cores=nw, kind="oracle",
+                sample=f"matrix-free oracle H*X (explicit DFT sums, FP64 NumPy) on {nsample} of the 64 block "
+                f"vectors of {w.name}, one worker process per core, {wall:.1f} s wall",
+                cpu_model=cpu_model(), nproc=os.cpu_count())
 
 
-def time_to_eigenpairs(b, w, torch, tol=1e-8, solvers=("lobpcg", "chefsi")):
-    """Lowest w.nev eigenpairs to ||H x - lambda x|| <= tol from the same
-    seeded random start, FP64 H*X and mixed (FP32 H*X, FP64 refinement); all
-    keep the FP64 Rayleigh-Ritz.  Two solvers: LOBPCG with the TPA
-    preconditioner and Chebyshev-filtered subspace iteration (automatic degree
-    and guard).  Reports wall time, iterations (outer filter steps for the
-    latter), the H*X and Rayleigh-Ritz shares and the largest eigenvalue
-    difference against LOBPCG in FP64."""
+def _solve_record(st, status, res, wall):
     import numpy as np
-    out = {"nev": w.nev, "tol_Ha": tol}
+    return dict(seconds=round(wall, 3), converged=bool(status == 0), iters=st["iters"], iters_low=st["iters_low"],
+                iters_bf16=st["iters_bf16"], hx_columns=st["n_apply"], hx_s=round(st["t_apply_ms"] / 1e3, 3),
+                rayleigh_ritz_s=round(st["t_rr_ms"] / 1e3, 3), max_resid=float(np.max(res)))
+
+
+def time_to_eigenpairs(b, w, torch, tol=1e-8, solvers=("lobpcg", "chefsi"), table=None):
+    """Lowest w.nev eigenpairs to ||H x - lambda x|| <= tol from the same
+    seeded random start, by LOBPCG (TPA preconditioner) and by
+    Chebyshev-filtered subspace iteration, each with FP64 H*X and along the
+    precision ladders FP32 -> FP64 and BF16 -> FP32 -> FP64; all keep the
+    FP64 Rayleigh-Ritz.  The filtered solver also runs each ladder stopped at
+    its first switch (the low-precision result before refinement).  Reports
+    wall time, iterations (outer filter steps for the latter), the H*X and
+    Rayleigh-Ritz shares and the eigenvalue errors against the FP64 solve of
+    the same solver; `table` (a path) receives the per-eigenvalue errors."""
+    import numpy as np
+    out = {"workload": w.name, "L": b.L, "nev": w.nev, "tol_Ha": tol}
     evs = {}
-    # warm-up: library handles and kernels of both solvers loaded before timing
     b.eigensolve_ex(4, tol=1e-3, maxit=2)
     b.eigensolve_ex(4, tol=1e-3, maxit=1, cheb_degree=2)
-    runs = ((("fp64", None, "fp64"), ("fp32", None, "mixed_fp32_fp64")) if "lobpcg" in solvers else ()) + \
-           ((("fp64", 0, "chefsi_fp64"), ("fp32", 0, "chefsi_mixed_fp32_fp64")) if "chefsi" in solvers else ())
-    for prec, deg, key in runs:
+    runs = []
+    for solver in solvers:
+        deg = None if solver == "lobpcg" else 0
+        for prec in ("fp64", "fp32", "bf16"):
+            runs.append((solver, deg, prec, f"{solver}_{prec}" if prec == "fp64" else f"{solver}_{prec}_ladder", False))
+    if "chefsi" in solvers:
+        for prec in ("fp32", "bf16"):
+            runs.append(("chefsi", 0, prec, f"chefsi_{prec}_before_refinement", True))
+    for solver, deg, prec, key, low in runs:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev, res, st, status = b.eigensolve_ex(w.nev, block=64, tol=tol, maxit=1000 if deg is None else 200,
-                                              prec=prec, seed=7, log_every=LOG_EVERY, cheb_degree=deg)
+                                              prec=prec, seed=7, log_every=LOG_EVERY, cheb_degree=deg,
+                                              stop_low=low)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        out[key] = dict(seconds=round(wall, 3), converged=bool(status == 0), iters=st["iters"],
-                        iters_fp32=st["iters_low"], hx_columns=st["n_apply"], hx_s=round(st["t_apply_ms"] / 1e3, 3),
-                        rayleigh_ritz_s=round(st["t_rr_ms"] / 1e3, 3), max_resid=float(np.max(res)))
+        out[key] = _solve_record(st, status, res, wall)
         evs[key] = ev
         print(f"[bench] eigensolve {key}: {wall:.2f} s, {st['iters']} iterations, converged {status == 0}",
               file=sys.stderr, flush=True)
-    if "lobpcg" not in solvers or "chefsi" not in solvers:
-        return out
-    d = np.abs(evs["mixed_fp32_fp64"] - evs["fp64"])
-    out["mixed_vs_fp64_max_abs_Ha"] = float(d.max())
-    out["speedup_mixed"] = round(out["fp64"]["seconds"] / out["mixed_fp32_fp64"]["seconds"], 3)
-    out["chefsi_vs_lobpcg_max_abs_Ha"] = float(max(np.abs(evs["chefsi_fp64"] - evs["fp64"]).max(),
-                                                   np.abs(evs["chefsi_mixed_fp32_fp64"] - evs["fp64"]).max()))
-    out["speedup_chefsi"] = round(out["fp64"]["seconds"] / out["chefsi_fp64"]["seconds"], 3)
-    out["speedup_chefsi_mixed"] = round(out["fp64"]["seconds"] / out["chefsi_mixed_fp32_fp64"]["seconds"], 3)
+    for solver in solvers:
+        ref = evs[f"{solver}_fp64"]
+        for prec in ("fp32", "bf16"):
+            key = f"{solver}_{prec}_ladder"
+            out[key]["max_abs_dlambda_vs_fp64_Ha"] = float(np.max(np.abs(evs[key] - ref)))
+            out[key]["speedup_vs_fp64"] = round(out[f"{solver}_fp64"]["seconds"] / out[key]["seconds"], 3)
+    if "lobpcg" in solvers and "chefsi" in solvers:
+        out["chefsi_vs_lobpcg_max_abs_Ha"] = float(np.max(np.abs(evs["chefsi_fp64"] - evs["lobpcg_fp64"])))
+        out["speedup_chefsi_vs_lobpcg_fp64"] = round(out["lobpcg_fp64"]["seconds"] / out["chefsi_fp64"]["seconds"], 3)
+    if "chefsi" in solvers:
+        ref = evs["chefsi_fp64"]
+        per = {}
+        for prec in ("fp32", "bf16"):
+            before = np.abs(evs[f"chefsi_{prec}_before_refinement"] - ref)
+            after = np.abs(evs[f"chefsi_{prec}_ladder"] - ref)
+            per[prec] = {"before_refinement": dict(max=float(before.max()), median=float(np.median(before))),
+                         "after_refinement": dict(max=float(after.max()), median=float(np.median(after)))}
+        out["per_eigenvalue_error_vs_fp64_Ha"] = per
+        if table:
+            with open(table, "w") as fh:
+                fh.write(f"# Per-eigenvalue error of the low-precision ladders, {w.name} (L = {b.L}), lowest "
+                         f"{w.nev}\n\n")
+                fh.write("Filtered subspace iteration from the same seeded start; |lambda - lambda_FP64| in Ha "
+                         "against its FP64 solve (tol 1e-8).  'before': the ladder stopped at its first "
+                         "precision switch (FP32: residual <= 1e-4, BF16: <= 3e-2); 'after': refined to 1e-8 in "
+                         "FP64.\n\n")
+                fh.write("Command: `python bench.py --eig-table <this file>` (the eigensolve leg).\n\n")
+                fh.write("| j | lambda_FP64 (Ha) | FP32 before | FP32 after | BF16 before | BF16 after |\n")
+                fh.write("|---:|---:|---:|---:|---:|---:|\n")
+                for j in range(w.nev):
+                    fh.write(f"| {j} | {ref[j]:.10f} | "
+                             f"{abs(evs['chefsi_fp32_before_refinement'][j] - ref[j]):.2e} | "
+                             f"{abs(evs['chefsi_fp32_ladder'][j] - ref[j]):.2e} | "
+                             f"{abs(evs['chefsi_bf16_before_refinement'][j] - ref[j]):.2e} | "
+                             f"{abs(evs['chefsi_bf16_ladder'][j] - ref[j]):.2e} |\n")
     return out
 
 
@@ -171,15 +258,16 @@ def angular_kernel_name(n1, n2):
     return "register-fft" if (n1, n2) in REGFFT_GRIDS else "general"
 
 
-def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e-8, learned=True):
+def batched_leg(torch, structures, nvec=8, steps=20, nev=60, tol=1e-8, extra=False, eig_every=8):
     """Many Bloch parameters of seeded structures (64 eta each, R ~ U[5, 12],
     E_cut ~ U[15, 35]): per structure one batch with a common grid (the
     largest automatic grid over its eta), tuned, captured in a HIP graph and
-    replayed; and the lowest `nev` eigenpairs of every `eig_every`-th eta,
-    solved concurrently on 8 streams, with the plain preconditioner, by
-    Chebyshev-filtered subspace iteration (also with time-reversal halving of
-    the eta points), and (if `learned`) with a network trained on one other
-    eta of the structure."""
+    replayed (FP64; BF16 eager), and the lowest `nev` eigenpairs of all 64
+    problems by Chebyshev-filtered subspace iteration along the FP32 -> FP64
+    ladder, with time-reversal halving of the eta points, concurrently on 8
+    streams.  With `extra`, every `eig_every`-th problem is also solved by
+    FP64 LOBPCG with the plain and with a learned preconditioner (trained on
+    another eta of the structure)."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -222,38 +310,40 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
             batch.replay()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - ta) / steps
+        batch.apply(X, Y, nvec, prec="bf16")
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(steps):
+            batch.apply(X, Y, nvec, prec="bf16")
+        torch.cuda.synchronize()
+        dt16 = (time.perf_counter() - ta) / steps
         Ls = np.diff(batch.offsets)
         rec = dict(structure=s, R=round(w0.R, 3), ecut=round(w0.ecut, 3), n_eta=len(probs),
                    grid=f"{n1}x{n2}x{nr}", L_min=int(Ls.min()), L_max=int(Ls.max()),
                    kernel=angular_kernel_name(n1, n2),
                    setup_s=round(setup, 2), tuned_items_per_wg=chosen, ms_per_batched_apply=round(1e3 * dt, 3),
-                   vec_applies_per_s=round(len(probs) * nvec / dt, 1))
-        sub = bases[::eig_every]
-        eb = helic.Batch(sub)
+                   vec_applies_per_s=round(len(probs) * nvec / dt, 1),
+                   bf16_ms_per_batched_apply=round(1e3 * dt16, 3),
+                   bf16_vec_applies_per_s=round(len(probs) * nvec / dt16, 1))
+        # every problem: filtered solver, FP32 -> FP64 ladder, time-reversal halving
+        npairs = batch.time_reversal(True)
         torch.cuda.synchronize()
         te = time.perf_counter()
-        ev, res, st, status = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000)
+        ev, res, st, status = batch.eigensolve(nev, nstreams=8, tol=tol, maxit=200, cheb_degree=0, prec="fp32")
         te = time.perf_counter() - te
-        rec.update(eig_problems=len(sub), eig_nev=nev, eig_seconds=round(te, 2),
-                   eig_converged=int(np.sum(status == 0)), eig_iters_mean=float(np.mean([x["iters"] for x in st])))
-        te = time.perf_counter()
-        evc, resc, stc, statusc = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=200, cheb_degree=0)
-        te = time.perf_counter() - te
-        rec.update(chefsi_eig_seconds=round(te, 2), chefsi_converged=int(np.sum(statusc == 0)),
-                   chefsi_steps_mean=float(np.mean([x["iters"] for x in stc])),
-                   chefsi_max_abs_dlambda=float(np.max(np.abs(evc - ev))))
-        # time-reversal halving: eta and -eta of the subset share one solve
-        npairs = eb.time_reversal(True)
-        te = time.perf_counter()
-        evt, _, _, statust = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=200, cheb_degree=0)
-        te = time.perf_counter() - te
-        eb.time_reversal(False)
-        rec.update(time_reversal_pairs=npairs, chefsi_tr_eig_seconds=round(te, 2),
-                   chefsi_tr_converged=int(np.sum(statust == 0)),
-                   chefsi_tr_max_abs_dlambda=float(np.max(np.abs(evt - ev))))
-        if learned:
-            # one network per structure, trained on pairs from the solve at an
-            # eta outside the solved subset, attached to every solved problem
+        batch.time_reversal(False)
+        rec.update(eig_problems=len(probs), eig_nev=nev, eig_prec="fp32 -> fp64 ladder", time_reversal_pairs=npairs,
+                   eig_seconds=round(te, 2), eig_converged=int(np.sum(status == 0)), eig_max_resid=float(res.max()),
+                   eig_steps_mean=float(np.mean([x["iters"] for x in st if x["iters"] > 0])))
+        if extra:
+            sub = bases[::eig_every]
+            eb = helic.Batch(sub)
+            te = time.perf_counter()
+            evl, _, stl, statusl = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000)
+            te = time.perf_counter() - te
+            rec.update(lobpcg_problems=len(sub), lobpcg_seconds=round(te, 2),
+                       lobpcg_converged=int(np.sum(statusl == 0)),
+                       lobpcg_max_abs_dlambda=float(np.max(np.abs(evl - ev[::eig_every]))))
             tl = time.perf_counter()
             tb = bases[eig_every // 2]
             Rh, Th, lh, ncol, _ = tb.lpc_harvest(nev, n_snap=12, tol=tol, maxit=1000, seed=3)
@@ -265,18 +355,17 @@ def batched_leg(torch, structures, nvec=8, steps=20, eig_every=8, nev=60, tol=1e
             for sb in sub:
                 sb.attach(net)
             te = time.perf_counter()
-            evl, resl, stl, statusl = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000, precond="learned")
+            evn, _, stn, statusn = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000, precond="learned")
             te = time.perf_counter() - te
             for sb in sub:
                 sb.attach(None)
             net.close()
-            rec.update(learned_train_s=round(tl, 2), learned_eig_seconds=round(te, 2),
-                       learned_converged=int(np.sum(statusl == 0)),
-                       learned_iters_mean=float(np.mean([x["iters"] for x in stl])),
-                       learned_max_abs_dlambda=float(np.max(np.abs(evl - ev))))
+            eb.close()
+            rec.update(learned_train_s=round(tl, 2), learned_seconds=round(te, 2),
+                       learned_converged=int(np.sum(statusn == 0)),
+                       learned_max_abs_dlambda=float(np.max(np.abs(evn - ev[::eig_every]))))
         print(f"[bench] batched structure {s}: {rec}", file=sys.stderr, flush=True)
         out.append(rec)
-        eb.close()
         batch.close()
         for b in bases:
             b.close()
@@ -333,6 +422,13 @@ def learned_leg(torch, b, w, tol=1e-8, train_eta=0.25, n_snap=12, steps=400, bat
               flush=True)
     b.attach(None)
     net.close()
+    # the filtered solver on the same problem, for context (no preconditioner)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, res, st, status = b.eigensolve_ex(w.nev, tol=tol, maxit=200, seed=7, cheb_degree=0)
+    torch.cuda.synchronize()
+    out["chefsi_fp64"] = _solve_record(st, status, res, time.perf_counter() - t0)
+    out["chefsi_fp64"]["max_abs_dlambda_vs_tpa_Ha"] = float(np.max(np.abs(ev - evs["tpa"])))
     out["max_abs_dlambda_Ha"] = float(np.max(np.abs(evs["learned"] - evs["tpa"])))
     out["speedup_time"] = round(out["tpa"]["seconds"] / out["learned"]["seconds"], 3)
     out["iteration_ratio"] = round(out["learned"]["iters"] / max(out["tpa"]["iters"], 1), 3)
@@ -356,18 +452,25 @@ def load_traffic(name: str, nvec: int, workload: str):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="nanotube-ecut25")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="nanowire-ecut30", help="headline H*X workload")
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32", "bf16"))
     ap.add_argument("--cpu-sample", type=int, default=64, help="vectors for the CPU oracle leg (0: skip)")
-    ap.add_argument("--eig", type=int, default=1, help="also time the eigensolve (FP64 and mixed) (0: skip)")
+    ap.add_argument("--eig", type=int, default=1, help="time-to-eigenpairs leg (0: skip)")
+    ap.add_argument("--eig-workload", default="nanotube-ecut40",
+                    help="workload of the time-to-eigenpairs leg (FP64 and the BF16 / FP32 ladders)")
     ap.add_argument("--eig-solvers", default="lobpcg,chefsi",
                     help="comma list of eigensolvers the eigensolve leg times (lobpcg, chefsi)")
-    ap.add_argument("--batched", default="4",
+    ap.add_argument("--eig-table", default="", help="write the per-eigenvalue error table to this path")
+    ap.add_argument("--batched", default="all",
                     help="structures (0..7, comma list, 'all' or 'none') for the batched Bloch-parameter leg")
+    ap.add_argument("--batched-extra", type=int, default=0,
+                    help="batched leg: also LOBPCG and learned-preconditioner solves of every 8th eta")
     ap.add_argument("--learned", default="same",
-                    help="learned-preconditioner leg: 'same' (the benchmark workload), a workload name, or 'none'")
+                    help="learned-preconditioner leg: 'same' (the headline workload), a workload name, or 'none'")
+    ap.add_argument("--other-precisions", type=int, default=1,
+                    help="also time the headline block in the two other precisions")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args(argv)
@@ -386,14 +489,18 @@ def main(argv=None):
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+
+    def load_problem(w):
+        b = helic.Basis.from_workload(w)
+        t1, t2, r, _ = b.grid()
+        atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
+        b.set_potential(torch.from_numpy(synth.potential_at(t1, t2, r, w.tau, w.alpha, atoms)).to(dev))
+        return b
+
     w = synth.workload(args.workload)
     nvec = 64
     t_setup = time.perf_counter()
-    b = helic.Basis.from_workload(w)
-    t1, t2, r, _ = b.grid()
-    atoms = synth.atoms_for(w.structure, w.seed, w.tau, w.R)
-    V = synth.potential_at(t1, t2, r, w.tau, w.alpha, atoms)
-    b.set_potential(torch.from_numpy(V).to(dev))
+    b = load_problem(w)
     mnk, _ = b.indices()
     X = torch.from_numpy(np.ascontiguousarray(synth.random_block(mnk, nvec, 1234).T)).to(dev)
     Y = torch.empty_like(X)
@@ -455,7 +562,7 @@ def main(argv=None):
         peak_tf = FP64_PEAK_TFLOPS if elem == 8 else FP32_VALU_PEAK_TFLOPS
         compute_kind = "alu"
     else:
-        peak_tf = FP64_PEAK_TFLOPS if elem == 8 else FP32_MFMA_PEAK_TFLOPS
+        peak_tf = FP64_PEAK_TFLOPS if elem == 8 else FP32_MFMA_PEAK_TFLOPS if elem == 4 else BF16_MFMA_PEAK_TFLOPS
         compute_kind = "mfma"
     ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
     traffic = load_traffic(dom, nvec, w.name)
@@ -481,7 +588,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.prec],
         "data": "synthetic",
         "config": {"workload": w.name, "L": b.L, "block": nvec, "grid": f"{b.n_t1}x{b.n_t2}x{b.n_r}",
                    "modes": b.n_modes, "R": w.R, "tau": w.tau, "alpha": round(w.alpha, 6), "ecut": w.ecut,
@@ -489,27 +596,47 @@ def main(argv=None):
         "roofline": roof,
         "stages": stage_info,
     }
-    if args.eig:
-        line["eigensolve"] = time_to_eigenpairs(b, w, torch, solvers=tuple(args.eig_solvers.split(",")))
-        line["density"] = density_leg(b, w, torch)
-    if args.batched != "none":
-        structs = list(range(8)) if args.batched == "all" else [int(x) for x in args.batched.split(",")]
-        line["batched"] = batched_leg(torch, structs)
+    if args.other_precisions:
+        other = {}
+        for p in ("fp64", "fp32", "bf16"):
+            if p == args.prec:
+                continue
+            for _ in range(3):
+                b.apply_H(X, Y, prec=p)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(args.steps):
+                b.apply_H(X, Y, prec=p)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - ta) / args.steps
+            ms3, _ = b.profile_apply(X, Y, prec=p, nrep=3)
+            other[p] = dict(ms_per_step=round(1e3 * dt, 4), vec_applies_per_s=round(nvec / dt, 1),
+                            stages_ms={s: round(m, 4) for s, m in zip(STAGES, ms3)})
+            print(f"[bench] {p}: {1e3 * dt:.3f} ms/step", file=sys.stderr, flush=True)
+        line["hx_other_precisions"] = other
     if args.learned != "none":
         if args.learned in ("same", w.name):
             lw, lb = w, b
         else:
             lw = synth.workload(args.learned)
-            lb = helic.Basis.from_workload(lw)
-            t1, t2, r, _ = lb.grid()
-            lb.set_potential(torch.from_numpy(synth.potential_at(
-                t1, t2, r, lw.tau, lw.alpha, synth.atoms_for(lw.structure, lw.seed, lw.tau, lw.R))).cuda())
+            lb = load_problem(lw)
         line["learned_preconditioner"] = learned_leg(torch, lb, lw)
         if lb is not b:
             lb.close()
+    line["density"] = density_leg(b, w, torch)
+    b.close()
+    del X, Y
+    if args.eig:
+        ew = synth.workload(args.eig_workload)
+        eb = load_problem(ew)
+        line["eigensolve"] = time_to_eigenpairs(eb, ew, torch, solvers=tuple(args.eig_solvers.split(",")),
+                                                table=args.eig_table or None)
+        eb.close()
+    if args.batched != "none":
+        structs = list(range(8)) if args.batched == "all" else [int(x) for x in args.batched.split(",")]
+        line["batched"] = batched_leg(torch, structs, extra=bool(args.batched_extra))
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
-    b.close()
     print(json.dumps(line), flush=True)
     return 0
 
