@@ -103,17 +103,18 @@ class Basis:
         sqrt(N/(pi tau)) J_{nN}(b r/R) / (R J_{nN+1}(b)) (App. B)."""
         rr = self.r if r is None else np.asarray(r, dtype=np.float64)
         k = np.asarray(k, dtype=np.int64)
-        b = bessel_zeros(n, int(k.max()) if k.size else 0)[k - 1] if k.size else np.zeros(0)
         p = n * self.ncyc
+        b = bessel_zeros(p, int(k.max()) if k.size else 0)[k - 1] if k.size else np.zeros(0)
         c = math.sqrt(self.ncyc / (math.pi * self.tau)) / (self.R * sp.jv(p + 1, b))
         return sp.jv(p, np.outer(rr, b) / self.R) * c[None, :]
 
 
-def kinetic_diagonal(bz, m, n, R, tau, alpha, eta):
-    """kappa = (1/2)[(b/R)^2 + (2 pi/tau)^2 (m - alpha n - eta)^2] (nu = 0)."""
+def kinetic_diagonal(bz, m, n, R, tau, alpha, eta, ncyc=1):
+    """kappa = (1/2)[(b/R)^2 + (2 pi/tau)^2 (m - alpha n N - eta)^2] (nu = 0,
+    cyclic order N)."""
     m = np.asarray(m, dtype=np.float64)
     n = np.asarray(n, dtype=np.float64)
-    return 0.5 * ((np.asarray(bz) / R) ** 2 + (2.0 * math.pi / tau) ** 2 * (m - alpha * n - eta) ** 2)
+    return 0.5 * ((np.asarray(bz) / R) ** 2 + (2.0 * math.pi / tau) ** 2 * (m - alpha * n * ncyc - eta) ** 2)
 
 
 def kinetic_alg5(bz, m, n, R, tau, alpha, eta, nu=0, ncyc=1):
@@ -134,10 +135,13 @@ def make_basis(R, tau, alpha, ecut, eta=0.0, m_max=-1, n_max=-1, k_max=-1,
                n_t1=0, n_t2=0, n_r=0, ncyc=1, nu=0) -> Basis:
     """Enumerate the cutoff-masked index set and build the grid.
 
-    Raises ValueError on unsupported or inconsistent parameters and on a
-    cutoff tie (some |kappa - E_cut| < 1e-10)."""
-    if ncyc != 1 or nu != 0:
-        raise ValueError("only cyclic order 1 and nu = 0 are handled")
+    Cyclic order N >= 1 (Sec. 2.3): mode (m, n) has the angular factor
+    exp(i 2 pi (m theta1 + n N theta2)), the Bessel order |n| N and its
+    zeros, and theta2 spans [0, 1/N).  Raises ValueError on unsupported or
+    inconsistent parameters (nu != 0) and on a cutoff tie (some |kappa -
+    E_cut| < 1e-10)."""
+    if ncyc < 1 or nu != 0:
+        raise ValueError("only cyclic order >= 1 with nu = 0 is handled")
     if not (R > 0 and tau > 0 and ecut > 0 and 0.0 <= alpha < 1.0 and -0.5 <= eta < 0.5):
         raise ValueError("invalid parameters")
     grid_given = n_t1 > 0 and n_t2 > 0
@@ -152,7 +156,7 @@ def make_basis(R, tau, alpha, ecut, eta=0.0, m_max=-1, n_max=-1, k_max=-1,
     # |n| limit from the smallest radial energy j_{|n|,1}^2 / (2 R^2).
     if n_max < 0:
         n_lim = 0
-        while 0.5 * (bessel_zeros(n_lim + 1, 1)[0] / R) ** 2 <= ecut + TIE_TOL:
+        while 0.5 * (bessel_zeros((n_lim + 1) * ncyc, 1)[0] / R) ** 2 <= ecut + TIE_TOL:
             n_lim += 1
     else:
         n_lim = n_max
@@ -161,7 +165,7 @@ def make_basis(R, tau, alpha, ecut, eta=0.0, m_max=-1, n_max=-1, k_max=-1,
         # enough zeros so that the radial energy alone exceeds the cutoff
         cnt = 8
         while True:
-            z = bessel_zeros(n, cnt)
+            z = bessel_zeros(n * ncyc, cnt)
             if 0.5 * (z[-1] / R) ** 2 > ecut + 1.0 or (k_max > 0 and cnt >= k_max):
                 break
             cnt *= 2
@@ -169,12 +173,12 @@ def make_basis(R, tau, alpha, ecut, eta=0.0, m_max=-1, n_max=-1, k_max=-1,
             z = z[:k_max]
         # m range allowed by the axial energy alone
         span = math.sqrt(2.0 * ecut) / two_pi_tau + 1.0
-        c0 = alpha * n + eta
+        c0 = alpha * n * ncyc + eta
         m_lo, m_hi = int(math.floor(c0 - span)), int(math.ceil(c0 + span))
         if m_max >= 0:
             m_lo, m_hi = max(m_lo, -m_max), min(m_hi, m_max)
         for m in range(m_lo, m_hi + 1):
-            kap = kinetic_diagonal(z, m, n, R, tau, alpha, eta)
+            kap = kinetic_diagonal(z, m, n, R, tau, alpha, eta, ncyc)
             if np.any(np.abs(kap - ecut) < TIE_TOL):
                 raise ValueError("cutoff tie: a kinetic energy equals E_cut to 1e-10")
             for k in np.nonzero(kap <= ecut)[0]:
@@ -210,4 +214,4 @@ def basis_for(workload) -> Basis:
     """Basis of a ``synth.Workload`` (duck-typed: reads its attributes)."""
     w = workload
     return make_basis(w.R, w.tau, w.alpha, w.ecut, eta=w.eta, m_max=w.m_max, n_max=w.n_max,
-                      k_max=w.k_max, n_t1=w.n_t1, n_t2=w.n_t2, n_r=w.n_r)
+                      k_max=w.k_max, n_t1=w.n_t1, n_t2=w.n_t2, n_r=w.n_r, ncyc=getattr(w, "ncyc", 1))

@@ -8,5 +8,5 @@ arithmetic (no basis functions, quadrature, transforms or Hamiltonian): both
 the CPU oracle and the GPU library receive what is generated here as input.
 """
 from .configs import Workload, WORKLOADS, workload  # noqa: F401
-from .structures import atoms_for, potential_at, Atom  # noqa: F401
+from .structures import atoms_for, potential_at, cyclic_images, Atom  # noqa: F401
 from .blocks import random_block  # noqa: F401

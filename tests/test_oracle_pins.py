@@ -221,6 +221,49 @@ def test_mode_pair_assembly_equals_the_basis_matrix_form(tiny):
     assert np.max(np.abs(oh.dense_dft_modes(b2, V2) - oh.dense_explicit(b2, V2))) < 1e-13
 
 
+@pytest.mark.parametrize("ncyc", [2, 3])
+def test_cyclic_operator_is_the_symmetric_sector_of_the_order_one_operator(ncyc):
+    """Cyclic order N (Sec. 2.3, App. B; nu = 0): for an N-fold symmetric
+    potential the order-1 operator does not couple angular index n' across
+    residues mod N, and its n' = N n sector is the order-N operator: same
+    index set (Bessel order N|n|, kinetic energy with alpha N n), and entry
+    for entry the same matrix, although the order-N basis lives on the wedge
+    theta2 in [0, 1/N) with its own normalisation sqrt(N / (pi tau)) and
+    wedge quadrature weights.  Eigenvalues therefore agree too."""
+    n1, n2, nr = 12, 8, 32
+    kw = dict(R=6.5, tau=5.0, alpha=0.15, ecut=7.0, eta=0.2, n_t1=n1, n_r=nr)
+    bN = ob.make_basis(n_t2=n2, ncyc=ncyc, **kw)
+    b1 = ob.make_basis(n_t2=ncyc * n2, ncyc=1, **kw)
+    motif = synth.atoms_for("helix6", 8, bN.tau, bN.R)[:2]
+    atoms = synth.cyclic_images(motif, ncyc)
+    V1 = synth.potential_at(b1.theta1, b1.theta2, b1.r, b1.tau, b1.alpha, atoms)
+    VN = synth.potential_at(bN.theta1, bN.theta2, bN.r, bN.tau, bN.alpha, atoms)
+    np.testing.assert_allclose(bN.theta2, b1.theta2[:n2], rtol=0, atol=1e-16)
+    H1 = oh.dense_explicit(b1, V1)
+    HN = oh.dense_explicit(bN, VN)
+    sector = np.nonzero(b1.mnk[:, 1] % ncyc == 0)[0]
+    other = np.nonzero(b1.mnk[:, 1] % ncyc != 0)[0]
+    assert np.max(np.abs(H1[np.ix_(sector, other)])) < 1e-13 * np.max(np.abs(H1))
+    # the sector's index set is the order-N set with n' = N n
+    key1 = {(int(m), int(n) // ncyc, int(k)): i for i, (m, n, k) in enumerate(b1.mnk[sector])}
+    keyN = [(int(m), int(n), int(k)) for m, n, k in bN.mnk]
+    assert sorted(key1) == sorted(keyN)
+    perm = np.array([sector[key1[t]] for t in keyN])
+    np.testing.assert_allclose(bN.kappa, b1.kappa[perm], rtol=1e-15)
+    assert np.max(np.abs(HN - H1[np.ix_(perm, perm)])) < 1e-13
+    m, n = bN.mnk[:, 0], bN.mnk[:, 1]
+    alg5 = ob.kinetic_alg5(bN.bzero, m, n, bN.R, bN.tau, bN.alpha, bN.eta, ncyc=ncyc)
+    np.testing.assert_allclose(alg5.real, bN.kappa, rtol=1e-13)
+    assert np.max(np.abs(alg5.imag)) < 1e-13
+    lamN = oh.lowest(HN, 10)[0]
+    lam1 = np.linalg.eigvalsh(H1[np.ix_(sector, sector)])[:10]
+    assert np.max(np.abs(lamN - lam1)) < 1e-12
+    # the mode-B form and the matrix-free apply agree with mode A at order N
+    assert np.max(np.abs(oh.dense_dft(bN, VN) - HN)) < 1e-13
+    X = synth.random_block(bN.mnk, 3, 2)
+    assert np.max(np.abs(oh.apply(bN, VN, X) - HN @ X)) < 1e-13
+
+
 def test_matrix_free_apply_is_hermitian():
     b = small_basis()
     atoms = synth.atoms_for("helix6", 9, b.tau, b.R)
@@ -486,13 +529,15 @@ def test_gradient_of_one_function_closed_forms(tiny):
         assert np.max(np.abs(er - want)) < 1e-7 * np.max(np.abs(want))
 
 
-def test_cartesian_gradient_against_finite_differences():
+@pytest.mark.parametrize("ncyc", [1, 2])
+def test_cartesian_gradient_against_finite_differences(ncyc):
     """The chain rule of eq. Cartesian_Derivatives against central differences
     of the field evaluated at Cartesian points (x, y, z) mapped back to
     helical coordinates: theta1 = z / tau, phi = atan2(y, x),
-    theta2 = phi / (2 pi) - alpha theta1, r = sqrt(x^2 + y^2)."""
+    theta2 = phi / (2 pi) - alpha theta1, r = sqrt(x^2 + y^2); also at cyclic
+    order 2 (angular factor exp(i 2 pi n N theta2), Bessel order |n| N)."""
     from oracle import gradient as og
-    b = small_basis()
+    b = small_basis(ncyc=ncyc)
     rng = np.random.default_rng(8)
     idx = rng.choice(b.L, 6, replace=False)
     coef = rng.standard_normal(6) + 1j * rng.standard_normal(6)
@@ -506,7 +551,7 @@ def test_cartesian_gradient_against_finite_differences():
         s = 0.0
         for i, c in zip(idx, coef):
             m, n, k = (int(t) for t in b.mnk[i])
-            s += c * np.exp(2j * math.pi * (m * t1 + n * t2)) * b.xi(n, np.array([k]), np.array([rr]))[0, 0]
+            s += c * np.exp(2j * math.pi * (m * t1 + n * ncyc * t2)) * b.xi(n, np.array([k]), np.array([rr]))[0, 0]
         return s
 
     ex, ey, ez = og.cartesian(b, *og.helical_derivatives(b, x))
