@@ -8,15 +8,16 @@
  * is (Alg. 5, eqs. Simplify_2 and g_mnk)
  *
  *     (H x)_i = kappa_i x_i + [Fwd(V * Inv(x))]_i ,
- *     kappa_i = 1/2 [ (b_k^{|n|}/R)^2 + (2 pi/tau)^2 (m - alpha n - eta)^2 ],
+ *     kappa_i = 1/2 [ (b_k^{|n|N}/R)^2 + (2 pi/tau)^2 (m - alpha N n - eta)^2 ],
  *
  * with Inv the inverse basis transform (Alg. 1 and 2: radial sums per angular
  * mode, then a 2D inverse DFT per radius), V the real potential sampled on the
  * grid and Fwd the quadrature forward transform (Alg. 3 and 4: a 2D DFT per
- * radius, then weighted radial sums).  Basis functions are
- * F_{m,n,k} = c_{nk} exp(i 2 pi (m theta1 + n theta2)) J_n(b_k^{|n|} r/R),
- * c_{nk} = 1/(sqrt(pi tau) R J_{n+1}(b_k^{|n|})) (Sec. 2.3, App. B), kept
- * when kappa_i <= E_cut (Sec. 3.2).
+ * radius, then weighted radial sums).  For cyclic order N (an N-fold
+ * symmetric structure; theta2 spans the wedge [0, 1/N)) basis functions are
+ * F_{m,n,k} = c_{nk} exp(i 2 pi (m theta1 + n N theta2)) J_{nN}(b_k^{|n|N} r/R),
+ * c_{nk} = sqrt(N/(pi tau)) / (R J_{nN+1}(b_k^{|n|N})) (Sec. 2.3, App. B),
+ * kept when kappa_i <= E_cut (Sec. 3.2).
  *
  * Conventions shared by all entry points
  * - Every pointer argument documented "device" must point to memory of the
@@ -50,7 +51,7 @@ typedef struct helic_basis_s* helic_basis;
 typedef enum {
   HELIC_OK = 0,
   HELIC_ERR_INVALID = 1,      /* bad argument (null pointer, size, range)         */
-  HELIC_ERR_UNSUPPORTED = 2,  /* cyclic order != 1, nu != 0, unknown precision     */
+  HELIC_ERR_UNSUPPORTED = 2,  /* cyclic index nu != 0, unknown precision          */
   HELIC_ERR_GRID = 3,         /* grid too small to resolve the index set           */
   HELIC_ERR_NOMEM = 4,        /* device or host allocation failed                  */
   HELIC_ERR_HIP = 5,          /* a HIP runtime or library call failed              */
@@ -73,10 +74,10 @@ typedef struct {
   double R;       /* cylinder radius, Bohr (> 0); Dirichlet wall at r = R        */
   double tau;     /* axial period of the screw operation, Bohr (> 0)             */
   double alpha;   /* twist: rotation of 2*pi*alpha per period, 0 <= alpha < 1    */
-  int32_t ncyc;   /* cyclic order; must be 1                                      */
+  int32_t ncyc;   /* cyclic order N, 1..64; theta2 in [0, 1/N)                   */
   double ecut;    /* kinetic-energy cutoff, Ha (> 0), inclusive                  */
   double eta;     /* helical Bloch parameter, -1/2 <= eta < 1/2                  */
-  int32_t nu;     /* cyclic Bloch index; must be 0                               */
+  int32_t nu;     /* cyclic Bloch index; must be 0 (else HELIC_ERR_UNSUPPORTED)  */
   int32_t m_max;  /* clamp |m| <= m_max (-1: what the theta1 grid resolves)      */
   int32_t n_max;  /* clamp |n| <= n_max (-1: what the theta2 grid resolves)      */
   int32_t k_max;  /* clamp k <= k_max   (-1: none)                               */
@@ -85,11 +86,11 @@ typedef struct {
   int32_t n_r;    /* radial Gauss-Jacobi nodes; 0: 4 * (largest k kept)          */
 } helic_params;
 
-/* Build the basis on the host: Bessel zeros b_k^{|n|} (App. B), the index
+/* Build the basis on the host: Bessel zeros b_k^{|n|N} (App. B), the index
  * set {(m,n,k): kappa <= E_cut} under the clamps (Sec. 3.2), the grid
- * theta1_i = i/n_t1, theta2_j = j/n_t2 and the n_r-point Gauss-Jacobi rule for
- * int_0^1 f(q) q dq (Sec. 3.1, App. D), and the radial tables xi_{|n|,k}(r_l)
- * and (2 pi tau) omega_l xi_{|n|,k}(r_l) (Alg. 1, Alg. 3).  Automatic grids
+ * theta1_i = i/n_t1, theta2_j = j/(N n_t2) and the n_r-point Gauss-Jacobi rule
+ * for int_0^1 f(q) q dq (Sec. 3.1, App. D), and the radial tables
+ * xi_{|n|,k}(r_l) and (2 pi tau / N) omega_l xi_{|n|,k}(r_l) (Alg. 1, Alg. 3).  Automatic grids
  * use the smallest 2,3,5-smooth sizes >= 2 max|m| + 2 and >= 2 max|n| + 2.
  * Synchronous; allocates no device memory (device tables are uploaded by the
  * first call that needs them).  *out receives a handle owned by the caller,
@@ -159,7 +160,7 @@ helic_status helic_transform_forward(helic_basis h, const double* g, double* X, 
  * grad (device) receives three blocks of nvec real-space arrays of complex
  * doubles (n_t1*n_t2*n_r each, the inverse transform's layout): with
  * cartesian = 0 the helical derivatives E_theta1 (transform of the
- * coefficients times i 2 pi m), E_theta2 (times i 2 pi n) and E_r (the
+ * coefficients times i 2 pi m), E_theta2 (times i 2 pi N n) and E_r (the
  * transform with d xi_{|n|,k} / dr as radial functions, eqs. E_r and B_r);
  * with cartesian = 1 the Cartesian E_x, E_y, E_z from them by eq.
  * Cartesian_Derivatives.  FP64.  The first call uploads the derivative

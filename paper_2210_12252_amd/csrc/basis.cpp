@@ -54,8 +54,8 @@ std::vector<int32_t> radix_plan(int n) {
 
 helic_status build(helic_basis_s* h) {
   const helic_params& p = h->p;
-  if (p.ncyc != 1 || p.nu != 0)
-    return fail(HELIC_ERR_UNSUPPORTED, "only cyclic order 1 and nu = 0 are supported");
+  if (p.ncyc < 1 || p.ncyc > 64) return fail(HELIC_ERR_INVALID, "cyclic order must be 1..64");
+  if (p.nu != 0) return fail(HELIC_ERR_UNSUPPORTED, "only the cyclic Bloch index nu = 0 is supported");
   if (!(p.R > 0) || !(p.tau > 0) || !(p.ecut > 0) || !(p.alpha >= 0.0 && p.alpha < 1.0) ||
       !(p.eta >= -0.5 && p.eta < 0.5) || !std::isfinite(p.R) || !std::isfinite(p.tau) ||
       !std::isfinite(p.ecut))
@@ -69,24 +69,27 @@ helic_status build(helic_basis_s* h) {
     if (n_max < 0) n_max = (p.n_t2 - 1) / 2;
   }
   const double R = p.R, tau = p.tau, ecut = p.ecut, alpha = p.alpha, eta = p.eta;
+  // cyclic order: mode (m, n) carries exp(i 2 pi (m theta1 + n N theta2)) and
+  // the Bessel order |n| N (Sec. 2.3); theta2 spans [0, 1/N)
+  const int N = p.ncyc;
   const double w = 2.0 * PI / tau;
   const double xmax = R * std::sqrt(2.0 * ecut);   // largest admissible zero
   int g_lim = n_max;
   if (g_lim < 0) {
     g_lim = 0;
-    while (bessel_zeros(g_lim + 1, 1)[0] <= xmax * (1.0 + 1e-15)) ++g_lim;
+    while (bessel_zeros((g_lim + 1) * N, 1)[0] <= xmax * (1.0 + 1e-15)) ++g_lim;
   }
   h->modes.clear();
   h->groups.clear();
   int64_t row = 0;
   for (int g = 0; g <= g_lim; ++g) {
-    // zeros of J_g below xmax (at most k_max of them)
+    // zeros of J_{g N} below xmax (at most k_max of them)
     int cnt = (int)(xmax / PI) + 4;
     if (p.k_max > 0) cnt = std::min(cnt, p.k_max);
-    std::vector<double> z = bessel_zeros(g, cnt);
+    std::vector<double> z = bessel_zeros(g * N, cnt);
     while (p.k_max <= 0 && z.back() <= xmax) {
       cnt *= 2;
-      z = bessel_zeros(g, cnt);
+      z = bessel_zeros(g * N, cnt);
     }
     Group grp;
     grp.g = g;
@@ -96,11 +99,11 @@ helic_status build(helic_basis_s* h) {
     const double span = std::sqrt(2.0 * ecut) / w + 1.0;
     for (int sgn = 0; sgn < (g == 0 ? 1 : 2); ++sgn) {
       const int n = sgn == 0 ? g : -g;
-      const double c0 = alpha * n + eta;
+      const double c0 = alpha * n * N + eta;
       int mlo = (int)std::floor(c0 - span), mhi = (int)std::ceil(c0 + span);
       if (m_max >= 0) { mlo = std::max(mlo, -m_max); mhi = std::min(mhi, m_max); }
       for (int m = mlo; m <= mhi; ++m) {
-        const double ax = w * (m - alpha * n - eta);
+        const double ax = w * (m - alpha * n * N - eta);
         int K = 0;
         for (size_t k = 0; k < z.size(); ++k) {
           const double kap = 0.5 * ((z[k] / R) * (z[k] / R) + ax * ax);
@@ -164,7 +167,7 @@ helic_status build(helic_basis_s* h) {
       md.bin1 = ((md.m % h->n_t1) + h->n_t1) % h->n_t1;
       md.bin2 = ((md.n % h->n_t2) + h->n_t2) % h->n_t2;
       has_row1[md.bin1] = 1;
-      const double ax = w * (md.m - alpha * md.n - eta);
+      const double ax = w * (md.m - alpha * md.n * N - eta);
       for (int k = 0; k < md.K; ++k) {
         const int64_t r = md.row0 + k;
         h->mnk[3 * r] = md.m; h->mnk[3 * r + 1] = md.n; h->mnk[3 * r + 2] = k + 1;
@@ -182,7 +185,7 @@ helic_status build(helic_basis_s* h) {
   h->theta1.resize(h->n_t1);
   h->theta2.resize(h->n_t2);
   for (int i = 0; i < h->n_t1; ++i) h->theta1[i] = (double)i / h->n_t1;
-  for (int j = 0; j < h->n_t2; ++j) h->theta2[j] = (double)j / h->n_t2;
+  for (int j = 0; j < h->n_t2; ++j) h->theta2[j] = (double)j / ((double)N * h->n_t2);
   h->q.resize(h->n_r);
   h->wq.resize(h->n_r);
   gauss_jacobi01(h->n_r, h->q.data(), h->wq.data());
@@ -212,11 +215,11 @@ helic_status build(helic_basis_s* h) {
   h->tab_fwd.assign(fwd_total, 0.0);
   h->tab_inv16.assign(inv16_total * 4, 0);
   h->tab_fwd16.assign(fwd16_total * 4, 0);
-  const double norm0 = 1.0 / (std::sqrt(PI * tau) * R);
+  const double norm0 = std::sqrt((double)N / (PI * tau)) / R;
   std::vector<double> jv(2);
   for (const Group& grp : h->groups) {
     const int nks = (grp.Kmax + 3) / 4;
-    const int g = grp.g;
+    const int g = grp.g * N;   // Bessel order of the group
     std::vector<double> xi((size_t)nr * grp.Kmax);   // xi[l * Kmax + k]
     std::vector<double> dxi((size_t)nr * grp.Kmax);  // d xi / dr
     std::vector<double> buf(g + 2), buf2(g + 2);
@@ -242,7 +245,7 @@ helic_status build(helic_basis_s* h) {
             h->tab_dinv[grp.tinv_off + ((int64_t)t * nks + s) * FRAG + ln] = dxi[(size_t)l * grp.Kmax + k];
           }
         }
-    const double pref = 2.0 * PI * tau;   // 2 pi tau / N with N = 1
+    const double pref = 2.0 * PI * tau / N;   // 2 pi tau / N (Alg. 3)
     for (int t = 0; t < (grp.Kmax + 15) / 16; ++t)
       for (int s = 0; s < nrs; ++s)
         for (int ln = 0; ln < FRAG; ++ln) {

@@ -556,7 +556,7 @@ k_scale_imag(const double* __restrict__ X, int64_t ldx, double* __restrict__ Y, 
 // E_z = (E_theta1 - alpha E_theta2) / tau.
 __global__ void __launch_bounds__(NT)
 k_cartesian(double* __restrict__ G, int nv, int n1, int n2, int n_r, const double* __restrict__ rg, double alpha,
-            double tau) {
+            double tau, int ncyc) {
   const int64_t npts = (int64_t)n1 * n2 * n_r;
   double2* g = reinterpret_cast<double2*>(G);
   const int v = blockIdx.y;
@@ -564,7 +564,7 @@ k_cartesian(double* __restrict__ G, int nv, int n1, int n2, int n_r, const doubl
     const int l = (int)(p % n_r);
     const int64_t a = p / n_r;
     const int i2 = (int)(a % n2), i1 = (int)(a / n2);
-    const double phi = 2.0 * PI_D * (alpha * ((double)i1 / n1) + (double)i2 / n2);
+    const double phi = 2.0 * PI_D * (alpha * ((double)i1 / n1) + (double)i2 / ((double)ncyc * n2));
     double sn, cs;
     sincos(phi, &sn, &cs);
     const double ir = 1.0 / (2.0 * PI_D * rg[l]);
@@ -1694,7 +1694,7 @@ helic_status helic_gradient(helic_basis h, const double* X, int64_t ldx, int32_t
     std::vector<double> fac(2 * (size_t)h->L), rg(h->n_r);
     for (int64_t i = 0; i < h->L; ++i) {
       fac[i] = 2.0 * PI_D * h->mnk[3 * i];
-      fac[h->L + i] = 2.0 * PI_D * h->mnk[3 * i + 1];
+      fac[h->L + i] = 2.0 * PI_D * h->p.ncyc * h->mnk[3 * i + 1];   // theta2 derivative: i 2 pi N n
     }
     for (int l = 0; l < h->n_r; ++l) rg[l] = h->p.R * h->q[l];
     if (!d->tdinv64 && (s = upload(h->tab_dinv, &d->tdinv64))) return s;
@@ -1730,7 +1730,7 @@ helic_status helic_gradient(helic_basis h, const double* X, int64_t ldx, int32_t
   if ((s = inverse_transform(h, X, ldx, grad + (int64_t)2 * nvec * npts * 2, nvec, st, d->probs_dr))) return s;
   if (cartesian) {
     hipLaunchKernelGGL(k_cartesian, dim3((unsigned)std::min<int64_t>(1024, (npts + NT - 1) / NT), nvec), dim3(NT), 0,
-                       st, grad, nvec, h->n_t1, h->n_t2, h->n_r, d->rgrid, h->p.alpha, h->p.tau);
+                       st, grad, nvec, h->n_t1, h->n_t2, h->n_r, d->rgrid, h->p.alpha, h->p.tau, h->p.ncyc);
     HIP_TRY(hipGetLastError());
   }
   return HELIC_OK;

@@ -101,13 +101,27 @@ def test_auto_grid_and_bloch_shift_match_oracle():
         b.close()
 
 
+@pytest.mark.parametrize("ncyc", [2, 3, 6])
+def test_cyclic_index_set_grid_and_tables_match_oracle(ncyc):
+    """Cyclic order N (nu = 0): the index set (Bessel order |n| N), kinetic
+    energies (alpha N n), the wedge grid theta2 = j / (N n_t2) and the radial
+    weights agree with the oracle, automatic grid and given grid."""
+    for grid in ({}, dict(n_t1=16, n_t2=12, n_r=40)):
+        w = synth.Workload(name="cyc", R=7.5, tau=5.5, alpha=0.13, ecut=9.0, eta=0.17, ncyc=ncyc, **grid)
+        b, _ = _compare_with_oracle(w)
+        b.close()
+
+
 def test_parameter_errors():
     with pytest.raises(helic.HelicError) as e:
         helic.basis_create(R=-1.0, tau=5.0, alpha=0.0, ecut=5.0)
     assert e.value.status == helic.ERR_INVALID
-    with pytest.raises(helic.HelicError) as e:
-        helic.basis_create(R=5.0, tau=5.0, alpha=0.0, ecut=5.0, ncyc=2)
+    with pytest.raises(helic.HelicError) as e:   # cyclic Bloch index nu != 0: not built
+        helic.basis_create(R=5.0, tau=5.0, alpha=0.0, ecut=5.0, ncyc=2, nu=1)
     assert e.value.status == helic.ERR_UNSUPPORTED
+    with pytest.raises(helic.HelicError) as e:
+        helic.basis_create(R=5.0, tau=5.0, alpha=0.0, ecut=5.0, ncyc=0)
+    assert e.value.status == helic.ERR_INVALID
     with pytest.raises(helic.HelicError) as e:
         helic.basis_create(R=5.0, tau=5.0, alpha=0.0, ecut=5.0, eta=0.5)
     assert e.value.status == helic.ERR_INVALID
