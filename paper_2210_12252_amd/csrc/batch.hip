@@ -125,7 +125,8 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
     if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "every problem needs a potential first");
     if (h->n_t1 != h0->n_t1 || h->n_t2 != h0->n_t2 || h->n_r != h0->n_r)
       return fail(HELIC_ERR_GRID, "problems of a batch must share the grid");
-    if (h->dev->fast_mpad != h0->dev->fast_mpad || h->dev->grid_var != h0->dev->grid_var ||
+    if (h->dev->fast_mpad != h0->dev->fast_mpad || h->dev->fast_ntf != h0->dev->fast_ntf ||
+        h->dev->grid_var != h0->dev->grid_var ||
         h->dev->device != h0->dev->device)
       return fail(HELIC_ERR_GRID, "problems of a batch must share the angular kernel variant and device");
   }

@@ -896,11 +896,11 @@ helic_status set_fast_limits() {
 
 // Resident workgroups of the chosen angular kernel on the whole device.
 template <typename T, typename E>
-int fast_slots(int n2, int mpad, int ncu) {
+int fast_slots(int n2, int mpad, int ntf, int ncu) {
   int nb = 0;
   const size_t lds = fast_lds_bytes<T>(n2, mpad);
 #define HELIC_OCC_CASE(N2_, MP_, NTF_)                                                                 \
-  if (n2 == N2_ && mpad == MP_)                                                                       \
+  if (n2 == N2_ && mpad == MP_ && ntf == NTF_)                                                        \
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_fast<T, E, N2_, MP_, NTF_>, NTF_, lds);
   HELIC_OCC_CASE(16, 12, 256)
   HELIC_OCC_CASE(16, 16, 256)
@@ -941,7 +941,7 @@ helic_status launch_fast(const LaunchSet& ls, E* gh, int nvec, hipStream_t st, h
   const dim3 grid(angular_grid_size(ls, nvec, ipw));
   const size_t lds = fast_lds_bytes<T>(ls.n_t2, ls.fast_mpad);
 #define HELIC_FAST_CASE(N2_, MP_, NTF_)                                                                   \
-  if (ls.n_t2 == N2_ && ls.fast_mpad == MP_) {                                                          \
+  if (ls.n_t2 == N2_ && ls.fast_mpad == MP_ && ls.fast_ntf == NTF_) {                                    \
     HELIC_LAUNCH((k_angular_fast<T, E, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, e0, e1, gh, ls.nprob, nvec, \
                  ls.n_r, probs, tw2, ipw);                                                              \
     HIP_TRY(hipGetLastError());                                                                         \
@@ -1248,9 +1248,9 @@ helic_status ensure_device(helic_basis_s* h) {
     if ((s = set_fast_limits<double, cplx<double>>()) || (s = set_fast_limits<float, cplx<float>>()) ||
         (s = set_fast_limits<float, bf16x2>()))
       return s;
-    d->ang_slots64 = fast_slots<double, cplx<double>>(h->n_t2, d->fast_mpad, ncu);
-    d->ang_slots32 = fast_slots<float, cplx<float>>(h->n_t2, d->fast_mpad, ncu);
-    d->ang_slots16 = fast_slots<float, bf16x2>(h->n_t2, d->fast_mpad, ncu);
+    d->ang_slots64 = fast_slots<double, cplx<double>>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu);
+    d->ang_slots32 = fast_slots<float, cplx<float>>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu);
+    d->ang_slots16 = fast_slots<float, bf16x2>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu);
     const int rs = ang_rs(h->n_t2);
     std::vector<int32_t> mp(h->modes.size());
     for (size_t i = 0; i < h->modes.size(); ++i) {
@@ -1334,6 +1334,7 @@ LaunchSet launch_set(const helic_basis_s* h) {
   }
   ls.lds_ang64 = angular_lds_bytes(h, sizeof(double));
   ls.fast_mpad = d->fast_mpad;
+  ls.fast_ntf = d->fast_ntf;
   ls.grid_var = d->grid_var;
   ls.vchunk = d->vchunk;
   ls.ang_slots64 = d->ang_slots64;
