@@ -141,7 +141,7 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
   size_t lds_inv = 0, lds_fwd = 0, lds_ang = 0, lds_fwd_plain = 0, lds_fwd32 = 0, lds_inv16 = 0, lds_fwd16 = 0;
   bool kx64 = true, kx32 = true;
   int tm64 = 4, tm32 = 4;
-  int fwd_tmax_plain = 4, inv_ks = 8;
+  int fwd_tmax_plain = 4, inv_ks = 8, max_colpad = 0, tm16 = 8;
   bool all_pf = true, pf_wide = false;
   for (int p = 0; p < nprob; ++p) {
     const helic_basis_s* h = bases[p];
@@ -157,6 +157,8 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
     const LaunchSet one = launch_set(h);
     lds_inv = std::max(lds_inv, one.lds_inv64);
     lds_inv16 = std::max(lds_inv16, one.lds_inv16);
+    max_colpad = std::max(max_colpad, one.max_colpad);
+    tm16 = std::max(tm16, one.fwd_tm16);
     lds_fwd16 = std::max(lds_fwd16, one.lds_fwd16);
     lds_fwd = std::max(lds_fwd, one.lds_fwd64);
     lds_fwd32 = std::max(lds_fwd32, one.lds_fwd32);
@@ -191,6 +193,8 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
   b->ls.nprob = nprob;
   b->ls.lds_inv16 = lds_inv16;
   b->ls.lds_fwd16 = lds_fwd16;
+  b->ls.max_colpad = max_colpad;
+  b->ls.fwd_tm16 = tm16;
   b->ls.lds_inv64 = lds_inv;
   // the pipelined radial forward variant only if every problem fits it
   b->ls.inv_ks = inv_ks;

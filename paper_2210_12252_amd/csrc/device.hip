@@ -1065,7 +1065,7 @@ size_t lds_inv16_bytes(int max_kpad, int max_colpad) {
   return (size_t)max_colpad * bf16_col_stride(16 * ((max_kpad + 15) / 16)) * sizeof(uint16_t);
 }
 size_t lds_fwd16_bytes(int max_colpad) {
-  return (size_t)max_colpad * bf16_col_stride(FWD16_RC) * sizeof(uint16_t);
+  return fwd16_table_off(max_colpad) + (size_t)FWD16_KT * (FWD16_RC / 16) * 64 * sizeof(uint64_t);
 }
 
 void launch_radial_inverse_bf16(int kt16, int nwg, size_t lds, hipStream_t st, const double* X, int64_t ldx,
@@ -1082,11 +1082,26 @@ void launch_radial_inverse_bf16(int kt16, int nwg, size_t lds, hipStream_t st, c
                  groups, probs);
 }
 
-void launch_radial_forward_bf16(int nwg, size_t lds, hipStream_t st, const bf16x2* gh, const double* X, int64_t ldx,
-                                double* Y, int64_t ldy, int nvec, int ngroups, int n_r, const DGroup* groups,
-                                const DProb* probs, int mode, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  HELIC_LAUNCH((k_radial_forward_bf16<FWD16_TM>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
-               ngroups, n_r, groups, probs, mode);
+void launch_radial_forward_bf16(int tm, int nwg, size_t lds, hipStream_t st, const bf16x2* gh, const double* X,
+                                int64_t ldx, double* Y, int64_t ldy, int nvec, int ngroups, int n_r,
+                                const DGroup* groups, const DProb* probs, int mode, hipEvent_t e0 = nullptr,
+                                hipEvent_t e1 = nullptr) {
+  if (tm == 12)
+    HELIC_LAUNCH((k_radial_forward_bf16<12>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec, ngroups,
+                 n_r, groups, probs, mode);
+  else
+    HELIC_LAUNCH((k_radial_forward_bf16<8>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec, ngroups,
+                 n_r, groups, probs, mode);
+}
+
+// Register tiles per wave of the BF16 forward kernel: 8 (three waves per
+// SIMD), also where the widest group then needs a second pass over the slab
+// (measured: 12 tiles, two waves per SIMD, 22 % slower on the nanowire);
+// HELIC_FWD16_TILES = 12 selects the wider variant (for comparison).
+int fwd16_tiles(int tiles_max) {
+  (void)tiles_max;
+  const char* e = std::getenv("HELIC_FWD16_TILES");
+  return (e && std::atoi(e) == 12) ? 12 : 8;
 }
 
 helic_status set_bf16_limits() {
@@ -1094,8 +1109,8 @@ helic_status set_bf16_limits() {
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse_bf16<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse_bf16<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_inverse_bf16<6>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_bf16<FWD16_TM>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_bf16<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_bf16<12>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_angular<float, 0, bf16x2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lim));
   return HELIC_OK;
@@ -1342,6 +1357,8 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.ang_slots16 = d->ang_slots16;
   ls.lds_inv16 = lds_inv16_bytes(h->max_kpad, h->max_colpad);
   ls.lds_fwd16 = lds_fwd16_bytes(h->max_colpad);
+  ls.max_colpad = h->max_colpad;
+  ls.fwd_tm16 = fwd16_tiles(fwd_tiles_max(h));
   ls.rows1 = d->rows1;
   ls.nrows1 = (int)h->rows1.size();
   ls.plan1 = d->plan1;
@@ -1409,6 +1426,8 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
   // ev (optional): start and end events of each of the three kernels
   auto e = [&](int k) { return ev ? ev[k] : (hipEvent_t) nullptr; };
   if constexpr (BF) {
+    if (ls.max_colpad > FWD16_COLS)
+      return fail(HELIC_ERR_UNSUPPORTED, "BF16 mode takes |n| groups of at most 128 angular modes");
     launch_radial_inverse_bf16(inv_kt16_for(4 * ls.inv_ks), wg_rad, ls.lds_inv16, st, X, ldx, gh, nvec, ls.ngroups,
                                ls.n_r, ls.groups, probs, e(0), e(1));
   } else {
@@ -1431,8 +1450,8 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
     HIP_TRY(hipGetLastError());
   }
   if constexpr (BF) {
-    launch_radial_forward_bf16(wg_rad, ls.lds_fwd16, st, gh, X, ldx, Y, ldy, nvec, ls.ngroups, ls.n_r, ls.groups,
-                               probs, mode, e(4), e(5));
+    launch_radial_forward_bf16(ls.fwd_tm16, wg_rad, ls.lds_fwd16, st, gh, X, ldx, Y, ldy, nvec, ls.ngroups, ls.n_r,
+                               ls.groups, probs, mode, e(4), e(5));
   } else {
     const bool kx_lds = ls.fwd_tmax <= 0 && mode && (f64 ? ls.kx_lds64 : ls.kx_lds32);
     launch_radial_forward<T>(ls.fwd_tmax, wg_rad, f64 ? ls.lds_fwd64 : ls.lds_fwd32, st, reinterpret_cast<T*>(gh),

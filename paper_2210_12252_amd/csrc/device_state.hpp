@@ -98,6 +98,8 @@ struct LaunchSet {
   int ang_slots64 = 1, ang_slots32 = 1, ang_slots16 = 1;
   bool grid_var = false;
   size_t lds_inv16 = 0, lds_fwd16 = 0;   // LDS bytes of the BF16 radial kernels
+  int max_colpad = 0;                    // widest group's real columns, padded to 16
+  int fwd_tm16 = 8;                      // register tiles per wave of the BF16 forward kernel
   int inv_ks = 24;                  // register k steps of the radial inverse stage
   int fwd_tmax = 4;                 // radial forward variant: register tiles per wave; 0, -1 = pipelined
                                     // with 2 or 4 staged columns per lane

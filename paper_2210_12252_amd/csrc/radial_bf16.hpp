@@ -15,8 +15,8 @@ namespace helic {
 // 16, so the 16 columns an MFMA operand reads (8 bytes per lane) start on
 // distinct LDS banks.
 __host__ __device__ constexpr int bf16_col_stride(int len16) { return len16 + 8; }
-constexpr int FWD16_RC = 32;   // radii staged per chunk of the forward kernel
-constexpr int FWD16_TM = 12;   // output tiles (16 k x 16 columns) per wave and pass
+constexpr int FWD16_RC = 16;   // radii staged per chunk of the forward kernel
+constexpr int FWD16_COLS = 256; // widest staged group (real columns) the forward kernel takes
 
 // G_{mn}(r_l) = sum_k xi_{|n|,k}(r_l) x_{mnk}: the group's coefficients are
 // staged in LDS as bfloat16 columns [2 modes][k] (re and im as separate real
@@ -91,17 +91,28 @@ k_radial_inverse_bf16(const double* __restrict__ X, int64_t ldx, bf16x2* __restr
 
 // y_{mnk} = kappa x_{mnk} + sum_l (2 pi tau omega_l xi_{|n|,k}(r_l)) H_{mn}(r_l):
 // chunks of FWD16_RC radii of the group's slab rows are staged in LDS as
-// bfloat16 columns [2 modes][r] (r contiguous); each wave accumulates up to TM
-// output tiles over all chunks, then adds kappa x in FP64 and writes rows
-// k <= K of each mode.
+// bfloat16 columns [2 modes][r] (r contiguous, one 8-byte word per four radii
+// of a real column), together with the chunk's table fragments of every k
+// tile; the next chunk is fetched into registers while the MFMAs of the
+// current one run.  Each wave accumulates up to TM output tiles over all
+// chunks, then adds kappa x in FP64 and writes rows k <= K of each mode.
+// LDS: colpad x FWD16_RC bfloat16 (+ padding) and 6 x 2 fragments of 512 B.
+constexpr int FWD16_KT = 6;                                   // k tiles (of 16) per group it supports
+constexpr int FWD16_CST = FWD16_RC / 4 + 2;                   // column stride in 8-byte words
+constexpr int FWD16_QMAX = 2;                                 // staged (mode, radius quad) items per thread
+__host__ __device__ constexpr size_t fwd16_table_off(int colpad) {
+  return ((size_t)colpad * FWD16_CST * 8 + 15) & ~(size_t)15;
+}
+
 template <int TM>
 __global__ void __launch_bounds__(NT)
 k_radial_forward_bf16(const bf16x2* __restrict__ GH, const double* __restrict__ X, int64_t ldx,
                       double* __restrict__ Y, int64_t ldy, int nvec, int ngroups, int n_r,
                       const DGroup* __restrict__ groups, const DProb* __restrict__ probs, int add_kinetic) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  uint16_t* Hs = reinterpret_cast<uint16_t*>(smem_raw);
-  constexpr int RST = bf16_col_stride(FWD16_RC);
+  constexpr int RQ = FWD16_RC / 4;             // radius quads per chunk
+  constexpr int RS = FWD16_RC / 16;            // MFMA k steps per chunk
+  uint64_t* Hs = reinterpret_cast<uint64_t*>(smem_raw);
   const int slot = xcd_slot(ngroups * nvec);
   if (slot >= ngroups * nvec) return;
   const int v = slot / ngroups, gi = slot - v * ngroups;
@@ -110,10 +121,12 @@ k_radial_forward_bf16(const bf16x2* __restrict__ GH, const double* __restrict__ 
   const int nmodes = gr.nmodes;
   const int ncol = 2 * nmodes;
   const int nct = (ncol + 15) / 16;
+  const int half = 8 * nct;   // staged (re, im) column pairs, padded to whole tiles
   const int nkt = (gr.Kmax + 15) / 16;
   const int ntiles = nkt * nct;
   const int nr16 = (n_r + 15) / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t* As = reinterpret_cast<uint64_t*>(smem_raw + fwd16_table_off(16 * nct));   // [kt][s][64]
   const uint64_t* tg = reinterpret_cast<const uint64_t*>(pb.tfwd) + gr.tfwd16_off;
   const bf16x2* hv = GH + slab_off(pb, nvec, n_r, v, 0) + gr.mode0;
   const DMode* modes = pb.modes;
@@ -121,7 +134,60 @@ k_radial_forward_bf16(const bf16x2* __restrict__ GH, const double* __restrict__ 
   const double* xv = add_kinetic ? X + col_off(pb, ldx, nvec, v) * 2 : nullptr;
   double* yv = Y + col_off(pb, ldy, nvec, v) * 2;
   const int ktile = tile_kmax(modes + gr.mode0, nmodes, lane);
-  const int half = 8 * nct;   // staged (re, im) column pairs, padded to whole tiles
+  const int nitems = half * RQ;                // (mode, radius quad) pairs of a chunk
+  const int nfrag = nkt * RS * 64;             // table fragment words of a chunk
+  uint64_t re4[FWD16_QMAX], im4[FWD16_QMAX], ta[(FWD16_KT * RS * 64 + NT - 1) / NT];
+  // item i = (quad q, mode c), modes fastest: coalesced 4-byte reads
+  auto fetch = [&](int r0) {
+#pragma unroll
+    for (int a = 0; a < FWD16_QMAX; ++a) {
+      const int i = threadIdx.x + NT * a;
+      uint32_t u[4] = {0u, 0u, 0u, 0u};
+      if (i < nitems) {
+        const int q = i / half, c = i - q * half;
+        if (c < nmodes) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int r = r0 + 4 * q + j;
+            if (r < n_r) u[j] = hv[(int64_t)r * pb.n_modes + c].u;
+          }
+        }
+      }
+      re4[a] = (uint64_t)(u[0] & 0xffffu) | ((uint64_t)(u[1] & 0xffffu) << 16) |
+               ((uint64_t)(u[2] & 0xffffu) << 32) | ((uint64_t)(u[3] & 0xffffu) << 48);
+      im4[a] = (uint64_t)(u[0] >> 16) | ((uint64_t)(u[1] >> 16) << 16) | ((uint64_t)(u[2] >> 16) << 32) |
+               ((uint64_t)(u[3] >> 16) << 48);
+    }
+    const int rs0 = r0 / 16;
+#pragma unroll
+    for (int a = 0; a < (FWD16_KT * RS * 64 + NT - 1) / NT; ++a) {
+      const int i = threadIdx.x + NT * a;
+      uint64_t w = 0ull;
+      if (i < nfrag) {
+        const int ln = i & 63, ks = i >> 6;
+        const int kt = ks / RS, s = ks - kt * RS;
+        if (rs0 + s < nr16) w = tg[((int64_t)kt * nr16 + rs0 + s) * 64 + ln];
+      }
+      ta[a] = w;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int a = 0; a < FWD16_QMAX; ++a) {
+      const int i = threadIdx.x + NT * a;
+      if (i < nitems) {
+        const int q = i / half, c = i - q * half;
+        Hs[(2 * c) * FWD16_CST + q] = re4[a];
+        Hs[(2 * c + 1) * FWD16_CST + q] = im4[a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < (FWD16_KT * RS * 64 + NT - 1) / NT; ++a) {
+      const int i = threadIdx.x + NT * a;
+      if (i < nfrag) As[i] = ta[a];
+    }
+  };
+  const int nchunk = (n_r + FWD16_RC - 1) / FWD16_RC;
   for (int tbase = 0; tbase < ntiles; tbase += (NT / 64) * TM) {
     f32x4_t acc[TM];
     int tk[TM], tc[TM];
@@ -134,29 +200,19 @@ k_radial_forward_bf16(const bf16x2* __restrict__ GH, const double* __restrict__ 
       tc[i] = t - tk[i] * nct;
       live[i] = t < ntiles && (nct > 64 || 16 * tk[i] < __builtin_amdgcn_readlane(ktile, tc[i]));
     }
-    for (int r0 = 0; r0 < n_r; r0 += FWD16_RC) {
+    fetch(0);
+    for (int ch = 0; ch < nchunk; ++ch) {
       __syncthreads();
-      // (radius, mode) pairs, modes fastest: coalesced 4-byte reads
-      for (int idx = threadIdx.x; idx < FWD16_RC * half; idx += NT) {
-        const int rr = idx / half, c = idx - rr * half;
-        const int r = r0 + rr;
-        const uint32_t u = (c < nmodes && r < n_r) ? hv[(int64_t)r * pb.n_modes + c].u : 0u;
-        Hs[(2 * c) * RST + rr] = (uint16_t)(u & 0xffffu);
-        Hs[(2 * c + 1) * RST + rr] = (uint16_t)(u >> 16);
-      }
+      store();
       __syncthreads();
-      const int rs0 = r0 / 16;
+      if (ch + 1 < nchunk) fetch((ch + 1) * FWD16_RC);
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         if (!live[i]) continue;
-        const uint16_t* bt = Hs + (16 * tc[i] + (lane & 15)) * RST + 4 * (lane >> 4);
+        const uint64_t* bt = Hs + (16 * tc[i] + (lane & 15)) * FWD16_CST + (lane >> 4);
 #pragma unroll
-        for (int s = 0; s < FWD16_RC / 16; ++s) {
-          if (rs0 + s < nr16) {
-            const uint64_t a = tg[((int64_t)tk[i] * nr16 + rs0 + s) * 64 + lane];
-            acc[i] = mfma_bf16(a, *reinterpret_cast<const uint64_t*>(bt + 16 * s), acc[i]);
-          }
-        }
+        for (int s = 0; s < RS; ++s)
+          acc[i] = mfma_bf16(As[(tk[i] * RS + s) * 64 + lane], bt[4 * s], acc[i]);
       }
     }
 #pragma unroll
