@@ -268,29 +268,57 @@ helic_status helic_eigensolve_chefsi(helic_basis h, const helic_solve_opts* opts
                                      helic_solve_stats* stats, void* stream);
 
 /* ---- batches of Bloch parameters / structures (Sec. 3.3) ----------------
- * A batch groups problems (basis handles, each with its potential set) that
- * share the grid (n_t1, n_t2, n_r) and the angular kernel variant -- e.g. the
- * Bloch parameters eta_b of one structure -- so that each H*X stage runs as
- * one launch over the ragged work of all problems.  The batch borrows the
- * handles (they must outlive it).  Batched blocks are concatenated: problem
- * p's nvec columns (ld = L_p, column-major, complex) start at complex offset
- * nvec * offsets[p], offsets from helic_batch_info (nprob + 1 entries). */
+ * A batch groups problems (basis handles, each with its potential set, all on
+ * one device) -- e.g. the Bloch parameters eta_b of several structures.
+ * Problems that share the grid (n_t1, n_t2, n_r) and the angular kernel
+ * variant form a class; each H*X stage runs as one launch over the ragged
+ * work of all problems of a class, the classes one after another on the
+ * stream.  The batch borrows the handles (they must outlive it).  Batched
+ * blocks are concatenated: problem p's nvec columns (ld = L_p, column-major,
+ * complex) start at complex offset nvec * offsets[p], offsets from
+ * helic_batch_info (nprob + 1 entries). */
 typedef struct helic_batch_s* helic_batch;
 helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_batch* out);
 helic_status helic_batch_destroy(helic_batch b);
 helic_status helic_batch_info(helic_batch b, int64_t* offsets /* host, nprob + 1 */);
+/* Number of classes (host, may be NULL) and each problem's class (host,
+ * nprob entries, may be NULL). */
+helic_status helic_batch_classes(helic_batch b, int32_t* nclasses, int32_t* class_of);
 /* Y = H X for every problem of the batch, 1 <= nvec <= 64 (device blocks). */
 helic_status helic_batch_apply(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec,
                                void* stream);
-/* Capture the batched apply on these buffers into a HIP graph (replaces any
- * previous one); helic_batch_replay launches it on `stream`.  A replay reads
- * X and writes Y as captured. */
+/* Capture the batched apply on these buffers (every class) into one HIP
+ * graph (replaces any previous one); helic_batch_replay launches it on
+ * `stream`.  A replay reads X and writes Y as captured.  Tuning releases the
+ * graph. */
 helic_status helic_batch_capture(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec);
 helic_status helic_batch_replay(helic_batch b, void* stream);
-/* Tuner: times the batched apply for each candidate number of (problem,
- * radius, vector) items per workgroup of the angular stage (0: spread evenly
- * over the workgroups the device holds at once, the default) and keeps the
- * fastest (*chosen, *ms_best: host, may be NULL).  Synchronises `stream`. */
+/* Choices of the tuner for one class. */
+typedef struct {
+  int32_t n_t1, n_t2, n_r;   /* the class's grid                                        */
+  int32_t nprob;             /* problems in the class                                   */
+  int32_t items_per_wg;      /* angular stage: (problem, radius, vector) items per      */
+                             /* workgroup, 0 = spread over the resident workgroups      */
+  int32_t inv_ksteps;        /* radial inverse: k steps (of 4) held in registers        */
+  int32_t fwd_pipelined;     /* radial forward: 1 pipelined kernel, 0 plain kernel      */
+  int32_t fwd_tiles;         /* radial forward: 16 x 16 output tiles per wave           */
+  double ms;                 /* the class's three stages with these choices (ms)         */
+} helic_batch_class_tuning;
+/* Tuner: per class, times the class's three stages with each candidate of
+ * one knob at a time -- the angular work split (0, 2, 4, 8, 16 items per
+ * workgroup, where the specialised angular kernels serve the class), the
+ * radial inverse's register k steps (the smallest that covers the class, or
+ * 24) and the radial forward variant (pipelined with 8 or 4 register tiles
+ * per wave where every problem fits it, plain with 4 or 8; BF16 keeps its
+ * kernels) -- on these buffers, keeps the fastest and records it: out (host,
+ * max_classes entries, may be NULL), *nclasses (host, may be NULL).
+ * Synchronises `stream`; results are unchanged to rounding order. */
+helic_status helic_batch_tune_classes(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec,
+                                      void* stream, helic_batch_class_tuning* out, int32_t max_classes,
+                                      int32_t* nclasses);
+/* The same tuner; *chosen (host, may be NULL) receives the first class's
+ * angular work split and *ms_best (host, may be NULL) the sum over classes
+ * of the tuned stage times. */
 helic_status helic_batch_tune(helic_batch b, const double* X, double* Y, int32_t nvec, helic_prec prec,
                               void* stream, int32_t* chosen, double* ms_best);
 /* Lowest opts->nev eigenpairs of every problem, solved concurrently on

@@ -28,7 +28,7 @@ EXPORTS = ("helic_basis_create", "helic_basis_destroy", "helic_basis_info", "hel
            "helic_grid", "helic_set_potential", "helic_apply_H", "helic_apply_H_noalloc", "helic_transform_inverse",
            "helic_transform_forward", "helic_gradient", "helic_density", "helic_profile_apply", "helic_precondition", "helic_eigensolve",
            "helic_eigensolve_ex", "helic_eigensolve_chefsi", "helic_batch_create", "helic_batch_destroy", "helic_batch_info",
-           "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
+           "helic_batch_classes", "helic_batch_tune_classes", "helic_batch_apply", "helic_batch_capture", "helic_batch_replay", "helic_batch_tune",
            "helic_batch_eigensolve", "helic_batch_eigensolve_chefsi",
            "helic_batch_time_reversal",
            "helic_lpc_create", "helic_lpc_destroy", "helic_lpc_get_params", "helic_lpc_set_params",
@@ -50,6 +50,12 @@ class SolveOpts(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("prec", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("precond", ctypes.c_int32), ("guard", ctypes.c_int32), ("switch_tol", ctypes.c_double),
                 ("log_every", ctypes.c_int32), ("switch_tol_bf16", ctypes.c_double), ("stop_low", ctypes.c_int32)]
+
+
+class ClassTuning(ctypes.Structure):
+    _fields_ = [("n_t1", ctypes.c_int32), ("n_t2", ctypes.c_int32), ("n_r", ctypes.c_int32),
+                ("nprob", ctypes.c_int32), ("items_per_wg", ctypes.c_int32), ("inv_ksteps", ctypes.c_int32),
+                ("fwd_pipelined", ctypes.c_int32), ("fwd_tiles", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -113,6 +119,8 @@ def load() -> ctypes.CDLL:
         "helic_batch_create": [ctypes.POINTER(_P), _I32, ctypes.POINTER(_P)],
         "helic_batch_destroy": [_P],
         "helic_batch_info": [_P, _PI64],
+        "helic_batch_classes": [_P, _PI32, _PI32],
+        "helic_batch_tune_classes": [_P, _P, _P, _I32, _I32, _P, ctypes.POINTER(ClassTuning), _I32, _PI32],
         "helic_batch_apply": [_P, _P, _P, _I32, _I32, _P],
         "helic_batch_capture": [_P, _P, _P, _I32, _I32],
         "helic_batch_replay": [_P, _P],
@@ -438,10 +446,11 @@ class Lpc:
 
 
 class Batch:
-    """A batch of grid-compatible problems (borrows the Basis objects, which
-    must stay alive).  Batched blocks are complex128 device tensors of
-    nvec * offsets[-1] elements: problem p's block is the slice
-    [nvec * offsets[p], nvec * offsets[p + 1]) viewed as (nvec, L_p)."""
+    """A batch of problems (borrows the Basis objects, which must stay
+    alive), grouped internally into classes of equal grid and angular kernel.
+    Batched blocks are complex128 device tensors of nvec * offsets[-1]
+    elements: problem p's block is the slice [nvec * offsets[p],
+    nvec * offsets[p + 1]) viewed as (nvec, L_p)."""
 
     def __init__(self, bases):
         self.bases = list(bases)
@@ -484,6 +493,22 @@ class Batch:
 
     def replay(self, stream=None):
         _check(load().helic_batch_replay(self.h, _stream(stream)))
+
+    def classes(self):
+        """(number of classes, class index of every problem)."""
+        n = ctypes.c_int32(0)
+        cls = np.zeros(len(self.bases), dtype=np.int32)
+        _check(load().helic_batch_classes(self.h, ctypes.byref(n), _ptr(cls, ctypes.c_int32)))
+        return n.value, cls
+
+    def tune_classes(self, X, Y, nvec, prec="fp64", stream=None):
+        """Tune every class; returns one dict of choices per class."""
+        nmax = len(self.bases)
+        out = (ClassTuning * nmax)()
+        n = ctypes.c_int32(0)
+        _check(load().helic_batch_tune_classes(self.h, self._flat(X, "X"), self._flat(Y, "Y"), nvec, PREC[prec],
+                                               _stream(stream), out, nmax, ctypes.byref(n)))
+        return [{f: getattr(out[i], f) for f, _ in ClassTuning._fields_} for i in range(n.value)]
 
     def tune(self, X, Y, nvec, prec="fp64", stream=None):
         chosen = ctypes.c_int32(0)
