@@ -260,14 +260,16 @@ def angular_kernel_name(n1, n2):
 
 def batched_leg(torch, structures, nvec=8, steps=20, nev=60, tol=1e-8, extra=False, eig_every=8):
     """Many Bloch parameters of seeded structures (64 eta each, R ~ U[5, 12],
-    E_cut ~ U[15, 35]): per structure one batch with a common grid (the
-    largest automatic grid over its eta), tuned, captured in a HIP graph and
-    replayed (FP64; BF16 eager), and the lowest `nev` eigenpairs of all 64
-    problems by Chebyshev-filtered subspace iteration along the FP32 -> FP64
-    ladder, with time-reversal halving of the eta points, concurrently on 8
-    streams.  With `extra`, every `eig_every`-th problem is also solved by
-    FP64 LOBPCG with the plain and with a learned preconditioner (trained on
-    another eta of the structure)."""
+    E_cut ~ U[15, 35]), all in ONE batch: per structure a common grid (the
+    largest automatic grid over its eta), so the batch holds one class per
+    structure grid.  The batch is tuned per class (choices recorded),
+    captured in one HIP graph and replayed (FP64; BF16 eager), and the lowest
+    `nev` eigenpairs of every problem are solved by Chebyshev-filtered
+    subspace iteration along the FP32 -> FP64 ladder with time-reversal
+    halving of the eta points, concurrently on 8 streams.  With `extra`, every
+    `eig_every`-th problem of each structure is also solved by FP64 LOBPCG with
+    the plain and with a learned preconditioner (trained on another eta of
+    the structure)."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -276,10 +278,10 @@ def batched_leg(torch, structures, nvec=8, steps=20, nev=60, tol=1e-8, extra=Fal
     from synth.configs import batched_problems
     from paper_2210_12252_amd import helic
     allp = batched_problems()
-    out = []
+    t0 = time.perf_counter()
+    bases, per = [], []
     for s in structures:
         probs = allp[64 * s: 64 * (s + 1)]
-        t0 = time.perf_counter()
         with cf.ThreadPoolExecutor(8) as ex:
             auto = list(ex.map(lambda w: helic.Basis.from_workload(w), probs))
         n1 = max(b.n_t1 for b in auto)
@@ -289,63 +291,71 @@ def batched_leg(torch, structures, nvec=8, steps=20, nev=60, tol=1e-8, extra=Fal
             b.close()
         grid_w = [w.with_(n_t1=n1, n_t2=n2, n_r=nr, m_max=(n1 - 1) // 2, n_max=(n2 - 1) // 2) for w in probs]
         with cf.ThreadPoolExecutor(8) as ex:
-            bases = list(ex.map(lambda w: helic.Basis.from_workload(w), grid_w))
-        t1, t2, r, _ = bases[0].grid()
+            sb = list(ex.map(lambda w: helic.Basis.from_workload(w), grid_w))
+        t1, t2, r, _ = sb[0].grid()
         w0 = probs[0]
         V = torch.from_numpy(synth.potential_at(t1, t2, r, w0.tau, w0.alpha,
                                                 synth.atoms_for(w0.structure, w0.seed, w0.tau, w0.R))).cuda()
-        for b in bases:
+        for b in sb:
             b.set_potential(V)
-        batch = helic.Batch(bases)
-        setup = time.perf_counter() - t0
-        total = nvec * int(batch.offsets[-1])
-        X = torch.randn(total, dtype=torch.complex128, device="cuda")
-        Y = torch.zeros_like(X)
-        chosen, _ = batch.tune(X, Y, nvec)
-        batch.capture(X, Y, nvec)
+        Ls = [b.L for b in sb]
+        per.append(dict(structure=s, R=round(w0.R, 3), ecut=round(w0.ecut, 3), n_eta=len(probs),
+                        grid=f"{n1}x{n2}x{nr}", L_min=int(min(Ls)), L_max=int(max(Ls)),
+                        kernel=angular_kernel_name(n1, n2), first=len(bases)))
+        bases += sb
+    batch = helic.Batch(bases)
+    setup = time.perf_counter() - t0
+    nclass, _ = batch.classes()
+    total = nvec * int(batch.offsets[-1])
+    X = torch.randn(total, dtype=torch.complex128, device="cuda")
+    Y = torch.zeros_like(X)
+    tuning = batch.tune_classes(X, Y, nvec)
+    batch.capture(X, Y, nvec)
+    batch.replay()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(steps):
         batch.replay()
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(steps):
-            batch.replay()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - ta) / steps
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - ta) / steps
+    batch.apply(X, Y, nvec, prec="bf16")
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(steps):
         batch.apply(X, Y, nvec, prec="bf16")
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(steps):
-            batch.apply(X, Y, nvec, prec="bf16")
-        torch.cuda.synchronize()
-        dt16 = (time.perf_counter() - ta) / steps
-        Ls = np.diff(batch.offsets)
-        rec = dict(structure=s, R=round(w0.R, 3), ecut=round(w0.ecut, 3), n_eta=len(probs),
-                   grid=f"{n1}x{n2}x{nr}", L_min=int(Ls.min()), L_max=int(Ls.max()),
-                   kernel=angular_kernel_name(n1, n2),
-                   setup_s=round(setup, 2), tuned_items_per_wg=chosen, ms_per_batched_apply=round(1e3 * dt, 3),
-                   vec_applies_per_s=round(len(probs) * nvec / dt, 1),
-                   bf16_ms_per_batched_apply=round(1e3 * dt16, 3),
-                   bf16_vec_applies_per_s=round(len(probs) * nvec / dt16, 1))
-        # every problem: filtered solver, FP32 -> FP64 ladder, time-reversal halving
-        npairs = batch.time_reversal(True)
-        torch.cuda.synchronize()
-        te = time.perf_counter()
-        ev, res, st, status = batch.eigensolve(nev, nstreams=8, tol=tol, maxit=200, cheb_degree=0, prec="fp32")
-        te = time.perf_counter() - te
-        batch.time_reversal(False)
-        rec.update(eig_problems=len(probs), eig_nev=nev, eig_prec="fp32 -> fp64 ladder", time_reversal_pairs=npairs,
-                   eig_seconds=round(te, 2), eig_converged=int(np.sum(status == 0)), eig_max_resid=float(res.max()),
-                   eig_steps_mean=float(np.mean([x["iters"] for x in st if x["iters"] > 0])))
+    torch.cuda.synchronize()
+    dt16 = (time.perf_counter() - ta) / steps
+    del X, Y
+    out = dict(problems=len(bases), structures=list(structures), classes=nclass, setup_s=round(setup, 2),
+               tuning=tuning, ms_per_batched_apply=round(1e3 * dt, 3),
+               vec_applies_per_s=round(len(bases) * nvec / dt, 1), bf16_ms_per_batched_apply=round(1e3 * dt16, 3),
+               bf16_vec_applies_per_s=round(len(bases) * nvec / dt16, 1))
+    # every problem: filtered solver, FP32 -> FP64 ladder, time-reversal halving
+    npairs = batch.time_reversal(True)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    ev, res, st, status = batch.eigensolve(nev, nstreams=8, tol=tol, maxit=200, cheb_degree=0, prec="fp32")
+    te = time.perf_counter() - te
+    batch.time_reversal(False)
+    out.update(eig_problems=len(bases), eig_nev=nev, eig_prec="fp32 -> fp64 ladder", time_reversal_pairs=npairs,
+               eig_seconds=round(te, 2), eig_converged=int(np.sum(status == 0)), eig_max_resid=float(res.max()))
+    for rec in per:
+        a = rec.pop("first")
+        sl = slice(a, a + rec["n_eta"])
+        rec.update(eig_converged=int(np.sum(status[sl] == 0)), eig_max_resid=float(res[sl].max()),
+                   eig_steps_mean=float(np.mean([x["iters"] for x in st[sl] if x["iters"] > 0])),
+                   eig_solve_s=round(sum(x["t_total_ms"] for x in st[sl]) / 1e3, 2))
         if extra:
-            sub = bases[::eig_every]
+            sub = bases[a: a + rec["n_eta"]: eig_every]
             eb = helic.Batch(sub)
-            te = time.perf_counter()
-            evl, _, stl, statusl = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000)
-            te = time.perf_counter() - te
-            rec.update(lobpcg_problems=len(sub), lobpcg_seconds=round(te, 2),
-                       lobpcg_converged=int(np.sum(statusl == 0)),
-                       lobpcg_max_abs_dlambda=float(np.max(np.abs(evl - ev[::eig_every]))))
             tl = time.perf_counter()
-            tb = bases[eig_every // 2]
+            evl, _, _, statusl = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000)
+            tl = time.perf_counter() - tl
+            rec.update(lobpcg_problems=len(sub), lobpcg_seconds=round(tl, 2),
+                       lobpcg_converged=int(np.sum(statusl == 0)),
+                       lobpcg_max_abs_dlambda=float(np.max(np.abs(evl - ev[sl][::eig_every]))))
+            tb = bases[a + eig_every // 2]
+            tl = time.perf_counter()
             Rh, Th, lh, ncol, _ = tb.lpc_harvest(nev, n_snap=12, tol=tol, maxit=1000, seed=3)
             net = helic.Lpc(seed=0)
             tb.lpc_train(net, Rh, Th, lh, ncol, batch=min(16, ncol), steps=400, lr=3e-3, seed=0)
@@ -354,22 +364,23 @@ def batched_leg(torch, structures, nvec=8, steps=20, nev=60, tol=1e-8, extra=Fal
             del Rh, Th, lh
             for sb in sub:
                 sb.attach(net)
-            te = time.perf_counter()
-            evn, _, stn, statusn = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000, precond="learned")
-            te = time.perf_counter() - te
+            te2 = time.perf_counter()
+            evn, _, _, statusn = eb.eigensolve(nev, nstreams=8, tol=tol, maxit=1000, precond="learned")
+            te2 = time.perf_counter() - te2
             for sb in sub:
                 sb.attach(None)
             net.close()
             eb.close()
-            rec.update(learned_train_s=round(tl, 2), learned_seconds=round(te, 2),
+            rec.update(learned_train_s=round(tl, 2), learned_seconds=round(te2, 2),
                        learned_converged=int(np.sum(statusn == 0)),
-                       learned_max_abs_dlambda=float(np.max(np.abs(evn - ev[::eig_every]))))
-        print(f"[bench] batched structure {s}: {rec}", file=sys.stderr, flush=True)
-        out.append(rec)
-        batch.close()
-        for b in bases:
-            b.close()
-        del X, Y
+                       learned_max_abs_dlambda=float(np.max(np.abs(evn - ev[sl][::eig_every]))))
+        print(f"[bench] batched structure {rec['structure']}: {rec}", file=sys.stderr, flush=True)
+    out["per_structure"] = per
+    print(f"[bench] batched: {len(bases)} problems in {nclass} classes, {1e3 * dt:.2f} ms per replay, "
+          f"eigensolve {te:.2f} s, converged {out['eig_converged']}", file=sys.stderr, flush=True)
+    batch.close()
+    for b in bases:
+        b.close()
     return out
 
 

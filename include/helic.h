@@ -242,6 +242,7 @@ typedef struct {
   double t_precond_ms;  /* time in residuals and the preconditioner                   */
   double t_total_ms;    /* wall time of the call                                      */
   int32_t iters_bf16;   /* of iters_low, iterations with BF16 H*X                     */
+  int32_t n_graphs;     /* filtered solver: filter recurrences captured as HIP graphs */
 } helic_solve_stats;
 
 /* As helic_eigensolve with all options; stats (host) may be NULL. */
@@ -262,7 +263,11 @@ helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* opts, do
  * opts->precond is not used (the filter takes the preconditioner's place);
  * stats->iters counts outer steps, t_apply_ms the filter recurrence (H*X
  * and its elementwise steps, queued without host synchronisation) and
- * t_precond_ms the residuals. */
+ * t_precond_ms the residuals.  The recurrence of an outer step (m - 1
+ * applications of H and m elementwise steps, coefficients read from device
+ * memory) is captured into a HIP graph and replayed while the locked count
+ * and the precision stay the same (stats->n_graphs counts the captures); a
+ * null `stream` is replaced by a stream of the solver's own. */
 helic_status helic_eigensolve_chefsi(helic_basis h, const helic_solve_opts* opts, int32_t degree,
                                      double* evals, double* resid, double* evecs, int64_t ldv,
                                      helic_solve_stats* stats, void* stream);

@@ -31,7 +31,7 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
 struct Harvest;
 helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double* evals, double* resid,
                              double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st, Harvest* hv,
-                             int cheb_degree);
+                             int cheb_degree, bool allow_graph);
 void release_workspace(helic_basis_s* h);
 size_t slab_elem_bytes(helic_prec prec);
 
@@ -499,7 +499,7 @@ static helic_status batch_eigensolve(helic_batch b, const helic_solve_opts* o, i
       helic_solve_stats ss;
       std::memset(&ss, 0, sizeof(ss));
       st[p] = s ? eigensolve_impl(b->bases[p], *o, evals + (size_t)p * o->nev, resid + (size_t)p * o->nev, nullptr, 0,
-                                  &ss, s, nullptr, cheb_degree)
+                                  &ss, s, nullptr, cheb_degree, false)
                 : HELIC_ERR_HIP;
       if (st[p] != HELIC_OK) msg[p] = helic_last_error();
       if (stats) stats[p] = ss;

@@ -29,6 +29,8 @@ namespace helic {
 
 helic_status apply_H_impl(helic_basis_s* h, const double* X, int64_t ldx, double* Y, int64_t ldy, int nvec,
                           helic_prec prec, hipStream_t st, int chunk);
+helic_status ensure_workspace(helic_basis_s* h, int nvec, size_t elem);
+size_t slab_elem_bytes(helic_prec prec);
 helic_status precondition_impl(helic_basis_s* h, const double* Rr, int64_t ldr, double* W, int64_t ldw,
                                int nvec, hipStream_t st);
 helic_status lpc_precondition(helic_basis_s* h, const double* Rr, int64_t ldr, const double* lam, double* W,
@@ -217,6 +219,19 @@ k_cheb_step(const double* __restrict__ AY, const double* __restrict__ Y, const d
   }
 }
 
+// The same step with its coefficients (alpha, c, beta) read from device
+// memory, so that a captured graph of the recurrence replays with the
+// coefficients of each outer step.
+__global__ void __launch_bounds__(NTS)
+k_cheb_step_c(const double* __restrict__ AY, const double* __restrict__ Y, const double* Xp, double* Out, int64_t n,
+              const double* __restrict__ coef) {
+  const double alpha = coef[0], c = coef[1], beta = coef[2];
+  for (int64_t i = blockIdx.x * (int64_t)NTS + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTS) {
+    const double f = alpha * (AY[i] - c * Y[i]);
+    Out[i] = beta != 0.0 ? f + beta * Xp[i] : f;
+  }
+}
+
 // Number of eigenvalues below x of the symmetric tridiagonal matrix with
 // diagonal d and off-diagonal e (Sturm sequence of the LDL^T pivots).
 int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
@@ -269,11 +284,28 @@ struct Timer {
 
 helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double* evals, double* resid,
                              double* evecs, int64_t ldv, helic_solve_stats* stats, hipStream_t st, Harvest* hv,
-                             int cheb_degree) {
+                             int cheb_degree, bool allow_graph) {
   Timer total;
   helic_solve_stats S_;
   std::memset(&S_, 0, sizeof(S_));
   const int64_t L = h->L;
+  // The solve runs on a stream of its own when the caller passes the null
+  // stream (which cannot be captured into a graph); the caller's earlier work
+  // is waited for first, and everything is synchronised before returning.
+  struct OwnStream {
+    hipStream_t s = nullptr;
+    ~OwnStream() {
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+      }
+    }
+  } own;
+  if (!st) {
+    HIP_TRY_S(hipStreamSynchronize(nullptr));
+    HIP_TRY_S(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking));
+    st = own.s;
+  }
   const int nev = o.nev;
   // automatic guard: a wider block speeds the filter's convergence (the
   // damped interval starts further above the wanted eigenvalues)
@@ -594,6 +626,30 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
     // rotated by FP64 Rayleigh-Ritz.  Scaled three-term recurrence (Zhou and
     // Saad, 2007), applied to the columns not yet locked.
     const int m = cheb_degree;
+    std::vector<double> cheb_h(3 * (size_t)m);
+    double* cheb_d = nullptr;
+    if ((s = B.get(&cheb_d, 3 * (size_t)m))) return s;
+    // captured filter recurrence (HELIC_CHEB_GRAPH=0 keeps eager launches).
+    // Not for the concurrent solves of a batch: a capture in one host thread
+    // makes the null-stream work that other threads' library set-up does
+    // (rocBLAS / hipBLASLt initialisation, synchronous copies) fail with
+    // hipErrorStreamCaptureImplicit.
+    const char* ge = std::getenv("HELIC_CHEB_GRAPH");
+    const bool use_graph = allow_graph && !(ge && ge[0] == '0');
+    struct FilterGraph {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t x = nullptr;
+      int nl = -1;
+      helic_prec prec = HELIC_FP64;
+      void reset() {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+        x = nullptr;
+        g = nullptr;
+        nl = -1;
+      }
+      ~FilterGraph() { reset(); }
+    } fgraph;
     double b_up = 0.0;
     {
       // K-step Lanczos from one random column in FP64: the largest Ritz
@@ -701,28 +757,73 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
       const double e = 0.5 * (b_up - a), c = 0.5 * (b_up + a);
       double sigma = e / (a0 - c);
       const double tau = 2.0 / sigma;
-      // Y1 = (H X - c X) sigma / e from the Rayleigh-Ritz block and its H X
+      // Y1 = (H X - c X) sigma / e from the Rayleigh-Ritz block and its H X;
+      // Y_i = (H Y_{i-1} - c Y_{i-1}) 2 sigma2 / e - sigma sigma2 Y_{i-2},
+      // written over Y_{i-2}.  The coefficients of the m steps go to the
+      // device first; the recurrence itself (m - 1 applications of H and m
+      // elementwise steps) is the same launch sequence at every outer step
+      // with the same locked count and precision, so it is captured once
+      // into a HIP graph and replayed.
       double* const X0 = col(S, nl);
       double* const AX0 = col(AS, nl);
-      double* prev = X0;
-      double* cur = col(S, n);
-      // the recurrence is queued without host synchronisation; its time,
-      // H*X and the elementwise steps together, counts as H*X time
-      Timer tf;
-      hipLaunchKernelGGL(k_cheb_step, dim3(gridc), dim3(NTS), 0, st, AX0, X0, (const double*)nullptr, cur, nd,
-                         sigma / e, c, 0.0);
-      HIP_TRY_S(hipGetLastError());
-      for (int i = 2; i <= m; ++i) {
-        if ((s = apply_H_impl(h, cur, L, AX0, L, nu, prec, st, chunk))) return s;
-        S_.n_apply += nu;
-        const double sigma2 = 1.0 / (tau - sigma);
-        // Y_i = (H Y_{i-1} - c Y_{i-1}) 2 sigma2 / e - sigma sigma2 Y_{i-2}, over Y_{i-2}
-        hipLaunchKernelGGL(k_cheb_step, dim3(gridc), dim3(NTS), 0, st, AX0, cur, prev, prev, nd, 2.0 * sigma2 / e,
-                           c, -sigma * sigma2);
-        HIP_TRY_S(hipGetLastError());
-        std::swap(prev, cur);
-        sigma = sigma2;
+      for (int i = 1; i <= m; ++i) {
+        if (i == 1) {
+          cheb_h[0] = sigma / e;
+          cheb_h[1] = c;
+          cheb_h[2] = 0.0;
+        } else {
+          const double sigma2 = 1.0 / (tau - sigma);
+          cheb_h[3 * (i - 1)] = 2.0 * sigma2 / e;
+          cheb_h[3 * (i - 1) + 1] = c;
+          cheb_h[3 * (i - 1) + 2] = -sigma * sigma2;
+          sigma = sigma2;
+        }
       }
+      Timer tf;
+      HIP_TRY_S(hipMemcpyAsync(cheb_d, cheb_h.data(), sizeof(double) * 3 * m, hipMemcpyHostToDevice, st));
+      auto enqueue = [&]() -> helic_status {
+        double* prev = X0;
+        double* cur = col(S, n);
+        hipLaunchKernelGGL(k_cheb_step_c, dim3(gridc), dim3(NTS), 0, st, AX0, X0, (const double*)nullptr, cur, nd,
+                           (const double*)cheb_d);
+        HIP_TRY_S(hipGetLastError());
+        for (int i = 2; i <= m; ++i) {
+          helic_status r = apply_H_impl(h, cur, L, AX0, L, nu, prec, st, chunk);
+          if (r != HELIC_OK) return r;
+          hipLaunchKernelGGL(k_cheb_step_c, dim3(gridc), dim3(NTS), 0, st, AX0, cur, prev, prev, nd,
+                             (const double*)(cheb_d + 3 * (i - 1)));
+          HIP_TRY_S(hipGetLastError());
+          std::swap(prev, cur);
+        }
+        return HELIC_OK;
+      };
+      if (use_graph) {
+        if (!fgraph.x || fgraph.nl != nl || fgraph.prec != prec) {
+          fgraph.reset();
+          // the intermediate buffer must not grow inside the capture
+          if ((s = ensure_workspace(h, std::min(nu, chunk), slab_elem_bytes(prec) / 2))) return s;
+          HIP_TRY_S(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          const helic_status r = enqueue();
+          hipGraph_t g = nullptr;
+          const hipError_t e2 = hipStreamEndCapture(st, &g);
+          if (r != HELIC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+          }
+          if (e2 != hipSuccess) return fail(HELIC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+          fgraph.g = g;
+          HIP_TRY_S(hipGraphInstantiate(&fgraph.x, g, nullptr, nullptr, 0));
+          fgraph.nl = nl;
+          fgraph.prec = prec;
+          ++S_.n_graphs;
+        }
+        HIP_TRY_S(hipGraphLaunch(fgraph.x, st));
+      } else if ((s = enqueue())) {
+        return s;
+      }
+      S_.n_apply += (int64_t)(m - 1) * nu;
+      // the output block after m - 1 exchanges of the two work blocks
+      double* cur = (m - 1) % 2 ? X0 : col(S, n);
       if ((s = sync())) return s;
       S_.t_apply_ms += tf.ms();
       Timer t;
@@ -947,7 +1048,8 @@ helic_status helic_eigensolve_ex(helic_basis h, const helic_solve_opts* o, doubl
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
   if (o->precond == 2 && !lpc_attached(h)) return fail(HELIC_ERR_STATE, "no learned preconditioner attached");
   try {
-    return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream), nullptr, 0);
+    return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream), nullptr, 0,
+                           true);
   } catch (const std::bad_alloc&) {
     return fail(HELIC_ERR_NOMEM, "host allocation failed");
   }
@@ -965,7 +1067,7 @@ helic_status helic_eigensolve_chefsi(helic_basis h, const helic_solve_opts* o, i
   if (!h->dev || !h->dev->have_potential) return fail(HELIC_ERR_STATE, "no potential set");
   try {
     return eigensolve_impl(h, *o, evals, resid, evecs, ldv, stats, reinterpret_cast<hipStream_t>(stream), nullptr,
-                           degree > 0 ? degree : CHEB_DEGREE_AUTO);
+                           degree > 0 ? degree : CHEB_DEGREE_AUTO, true);
   } catch (const std::bad_alloc&) {
     return fail(HELIC_ERR_NOMEM, "host allocation failed");
   }
@@ -993,7 +1095,7 @@ helic_status helic_lpc_harvest(helic_basis h, const helic_solve_opts* o, int32_t
     hv.lam = lam;
     std::vector<double> ev(o->nev), rs(o->nev);
     helic_status s = eigensolve_impl(h, *o, ev.data(), rs.data(), nullptr, 0, stats,
-                                     reinterpret_cast<hipStream_t>(stream), &hv, 0);
+                                     reinterpret_cast<hipStream_t>(stream), &hv, 0, true);
     if (s) return s;
     *ncol = hv.ncol;
     return HELIC_OK;

@@ -61,7 +61,8 @@ class ClassTuning(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("iters_low", ctypes.c_int32), ("n_apply", ctypes.c_int64),
                 ("n_fallback", ctypes.c_int32), ("t_apply_ms", ctypes.c_double), ("t_rr_ms", ctypes.c_double),
-                ("t_precond_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double), ("iters_bf16", ctypes.c_int32)]
+                ("t_precond_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double), ("iters_bf16", ctypes.c_int32),
+                ("n_graphs", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -283,6 +283,22 @@ def test_chefsi_full_size_certified_by_the_oracle():
         assert r <= 1.05e-8
 
 
+def test_chefsi_filter_graph_matches_eager_launches(monkeypatch):
+    """The filter recurrence captured into a HIP graph and replayed (default)
+    computes exactly what the eager launches compute, through the FP32 -> FP64
+    ladder (a recapture at the precision switch)."""
+    w = synth.workload("tiny-helix")
+    o, b, V = _setup(w)
+    ev1, res1, st1, s1 = b.eigensolve_ex(w.nev, tol=1e-9, maxit=300, prec="fp32", seed=3, cheb_degree=0)
+    monkeypatch.setenv("HELIC_CHEB_GRAPH", "0")
+    ev0, res0, st0, s0 = b.eigensolve_ex(w.nev, tol=1e-9, maxit=300, prec="fp32", seed=3, cheb_degree=0)
+    print(f"[filter graph] captures {st1['n_graphs']} steps {st1['iters']} (eager {st0['iters']})", flush=True)
+    assert s1 == helic.OK and s0 == helic.OK
+    assert st1["n_graphs"] >= 2 and st0["n_graphs"] == 0
+    np.testing.assert_array_equal(ev0, ev1)
+    np.testing.assert_array_equal(res0, res1)
+
+
 def test_chefsi_argument_errors():
     w = synth.workload("tiny-helix")
     o, b, V = _setup(w)
