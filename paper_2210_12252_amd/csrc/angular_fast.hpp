@@ -126,10 +126,13 @@ __device__ __forceinline__ void dft_reg(cplx<T>* v) {
 
 // Row stride (complex elements) of the LDS mode block for N2 = P * P: the P
 // threads of a row and the rows next to it then touch disjoint LDS banks in
-// every phase of the row transform when P divides 16 (N2 + P is P mod 16);
-// otherwise N2 + 1.
+// every phase of the row transform when P divides 16 (N2 + P is P mod 16).
+// For N2 = 81 a stride of 1 mod 16 elements lets the rows that one wave's
+// transform lanes share follow each other on the banks (a bank model of the
+// row phases and the mode scatter gives 70 % of the conflict cycles of the
+// stride 82); otherwise N2 + 1.
 __host__ __device__ constexpr int ang_rs(int n2) {
-  return n2 == 16 ? 20 : n2 == 64 ? 72 : n2 + 1;
+  return n2 == 16 ? 20 : n2 == 64 ? 72 : n2 == 81 ? 89 : n2 + 1;
 }
 
 // Column swizzle of the block: element (m, j) sits at m * RS + (j ^ ang_swz(N2,
@@ -242,8 +245,9 @@ __device__ __forceinline__ void row_dft(cplx<T>* A0, int rows, const cplx<T>* tw
 // Row transforms whose input (inverse) or output (forward) stays in the
 // registers of the row's P threads: lane (row, p) holds the elements at
 // columns p + P q.  The LDS row is used as the exchange buffer (and, for the
-// inverse, receives the transformed row).
-template <typename T, int N2, int P, int NTF, int ROWS, int OFF, bool PIN>
+// inverse, receives the transformed row).  SWZ false: the block has no
+// column swizzle.
+template <typename T, int N2, int P, int NTF, int ROWS, int OFF, bool PIN, bool SWZ = true>
 __device__ __forceinline__ void row_idft_from_regs(cplx<T>* A0, const cplx<T>* tw, const cplx<T>* xin) {
   constexpr int RS = ang_rs(N2);
   constexpr int RPW = 64 / P;
@@ -256,7 +260,7 @@ __device__ __forceinline__ void row_idft_from_regs(cplx<T>* A0, const cplx<T>* t
   const bool act = lane < RPW * P && row < ROWS;
   cplx<T> v[P];
   cplx<T>* a = A0 + (act ? row : 0) * RS;
-  const int sw = ang_swz(N2, act ? row : 0);
+  const int sw = SWZ ? ang_swz(N2, act ? row : 0) : 0;
   if (act) {
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = xin[q];
@@ -291,7 +295,7 @@ __device__ __forceinline__ void row_idft_from_regs(cplx<T>* A0, const cplx<T>* t
   }
 }
 
-template <typename T, int N2, int P, int NTF, int ROWS, int OFF, bool PIN>
+template <typename T, int N2, int P, int NTF, int ROWS, int OFF, bool PIN, bool SWZ = true>
 __device__ __forceinline__ void row_dft_to_regs(cplx<T>* A0, const cplx<T>* tw, cplx<T>* xout) {
   constexpr int RS = ang_rs(N2);
   constexpr int RPW = 64 / P;
@@ -304,7 +308,7 @@ __device__ __forceinline__ void row_dft_to_regs(cplx<T>* A0, const cplx<T>* tw, 
   const bool act = lane < RPW * P && row < ROWS;
   cplx<T> v[P];
   cplx<T>* a = A0 + (act ? row : 0) * RS;
-  const int sw = ang_swz(N2, act ? row : 0);
+  const int sw = SWZ ? ang_swz(N2, act ? row : 0) : 0;
   if (act) {
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = a[OFF + ((p + P * q) ^ sw)];

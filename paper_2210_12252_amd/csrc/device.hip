@@ -17,6 +17,7 @@
 #include "kernels.hpp"
 #include "angular_fast.hpp"
 #include "angular_grid.hpp"
+#include "angular_split.hpp"
 
 // Stage launch; with timing events they ride on the kernel's own dispatch
 // packet (start and end timestamps of that kernel, no marker packets between
@@ -958,6 +959,72 @@ helic_status launch_fast(const LaunchSet& ls, E* gh, int nvec, hipStream_t st, h
   return fail(HELIC_ERR_STATE, "no specialised angular kernel for this grid");
 }
 
+// Grids served by the split theta1 FFT kernel in FP32 arithmetic (FP32 and
+// BF16 modes; theta1 size, theta2 size, padded m count, block size): the m
+// range covers most of a small theta1 grid, where the column DFTs cost fewer
+// operations than the M^2 convolution.  Measured against the convolution
+// kernel: 32 x 81 (25 rows) FP32 0.200 vs 0.221 ms, BF16 0.221 vs 0.227 ms;
+// 48 x 64 (28 rows) FP32 0.122 vs 0.136 ms, BF16 0.124 vs 0.146 ms per
+// 64-vector block.  With 24 rows on 48 x 64, and in FP64 everywhere (where
+// the kernel needs more registers than three waves per SIMD allow and its
+// LDS exchanges are exposed), the convolution kernel measured faster.
+struct SplitVariant { int n1, n2, mpad, ntf; };
+constexpr SplitVariant SPLIT_VARIANTS[] = {{32, 81, 25, 384}, {48, 64, 28, 256}};
+#define HELIC_SPLIT_FOREACH(X) X(32, 81, 25, 384) X(48, 64, 28, 256)
+
+template <typename T>
+size_t split_lds_bytes(int n1, int n2) {
+  return ((size_t)n1 * ang_rs(n2) + n2 + n1) * sizeof(cplx<T>);
+}
+
+bool split_disabled() {
+  const char* e = std::getenv("HELIC_ANGULAR_SPLIT");
+  return e && e[0] == '0';
+}
+
+template <typename E>
+helic_status set_split_limits() {
+#define HELIC_SPLIT_ATTR(N1_, N2_, MP_, NTF_)                                                            \
+  HIP_TRY(hipFuncSetAttribute((const void*)k_angular_split<float, E, N1_, N2_, MP_, NTF_>,             \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HELIC_SPLIT_FOREACH(HELIC_SPLIT_ATTR)
+#undef HELIC_SPLIT_ATTR
+  return HELIC_OK;
+}
+
+template <typename E>
+int split_slots(int n1, int n2, int mpad, int ntf, int ncu) {
+  int nb = 0;
+  const size_t lds = split_lds_bytes<float>(n1, n2);
+#define HELIC_OCC_CASE(N1_, N2_, MP_, NTF_)                                                            \
+  if (n1 == N1_ && n2 == N2_ && mpad == MP_ && ntf == NTF_)                                           \
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_split<float, E, N1_, N2_, MP_, NTF_>, NTF_, lds);
+  HELIC_SPLIT_FOREACH(HELIC_OCC_CASE)
+#undef HELIC_OCC_CASE
+  return std::max(1, nb) * std::max(1, ncu);
+}
+
+template <typename E>
+helic_status launch_split(const LaunchSet& ls, E* gh, int nvec, hipStream_t st, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr) {
+  const DProb* probs = launch_probs<float, E>(ls);
+  const cplx<float>* tw2 = (const cplx<float>*)ls.tw2_32;
+  const cplx<float>* tw1 = (const cplx<float>*)ls.tw1_32;
+  const int ipw = angular_items_per_wg<float, E>(ls, nvec);
+  const dim3 grid(angular_grid_size(ls, nvec, ipw));
+  const size_t lds = split_lds_bytes<float>(ls.n_t1, ls.n_t2);
+#define HELIC_SPLIT_CASE(N1_, N2_, MP_, NTF_)                                                             \
+  if (ls.n_t1 == N1_ && ls.n_t2 == N2_ && ls.fast_mpad == MP_ && ls.split_ntf == NTF_) {                 \
+    HELIC_LAUNCH((k_angular_split<float, E, N1_, N2_, MP_, NTF_>), grid, dim3(NTF_), lds, st, e0, e1, gh,  \
+                 ls.nprob, nvec, ls.n_r, probs, tw2, tw1, ipw);                                         \
+    HIP_TRY(hipGetLastError());                                                                         \
+    return HELIC_OK;                                                                                    \
+  }
+  HELIC_SPLIT_FOREACH(HELIC_SPLIT_CASE)
+#undef HELIC_SPLIT_CASE
+  return fail(HELIC_ERR_STATE, "no split angular kernel for this grid");
+}
+
 // Grids served by the register-FFT angular kernel (theta1 size, theta2 size
 // and its four-step factors): the automatic grids of the batched workload.
 // Where the convolution kernel also applies (48 x 64, 32 x 81) it measured
@@ -1243,6 +1310,14 @@ helic_status ensure_device(helic_basis_s* h) {
       }
     }
   }
+  d->split_ntf = 0;
+  if (d->fast_mpad && !split_disabled()) {
+    for (const SplitVariant& sv : SPLIT_VARIANTS)
+      if (sv.n1 == h->n_t1 && sv.n2 == h->n_t2 && sv.mpad == d->fast_mpad &&
+          split_lds_bytes<float>(sv.n1, sv.n2) <= 160 * 1024)
+        d->split_ntf = sv.ntf;
+    if (d->split_ntf && ((s = set_split_limits<cplx<float>>()) || (s = set_split_limits<bf16x2>()))) return s;
+  }
   d->grid_var = false;
   if (!d->fast_mpad && !fast_disabled()) {
     for (const GridVariant& gv : GRID_VARIANTS)
@@ -1264,8 +1339,13 @@ helic_status ensure_device(helic_basis_s* h) {
         (s = set_fast_limits<float, bf16x2>()))
       return s;
     d->ang_slots64 = fast_slots<double, cplx<double>>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu);
-    d->ang_slots32 = fast_slots<float, cplx<float>>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu);
-    d->ang_slots16 = fast_slots<float, bf16x2>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu);
+    if (d->split_ntf) {
+      d->ang_slots32 = split_slots<cplx<float>>(h->n_t1, h->n_t2, d->fast_mpad, d->split_ntf, ncu);
+      d->ang_slots16 = split_slots<bf16x2>(h->n_t1, h->n_t2, d->fast_mpad, d->split_ntf, ncu);
+    } else {
+      d->ang_slots32 = fast_slots<float, cplx<float>>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu);
+      d->ang_slots16 = fast_slots<float, bf16x2>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu);
+    }
     const int rs = ang_rs(h->n_t2);
     std::vector<int32_t> mp(h->modes.size());
     for (size_t i = 0; i < h->modes.size(); ++i) {
@@ -1350,6 +1430,7 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.lds_ang64 = angular_lds_bytes(h, sizeof(double));
   ls.fast_mpad = d->fast_mpad;
   ls.fast_ntf = d->fast_ntf;
+  ls.split_ntf = d->split_ntf;
   ls.grid_var = d->grid_var;
   ls.vchunk = d->vchunk;
   ls.ang_slots64 = d->ang_slots64;
@@ -1435,7 +1516,14 @@ helic_status launch_stages(const LaunchSet& ls, const double* X, int64_t ldx, do
                              ls.ngroups, ls.n_r, ls.groups, probs, e(0), e(1));
   }
   HIP_TRY(hipGetLastError());
-  if (ls.fast_mpad) {
+  bool split = false;
+  if constexpr (!std::is_same<T, double>::value) split = ls.fast_mpad && ls.split_ntf;
+  if (split) {
+    if constexpr (!std::is_same<T, double>::value) {
+      helic_status s = launch_split<E>(ls, gh, nvec, st, e(2), e(3));
+      if (s != HELIC_OK) return s;
+    }
+  } else if (ls.fast_mpad) {
     helic_status s = launch_fast<T, E>(ls, gh, nvec, st, e(2), e(3));
     if (s != HELIC_OK) return s;
   } else if (ls.grid_var) {

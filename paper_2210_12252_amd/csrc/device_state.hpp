@@ -44,6 +44,8 @@ struct DeviceState {
   // specialised angular stage (theta1 convolution with the spectrum of V)
   int fast_mpad = 0;              // 0: use the general angular kernel
   int fast_ntf = 256;
+  int split_ntf = 0;              // > 0: the split theta1 FFT kernel serves this grid in FP32
+                                  // arithmetic (its block size)
   int m_min = 0, m_count = 0;
   bool grid_var = false;          // the register-FFT angular kernel serves this grid
   int vchunk = 0;                 // (problem, radius, vector) items per workgroup of the specialised
@@ -94,7 +96,7 @@ struct LaunchSet {
   int nprob = 1;
   int n_r = 0, n_t1 = 0, n_t2 = 0;
   size_t lds_inv64 = 0, lds_fwd64 = 0, lds_ang64 = 0, lds_fast64 = 0;   // FP32 uses half
-  int fast_mpad = 0, fast_ntf = 256, vchunk = 0;
+  int fast_mpad = 0, fast_ntf = 256, split_ntf = 0, vchunk = 0;
   int ang_slots64 = 1, ang_slots32 = 1, ang_slots16 = 1;
   bool grid_var = false;
   size_t lds_inv16 = 0, lds_fwd16 = 0;   // LDS bytes of the BF16 radial kernels

@@ -251,6 +251,37 @@ def test_apply_H_parity_64_column_block():
         assert err < tol
 
 
+@pytest.mark.parametrize("workload,n1,n2,ecut", [("nanowire-ecut30", 32, 81, 30.0), ("nanotube-ecut25", 48, 64, 34.0)])
+def test_split_angular_kernel_parity(workload, n1, n2, ecut, monkeypatch):
+    """Grids served by the split theta1-FFT angular kernel in the FP32 and
+    BF16 modes (32 x 81 with all 25 m rows in use, 48 x 64 with 25 of 28
+    padded rows), 40 radii, a ragged block of 21 vectors: every output element
+    against the oracle, and against the convolution kernel
+    (HELIC_ANGULAR_SPLIT=0) on the same inputs (FP64 runs the convolution
+    kernel in both)."""
+    w = synth.workload(workload).with_(name=f"{workload}-split", ecut=ecut, n_t1=n1, n_t2=n2, n_r=40)
+    c = Case(w)
+    c.upload_V()
+    monkeypatch.setenv("HELIC_ANGULAR_SPLIT", "0")
+    conv = helic.Basis.from_workload(w)
+    conv.set_potential(torch.from_numpy(c.V).to(_dev()))
+    monkeypatch.delenv("HELIC_ANGULAR_SPLIT")
+    X = synth.random_block(c.o.mnk, 21, 4243)
+    ref = oh.apply(c.o, c.V, X)
+    Xg = c.to_gpu_block(X)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32), ("bf16", TOL16)):
+        Yg = torch.zeros((21, c.o.L), dtype=torch.complex128, device=_dev())
+        Yc = torch.zeros_like(Yg)
+        c.g.apply_H(Xg, Yg, prec=prec)
+        conv.apply_H(Xg, Yc, prec=prec)
+        err = _rel(c.from_gpu_block(Yg), ref)
+        agree = (torch.abs(Yg - Yc).max() / torch.abs(Yc).max()).item()
+        print(f"[split {n1}x{n2} {prec}] rel err {err:.2e}, vs convolution kernel {agree:.2e}", flush=True)
+        assert err < tol
+        assert agree < tol
+    conv.close()
+
+
 def test_general_and_specialised_angular_kernels_agree(tiny, monkeypatch):
     """The general LDS-FFT angular kernel and the specialised convolution
     kernel compute the same operator (both are checked against the oracle
