@@ -7,7 +7,8 @@
         --copy-bytes B --nvec V --hash H --workload W [--command C]
 
 Prints a short markdown table: per kernel the dispatch count and the mean /
-min / max duration in microseconds (``stats``), or the mean of every
+min / max duration in microseconds, and the mean over the later half of the
+dispatches (``stats``), or the mean of every
 collected counter per dispatch (``counters``).  Kernel names are shortened
 to the function name and its template arguments.
 
@@ -45,10 +46,18 @@ def short_name(name: str) -> str:
 
 
 def kernel_stats(db: str):
+    """Per kernel: dispatches, mean / min / max / total duration (us) and the
+    mean over the later half of its dispatches in launch order (with as many
+    timed steps as warm-up steps, the timed steps of the bench command)."""
     c = sqlite3.connect(db)
     rows = c.execute("select name, count(*), avg(duration), min(duration), max(duration), sum(duration) "
                      "from kernels group by name order by sum(duration) desc").fetchall()
-    return [(short_name(n), cnt, avg / 1e3, mn / 1e3, mx / 1e3, tot / 1e3) for n, cnt, avg, mn, mx, tot in rows]
+    out = []
+    for n, cnt, avg, mn, mx, tot in rows:
+        durs = [d for (d,) in c.execute("select duration from kernels where name = ? order by start", (n,))]
+        late = durs[len(durs) // 2:]
+        out.append((short_name(n), cnt, avg / 1e3, mn / 1e3, mx / 1e3, tot / 1e3, sum(late) / len(late) / 1e3))
+    return out
 
 
 def counter_means(db: str):
@@ -183,10 +192,10 @@ def main(argv=None):
         for r in rows:
             out.append(f"- `{r['kernel']}`: " + ", ".join(f"{k} {v:.4g}" for k, v in sorted(r["raw"].items())))
     elif a.mode == "stats":
-        out.append("| kernel | dispatches | mean us | min us | max us | total us |")
-        out.append("|---|---:|---:|---:|---:|---:|")
-        for n, cnt, avg, mn, mx, tot in kernel_stats(a.db):
-            out.append(f"| `{n}` | {cnt} | {avg:.2f} | {mn:.2f} | {mx:.2f} | {tot:.1f} |")
+        out.append("| kernel | dispatches | mean us | mean us, later half | min us | max us | total us |")
+        out.append("|---|---:|---:|---:|---:|---:|---:|")
+        for n, cnt, avg, mn, mx, tot, late in kernel_stats(a.db):
+            out.append(f"| `{n}` | {cnt} | {avg:.2f} | {late:.2f} | {mn:.2f} | {mx:.2f} | {tot:.1f} |")
     else:
         out.append("| kernel | counter | mean per dispatch | dispatches |")
         out.append("|---|---|---:|---:|")
