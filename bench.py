@@ -1,6 +1,6 @@
 """Benchmark of the helical-wave Hamiltonian apply on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload nanowire-ecut30]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 30] [--workload nanowire-ecut30]
 
 One step applies H to a block of 64 coefficient vectors of the largest
 single-GPU workload (the filled nanowire, 88,951 basis functions): the whole
@@ -465,7 +465,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", default="nanowire-ecut30", help="headline H*X workload")
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32", "bf16"))
     ap.add_argument("--cpu-sample", type=int, default=64, help="vectors for the CPU oracle leg (0: skip)")
