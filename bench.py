@@ -203,7 +203,7 @@ def time_to_eigenpairs(b, w, torch, tol=1e-8, solvers=("lobpcg", "chefsi"), tabl
                          f"{w.nev}\n\n")
                 fh.write("Filtered subspace iteration from the same seeded start; |lambda - lambda_FP64| in Ha "
                          "against its FP64 solve (tol 1e-8).  'before': the ladder stopped at its first "
-                         "precision switch (FP32: residual <= 1e-4, BF16: <= 3e-2); 'after': refined to 1e-8 in "
+                         "precision switch (FP32: residual <= 1e-5, BF16: <= 1e-2); 'after': refined to 1e-8 in "
                          "FP64.\n\n")
                 fh.write("Command: `python bench.py --eig-table <this file>` (the eigensolve leg).\n\n")
                 fh.write("| j | lambda_FP64 (Ha) | FP32 before | FP32 after | BF16 before | BF16 after |\n")

@@ -205,7 +205,9 @@ helic_status helic_precondition(helic_basis h, const double* Rres, int64_t ldr, 
 /* Lowest nev eigenpairs by block LOBPCG (Sec. 3.5) with the preconditioner
  * above, FP64 Rayleigh-Ritz, H applied in `prec` with a final FP64
  * refinement when prec != HELIC_FP64 (a precision ladder: BF16 until the
- * worst wanted residual is below 3e-2, FP32 until 1e-4, then FP64).  Converged when every
+ * worst wanted residual is below 1e-2, FP32 until 1e-5, then FP64; a lower
+ * rung also ends when that residual has not improved by 10 % for 10
+ * iterations, or 3 filter steps in the filtered solver).  Converged when every
  * ||H x - lambda x||_2 <= tol with ||x||_2 = 1.  evals, resid (host, nev):
  * eigenvalues ascending and residual norms; evecs (device, ld >= L, nev
  * columns) may be NULL; iters (host) may be NULL.  seed fixes the random
@@ -226,10 +228,12 @@ typedef struct {
   int32_t precond;    /* 0: Teter-Payne-Allan, 1: none, 2: learned (helic_lpc_*)       */
   int32_t guard;      /* extra iterated columns beyond nev (-1: automatic)             */
   double switch_tol;  /* FP32/BF16: residual below which FP64 applications take over  */
+                      /* (0: 1e-5)                                                     */
   int32_t log_every;  /* > 0: one progress line on stderr every log_every iterations   */
-  double switch_tol_bf16; /* BF16 mode: residual below which FP32 takes over (0: 3e-2)  */
-  int32_t stop_low;   /* 1: stop at the first precision switch (results of the lower   */
-                      /* precision alone, for error studies); 0: refine to tol in FP64  */
+  double switch_tol_bf16; /* BF16 mode: residual below which FP32 takes over (0: 1e-2)  */
+  int32_t stop_low;   /* 1: stop at the first precision switch, by tolerance or by     */
+                      /* stagnation (results of the lower precision alone, for error   */
+                      /* studies); 0: refine to tol in FP64                            */
 } helic_solve_opts;
 
 typedef struct {

@@ -314,9 +314,25 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
   const int chunk = std::max(1, std::min(o.block, 64));
   const int kmax = 3 * n;
   helic_prec prec = (helic_prec)o.prec;
-  const double switch_tol = o.switch_tol > 0 ? o.switch_tol : 1e-4;
+  const double switch_tol = o.switch_tol > 0 ? o.switch_tol : 1e-5;
   // BF16 start: FP32 takes over below switch_bf16, FP64 below switch_tol
-  const double switch_bf16 = std::max(switch_tol, o.switch_tol_bf16 > 0 ? o.switch_tol_bf16 : 3e-2);
+  const double switch_bf16 = std::max(switch_tol, o.switch_tol_bf16 > 0 ? o.switch_tol_bf16 : 1e-2);
+  // A low-precision phase also ends when its worst wanted residual has not
+  // improved by 10 % for this many iterations (filter steps): below the
+  // precision's own error floor its switch tolerance may be out of reach.
+  const int stall_limit = cheb_degree > 0 ? 3 : 10;
+  double phase_best = HUGE_VAL;
+  int phase_stall = 0;
+  auto stalled = [&](double worst) {
+    if (prec == HELIC_FP64) return false;
+    if (worst < 0.9 * phase_best) {
+      phase_best = worst;
+      phase_stall = 0;
+    } else {
+      ++phase_stall;
+    }
+    return phase_stall >= stall_limit;
+  };
   auto prec_name = [&]() { return prec == HELIC_FP64 ? "FP64" : prec == HELIC_FP32 ? "FP32" : "BF16"; };
   // lock tolerance of the low-precision phases: where their H*X stops improving a column
   auto phase_tol = [&]() { return prec == HELIC_FP64 ? o.tol : std::max(o.tol, prec == HELIC_FP32 ? switch_tol : switch_bf16); };
@@ -714,13 +730,16 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
         converged = true;
         break;
       }
-      const bool to64 = prec != HELIC_FP64 && worst <= switch_tol;
-      const bool to32 = !to64 && prec == HELIC_BF16 && worst <= switch_bf16;
+      const bool stagnant = stalled(worst);
+      const bool to64 = prec != HELIC_FP64 && (worst <= switch_tol || (stagnant && prec == HELIC_FP32));
+      const bool to32 = !to64 && prec == HELIC_BF16 && (worst <= switch_bf16 || stagnant);
       if ((to64 || to32) && o.stop_low) {
         stopped_low = true;
         break;
       }
       if (to64 || to32) {
+        phase_best = HUGE_VAL;
+        phase_stall = 0;
         // precision ladder: H X in the next precision and a fresh
         // Rayleigh-Ritz over every column (the locks of the lower phase are
         // released), then filters in that precision
@@ -874,13 +893,16 @@ helic_status eigensolve_impl(helic_basis_s* h, const helic_solve_opts& o, double
         converged = true;
         break;
       }
-      const bool to64 = prec != HELIC_FP64 && worst <= switch_tol;
-      const bool to32 = !to64 && prec == HELIC_BF16 && worst <= switch_bf16;
+      const bool stagnant = stalled(worst);
+      const bool to64 = prec != HELIC_FP64 && (worst <= switch_tol || (stagnant && prec == HELIC_FP32));
+      const bool to32 = !to64 && prec == HELIC_BF16 && (worst <= switch_bf16 || stagnant);
       if ((to64 || to32) && o.stop_low) {
         stopped_low = true;
         break;
       }
       if (to64 || to32) {
+        phase_best = HUGE_VAL;
+        phase_stall = 0;
         // precision ladder: recompute H X and H P in the next precision and go on
         prec = to64 ? HELIC_FP64 : HELIC_FP32;
         exact_x = false;   // H X recomputed: X^H H X is no longer exactly diagonal
@@ -1117,7 +1139,7 @@ helic_status helic_eigensolve(helic_basis h, int32_t nev, int32_t block, double 
   o.seed = seed;
   o.precond = 0;
   o.guard = -1;
-  o.switch_tol = 1e-4;
+  o.switch_tol = 1e-5;
   o.log_every = 0;
   helic_solve_stats st;
   std::memset(&st, 0, sizeof(st));

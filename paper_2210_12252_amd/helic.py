@@ -363,7 +363,7 @@ def eigensolve(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, evecs
 
 
 def eigensolve_ex(h, nev, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa", guard=-1,
-                  switch_tol=1e-4, evecs=None, log_every=0, stream=None, cheb_degree=None, switch_tol_bf16=0.0,
+                  switch_tol=0.0, evecs=None, log_every=0, stream=None, cheb_degree=None, switch_tol_bf16=0.0,
                   stop_low=False):
     """Returns (evals, resid, stats dict, status); raises on errors other
     than non-convergence.  cheb_degree (an int, 0 = automatic) selects the
@@ -526,7 +526,7 @@ class Batch:
         return n.value
 
     def eigensolve(self, nev, nstreams=8, block=64, tol=1e-8, maxit=500, prec="fp64", seed=7, precond="tpa",
-                   guard=-1, switch_tol=1e-4, log_every=0, cheb_degree=None):
+                   guard=-1, switch_tol=0.0, log_every=0, cheb_degree=None):
         """cheb_degree (an int, 0 = automatic) selects the Chebyshev-filtered
         subspace iteration instead of LOBPCG."""
         n = len(self.bases)
@@ -669,7 +669,7 @@ class Basis:
         T = torch.zeros_like(R)
         lam = torch.zeros(max_cols, dtype=torch.float64, device=dev)
         o = SolveOpts(nev=nev, block=block, tol=tol, maxit=maxit, prec=FP64, seed=seed,
-                      precond=PRECOND[precond], guard=guard, switch_tol=1e-4, log_every=log_every)
+                      precond=PRECOND[precond], guard=guard, switch_tol=0.0, log_every=log_every)
         ncol = ctypes.c_int32(0)
         st = SolveStats()
         _check(load().helic_lpc_harvest(self.h, ctypes.byref(o), n_snap, max_cols, ctypes.c_void_p(R.data_ptr()),
