@@ -259,7 +259,7 @@ def angular_kernel_name(n1, n2):
     return "register-fft" if (n1, n2) in REGFFT_GRIDS else "general"
 
 
-def batched_leg(torch, structures, nvec=8, steps=20, nev=60, tol=1e-8, extra=False, eig_every=8):
+def batched_leg(torch, structures, nvec=8, steps=20, nev=60, tol=1e-8, extra=False, eig_every=8, prec="fp32"):
     """Many Bloch parameters of seeded structures (64 eta each, R ~ U[5, 12],
     E_cut ~ U[15, 35]), all in ONE batch: per structure a common grid (the
     largest automatic grid over its eta), so the batch holds one class per
@@ -331,14 +331,15 @@ def batched_leg(torch, structures, nvec=8, steps=20, nev=60, tol=1e-8, extra=Fal
                tuning=tuning, ms_per_batched_apply=round(1e3 * dt, 3),
                vec_applies_per_s=round(len(bases) * nvec / dt, 1), bf16_ms_per_batched_apply=round(1e3 * dt16, 3),
                bf16_vec_applies_per_s=round(len(bases) * nvec / dt16, 1))
-    # every problem: filtered solver, FP32 -> FP64 ladder, time-reversal halving
+    # every problem: filtered solver, precision ladder from `prec`, time-reversal halving
     npairs = batch.time_reversal(True)
     torch.cuda.synchronize()
     te = time.perf_counter()
-    ev, res, st, status = batch.eigensolve(nev, nstreams=8, tol=tol, maxit=200, cheb_degree=0, prec="fp32")
+    ev, res, st, status = batch.eigensolve(nev, nstreams=8, tol=tol, maxit=200, cheb_degree=0, prec=prec)
     te = time.perf_counter() - te
     batch.time_reversal(False)
-    out.update(eig_problems=len(bases), eig_nev=nev, eig_prec="fp32 -> fp64 ladder", time_reversal_pairs=npairs,
+    ladder = {"fp64": "fp64", "fp32": "fp32 -> fp64 ladder", "bf16": "bf16 -> fp32 -> fp64 ladder"}[prec]
+    out.update(eig_problems=len(bases), eig_nev=nev, eig_prec=ladder, time_reversal_pairs=npairs,
                eig_seconds=round(te, 2), eig_converged=int(np.sum(status == 0)), eig_max_resid=float(res.max()))
     for rec in per:
         a = rec.pop("first")
@@ -477,6 +478,8 @@ def main(argv=None):
     ap.add_argument("--eig-table", default="", help="write the per-eigenvalue error table to this path")
     ap.add_argument("--batched", default="all",
                     help="structures (0..7, comma list, 'all' or 'none') for the batched Bloch-parameter leg")
+    ap.add_argument("--batched-prec", default="fp32", choices=("fp64", "fp32", "bf16"),
+                    help="first rung of the batched leg's eigensolve ladder")
     ap.add_argument("--batched-extra", type=int, default=0,
                     help="batched leg: also LOBPCG and learned-preconditioner solves of every 8th eta")
     ap.add_argument("--learned", default="same",
@@ -651,7 +654,7 @@ def main(argv=None):
         eb.close()
     if args.batched != "none":
         structs = list(range(8)) if args.batched == "all" else [int(x) for x in args.batched.split(",")]
-        line["batched"] = batched_leg(torch, structs, extra=bool(args.batched_extra))
+        line["batched"] = batched_leg(torch, structs, extra=bool(args.batched_extra), prec=args.batched_prec)
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     print(json.dumps(line), flush=True)
