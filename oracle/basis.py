@@ -6,6 +6,9 @@ Paper passages followed:
 * basis functions F_{m,n,k} = c_{nk} exp(i 2 pi (m theta1 + n N theta2))
   J_{nN}(b_k^{nN} r / R), c_{nk} = sqrt(N/(pi tau)) / (R J_{nN+1}(b_k^{nN}))
   -- Sec. 2.3 and App. B (eq. Basis_fun_derived);
+* the operator at cyclic index nu (eq. Simplify_2 and constants_abc): the
+  terms a, b, c and the nu^2 / (2 r^2) and (i nu / (2 pi r^2)) d/dtheta2
+  terms added to -(1/2) Laplacian + V;
 * Laplacian eigenvalue lambda0 = (b/R)^2 + (2 pi/tau)^2 (m - alpha n N)^2
   -- eq. Laplacian_of_f_mnk;
 * kinetic-energy cutoff (1/2) lambda0 <= E_cut, applied at each Bloch point
@@ -22,6 +25,15 @@ Readings where the paper is silent (each listed in the design notes):
   operator and the cutoff is kappa = (1/2)[(b/R)^2 + (2 pi/tau)^2
   (m - alpha n - eta)^2], which equals Alg. 5's (1/2)Lambda - a - b M - c N
   with the constants of eq. constants_abc (checked in the tests).
+* Cyclic index nu != 0: the paper keeps J_{nN} and represents the 1/r^2
+  terms by the integrals I(n, k, k') of eq. I_nkk_prime, which diverge for
+  n = 0.  Acting on exp(i 2 pi n N theta2) R(r), those terms turn the Bessel
+  operator of order nN into that of order nN - nu, so the radial functions
+  here are J_p(b_k^p r / R) with p = nN - nu (zeros of J_|p|, the paper's
+  signed normalisation with J_{p+1}): the same operator in the basis that
+  diagonalises its kinetic part, kappa = (1/2)[(b^|p| / R)^2 + (2 pi/tau)^2
+  (m - alpha (nN - nu) - eta)^2], and no I table.  At nu = 0 it is the
+  paper's basis.
 * Mode (m, n) sits at DFT bin (m mod N_theta1, n mod N_theta2).
 * Index clamps default to what the grid resolves; an automatic grid uses the
   smallest 2,3,5-smooth sizes >= 2 max|m| + 2 and 2 max|n| + 2, and
@@ -76,6 +88,11 @@ class Basis:
     q: np.ndarray            # (n_r,) radial nodes on [0, 1]
     wq: np.ndarray           # (n_r,) weights for int_0^1 f(q) q dq
     ncyc: int = 1
+    nu: int = 0
+
+    def order(self, n):
+        """Bessel order p = n N - nu of angular index n."""
+        return n * self.ncyc - self.nu
 
     @property
     def L(self) -> int:
@@ -100,21 +117,21 @@ class Basis:
     def xi(self, n: int, k: np.ndarray, r: np.ndarray | None = None) -> np.ndarray:
         """Radial functions xi_{n,k}(r) on the radial grid (or at ``r``),
         shape (len(r), len(k)), with the paper's signed normalisation
-        sqrt(N/(pi tau)) J_{nN}(b r/R) / (R J_{nN+1}(b)) (App. B)."""
+        sqrt(N/(pi tau)) J_p(b r/R) / (R J_{p+1}(b)), p = nN - nu (App. B)."""
         rr = self.r if r is None else np.asarray(r, dtype=np.float64)
         k = np.asarray(k, dtype=np.int64)
-        p = n * self.ncyc
+        p = self.order(n)
         b = bessel_zeros(p, int(k.max()) if k.size else 0)[k - 1] if k.size else np.zeros(0)
         c = math.sqrt(self.ncyc / (math.pi * self.tau)) / (self.R * sp.jv(p + 1, b))
         return sp.jv(p, np.outer(rr, b) / self.R) * c[None, :]
 
 
-def kinetic_diagonal(bz, m, n, R, tau, alpha, eta, ncyc=1):
-    """kappa = (1/2)[(b/R)^2 + (2 pi/tau)^2 (m - alpha n N - eta)^2] (nu = 0,
-    cyclic order N)."""
+def kinetic_diagonal(bz, m, n, R, tau, alpha, eta, ncyc=1, nu=0):
+    """kappa = (1/2)[(b/R)^2 + (2 pi/tau)^2 (m - alpha (n N - nu) - eta)^2]
+    (cyclic order N, cyclic index nu)."""
     m = np.asarray(m, dtype=np.float64)
     n = np.asarray(n, dtype=np.float64)
-    return 0.5 * ((np.asarray(bz) / R) ** 2 + (2.0 * math.pi / tau) ** 2 * (m - alpha * n * ncyc - eta) ** 2)
+    return 0.5 * ((np.asarray(bz) / R) ** 2 + (2.0 * math.pi / tau) ** 2 * (m - alpha * (n * ncyc - nu) - eta) ** 2)
 
 
 def kinetic_alg5(bz, m, n, R, tau, alpha, eta, nu=0, ncyc=1):
@@ -135,13 +152,13 @@ def make_basis(R, tau, alpha, ecut, eta=0.0, m_max=-1, n_max=-1, k_max=-1,
                n_t1=0, n_t2=0, n_r=0, ncyc=1, nu=0) -> Basis:
     """Enumerate the cutoff-masked index set and build the grid.
 
-    Cyclic order N >= 1 (Sec. 2.3): mode (m, n) has the angular factor
-    exp(i 2 pi (m theta1 + n N theta2)), the Bessel order |n| N and its
-    zeros, and theta2 spans [0, 1/N).  Raises ValueError on unsupported or
-    inconsistent parameters (nu != 0) and on a cutoff tie (some |kappa -
-    E_cut| < 1e-10)."""
-    if ncyc < 1 or nu != 0:
-        raise ValueError("only cyclic order >= 1 with nu = 0 is handled")
+    Cyclic order N >= 1 and index 0 <= nu < N (Sec. 2.3): mode (m, n) has
+    the angular factor exp(i 2 pi (m theta1 + n N theta2)), the Bessel order
+    |n N - nu| and its zeros, and theta2 spans [0, 1/N).  Raises ValueError
+    on inconsistent parameters and on a cutoff tie (some |kappa - E_cut| <
+    1e-10)."""
+    if ncyc < 1 or not (0 <= nu < ncyc):
+        raise ValueError("need cyclic order N >= 1 and 0 <= nu < N")
     if not (R > 0 and tau > 0 and ecut > 0 and 0.0 <= alpha < 1.0 and -0.5 <= eta < 0.5):
         raise ValueError("invalid parameters")
     grid_given = n_t1 > 0 and n_t2 > 0
@@ -153,19 +170,26 @@ def make_basis(R, tau, alpha, ecut, eta=0.0, m_max=-1, n_max=-1, k_max=-1,
         if n_max < 0:
             n_max = (n_t2 - 1) // 2
     two_pi_tau = 2.0 * math.pi / tau
-    # |n| limit from the smallest radial energy j_{|n|,1}^2 / (2 R^2).
+    # n limits from the smallest radial energy j_{|p|,1}^2 / (2 R^2) of the
+    # order p = n N - nu, which grows with |n| on either side
+    def admissible(n):
+        return 0.5 * (bessel_zeros(n * ncyc - nu, 1)[0] / R) ** 2 <= ecut + TIE_TOL
     if n_max < 0:
-        n_lim = 0
-        while 0.5 * (bessel_zeros((n_lim + 1) * ncyc, 1)[0] / R) ** 2 <= ecut + TIE_TOL:
-            n_lim += 1
+        n_hi = 0
+        while admissible(n_hi + 1):
+            n_hi += 1
+        n_lo = 0
+        while admissible(n_lo - 1):
+            n_lo -= 1
     else:
-        n_lim = n_max
+        n_lo, n_hi = -n_max, n_max
     rows = []
-    for n in range(-n_lim, n_lim + 1):
+    for n in range(n_lo, n_hi + 1):
+        p = n * ncyc - nu
         # enough zeros so that the radial energy alone exceeds the cutoff
         cnt = 8
         while True:
-            z = bessel_zeros(n * ncyc, cnt)
+            z = bessel_zeros(p, cnt)
             if 0.5 * (z[-1] / R) ** 2 > ecut + 1.0 or (k_max > 0 and cnt >= k_max):
                 break
             cnt *= 2
@@ -173,12 +197,12 @@ def make_basis(R, tau, alpha, ecut, eta=0.0, m_max=-1, n_max=-1, k_max=-1,
             z = z[:k_max]
         # m range allowed by the axial energy alone
         span = math.sqrt(2.0 * ecut) / two_pi_tau + 1.0
-        c0 = alpha * n * ncyc + eta
+        c0 = alpha * p + eta
         m_lo, m_hi = int(math.floor(c0 - span)), int(math.ceil(c0 + span))
         if m_max >= 0:
             m_lo, m_hi = max(m_lo, -m_max), min(m_hi, m_max)
         for m in range(m_lo, m_hi + 1):
-            kap = kinetic_diagonal(z, m, n, R, tau, alpha, eta, ncyc)
+            kap = kinetic_diagonal(z, m, n, R, tau, alpha, eta, ncyc, nu)
             if np.any(np.abs(kap - ecut) < TIE_TOL):
                 raise ValueError("cutoff tie: a kinetic energy equals E_cut to 1e-10")
             for k in np.nonzero(kap <= ecut)[0]:
@@ -207,11 +231,12 @@ def make_basis(R, tau, alpha, ecut, eta=0.0, m_max=-1, n_max=-1, k_max=-1,
                  ecut=float(ecut), n_t1=int(n_t1), n_t2=int(n_t2), n_r=int(n_r),
                  mnk=mnk, bzero=bz, kappa=kap,
                  theta1=np.arange(n_t1) / n_t1, theta2=np.arange(n_t2) / (ncyc * n_t2),
-                 q=q, wq=wq, ncyc=ncyc)
+                 q=q, wq=wq, ncyc=ncyc, nu=nu)
 
 
 def basis_for(workload) -> Basis:
     """Basis of a ``synth.Workload`` (duck-typed: reads its attributes)."""
     w = workload
     return make_basis(w.R, w.tau, w.alpha, w.ecut, eta=w.eta, m_max=w.m_max, n_max=w.n_max,
-                      k_max=w.k_max, n_t1=w.n_t1, n_t2=w.n_t2, n_r=w.n_r, ncyc=getattr(w, "ncyc", 1))
+                      k_max=w.k_max, n_t1=w.n_t1, n_t2=w.n_t2, n_r=w.n_r, ncyc=getattr(w, "ncyc", 1),
+                      nu=getattr(w, "nu", 0))

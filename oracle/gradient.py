@@ -27,7 +27,7 @@ def radial_derivative(b: Basis, n: int, k: np.ndarray, r: np.ndarray | None = No
     """d xi_{n,k}/dr on the radial grid (or at ``r``), shape (len(r), len(k))."""
     rr = b.r if r is None else np.asarray(r, dtype=np.float64)
     k = np.asarray(k, dtype=np.int64)
-    p = n * b.ncyc
+    p = b.order(n)
     bz = bessel_zeros(p, int(k.max()))[k - 1]
     c = math.sqrt(b.ncyc / (math.pi * b.tau)) / (b.R * sp.jv(p + 1, bz))
     return sp.jvp(p, np.outer(rr, bz) / b.R) * (c * bz / b.R)[None, :]

@@ -8,7 +8,7 @@ real-space grid ``n_t1 x n_t2 x n_r`` (axial Fourier nodes x angular Fourier
 nodes x radial Gauss-Jacobi nodes).  Index clamps of -1 and grid sizes of 0
 mean "derive from the cutoff / the grid".  The cyclic order is 1 unless a
 workload sets ``ncyc`` (an ncyc-fold symmetric structure, theta2 in
-[0, 1/ncyc)).
+[0, 1/ncyc)), with cyclic Bloch index ``nu`` (0 unless set).
 
 The index letters follow the paper: m is the Fourier index along theta1 (the
 axial coordinate z / tau), n the Fourier index along theta2 (the angular
@@ -39,11 +39,12 @@ class Workload:
     structure: str = "none"      # key understood by synth.structures.atoms_for
     seed: int = 0
     ncyc: int = 1                # cyclic order: theta2 spans [0, 1/ncyc)
+    nu: int = 0                  # cyclic Bloch index, 0 <= nu < ncyc
 
     def params(self) -> dict:
         """Plain parameter dictionary in the library's parameter-struct order."""
         return dict(R=self.R, tau=self.tau, alpha=self.alpha, ncyc=self.ncyc,
-                    ecut=self.ecut, eta=self.eta, nu=0,
+                    ecut=self.ecut, eta=self.eta, nu=self.nu,
                     m_max=self.m_max, n_max=self.n_max, k_max=self.k_max,
                     n_t1=self.n_t1, n_t2=self.n_t2, n_r=self.n_r)
 

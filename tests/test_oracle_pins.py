@@ -170,6 +170,81 @@ def test_kinetic_diagonal_is_eigenvalue_of_cartesian_laplacian():
             assert abs(-0.5 * lap - b.kappa[i] * p0) < 1e-5 * max(1.0, b.kappa[i]) * max(abs(p0), 1e-2), (i, rr)
 
 
+@pytest.mark.parametrize("ncyc,nu", [(2, 1), (3, 2), (4, 1)])
+def test_cyclic_index_kinetic_diagonal_is_eigenvalue_of_cartesian_laplacian(ncyc, nu):
+    """Cyclic index nu != 0: the Bloch wave exp(-i 2 pi (eta theta1 + nu
+    theta2)) F_{m,n,k}, with the radial function of order nN - nu, is an
+    eigenfunction of -1/2 Laplacian (Cartesian, 4th-order finite differences)
+    with eigenvalue kappa = (1/2)[(b/R)^2 + (2 pi/tau)^2 (m - alpha (nN - nu)
+    - eta)^2]: the reading of the nu terms of eq. Simplify_2 is the free
+    particle's own operator, and its kinetic part is diagonal."""
+    b = ob.make_basis(R=6.0, tau=5.0, alpha=0.3, ecut=6.0, eta=0.2, ncyc=ncyc, nu=nu)
+    rng = np.random.default_rng(5 + nu)
+    picks = rng.choice(b.L, size=6, replace=False)
+    assert np.any(b.mnk[:, 1] == 0)
+
+    def psi(i, x, y, z):
+        m, n, k = b.mnk[i]
+        r = math.hypot(x, y)
+        th1 = z / b.tau
+        th2 = math.atan2(y, x) / (2 * math.pi) - b.alpha * z / b.tau
+        rad = b.xi(int(n), np.array([k]), np.array([r]))[0, 0]
+        return (np.exp(-2j * math.pi * (b.eta * th1 + nu * th2))
+                * np.exp(2j * math.pi * (m * th1 + n * ncyc * th2)) * rad)
+
+    h = 1e-2
+    c = np.array([-1.0, 16.0, -30.0, 16.0, -1.0]) / (12 * h * h)
+    for i in list(picks) + list(np.nonzero(b.mnk[:, 1] == 0)[0][:2]):
+        for _ in range(3):
+            rr = rng.uniform(1.0, b.R - 1.0)
+            ph = rng.uniform(0, 2 * math.pi)
+            x0, y0, z0 = rr * math.cos(ph), rr * math.sin(ph), rng.uniform(0, b.tau)
+            lap = 0.0
+            for e in np.eye(3):
+                vals = [psi(i, x0 + s * h * e[0], y0 + s * h * e[1], z0 + s * h * e[2]) for s in (-2, -1, 0, 1, 2)]
+                lap += np.dot(c, vals)
+            p0 = psi(i, x0, y0, z0)
+            assert abs(-0.5 * lap - b.kappa[i] * p0) < 1e-5 * max(1.0, b.kappa[i]) * max(abs(p0), 1e-2), (i, rr)
+
+
+@pytest.mark.parametrize("ncyc,nu", [(2, 1), (3, 1), (3, 2)])
+def test_cyclic_index_operator_is_a_sector_of_the_order_one_operator(ncyc, nu):
+    """Cyclic index nu != 0 (Sec. 2.3): for an N-fold symmetric potential the
+    order-1 operator's angular indices n' = nN - nu (n' = -nu mod N) form a
+    block, and that block is the (N, nu) operator entry for entry: same index
+    set (radial order |n'|, kinetic energy with alpha n'), same matrix,
+    although the (N, nu) basis lives on the wedge theta2 in [0, 1/N) with the
+    Bloch factor exp(-i 2 pi nu theta2) taken out.  The cutoff, not the grid,
+    limits n' here, so both index sets are complete."""
+    n1, n2, nr = 12, 16, 32
+    kw = dict(R=6.5, tau=5.0, alpha=0.15, ecut=3.5, eta=0.2, n_t1=n1, n_r=nr)
+    bN = ob.make_basis(n_t2=n2, ncyc=ncyc, nu=nu, **kw)
+    b1 = ob.make_basis(n_t2=ncyc * n2, ncyc=1, **kw)
+    assert np.abs(b1.mnk[:, 1]).max() < (ncyc * n2 - 1) // 2 and np.abs(bN.mnk[:, 1]).max() < (n2 - 1) // 2
+    motif = synth.atoms_for("helix6", 8, bN.tau, bN.R)[:2]
+    atoms = synth.cyclic_images(motif, ncyc)
+    V1 = synth.potential_at(b1.theta1, b1.theta2, b1.r, b1.tau, b1.alpha, atoms)
+    VN = synth.potential_at(bN.theta1, bN.theta2, bN.r, bN.tau, bN.alpha, atoms)
+    H1 = oh.dense_explicit(b1, V1)
+    HN = oh.dense_explicit(bN, VN)
+    sector = np.nonzero((b1.mnk[:, 1] + nu) % ncyc == 0)[0]
+    other = np.nonzero((b1.mnk[:, 1] + nu) % ncyc != 0)[0]
+    assert np.max(np.abs(H1[np.ix_(sector, other)])) < 1e-13 * np.max(np.abs(H1))
+    key1 = {(int(m), (int(n) + nu) // ncyc, int(k)): i for i, (m, n, k) in enumerate(b1.mnk[sector])}
+    keyN = [(int(m), int(n), int(k)) for m, n, k in bN.mnk]
+    assert sorted(key1) == sorted(keyN)
+    perm = np.array([sector[key1[t]] for t in keyN])
+    np.testing.assert_allclose(bN.kappa, b1.kappa[perm], rtol=1e-15)
+    assert np.max(np.abs(HN - H1[np.ix_(perm, perm)])) < 1e-13
+    lamN = oh.lowest(HN, 10)[0]
+    lam1 = np.linalg.eigvalsh(H1[np.ix_(sector, sector)])[:10]
+    assert np.max(np.abs(lamN - lam1)) < 1e-12
+    # the mode-B form and the matrix-free apply agree with mode A
+    assert np.max(np.abs(oh.dense_dft(bN, VN) - HN)) < 1e-13
+    X = synth.random_block(bN.mnk, 3, 2)
+    assert np.max(np.abs(oh.apply(bN, VN, X) - HN @ X)) < 1e-13
+
+
 # ------------------------------------------------------------------ transforms
 def test_fast_equals_naive_transforms(tiny):
     """The paper's own check: separated sums agree with the naive sums."""
@@ -344,6 +419,21 @@ def test_time_reversal():
     bp = small_basis(eta=0.23)
     bm = small_basis(eta=-0.23)
     atoms = synth.atoms_for("helix6", 6, bp.tau, bp.R)
+    V = synth.potential_at(bp.theta1, bp.theta2, bp.r, bp.tau, bp.alpha, atoms)
+    assert bp.L == bm.L
+    evp, _ = oh.lowest(oh.dense_dft(bp, V), 10)
+    evm, _ = oh.lowest(oh.dense_dft(bm, V), 10)
+    np.testing.assert_allclose(evp, evm, atol=1e-12)
+
+
+@pytest.mark.parametrize("ncyc,nu", [(3, 1), (4, 1), (4, 2)])
+def test_time_reversal_with_cyclic_index(ncyc, nu):
+    """lambda_j(eta, nu) = lambda_j(-eta, N - nu) for a real N-fold symmetric
+    potential (Sec. 3.3); at nu = N/2 the index is its own partner."""
+    kw = dict(R=6.5, tau=5.0, alpha=0.15, ecut=5.0, n_t1=12, n_t2=16, n_r=32, ncyc=ncyc)
+    bp = ob.make_basis(eta=0.23, nu=nu, **kw)
+    bm = ob.make_basis(eta=-0.23, nu=(ncyc - nu) % ncyc, **kw)
+    atoms = synth.cyclic_images(synth.atoms_for("helix6", 8, bp.tau, bp.R)[:2], ncyc)
     V = synth.potential_at(bp.theta1, bp.theta2, bp.r, bp.tau, bp.alpha, atoms)
     assert bp.L == bm.L
     evp, _ = oh.lowest(oh.dense_dft(bp, V), 10)
