@@ -4,20 +4,27 @@
  * The library applies the discrete Hamiltonian of the helical-wave spectral
  * method (Agarwal & Banerjee, arXiv 2210.12252) to blocks of coefficient
  * vectors on one AMD Instinct MI355X (gfx950), and solves for its lowest
- * eigenpairs.  For a Bloch parameter eta and cyclic index nu = 0 the operator
+ * eigenpairs.  For a Bloch parameter eta and cyclic index nu the operator
  * is (Alg. 5, eqs. Simplify_2 and g_mnk)
  *
  *     (H x)_i = kappa_i x_i + [Fwd(V * Inv(x))]_i ,
- *     kappa_i = 1/2 [ (b_k^{|n|N}/R)^2 + (2 pi/tau)^2 (m - alpha N n - eta)^2 ],
+ *     kappa_i = 1/2 [ (b_k^{p}/R)^2 + (2 pi/tau)^2 (m - alpha p_s - eta)^2 ],
+ *     p_s = n N - nu,  p = |p_s|,
  *
  * with Inv the inverse basis transform (Alg. 1 and 2: radial sums per angular
  * mode, then a 2D inverse DFT per radius), V the real potential sampled on the
  * grid and Fwd the quadrature forward transform (Alg. 3 and 4: a 2D DFT per
  * radius, then weighted radial sums).  For cyclic order N (an N-fold
  * symmetric structure; theta2 spans the wedge [0, 1/N)) basis functions are
- * F_{m,n,k} = c_{nk} exp(i 2 pi (m theta1 + n N theta2)) J_{nN}(b_k^{|n|N} r/R),
- * c_{nk} = sqrt(N/(pi tau)) / (R J_{nN+1}(b_k^{|n|N})) (Sec. 2.3, App. B),
- * kept when kappa_i <= E_cut (Sec. 3.2).
+ * F_{m,n,k} = c_{nk} exp(i 2 pi (m theta1 + n N theta2)) J_{p_s}(b_k^{p} r/R),
+ * c_{nk} = sqrt(N/(pi tau)) / (R J_{p_s+1}(b_k^{p})) (Sec. 2.3, App. B),
+ * kept when kappa_i <= E_cut (Sec. 3.2).  At nu = 0 these are the paper's
+ * functions.  For nu != 0 the paper keeps the order nN and adds the
+ * nu^2/(2 r^2) and (i nu/(2 pi r^2)) d/dtheta2 terms of eq. Simplify_2
+ * through the integrals of eq. I_nkk_prime, which diverge for n = 0; those
+ * terms turn the Bessel operator of order nN into that of order nN - nu, so
+ * the library uses radial functions of that order, in which the same
+ * operator's kinetic part is the diagonal kappa above.
  *
  * Conventions shared by all entry points
  * - Every pointer argument documented "device" must point to memory of the
@@ -51,7 +58,7 @@ typedef struct helic_basis_s* helic_basis;
 typedef enum {
   HELIC_OK = 0,
   HELIC_ERR_INVALID = 1,      /* bad argument (null pointer, size, range)         */
-  HELIC_ERR_UNSUPPORTED = 2,  /* cyclic index nu != 0, unknown precision          */
+  HELIC_ERR_UNSUPPORTED = 2,  /* unsupported mode (precision, group width)          */
   HELIC_ERR_GRID = 3,         /* grid too small to resolve the index set           */
   HELIC_ERR_NOMEM = 4,        /* device or host allocation failed                  */
   HELIC_ERR_HIP = 5,          /* a HIP runtime or library call failed              */
@@ -77,7 +84,7 @@ typedef struct {
   int32_t ncyc;   /* cyclic order N, 1..64; theta2 in [0, 1/N)                   */
   double ecut;    /* kinetic-energy cutoff, Ha (> 0), inclusive                  */
   double eta;     /* helical Bloch parameter, -1/2 <= eta < 1/2                  */
-  int32_t nu;     /* cyclic Bloch index; must be 0 (else HELIC_ERR_UNSUPPORTED)  */
+  int32_t nu;     /* cyclic Bloch index, 0 <= nu < ncyc                           */
   int32_t m_max;  /* clamp |m| <= m_max (-1: what the theta1 grid resolves)      */
   int32_t n_max;  /* clamp |n| <= n_max (-1: what the theta2 grid resolves)      */
   int32_t k_max;  /* clamp k <= k_max   (-1: none)                               */
@@ -345,7 +352,8 @@ helic_status helic_batch_eigensolve(helic_batch b, const helic_solve_opts* opts,
  * *npairs (host, may be NULL) receives the number of such problems.
  * enable = 0 solves every problem again.  Reads the potentials back once
  * (synchronous); the pairing holds until the next call, so call again after
- * changing a potential. */
+ * changing a potential.  Partners are (eta, nu) and (-eta, (N - nu) mod N)
+ * (Sec. 3.3). */
 helic_status helic_batch_time_reversal(helic_batch b, int32_t enable, int32_t* npairs);
 /* As helic_batch_eigensolve, each problem by Chebyshev-filtered subspace
  * iteration (helic_eigensolve_chefsi; degree 0 picks 32). */

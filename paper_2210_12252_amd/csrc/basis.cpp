@@ -13,6 +13,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "helic_internal.h"
 #include "setup_math.h"
@@ -55,7 +57,7 @@ std::vector<int32_t> radix_plan(int n) {
 helic_status build(helic_basis_s* h) {
   const helic_params& p = h->p;
   if (p.ncyc < 1 || p.ncyc > 64) return fail(HELIC_ERR_INVALID, "cyclic order must be 1..64");
-  if (p.nu != 0) return fail(HELIC_ERR_UNSUPPORTED, "only the cyclic Bloch index nu = 0 is supported");
+  if (p.nu < 0 || p.nu >= p.ncyc) return fail(HELIC_ERR_INVALID, "cyclic Bloch index nu must be 0..ncyc-1");
   if (!(p.R > 0) || !(p.tau > 0) || !(p.ecut > 0) || !(p.alpha >= 0.0 && p.alpha < 1.0) ||
       !(p.eta >= -0.5 && p.eta < 0.5) || !std::isfinite(p.R) || !std::isfinite(p.tau) ||
       !std::isfinite(p.ecut))
@@ -69,41 +71,66 @@ helic_status build(helic_basis_s* h) {
     if (n_max < 0) n_max = (p.n_t2 - 1) / 2;
   }
   const double R = p.R, tau = p.tau, ecut = p.ecut, alpha = p.alpha, eta = p.eta;
-  // cyclic order: mode (m, n) carries exp(i 2 pi (m theta1 + n N theta2)) and
-  // the Bessel order |n| N (Sec. 2.3); theta2 spans [0, 1/N)
-  const int N = p.ncyc;
+  // cyclic order N and index nu: mode (m, n) carries exp(i 2 pi (m theta1 +
+  // n N theta2)) (Sec. 2.3; theta2 spans [0, 1/N)) and the radial functions of
+  // order p = n N - nu.  At nu = 0 these are the paper's J_{|n| N}.  For
+  // nu != 0 the paper keeps J_{nN} and adds the nu^2 / (2 r^2) and
+  // (i nu / (2 pi r^2)) d/dtheta2 terms of eq. Simplify_2 through the
+  // integrals of eq. I_nkk_prime, which diverge for n = 0; on
+  // exp(i 2 pi n N theta2) those terms turn the Bessel operator of order nN
+  // into that of order nN - nu, so order |nN - nu| diagonalises the same
+  // operator's kinetic part (no integral table).  A group holds the modes of
+  // one Bessel order: n = +-g at nu = 0, usually a single n otherwise.
+  const int N = p.ncyc, nu = p.nu;
   const double w = 2.0 * PI / tau;
   const double xmax = R * std::sqrt(2.0 * ecut);   // largest admissible zero
-  int g_lim = n_max;
-  if (g_lim < 0) {
-    g_lim = 0;
-    while (bessel_zeros((g_lim + 1) * N, 1)[0] <= xmax * (1.0 + 1e-15)) ++g_lim;
+  auto order = [&](int n) { return std::abs(n * N - nu); };
+  int n_lo = -n_max, n_hi = n_max;
+  if (n_max < 0) {
+    n_hi = 0;
+    while (bessel_zeros(order(n_hi + 1), 1)[0] <= xmax * (1.0 + 1e-15)) ++n_hi;
+    n_lo = 0;
+    while (bessel_zeros(order(n_lo - 1), 1)[0] <= xmax * (1.0 + 1e-15)) --n_lo;
   }
+  // orders in increasing value, each with its angular indices (larger n first)
+  std::vector<std::pair<int, std::vector<int>>> ords;
+  for (int n = n_hi; n >= n_lo; --n) {
+    const int o = order(n);
+    auto it = std::find_if(ords.begin(), ords.end(), [&](const std::pair<int, std::vector<int>>& e) {
+      return e.first == o;
+    });
+    if (it == ords.end()) ords.push_back({o, {n}});
+    else it->second.push_back(n);
+  }
+  std::sort(ords.begin(), ords.end(),
+            [](const std::pair<int, std::vector<int>>& a, const std::pair<int, std::vector<int>>& b) {
+              return a.first < b.first;
+            });
   h->modes.clear();
   h->groups.clear();
   int64_t row = 0;
-  for (int g = 0; g <= g_lim; ++g) {
-    // zeros of J_{g N} below xmax (at most k_max of them)
+  for (const auto& on : ords) {
+    const int po = on.first;
+    // zeros of J_po below xmax (at most k_max of them)
     int cnt = (int)(xmax / PI) + 4;
     if (p.k_max > 0) cnt = std::min(cnt, p.k_max);
-    std::vector<double> z = bessel_zeros(g * N, cnt);
+    std::vector<double> z = bessel_zeros(po, cnt);
     while (p.k_max <= 0 && z.back() <= xmax) {
       cnt *= 2;
-      z = bessel_zeros(g * N, cnt);
+      z = bessel_zeros(po, cnt);
     }
     Group grp;
-    grp.g = g;
+    grp.g = po;
     grp.mode0 = (int32_t)h->modes.size();
     grp.row0 = row;
     grp.Kmax = 0;
     const double span = std::sqrt(2.0 * ecut) / w + 1.0;
-    for (int sgn = 0; sgn < (g == 0 ? 1 : 2); ++sgn) {
-      const int n = sgn == 0 ? g : -g;
-      const double c0 = alpha * n * N + eta;
+    for (const int n : on.second) {
+      const double c0 = alpha * (n * N - nu) + eta;
       int mlo = (int)std::floor(c0 - span), mhi = (int)std::ceil(c0 + span);
       if (m_max >= 0) { mlo = std::max(mlo, -m_max); mhi = std::min(mhi, m_max); }
       for (int m = mlo; m <= mhi; ++m) {
-        const double ax = w * (m - alpha * n * N - eta);
+        const double ax = w * (m - alpha * (n * N - nu) - eta);
         int K = 0;
         for (size_t k = 0; k < z.size(); ++k) {
           const double kap = 0.5 * ((z[k] / R) * (z[k] / R) + ax * ax);
@@ -113,7 +140,7 @@ helic_status build(helic_basis_s* h) {
         }
         if (K == 0) continue;
         Mode md;
-        md.m = m; md.n = n; md.g = g; md.K = K; md.row0 = row;
+        md.m = m; md.n = n; md.g = std::abs(n); md.K = K; md.row0 = row;
         md.bin1 = md.bin2 = 0;
         h->modes.push_back(md);
         row += K;
@@ -167,7 +194,7 @@ helic_status build(helic_basis_s* h) {
       md.bin1 = ((md.m % h->n_t1) + h->n_t1) % h->n_t1;
       md.bin2 = ((md.n % h->n_t2) + h->n_t2) % h->n_t2;
       has_row1[md.bin1] = 1;
-      const double ax = w * (md.m - alpha * md.n * N - eta);
+      const double ax = w * (md.m - alpha * (md.n * N - nu) - eta);
       for (int k = 0; k < md.K; ++k) {
         const int64_t r = md.row0 + k;
         h->mnk[3 * r] = md.m; h->mnk[3 * r + 1] = md.n; h->mnk[3 * r + 2] = k + 1;
@@ -219,7 +246,7 @@ helic_status build(helic_basis_s* h) {
   std::vector<double> jv(2);
   for (const Group& grp : h->groups) {
     const int nks = (grp.Kmax + 3) / 4;
-    const int g = grp.g * N;   // Bessel order of the group
+    const int g = grp.g;   // Bessel order of the group
     std::vector<double> xi((size_t)nr * grp.Kmax);   // xi[l * Kmax + k]
     std::vector<double> dxi((size_t)nr * grp.Kmax);  // d xi / dr
     std::vector<double> buf(g + 2), buf2(g + 2);

@@ -514,7 +514,7 @@ static helic_status batch_eigensolve(helic_batch b, const helic_solve_opts* o, i
   const int nt = std::min(nstreams, nprob);
   for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
   for (auto& t : pool) t.join();
-  // time-reversal partners: lambda_j(eta) = lambda_j(-eta) (Sec. 3.3)
+  // time-reversal partners: lambda_j(eta, nu) = lambda_j(-eta, N - nu) (Sec. 3.3)
   for (int p = 0; tr && p < nprob; ++p) {
     const int q = b->mirror[p];
     if (q < 0) continue;
@@ -556,11 +556,14 @@ helic_status helic_batch_time_reversal(helic_batch b, int32_t enable, int32_t* n
   int pairs = 0;
   for (int p = 0; p < nprob; ++p) {
     const helic_params& a = b->bases[p]->p;
-    if (a.eta == 0.0 || std::fabs(a.eta) >= 0.5) continue;   // its own partner
+    // partner (-eta, (N - nu) mod N), with eta = -1/2 its own negative
+    const double eta_p = a.eta <= -0.5 ? a.eta : -a.eta;
+    if (eta_p == a.eta && (2 * a.nu) % a.ncyc == 0) continue;   // its own partner
     for (int q = 0; q < p; ++q) {
       const helic_params& c = b->bases[q]->p;
-      if (mirror[q] >= 0 || std::fabs(a.eta + c.eta) > 1e-12 || a.R != c.R || a.tau != c.tau ||
-          a.alpha != c.alpha || a.ecut != c.ecut || a.ncyc != c.ncyc || a.nu != c.nu || a.m_max != c.m_max ||
+      if (mirror[q] >= 0 || std::fabs(c.eta - eta_p) > 1e-12 || a.R != c.R || a.tau != c.tau ||
+          a.alpha != c.alpha || a.ecut != c.ecut || a.ncyc != c.ncyc || c.nu != (a.ncyc - a.nu) % a.ncyc ||
+          a.m_max != c.m_max ||
           a.n_max != c.n_max || a.k_max != c.k_max || b->bases[p]->L != b->bases[q]->L ||
           b->bases[p]->n_r != b->bases[q]->n_r)
         continue;

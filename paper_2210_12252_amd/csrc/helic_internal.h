@@ -19,9 +19,10 @@ struct Mode {
   int32_t bin1, bin2;
 };
 
-// All modes with the same |n| share the radial tables xi_{|n|,k}(r_l).
+// All modes whose radial functions have the same Bessel order share the
+// radial tables xi_{g,k}(r_l) (at nu = 0: the modes of n = +-g / N).
 struct Group {
-  int32_t g;
+  int32_t g;                // Bessel order |n N - nu|
   int32_t mode0, nmodes;    // modes [mode0, mode0 + nmodes) in compact order
   int32_t Kmax;
   int64_t row0, nrows;      // rows [row0, row0 + nrows) of the group

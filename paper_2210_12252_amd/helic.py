@@ -560,7 +560,8 @@ class Basis:
     @classmethod
     def from_workload(cls, w, **over):
         p = dict(R=w.R, tau=w.tau, alpha=w.alpha, ecut=w.ecut, eta=w.eta, m_max=w.m_max, n_max=w.n_max,
-                 k_max=w.k_max, n_t1=w.n_t1, n_t2=w.n_t2, n_r=w.n_r, ncyc=getattr(w, "ncyc", 1))
+                 k_max=w.k_max, n_t1=w.n_t1, n_t2=w.n_t2, n_r=w.n_r, ncyc=getattr(w, "ncyc", 1),
+                 nu=getattr(w, "nu", 0))
         p.update(over)
         return cls(**p)
 

@@ -112,13 +112,27 @@ def test_cyclic_index_set_grid_and_tables_match_oracle(ncyc):
         b.close()
 
 
+@pytest.mark.parametrize("ncyc,nu", [(2, 1), (3, 1), (3, 2), (4, 1)])
+def test_cyclic_index_nu_index_set_matches_oracle(ncyc, nu):
+    """Cyclic index nu != 0: radial order |n N - nu|, kinetic energies with
+    alpha (n N - nu), groups of one Bessel order (ascending), the wedge grid
+    and the radial weights agree with the oracle, automatic and given grid."""
+    for grid in ({}, dict(n_t1=16, n_t2=12, n_r=40)):
+        w = synth.Workload(name="cyc-nu", R=7.5, tau=5.5, alpha=0.13, ecut=9.0, eta=0.17, ncyc=ncyc, nu=nu, **grid)
+        b, mnk = _compare_with_oracle(w)
+        order = np.abs(mnk[:, 1] * ncyc - nu)
+        assert np.all(np.diff(order) >= 0)
+        b.close()
+
+
 def test_parameter_errors():
     with pytest.raises(helic.HelicError) as e:
         helic.basis_create(R=-1.0, tau=5.0, alpha=0.0, ecut=5.0)
     assert e.value.status == helic.ERR_INVALID
-    with pytest.raises(helic.HelicError) as e:   # cyclic Bloch index nu != 0: not built
-        helic.basis_create(R=5.0, tau=5.0, alpha=0.0, ecut=5.0, ncyc=2, nu=1)
-    assert e.value.status == helic.ERR_UNSUPPORTED
+    for nu in (-1, 2):   # the cyclic Bloch index runs over 0 .. N - 1
+        with pytest.raises(helic.HelicError) as e:
+            helic.basis_create(R=5.0, tau=5.0, alpha=0.0, ecut=5.0, ncyc=2, nu=nu)
+        assert e.value.status == helic.ERR_INVALID
     with pytest.raises(helic.HelicError) as e:
         helic.basis_create(R=5.0, tau=5.0, alpha=0.0, ecut=5.0, ncyc=0)
     assert e.value.status == helic.ERR_INVALID
