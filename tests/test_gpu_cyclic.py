@@ -1,6 +1,7 @@
-"""Cyclic order N > 1 at nu = 0 on the GPU (Sec. 2.3, App. B; Alg. 5 without
-its nu block) against the CPU oracle, which is itself pinned against the
-n = 0 (mod N) sector of the order-1 operator.
+"""Cyclic order N > 1 on the GPU (Sec. 2.3, App. B; Alg. 5) against the CPU
+oracle, which is itself pinned against the n' = -nu (mod N) sector of the
+order-1 operator: cyclic index nu = 0 and nu != 0 (radial functions of order
+nN - nu, groups of one Bessel order).
 
 The library changes nothing in the transform kernels for N > 1: the Bessel
 order |n| N and its zeros enter through the radial tables, alpha N n through
@@ -37,9 +38,9 @@ class Cyc:
     """An N-fold symmetric structure (a motif of wells and its rotations by
     2 pi mu / N) on the wedge grid, on both sides."""
 
-    def __init__(self, ncyc, n_t2, n_t1=16, n_r=40, ecut=9.0):
-        self.w = synth.Workload(name=f"cyc{ncyc}", R=7.5, tau=5.5, alpha=0.13, ecut=ecut, eta=0.17, ncyc=ncyc,
-                                n_t1=n_t1, n_t2=n_t2, n_r=n_r, structure="helix6", seed=21, nev=10)
+    def __init__(self, ncyc, n_t2, n_t1=16, n_r=40, ecut=9.0, nu=0, eta=0.17):
+        self.w = synth.Workload(name=f"cyc{ncyc}", R=7.5, tau=5.5, alpha=0.13, ecut=ecut, eta=eta, ncyc=ncyc,
+                                nu=nu, n_t1=n_t1, n_t2=n_t2, n_r=n_r, structure="helix6", seed=21, nev=10)
         self.o = ob.basis_for(self.w)
         self.g = helic.Basis.from_workload(self.w)
         mnk, _ = self.g.indices()
@@ -48,7 +49,7 @@ class Cyc:
         atoms = synth.cyclic_images(synth.atoms_for("helix6", 21, self.w.tau, self.w.R)[:3], ncyc)
         self.V = synth.potential_at(self.o.theta1, self.o.theta2, self.o.r, self.w.tau, self.w.alpha, atoms)
         self.g.set_potential(torch.from_numpy(self.V).to(_dev()))
-        print(f"[cyc N={ncyc}] L={self.o.L} grid {n_t1}x{n_t2}x{n_r}", flush=True)
+        print(f"[cyc N={ncyc} nu={nu}] L={self.o.L} grid {n_t1}x{n_t2}x{n_r}", flush=True)
 
     def to_gpu(self, X):
         return torch.from_numpy(np.ascontiguousarray(X[self.perm].T)).to(_dev())
@@ -60,11 +61,13 @@ class Cyc:
         return out
 
 
-@pytest.mark.parametrize("ncyc,n_t2", [(2, 12), (3, 12), (4, 16)])
-def test_cyclic_apply_matches_oracle(ncyc, n_t2):
+@pytest.mark.parametrize("ncyc,n_t2,nu", [(2, 12, 0), (3, 12, 0), (4, 16, 0), (2, 12, 1), (3, 12, 2), (4, 16, 1),
+                                          (4, 16, 2)])
+def test_cyclic_apply_matches_oracle(ncyc, n_t2, nu):
     """(N, n_t2) = (2, 12), (3, 12): the general angular kernel; (4, 16): the
-    specialised convolution kernel of 16-column blocks."""
-    c = Cyc(ncyc, n_t2)
+    specialised convolution kernel of 16-column blocks; cyclic index nu = 0
+    and nu != 0 (nu = N / 2: orders nN - nu shared by n and 1 - n)."""
+    c = Cyc(ncyc, n_t2, nu=nu)
     X = synth.random_block(c.o.mnk, 9, 7)
     ref = oh.dense_explicit(c.o, c.V) @ X
     for prec in ("fp64", "fp32", "bf16"):
@@ -72,12 +75,13 @@ def test_cyclic_apply_matches_oracle(ncyc, n_t2):
         c.g.apply_H(c.to_gpu(X), Yg, prec=prec)
         Y = c.from_gpu(Yg)
         err = max(np.max(np.abs(Y[:, j] - ref[:, j])) / np.max(np.abs(ref[:, j])) for j in range(9))
-        print(f"[cyc N={ncyc} {prec}] rel err {err:.2e}", flush=True)
+        print(f"[cyc N={ncyc} nu={nu} {prec}] rel err {err:.2e}", flush=True)
         assert err <= TOL[prec]
 
 
-def test_cyclic_eigenvalues_match_lapack():
-    c = Cyc(3, 12)
+@pytest.mark.parametrize("nu", [0, 1, 2])
+def test_cyclic_eigenvalues_match_lapack(nu):
+    c = Cyc(3, 12, nu=nu)
     ref, _ = oh.lowest(oh.dense_explicit(c.o, c.V), c.w.nev)
     for deg in (None, 0):
         ev, res, st, status = c.g.eigensolve_ex(c.w.nev, tol=1e-9, maxit=400, cheb_degree=deg)
@@ -86,11 +90,12 @@ def test_cyclic_eigenvalues_match_lapack():
         assert np.max(np.abs(ev - ref)) < 1e-8
 
 
-def test_cyclic_free_particle_closed_form():
+@pytest.mark.parametrize("nu", [0, 2])
+def test_cyclic_free_particle_closed_form(nu):
     """V = 0: the spectrum is the sorted kinetic energies
-    (1/2)[(b_k^{|n| N}/R)^2 + (2 pi/tau)^2 (m - alpha N n - eta)^2]."""
-    w = synth.Workload(name="cyc-free", R=6.0, tau=5.0, alpha=0.2, ecut=10.0, eta=0.3, ncyc=3, n_t1=24, n_t2=12,
-                       n_r=48)
+    (1/2)[(b_k^{|nN - nu|}/R)^2 + (2 pi/tau)^2 (m - alpha (nN - nu) - eta)^2]."""
+    w = synth.Workload(name="cyc-free", R=6.0, tau=5.0, alpha=0.2, ecut=10.0, eta=0.3, ncyc=3, nu=nu, n_t1=24,
+                       n_t2=12, n_r=48)
     o = ob.basis_for(w)
     g = helic.Basis.from_workload(w)
     g.set_potential(torch.zeros(o.n_t1 * o.n_t2 * o.n_r, dtype=torch.float64, device=_dev()))
@@ -99,8 +104,11 @@ def test_cyclic_free_particle_closed_form():
     np.testing.assert_allclose(ev, np.sort(o.kappa)[:12], atol=1e-8)
 
 
-def test_cyclic_gradient_and_density_match_oracle():
-    c = Cyc(2, 12)
+@pytest.mark.parametrize("nu", [0, 1])
+def test_cyclic_gradient_and_density_match_oracle(nu):
+    """Derivatives of the coefficient field (the periodic factor phi of the
+    Bloch state) and the density |phi|^2."""
+    c = Cyc(2, 12, nu=nu)
     X = synth.random_block(c.o.mnk, 4, 13)
     out = torch.full((3, 4, c.o.n_t1, c.o.n_t2, c.o.n_r), complex("nan"), dtype=torch.complex128, device=_dev())
     c.g.gradient(c.to_gpu(X), out, cartesian=True)
@@ -117,3 +125,23 @@ def test_cyclic_gradient_and_density_match_oracle():
     err = np.max(np.abs(rho.cpu().numpy().reshape(refr.shape) - refr)) / np.max(np.abs(refr))
     print(f"[cyc density] rel err {err:.2e}", flush=True)
     assert err < 1e-12
+
+
+def test_cyclic_time_reversal_pairs_in_a_batch():
+    """A batch of (eta, nu) problems of one 4-fold structure: (eta, nu) and
+    (-eta, 4 - nu) are paired (Sec. 3.3), nu = 2 at eta = 0 is its own
+    partner, and every problem's eigenvalues match LAPACK."""
+    cases = [(0.2, 1), (-0.2, 3), (0.0, 1), (0.0, 3), (0.0, 2), (0.3, 2), (-0.3, 2)]
+    cs = [Cyc(4, 16, nu=nu, eta=eta, ecut=7.0) for eta, nu in cases]
+    batch = helic.Batch([c.g for c in cs])
+    npairs = batch.time_reversal(True)
+    assert npairs == 3
+    ev, res, st, status = batch.eigensolve(cs[0].w.nev, nstreams=2, tol=1e-9, maxit=400, cheb_degree=0)
+    batch.time_reversal(False)
+    for i, c in enumerate(cs):
+        ref, _ = oh.lowest(oh.dense_explicit(c.o, c.V), c.w.nev)
+        err = np.max(np.abs(ev[i] - ref))
+        print(f"[cyc batch eta={cases[i][0]} nu={cases[i][1]}] max|dlambda| {err:.2e}", flush=True)
+        assert status[i] == helic.OK
+        assert err < 1e-8
+    batch.close()
