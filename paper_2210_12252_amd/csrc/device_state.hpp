@@ -97,6 +97,7 @@ struct LaunchSet {
   int n_r = 0, n_t1 = 0, n_t2 = 0;
   size_t lds_inv64 = 0, lds_fwd64 = 0, lds_ang64 = 0, lds_fast64 = 0;   // FP32 uses half
   int fast_mpad = 0, fast_ntf = 256, split_ntf = 0, vchunk = 0;
+  int rad_order = -1;                    // radial stages' work order (radial_item); -1: by precision
   int ang_slots64 = 1, ang_slots32 = 1, ang_slots16 = 1;
   bool grid_var = false;
   size_t lds_inv16 = 0, lds_fwd16 = 0;   // LDS bytes of the BF16 radial kernels

@@ -189,6 +189,28 @@ __device__ __forceinline__ int xcd_slot(int nwork) {
   return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
 }
 
+// (vector, group) of a workgroup of the radial stages, false if idle.
+// order 0: vector-major slots (each XCD runs every group of a few vectors);
+// order 1: XCD x takes vectors [x vpx, (x + 1) vpx), vpx = ceil(nvec / 8),
+// and runs them group by group (a grid of 8 vpx ngroups workgroups).
+__device__ __forceinline__ bool radial_item(int order, int ngroups, int nvec, int& v, int& gi) {
+  if (order == 0) {
+    const int slot = xcd_slot(ngroups * nvec);
+    v = slot / ngroups;
+    gi = slot - v * ngroups;
+    return slot < ngroups * nvec;
+  }
+  const int vpx = (nvec + 7) / 8;
+  const int x = (int)(blockIdx.x & 7), i = (int)(blockIdx.x >> 3);
+  gi = i / vpx;
+  v = x * vpx + (i - gi * vpx);
+  return gi < ngroups && v < nvec;
+}
+
+inline int radial_grid(int order, int nwg, int ngroups, int nvec) {
+  return order == 0 ? nwg : 8 * ((nvec + 7) / 8) * ngroups;
+}
+
 // ------------------------------------------------------------------ radix DFTs
 // In-register R-point DFT, y_p = sum_q v_q exp(s 2 pi i p q / R), s = -1
 // (forward) or +1 (inverse).

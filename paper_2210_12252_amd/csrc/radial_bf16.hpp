@@ -25,12 +25,11 @@ constexpr int FWD16_COLS = 256; // widest staged group (real columns) the forwar
 template <int KT16>
 __global__ void __launch_bounds__(NT)
 k_radial_inverse_bf16(const double* __restrict__ X, int64_t ldx, bf16x2* __restrict__ GH, int nvec, int ngroups,
-                      int n_r, const DGroup* __restrict__ groups, const DProb* __restrict__ probs) {
+                      int n_r, const DGroup* __restrict__ groups, const DProb* __restrict__ probs, int order) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   uint16_t* Bs = reinterpret_cast<uint16_t*>(smem_raw);
-  const int slot = xcd_slot(ngroups * nvec);
-  if (slot >= ngroups * nvec) return;
-  const int v = slot / ngroups, gi = slot - v * ngroups;
+  int v, gi;
+  if (!radial_item(order, ngroups, nvec, v, gi)) return;
   const DGroup gr = groups[gi];
   const DProb& pb = probs[gr.prob];
   const int nk16 = (gr.Kmax + 15) / 16;
@@ -108,14 +107,14 @@ template <int TM>
 __global__ void __launch_bounds__(NT)
 k_radial_forward_bf16(const bf16x2* __restrict__ GH, const double* __restrict__ X, int64_t ldx,
                       double* __restrict__ Y, int64_t ldy, int nvec, int ngroups, int n_r,
-                      const DGroup* __restrict__ groups, const DProb* __restrict__ probs, int add_kinetic) {
+                      const DGroup* __restrict__ groups, const DProb* __restrict__ probs, int add_kinetic,
+                      int order) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int RQ = FWD16_RC / 4;             // radius quads per chunk
   constexpr int RS = FWD16_RC / 16;            // MFMA k steps per chunk
   uint64_t* Hs = reinterpret_cast<uint64_t*>(smem_raw);
-  const int slot = xcd_slot(ngroups * nvec);
-  if (slot >= ngroups * nvec) return;
-  const int v = slot / ngroups, gi = slot - v * ngroups;
+  int v, gi;
+  if (!radial_item(order, ngroups, nvec, v, gi)) return;
   const DGroup gr = groups[gi];
   const DProb& pb = probs[gr.prob];
   const int nmodes = gr.nmodes;
