@@ -37,7 +37,8 @@ FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published (packed FP32 coun
 BF16_MFMA_PEAK_TFLOPS = 2500.0 # MI355X BF16 matrix (dense)
 STAGES = ("k_radial_inverse", "k_angular", "k_radial_forward")
 KERNEL_SOURCES = ("paper_2210_12252_amd/csrc/kernels.hpp", "paper_2210_12252_amd/csrc/angular_fast.hpp",
-                  "paper_2210_12252_amd/csrc/angular_split.hpp", "paper_2210_12252_amd/csrc/radial_bf16.hpp",
+                  "paper_2210_12252_amd/csrc/angular_split.hpp", "paper_2210_12252_amd/csrc/angular_pipe.hpp",
+                  "paper_2210_12252_amd/csrc/radial_bf16.hpp",
                   "paper_2210_12252_amd/csrc/device.hip")
 
 

@@ -349,6 +349,9 @@ __device__ __forceinline__ void row_dft_to_regs(cplx<T>* A0, const cplx<T>* tw, 
 #define HELIC_CONV_MB 8
 #endif
 constexpr int CONV_MB = HELIC_CONV_MB;
+#ifndef HELIC_CONV_ADJ
+#define HELIC_CONV_ADJ 1
+#endif
 
 template <typename T, int OPT>
 __device__ __forceinline__ void pin_acc(cplx<T>* acc) {
@@ -464,10 +467,14 @@ k_angular_fast(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
   const int64_t it_end = total < it + ipw ? total : it + ipw;
   const int t = threadIdx.x;
   for (int i = t; i < N2; i += NTF) tw[i] = tw2g[i];
-  const int j = t % N2, og = t / N2;
-  const bool conv_act = og < OG;
-  const int a0 = og * OPT;
   constexpr bool HERM = (N2 == 64);
+  // convolution threads: with HERM the output group is the wave index (its
+  // code specialised at compile time); otherwise the OG threads of a column
+  // are adjacent lanes, so their reads of the column are LDS broadcasts
+  constexpr bool ADJ = !HERM && HELIC_CONV_ADJ;
+  const int j = ADJ ? t / OG : t % N2, og = ADJ ? t % OG : t / N2;
+  const bool conv_act = ADJ ? t < OG * N2 : og < OG;
+  const int a0 = og * OPT;
   constexpr int NW = HERM ? MPAD : WN;
   constexpr int MS = (MPAD * N2 + NTF - 1) / NTF;   // every mode of a radius fits the block
   for (int i = t; i < BLK; i += NTF) A[i] = cplx<T>{(T)0, (T)0};

@@ -347,6 +347,7 @@ helic_status helic_batch_create(const helic_basis* bases, int32_t nprob, helic_b
       const helic_basis_s* g = bases[b->classes[c].members[0]];
       if (g->n_t1 == h->n_t1 && g->n_t2 == h->n_t2 && g->n_r == h->n_r && g->dev->fast_mpad == h->dev->fast_mpad &&
           g->dev->fast_ntf == h->dev->fast_ntf && g->dev->split_ntf == h->dev->split_ntf &&
+          g->dev->pipe64 == h->dev->pipe64 &&
           g->dev->grid_var == h->dev->grid_var)
         ci = (int)c;
     }

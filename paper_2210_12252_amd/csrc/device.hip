@@ -18,6 +18,7 @@
 #include "angular_fast.hpp"
 #include "angular_grid.hpp"
 #include "angular_split.hpp"
+#include "angular_pipe.hpp"
 
 // Stage launch; with timing events they ride on the kernel's own dispatch
 // packet (start and end timestamps of that kernel, no marker packets between
@@ -883,8 +884,26 @@ helic_status set_fast_limit() {
   return HELIC_OK;
 }
 
+// FP64 blocks whose convolution kernel runs one workgroup per CU with idle
+// waves in the row transforms take the two-vector pipeline of
+// k_angular_pipe instead (HELIC_ANGULAR_PIPE=0 keeps k_angular_fast).
+// Read when a basis is set up, so handles made under different settings
+// coexist in one process.
+bool pipe_for(int n2, int mpad, int ntf) {
+  const char* e = std::getenv("HELIC_ANGULAR_PIPE");
+  return n2 == 81 && mpad == 25 && ntf == 512 && !(e && e[0] == '0');
+}
+
+template <typename T>
+size_t pipe_lds_bytes(int n2, int mpad) {
+  return ((size_t)4 * mpad * ang_rs(n2) + n2) * sizeof(cplx<T>);
+}
+
 template <typename T, typename E>
 helic_status set_fast_limits() {
+  if constexpr (std::is_same<T, double>::value && std::is_same<E, cplx<double>>::value)
+    HIP_TRY(hipFuncSetAttribute((const void*)k_angular_pipe<double, cplx<double>, 81, 25, 512>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   helic_status s;
   if ((s = set_fast_limit<T, E, 16, 12, 256>()) || (s = set_fast_limit<T, E, 16, 16, 256>()) ||
       (s = set_fast_limit<T, E, 64, 24, 256>()) || (s = set_fast_limit<T, E, 64, 28, 256>()) ||
@@ -896,8 +915,15 @@ helic_status set_fast_limits() {
 
 // Resident workgroups of the chosen angular kernel on the whole device.
 template <typename T, typename E>
-int fast_slots(int n2, int mpad, int ntf, int ncu) {
+int fast_slots(int n2, int mpad, int ntf, int ncu, bool pipe = false) {
   int nb = 0;
+  if constexpr (std::is_same<T, double>::value && std::is_same<E, cplx<double>>::value) {
+    if (pipe) {
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_pipe<double, cplx<double>, 81, 25, 512>, 512,
+                                                         pipe_lds_bytes<double>(n2, mpad));
+      return std::max(1, nb) * std::max(1, ncu);
+    }
+  }
   const size_t lds = fast_lds_bytes<T>(n2, mpad);
 #define HELIC_OCC_CASE(N2_, MP_, NTF_)                                                                 \
   if (n2 == N2_ && mpad == MP_ && ntf == NTF_)                                                        \
@@ -939,6 +965,15 @@ helic_status launch_fast(const LaunchSet& ls, E* gh, int nvec, hipStream_t st, h
   const cplx<T>* tw2 = (const cplx<T>*)(std::is_same<T, double>::value ? ls.tw2_64 : ls.tw2_32);
   const int ipw = angular_items_per_wg<T, E>(ls, nvec);
   const dim3 grid(angular_grid_size(ls, nvec, ipw));
+  if constexpr (std::is_same<T, double>::value && std::is_same<E, cplx<double>>::value) {
+    if (ls.pipe64) {
+      HELIC_LAUNCH((k_angular_pipe<double, cplx<double>, 81, 25, 512>), grid, dim3(512),
+                   pipe_lds_bytes<double>(ls.n_t2, ls.fast_mpad), st, e0, e1, gh, ls.nprob, nvec, ls.n_r, probs, tw2,
+                   ipw);
+      HIP_TRY(hipGetLastError());
+      return HELIC_OK;
+    }
+  }
   const size_t lds = fast_lds_bytes<T>(ls.n_t2, ls.fast_mpad);
 #define HELIC_FAST_CASE(N2_, MP_, NTF_)                                                                   \
   if (ls.n_t2 == N2_ && ls.fast_mpad == MP_ && ls.fast_ntf == NTF_) {                                    \
@@ -1311,6 +1346,7 @@ helic_status ensure_device(helic_basis_s* h) {
       }
     }
   }
+  d->pipe64 = d->fast_mpad && pipe_for(h->n_t2, d->fast_mpad, d->fast_ntf);
   d->split_ntf = 0;
   if (d->fast_mpad && !split_disabled()) {
     for (const SplitVariant& sv : SPLIT_VARIANTS)
@@ -1339,7 +1375,7 @@ helic_status ensure_device(helic_basis_s* h) {
     if ((s = set_fast_limits<double, cplx<double>>()) || (s = set_fast_limits<float, cplx<float>>()) ||
         (s = set_fast_limits<float, bf16x2>()))
       return s;
-    d->ang_slots64 = fast_slots<double, cplx<double>>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu);
+    d->ang_slots64 = fast_slots<double, cplx<double>>(h->n_t2, d->fast_mpad, d->fast_ntf, ncu, d->pipe64);
     if (d->split_ntf) {
       d->ang_slots32 = split_slots<cplx<float>>(h->n_t1, h->n_t2, d->fast_mpad, d->split_ntf, ncu);
       d->ang_slots16 = split_slots<bf16x2>(h->n_t1, h->n_t2, d->fast_mpad, d->split_ntf, ncu);
@@ -1432,6 +1468,7 @@ LaunchSet launch_set(const helic_basis_s* h) {
   ls.fast_mpad = d->fast_mpad;
   ls.fast_ntf = d->fast_ntf;
   ls.split_ntf = d->split_ntf;
+  ls.pipe64 = d->pipe64;
   ls.rad_order = env_int("HELIC_RADIAL_ORDER", -1, -1, 1);
   ls.grid_var = d->grid_var;
   ls.vchunk = d->vchunk;

@@ -46,6 +46,7 @@ struct DeviceState {
   int fast_ntf = 256;
   int split_ntf = 0;              // > 0: the split theta1 FFT kernel serves this grid in FP32
                                   // arithmetic (its block size)
+  bool pipe64 = false;            // FP64 angular stage by the two-vector pipeline k_angular_pipe
   int m_min = 0, m_count = 0;
   bool grid_var = false;          // the register-FFT angular kernel serves this grid
   int vchunk = 0;                 // (problem, radius, vector) items per workgroup of the specialised
@@ -97,6 +98,7 @@ struct LaunchSet {
   int n_r = 0, n_t1 = 0, n_t2 = 0;
   size_t lds_inv64 = 0, lds_fwd64 = 0, lds_ang64 = 0, lds_fast64 = 0;   // FP32 uses half
   int fast_mpad = 0, fast_ntf = 256, split_ntf = 0, vchunk = 0;
+  bool pipe64 = false;
   int rad_order = -1;                    // radial stages' work order (radial_item); -1: by precision
   int ang_slots64 = 1, ang_slots32 = 1, ang_slots16 = 1;
   bool grid_var = false;
