@@ -15,7 +15,7 @@
 // gather or clearing), and the second half (convolution waves, the OG
 // threads of a column on adjacent lanes) does only the convolution.  LDS
 // holds two A blocks (inverse rows' output) and two B blocks (convolution
-// output).  In step s of a radius segment the row waves run the inverse
+// output), laid out (row stride, column swizzle) as in k_angular_fast.  In step s of a radius segment the row waves run the inverse
 // rows of vector s (slab -> A[s % 2], the next vector's slab fetched behind
 // them) and the forward rows of vector s - 2 (B[s % 2] -> slab), while the
 // convolution waves run vector s - 1 (A[(s - 1) % 2] -> B[(s - 1) % 2]); one
@@ -141,12 +141,12 @@ k_angular_pipe(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
 #pragma unroll
         for (int g = 0; g < (P + 3) / 4; ++g) asm volatile("" : "+v"(w[P + g].x), "+v"(w[P + g].y));
         if (s < nv) {
-          row_idft_from_regs<T, N2, P, NR, MPAD, 0, true, false>(Ab + (s & 1) * BLK, tw, w);
+          row_idft_from_regs<T, N2, P, NR, MPAD, 0, true, true>(Ab + (s & 1) * BLK, tw, w);
           if (s + 1 < nv) fetch(v0 + s + 1);
         }
         if (s >= 2) {
           cplx<T> xout[P];
-          row_dft_to_regs<T, N2, P, NR, MPAD, 0, true, false>(Bb + (s & 1) * BLK, tw, xout);
+          row_dft_to_regs<T, N2, P, NR, MPAD, 0, true, true>(Bb + (s & 1) * BLK, tw, xout);
           if (ract) {
             E* slab = GH + slab_off(pb, nvec, n_r, v0 + s - 2, r);
 #pragma unroll
@@ -163,7 +163,7 @@ k_angular_pipe(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
 #pragma unroll
         for (int m = 0; m < MPAD; ++m) {
           if (m % PIPE_MB == 0 && m > 0) pin_acc<T, OPT>(acc);
-          const cplx<T> x = A[m * RS + j];
+          const cplx<T> x = A[m * RS + (j ^ ang_swz(N2, m))];
 #pragma unroll
           for (int o = 0; o < OPT; ++o) {
             const cplx<T> wv = w[o - m + MPAD - 1];
@@ -175,7 +175,7 @@ k_angular_pipe(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
         }
 #pragma unroll
         for (int o = 0; o < OPT; ++o)
-          if (a0 + o < MPAD) B[(a0 + o) * RS + j] = acc[o];
+          if (a0 + o < MPAD) B[(a0 + o) * RS + (j ^ ang_swz(N2, a0 + o))] = acc[o];
       }
       __syncthreads();
     }

@@ -884,14 +884,21 @@ helic_status set_fast_limit() {
   return HELIC_OK;
 }
 
-// FP64 blocks whose convolution kernel runs one workgroup per CU with idle
-// waves in the row transforms take the two-vector pipeline of
-// k_angular_pipe instead (HELIC_ANGULAR_PIPE=0 keeps k_angular_fast).
+// FP64 blocks listed here take the wave-specialised k_angular_pipe instead
+// of k_angular_fast (HELIC_ANGULAR_PIPE=0 keeps k_angular_fast).  Measured
+// per 64-vector block: 32 x 81 with 25 rows 0.297 against 0.367 ms, 48 x 64
+// with 28 rows 0.206 against 0.219 ms; with 24 rows on 48 x 64 the direct
+// slab path of k_angular_fast is as fast (0.132 against 0.131 ms) and kept.
 // Read when a basis is set up, so handles made under different settings
 // coexist in one process.
-bool pipe_for(int n2, int mpad, int ntf) {
+#define HELIC_PIPE_FOREACH(X) X(81, 25) X(64, 28)
+bool pipe_for(int n2, int mpad) {
   const char* e = std::getenv("HELIC_ANGULAR_PIPE");
-  return n2 == 81 && mpad == 25 && ntf == 512 && !(e && e[0] == '0');
+  if (e && e[0] == '0') return false;
+#define HELIC_PIPE_HAS(N2_, MP_) if (n2 == N2_ && mpad == MP_) return true;
+  HELIC_PIPE_FOREACH(HELIC_PIPE_HAS)
+#undef HELIC_PIPE_HAS
+  return false;
 }
 
 template <typename T>
@@ -901,9 +908,13 @@ size_t pipe_lds_bytes(int n2, int mpad) {
 
 template <typename T, typename E>
 helic_status set_fast_limits() {
-  if constexpr (std::is_same<T, double>::value && std::is_same<E, cplx<double>>::value)
-    HIP_TRY(hipFuncSetAttribute((const void*)k_angular_pipe<double, cplx<double>, 81, 25, 512>,
+  if constexpr (std::is_same<T, double>::value && std::is_same<E, cplx<double>>::value) {
+#define HELIC_PIPE_ATTR(N2_, MP_)                                                                     \
+    HIP_TRY(hipFuncSetAttribute((const void*)k_angular_pipe<double, cplx<double>, N2_, MP_, 512>,     \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    HELIC_PIPE_FOREACH(HELIC_PIPE_ATTR)
+#undef HELIC_PIPE_ATTR
+  }
   helic_status s;
   if ((s = set_fast_limit<T, E, 16, 12, 256>()) || (s = set_fast_limit<T, E, 16, 16, 256>()) ||
       (s = set_fast_limit<T, E, 64, 24, 256>()) || (s = set_fast_limit<T, E, 64, 28, 256>()) ||
@@ -919,8 +930,12 @@ int fast_slots(int n2, int mpad, int ntf, int ncu, bool pipe = false) {
   int nb = 0;
   if constexpr (std::is_same<T, double>::value && std::is_same<E, cplx<double>>::value) {
     if (pipe) {
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_pipe<double, cplx<double>, 81, 25, 512>, 512,
-                                                         pipe_lds_bytes<double>(n2, mpad));
+#define HELIC_PIPE_OCC(N2_, MP_)                                                                      \
+      if (n2 == N2_ && mpad == MP_)                                                                   \
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_angular_pipe<double, cplx<double>, N2_, MP_, 512>, \
+                                                           512, pipe_lds_bytes<double>(n2, mpad));
+      HELIC_PIPE_FOREACH(HELIC_PIPE_OCC)
+#undef HELIC_PIPE_OCC
       return std::max(1, nb) * std::max(1, ncu);
     }
   }
@@ -967,11 +982,16 @@ helic_status launch_fast(const LaunchSet& ls, E* gh, int nvec, hipStream_t st, h
   const dim3 grid(angular_grid_size(ls, nvec, ipw));
   if constexpr (std::is_same<T, double>::value && std::is_same<E, cplx<double>>::value) {
     if (ls.pipe64) {
-      HELIC_LAUNCH((k_angular_pipe<double, cplx<double>, 81, 25, 512>), grid, dim3(512),
-                   pipe_lds_bytes<double>(ls.n_t2, ls.fast_mpad), st, e0, e1, gh, ls.nprob, nvec, ls.n_r, probs, tw2,
-                   ipw);
-      HIP_TRY(hipGetLastError());
-      return HELIC_OK;
+#define HELIC_PIPE_CASE(N2_, MP_)                                                                     \
+      if (ls.n_t2 == N2_ && ls.fast_mpad == MP_) {                                                    \
+        HELIC_LAUNCH((k_angular_pipe<double, cplx<double>, N2_, MP_, 512>), grid, dim3(512),            \
+                     pipe_lds_bytes<double>(N2_, MP_), st, e0, e1, gh, ls.nprob, nvec, ls.n_r, probs, tw2, ipw); \
+        HIP_TRY(hipGetLastError());                                                                   \
+        return HELIC_OK;                                                                              \
+      }
+      HELIC_PIPE_FOREACH(HELIC_PIPE_CASE)
+#undef HELIC_PIPE_CASE
+      return fail(HELIC_ERR_STATE, "no pipelined angular kernel for this grid");
     }
   }
   const size_t lds = fast_lds_bytes<T>(ls.n_t2, ls.fast_mpad);
@@ -1346,7 +1366,7 @@ helic_status ensure_device(helic_basis_s* h) {
       }
     }
   }
-  d->pipe64 = d->fast_mpad && pipe_for(h->n_t2, d->fast_mpad, d->fast_ntf);
+  d->pipe64 = d->fast_mpad && pipe_for(h->n_t2, d->fast_mpad);
   d->split_ntf = 0;
   if (d->fast_mpad && !split_disabled()) {
     for (const SplitVariant& sv : SPLIT_VARIANTS)

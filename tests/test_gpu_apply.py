@@ -282,18 +282,22 @@ def test_split_angular_kernel_parity(workload, n1, n2, ecut, monkeypatch):
     conv.close()
 
 
-@pytest.mark.parametrize("ecut,vchunk", [(30.0, 0), (30.0, 1), (30.0, 3), (14.0, 0), (14.0, 2)])
-def test_pipelined_angular_kernel_parity(ecut, vchunk, monkeypatch):
-    """FP64 on 32 x 81 blocks of 25 rows, where the angular stage overlaps
-    the theta2 row transforms of consecutive vectors: at 30 Ha every block
-    position holds a mode, at 14 Ha some rows and positions hold none (read
-    as zero through the inverse rows' mask, never cleared).  Work split even
-    over the resident workgroups (segments start and end inside radii), or
-    1, 2 or 3 items per workgroup (one- to three-vector segments, each
-    drained on its own).  Every output element against the oracle, and
+@pytest.mark.parametrize("workload,n1,n2,ecut,vchunk", [
+    ("nanowire-ecut30", 32, 81, 30.0, 0), ("nanowire-ecut30", 32, 81, 30.0, 1), ("nanowire-ecut30", 32, 81, 30.0, 3),
+    ("nanowire-ecut30", 32, 81, 14.0, 0), ("nanowire-ecut30", 32, 81, 14.0, 2),
+    ("nanotube-ecut25", 48, 64, 34.0, 0), ("nanotube-ecut25", 48, 64, 34.0, 3)])
+def test_pipelined_angular_kernel_parity(workload, n1, n2, ecut, vchunk, monkeypatch):
+    """FP64 blocks served by the wave-specialised angular kernel (row waves
+    move the slab straight through the theta2 transforms, convolution waves
+    convolve the vector between): 32 x 81 blocks of 25 rows (every position
+    holding a mode at 30 Ha; some rows and positions empty at 14 Ha) and
+    48 x 64 blocks of 28 rows (34 Ha, 25 in use).  Work
+    split even over the resident workgroups (segments start and end inside
+    radii), or 1, 2 or 3 items per workgroup (one- to three-vector segments,
+    each drained on its own).  Every output element against the oracle, and
     against the one-vector convolution kernel (HELIC_ANGULAR_PIPE=0) on the
     same inputs."""
-    w = synth.workload("nanowire-ecut30").with_(name=f"nanowire-pipe-{ecut:g}", ecut=ecut, n_t1=32, n_t2=81, n_r=40)
+    w = synth.workload(workload).with_(name=f"{workload}-pipe-{ecut:g}", ecut=ecut, n_t1=n1, n_t2=n2, n_r=40)
     if vchunk:
         monkeypatch.setenv("HELIC_VCHUNK", str(vchunk))
     c = Case(w)
@@ -303,7 +307,8 @@ def test_pipelined_angular_kernel_parity(ecut, vchunk, monkeypatch):
     one.set_potential(torch.from_numpy(c.V).to(_dev()))
     monkeypatch.delenv("HELIC_ANGULAR_PIPE")
     ms = sorted({int(m) for m in c.o.mnk[:, 0]})
-    print(f"[pipe ecut={ecut:g} vchunk={vchunk}] L={c.o.L}, m rows {len(ms)}", flush=True)
+    tag = f"[pipe {n1}x{n2} ecut={ecut:g} vchunk={vchunk}]"
+    print(f"{tag} L={c.o.L}, m rows {len(ms)}", flush=True)
     X = synth.random_block(c.o.mnk, 21, 4244)
     ref = oh.apply(c.o, c.V, X)
     Xg = c.to_gpu_block(X)
@@ -313,7 +318,7 @@ def test_pipelined_angular_kernel_parity(ecut, vchunk, monkeypatch):
     one.apply_H(Xg, Y1, prec="fp64")
     err = _rel(c.from_gpu_block(Yg), ref)
     agree = (torch.abs(Yg - Y1).max() / torch.abs(Y1).max()).item()
-    print(f"[pipe ecut={ecut:g} vchunk={vchunk}] rel err {err:.2e}, vs one-vector kernel {agree:.2e}", flush=True)
+    print(f"{tag} rel err {err:.2e}, vs one-vector kernel {agree:.2e}", flush=True)
     assert err < TOL64
     assert agree < 1e-14
     one.close()
