@@ -449,6 +449,39 @@ def learned_leg(torch, b, w, tol=1e-8, train_eta=0.25, n_snap=12, steps=400, bat
     return out
 
 
+def measured_peaks(torch, dev, copy_mib=1024, n_gemm=8192, reps=5):
+    """Attainable peaks on this GPU, next to the published ones: a plain
+    device copy (STREAM-like; 2 x copy_mib MiB moved per copy) and a large
+    FP64 GEMM on the matrix cores (rocBLAS through torch, 2 n^3 flops), each
+    timed with events on torch's stream, best of `reps` after one warm-up."""
+    n = copy_mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    a = torch.randn(n_gemm, n_gemm, dtype=torch.float64, device=dev)
+    bm = torch.randn(n_gemm, n_gemm, dtype=torch.float64, device=dev)
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1) * 1e-3)
+        return min(t)
+
+    t_copy = best(lambda: dst.copy_(src))
+    t_gemm = best(lambda: torch.matmul(a, bm))
+    out = dict(copy_GBs=round(2 * n * 8 / t_copy / 1e9, 1), copy_MiB=copy_mib,
+               dgemm_TFLOPs=round(2 * n_gemm ** 3 / t_gemm / 1e12, 2), dgemm_n=n_gemm)
+    del src, dst, a, bm
+    torch.cuda.synchronize()
+    return out
+
+
 def load_traffic(name: str, nvec: int, workload: str):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or
     None when absent or taken on other kernel sources, block size or
@@ -488,6 +521,8 @@ def main(argv=None):
     ap.add_argument("--density", type=int, default=1, help="electron-density leg (0: skip)")
     ap.add_argument("--other-precisions", type=int, default=1,
                     help="also time the headline block in the two other precisions")
+    ap.add_argument("--measure-peaks", type=int, default=1,
+                    help="time a 1 GiB device copy and an FP64 GEMM (attainable peaks; 0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args(argv)
@@ -634,6 +669,12 @@ def main(argv=None):
     }
     if args.other_precisions:
         line["hx_other_precisions"] = other
+    if args.measure_peaks:
+        mp = measured_peaks(torch, dev)
+        if roof["unit"] == "GB/s":
+            mp["dominant_frac_of_copy"] = round(roof["achieved"] / mp["copy_GBs"], 4)
+        line["measured_peaks"] = mp
+        print(f"[bench] measured peaks: {mp}", file=sys.stderr, flush=True)
     if args.learned != "none":
         if args.learned in ("same", w.name):
             lw, lb = w, b
