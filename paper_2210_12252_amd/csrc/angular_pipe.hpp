@@ -62,7 +62,13 @@ k_angular_pipe(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
   constexpr int OPT = (MPAD + OG - 1) / OG;       // outputs per convolution thread
   constexpr int RS = ang_rs(N2);
   constexpr int BLK = MPAD * RS;
-  constexpr int WN = OPT + MPAD - 1;              // Vhat window of one convolution thread
+  // With one output group per convolution wave (a column per lane: N2 = 64
+  // and four groups) the group's code is specialised at compile time and,
+  // V being real (Vhat_j[-d] = conj Vhat_j[d]), the thread holds
+  // Vhat_j[d], d = 0 .. MPAD - 1 only, as in k_angular_fast; otherwise the
+  // window w[q] = Vhat_j[a0 + q - (MPAD - 1)] of its outputs.
+  constexpr bool HERM = (N2 == 64 && OG * 64 == NR);
+  constexpr int WN = HERM ? MPAD : OPT + MPAD - 1;   // Vhat registers of one convolution thread
   static_assert(WN >= P + (P + 3) / 4, "the row waves' registers fit the window");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* const Ab = reinterpret_cast<cplx<T>*>(smem_raw);   // A[0], A[1]
@@ -85,7 +91,8 @@ k_angular_pipe(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
   // convolution waves: the OG threads of a column are adjacent lanes (their
   // reads of the column are LDS broadcasts)
   const int c = t - NR;
-  const int j = row_role ? 0 : c / OG, og = row_role ? 0 : c % OG;
+  const int j = row_role ? 0 : HERM ? (c & 63) : c / OG;
+  const int og = row_role ? 0 : HERM ? (c >> 6) : c % OG;
   const bool conv_act = !row_role && c < OG * N2;
   const int a0 = og * OPT;
   __syncthreads();
@@ -126,8 +133,9 @@ k_angular_pipe(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
       fetch(v0);
     } else {
       const cplx<T>* src = reinterpret_cast<const cplx<T>*>(pb.Vh) + ((int64_t)r * N2 + j) * ND;
+      const int base = HERM ? MPAD - 1 : a0;
 #pragma unroll
-      for (int q = 0; q < WN; ++q) w[q] = (conv_act && a0 + q < ND) ? src[a0 + q] : cplx<T>{(T)0, (T)0};
+      for (int q = 0; q < WN; ++q) w[q] = (conv_act && base + q < ND) ? src[base + q] : cplx<T>{(T)0, (T)0};
     }
     // step s: row waves take vector s through the inverse rows (slab ->
     // A[s % 2]) and vector s - 2 through the forward rows (B[s % 2] ->
@@ -154,7 +162,10 @@ k_angular_pipe(E* __restrict__ GH, int nprob, int nvec, int n_r, const DProb* __
               if (idx(q) >= 0) estore(slab + idx(q), xout[q]);
           }
         }
-      } else if (conv_act && s >= 1 && s <= nv) {
+      } else if (HERM && s >= 1 && s <= nv) {
+        conv_herm_group<T, N2, MPAD, OPT, 0, OG>(__builtin_amdgcn_readfirstlane(og), Ab + ((s - 1) & 1) * BLK,
+                                                 Bb + ((s - 1) & 1) * BLK, j, w);
+      } else if (!HERM && conv_act && s >= 1 && s <= nv) {
         const cplx<T>* A = Ab + ((s - 1) & 1) * BLK;
         cplx<T>* B = Bb + ((s - 1) & 1) * BLK;
         cplx<T> acc[OPT];
