@@ -887,11 +887,9 @@ helic_status set_fast_limit() {
 // FP64 blocks listed here take the wave-specialised k_angular_pipe instead
 // of k_angular_fast (HELIC_ANGULAR_PIPE=0 keeps k_angular_fast).  Measured
 // per 64-vector block: 32 x 81 with 25 rows 0.297 against 0.367 ms, 48 x 64
-// with 28 rows 0.206 against 0.219 ms; with 24 rows on 48 x 64 the direct
-// slab path of k_angular_fast is as fast (0.132 against 0.131 ms) and kept.
-// Read when a basis is set up, so handles made under different settings
-// coexist in one process.
-#define HELIC_PIPE_FOREACH(X) X(81, 25) X(64, 28)
+// with 28 rows 0.198 against 0.242 ms, with 24 rows 0.130 against 0.135 ms
+// (the last within the run-to-run spread of the box).
+#define HELIC_PIPE_FOREACH(X) X(81, 25) X(64, 24) X(64, 28)
 bool pipe_for(int n2, int mpad) {
   const char* e = std::getenv("HELIC_ANGULAR_PIPE");
   if (e && e[0] == '0') return false;

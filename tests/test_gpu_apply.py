@@ -285,13 +285,13 @@ def test_split_angular_kernel_parity(workload, n1, n2, ecut, monkeypatch):
 @pytest.mark.parametrize("workload,n1,n2,ecut,vchunk", [
     ("nanowire-ecut30", 32, 81, 30.0, 0), ("nanowire-ecut30", 32, 81, 30.0, 1), ("nanowire-ecut30", 32, 81, 30.0, 3),
     ("nanowire-ecut30", 32, 81, 14.0, 0), ("nanowire-ecut30", 32, 81, 14.0, 2),
-    ("nanotube-ecut25", 48, 64, 34.0, 0), ("nanotube-ecut25", 48, 64, 34.0, 3)])
+    ("nanotube-ecut25", 48, 64, 25.0, 0), ("nanotube-ecut25", 48, 64, 34.0, 0), ("nanotube-ecut25", 48, 64, 34.0, 3)])
 def test_pipelined_angular_kernel_parity(workload, n1, n2, ecut, vchunk, monkeypatch):
     """FP64 blocks served by the wave-specialised angular kernel (row waves
     move the slab straight through the theta2 transforms, convolution waves
     convolve the vector between): 32 x 81 blocks of 25 rows (every position
     holding a mode at 30 Ha; some rows and positions empty at 14 Ha) and
-    48 x 64 blocks of 28 rows (34 Ha, 25 in use).  Work
+    48 x 64 blocks of 24 rows (25 Ha) and 28 rows (34 Ha, 25 in use).  Work
     split even over the resident workgroups (segments start and end inside
     radii), or 1, 2 or 3 items per workgroup (one- to three-vector segments,
     each drained on its own).  Every output element against the oracle, and
