@@ -85,6 +85,40 @@ def test_batched_apply_matches_oracle_per_problem(base, etas):
     batch.close()
 
 
+@pytest.mark.parametrize("base", [
+    synth.workload("nanotube-ecut25").with_(name="tube-batch", ecut=12.0, n_t1=48, n_t2=64, n_r=40),
+    synth.workload("nanowire-ecut30").with_(name="wire-batch", ecut=14.0, n_t1=32, n_t2=81, n_r=40)])
+def test_batched_apply_on_wave_specialised_angular_grids(base, monkeypatch):
+    """Grid classes whose FP64 angular stage runs the wave-specialised kernel
+    (48 x 64 and 32 x 81 blocks): three Bloch parameters in one launch per
+    stage, work segments crossing problem boundaries, every problem's output
+    against the oracle, and the whole batch against the one-vector kernel
+    (HELIC_ANGULAR_PIPE=0) on the same inputs."""
+    etas = (-0.3, 0.0, 0.25)
+    probs, batch = make_batch(base, etas)
+    monkeypatch.setenv("HELIC_ANGULAR_PIPE", "0")
+    ones = [Problem(base.with_(name=f"{base.name}-one{e:+.3f}", eta=e), V=p.V) for e, p in zip(etas, probs)]
+    batch1 = helic.Batch([q.g for q in ones])
+    monkeypatch.delenv("HELIC_ANGULAR_PIPE")
+    nvec = 5
+    X, xs = pack(batch, probs, nvec, 500)
+    Y = torch.full_like(X, 3.0)
+    Y1 = torch.full_like(X, 3.0)
+    batch.apply(X, Y, nvec, prec="fp64")
+    batch1.apply(X, Y1, nvec, prec="fp64")
+    agree = (torch.abs(Y - Y1).max() / torch.abs(Y1).max()).item()
+    print(f"[batch {base.name}] vs one-vector kernel {agree:.2e}", flush=True)
+    assert agree < 1e-14
+    for i, p in enumerate(probs):
+        ref = oh.apply(p.o, p.V, xs[i])
+        y = unpack(batch, probs, Y, nvec, i)
+        err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+        print(f"[batch {base.name}] problem {i} rel err {err:.2e}", flush=True)
+        assert err <= TOL64, (i, err)
+    batch.close()
+    batch1.close()
+
+
 def test_graph_replay_matches_eager_apply():
     probs, batch = make_batch(TINY, (-0.25, 0.0, 0.25, 0.375))
     nvec = 16
