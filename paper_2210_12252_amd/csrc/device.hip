@@ -38,6 +38,10 @@ namespace helic {
 // widest group; up to 16 steps the table fragments of the wave's next tile
 // are fetched into registers while the current tile's MFMAs run (beyond, the
 // doubled registers cost more occupancy than the prefetch gains).
+// k steps per chunk of the inverse kernel's contraction for the widest
+// groups (more than 16 k steps; see k_radial_inverse).
+constexpr int INV_CH = 2;
+
 // Value of lane l ^ 1 (DPP quad permutation 1, 0, 3, 2; all lanes active).
 __device__ __forceinline__ double swap_lane_pairs(double x) {
   const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
@@ -81,6 +85,8 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   const DGroup gr = groups[gi];
   const DProb& pb = probs[gr.prob];
   const int nks = (gr.Kmax + 3) / 4;
+  constexpr bool CHUNKED = KS > 16;
+  static_assert(KS % INV_CH == 0, "chunks tile the k steps");
   const int kpad = 4 * nks;
   const int ncol = 2 * gr.nmodes;
   const int nct = (ncol + 15) / 16;
@@ -130,16 +136,54 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
       fetch(rt, a);
     }
     // two column tiles at a time: independent accumulators interleave; rows
-    // beyond a mode's own K are zero in Bs
+    // beyond a mode's own K are zero in Bs.  With CHUNKED (the widest groups,
+    // where LDS keeps two workgroups per CU and the one-step form waited on
+    // each MFMA's LDS read) the K of a pair's first tile also bounds its
+    // second's (modes by K descending), so the contraction runs in chunks of
+    // INV_CH steps with no test inside a chunk, the next chunk's B fragments
+    // read while the current chunk's MFMAs run.  The extra steps add exact
+    // zeros: below the group's nks the rows beyond each mode's K are zero,
+    // beyond it the table fragments are (those reads stay on the last row)
     for (int ct = 0; ct < nct; ct += 2) {
       const bool two = ct + 1 < nct;
       const int ks0 = tile_ks(ct);
-      const int ks1 = two ? tile_ks(ct + 1) : 0;
       acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+      if constexpr (CHUNKED) {
+        const int ct1 = two ? ct + 1 : ct;     // a lone last tile reads its own columns twice
+        T bn0[INV_CH], bn1[INV_CH];
+        auto read_chunk = [&](int c) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        if (s < ks0) acc0 = Mfma<T>::op(a[s], bcol[s % BP][4 * s * hs + 16 * ct], acc0);
-        if (s < ks1) acc1 = Mfma<T>::op(a[s], bcol[s % BP][4 * s * hs + 16 * ct + 16], acc1);
+          for (int u = 0; u < INV_CH; ++u) {
+            const int s = INV_CH * c + u;
+            const int sr = s < nks ? s : nks - 1;
+            bn0[u] = bcol[s % BP][4 * sr * hs + 16 * ct];
+            bn1[u] = bcol[s % BP][4 * sr * hs + 16 * ct1];
+          }
+        };
+        if (ks0 > 0) read_chunk(0);
+#pragma unroll
+        for (int c = 0; c < KS / INV_CH; ++c) {
+          if (INV_CH * c >= ks0) break;
+          T b0[INV_CH], b1[INV_CH];
+#pragma unroll
+          for (int u = 0; u < INV_CH; ++u) {
+            b0[u] = bn0[u];
+            b1[u] = bn1[u];
+          }
+          if (c + 1 < KS / INV_CH && INV_CH * (c + 1) < ks0) read_chunk(c + 1);
+#pragma unroll
+          for (int u = 0; u < INV_CH; ++u) {
+            acc0 = Mfma<T>::op(a[INV_CH * c + u], b0[u], acc0);
+            acc1 = Mfma<T>::op(a[INV_CH * c + u], b1[u], acc1);
+          }
+        }
+      } else {
+        const int ks1 = two ? tile_ks(ct + 1) : 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          if (s < ks0) acc0 = Mfma<T>::op(a[s], bcol[s % BP][4 * s * hs + 16 * ct], acc0);
+          if (s < ks1) acc1 = Mfma<T>::op(a[s], bcol[s % BP][4 * s * hs + 16 * ct + 16], acc1);
+        }
       }
       // lanes 2j and 2j + 1 hold re and im of one mode for the same four rows;
       // after a swap across the pair each lane stores two (re, im) pairs
