@@ -837,7 +837,10 @@ void launch_radial_inverse(int ks, int nwg, size_t lds, hipStream_t st, const do
 // workloads; HELIC_FWD_PF_TILES = 4 or 8 overrides.
 int fwd_pf_tiles(bool fp64, int tiles_max) {
   const char* e = std::getenv("HELIC_FWD_PF_TILES");
-  if (e && (e[0] == '4' || e[0] == '8')) return e[0] - '0';
+  if (e && (e[0] == '4' || e[0] == '8' || (fp64 && e[0] == '9'))) return e[0] - '0';
+  // FP64 groups of 33 to 36 tiles (the nanowire's widest): 9 tiles per wave
+  // keep them to one pass over the slab
+  if (fp64 && tiles_max > 8 * (NT / 64) && tiles_max <= 9 * (NT / 64)) return 9;
   return fp64 || tiles_max > 4 * (NT / 64) ? 8 : 4;
 }
 
@@ -851,6 +854,13 @@ void launch_radial_forward(int tmax, int nwg, size_t lds, hipStream_t st, const 
   nwg = radial_grid(order, nwg, ngroups, nvec);
   switch (tmax) {
     case 0:   // pipelined variants (columns staged per lane: 2 or 4 of 64; register tiles per wave)
+      if constexpr (sizeof(T) == 8) {
+        if (tm == 9) {
+          HELIC_LAUNCH((k_radial_forward_pf<T, 2, 9>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
+                             ngroups, n_r, groups, probs, mode, order);
+          break;
+        }
+      }
       if (tm == 8)
         HELIC_LAUNCH((k_radial_forward_pf<T, 2, 8>), dim3(nwg), dim3(NT), lds, st, e0, e1, gh, X, ldx, Y, ldy, nvec,
                            ngroups, n_r, groups, probs, mode, order);
@@ -1212,6 +1222,9 @@ helic_status set_lds_limits() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 4, 8>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  if constexpr (sizeof(T) == 8)
+    HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward_pf<T, 2, 9>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 12>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   HIP_TRY(hipFuncSetAttribute((const void*)k_radial_forward<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
