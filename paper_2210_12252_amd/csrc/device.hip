@@ -38,8 +38,8 @@ namespace helic {
 // widest group; up to 16 steps the table fragments of the wave's next tile
 // are fetched into registers while the current tile's MFMAs run (beyond, the
 // doubled registers cost more occupancy than the prefetch gains).
-// k steps per chunk of the inverse kernel's contraction for the widest
-// groups (more than 16 k steps; see k_radial_inverse).
+// k steps per chunk of the inverse kernel's contraction for the wider
+// groups (more than 12 k steps; see k_radial_inverse).
 constexpr int INV_CH = 2;
 
 // Value of lane l ^ 1 (DPP quad permutation 1, 0, 3, 2; all lanes active).
@@ -85,7 +85,7 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
   const DGroup gr = groups[gi];
   const DProb& pb = probs[gr.prob];
   const int nks = (gr.Kmax + 3) / 4;
-  constexpr bool CHUNKED = KS > 16;
+  constexpr bool CHUNKED = KS > 12;
   static_assert(KS % INV_CH == 0, "chunks tile the k steps");
   const int kpad = 4 * nks;
   const int ncol = 2 * gr.nmodes;
@@ -136,9 +136,10 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
       fetch(rt, a);
     }
     // two column tiles at a time: independent accumulators interleave; rows
-    // beyond a mode's own K are zero in Bs.  With CHUNKED (the widest groups,
-    // where LDS keeps two workgroups per CU and the one-step form waited on
-    // each MFMA's LDS read) the K of a pair's first tile also bounds its
+    // beyond a mode's own K are zero in Bs.  With CHUNKED (groups of more than
+    // 12 k steps, where the one-step form waited on each MFMA's LDS read; with
+    // at most 12 steps four workgroups share a CU and hide it, and a chunk
+    // buffer would not fit their registers) the K of a pair's first tile also bounds its
     // second's (modes by K descending), so the contraction runs in chunks of
     // INV_CH steps with no test inside a chunk, the next chunk's B fragments
     // read while the current chunk's MFMAs run.  The extra steps add exact
