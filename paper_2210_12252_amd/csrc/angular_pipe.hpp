@@ -15,12 +15,13 @@
 // gather or clearing), and the second half (convolution waves, the OG
 // threads of a column on adjacent lanes) does only the convolution.  LDS
 // holds two A blocks (inverse rows' output) and two B blocks (convolution
-// output), laid out (row stride, column swizzle) as in k_angular_fast.  In step s of a radius segment the row waves run the inverse
-// rows of vector s (slab -> A[s % 2], the next vector's slab fetched behind
-// them) and the forward rows of vector s - 2 (B[s % 2] -> slab), while the
-// convolution waves run vector s - 1 (A[(s - 1) % 2] -> B[(s - 1) % 2]); one
-// block barrier closes a step, and a segment of n vectors takes n + 2 steps.
-// On each SIMD a row wave and a convolution wave then share the issue slots.
+// output), laid out (row stride, column swizzle) as in k_angular_fast.  In
+// step s of a radius segment the row waves run the inverse rows of vector s
+// (slab -> A[s % 2], the next vector's slab fetched behind them) and the
+// forward rows of vector s - 2 (B[s % 2] -> slab), while the convolution
+// waves run vector s - 1 (A[(s - 1) % 2] -> B[(s - 1) % 2]); one block
+// barrier closes a step, and a segment of n vectors takes n + 2 steps.  On
+// each SIMD a row wave and a convolution wave then share the issue slots.
 #pragma once
 
 #include "angular_fast.hpp"
