@@ -37,9 +37,9 @@ namespace helic {
 // each wave takes 16-radius tiles.  KS bounds the k steps (of 4) of the
 // widest group; up to 16 steps the table fragments of the wave's next tile
 // are fetched into registers while the current tile's MFMAs run (beyond, the
-// doubled registers cost more occupancy than the prefetch gains).
-// k steps per chunk of the inverse kernel's contraction for the wider
-// groups (more than 12 k steps; see k_radial_inverse).
+// doubled registers cost more occupancy than the prefetch gains).  Groups of
+// more than 12 k steps run the contraction in chunks of INV_CH steps (see the
+// kernel).
 constexpr int INV_CH = 2;
 
 // Value of lane l ^ 1 (DPP quad permutation 1, 0, 3, 2; all lanes active).
@@ -136,15 +136,16 @@ k_radial_inverse(const double* __restrict__ X, int64_t ldx, T* __restrict__ GH, 
       fetch(rt, a);
     }
     // two column tiles at a time: independent accumulators interleave; rows
-    // beyond a mode's own K are zero in Bs.  With CHUNKED (groups of more than
-    // 12 k steps, where the one-step form waited on each MFMA's LDS read; with
-    // at most 12 steps four workgroups share a CU and hide it, and a chunk
-    // buffer would not fit their registers) the K of a pair's first tile also bounds its
-    // second's (modes by K descending), so the contraction runs in chunks of
-    // INV_CH steps with no test inside a chunk, the next chunk's B fragments
-    // read while the current chunk's MFMAs run.  The extra steps add exact
-    // zeros: below the group's nks the rows beyond each mode's K are zero,
-    // beyond it the table fragments are (those reads stay on the last row)
+    // beyond a mode's own K are zero in Bs.  With CHUNKED (groups of more
+    // than 12 k steps, where the one-step form waited on each MFMA's LDS
+    // read; with at most 12 steps four workgroups share a CU and hide it, and
+    // a chunk buffer would not fit their registers) the K of a pair's first
+    // tile also bounds its second's (modes by K descending), so the
+    // contraction runs in chunks of INV_CH steps with no test inside a chunk,
+    // the next chunk's B fragments read while the current chunk's MFMAs run.
+    // The extra steps add exact zeros: below the group's nks the rows beyond
+    // each mode's K are zero, beyond it the table fragments are (those reads
+    // stay on the last row)
     for (int ct = 0; ct < nct; ct += 2) {
       const bool two = ct + 1 < nct;
       const int ks0 = tile_ks(ct);
