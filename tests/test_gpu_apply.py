@@ -324,6 +324,28 @@ def test_pipelined_angular_kernel_parity(workload, n1, n2, ecut, vchunk, monkeyp
     one.close()
 
 
+def test_radial_forward_nine_tiles_per_wave(monkeypatch):
+    """FP64 radial forward on groups of 35 tiles (nanowire geometry, 40
+    radii): 9 output tiles per wave (one pass over the slab, the default
+    there) against 8 (a second pass for the widest groups), bit-identical
+    since every tile's sums are formed in the same order, and the oracle."""
+    w = synth.workload("nanowire-ecut30").with_(name="nanowire-fwd9", n_r=40)
+    c = Case(w)
+    c.upload_V()
+    X = synth.random_block(c.o.mnk, 9, 4245)
+    Xg = c.to_gpu_block(X)
+    Y9 = torch.zeros_like(Xg)
+    Y8 = torch.zeros_like(Xg)
+    c.g.apply_H(Xg, Y9, prec="fp64")
+    monkeypatch.setenv("HELIC_FWD_PF_TILES", "8")
+    c.g.apply_H(Xg, Y8, prec="fp64")
+    monkeypatch.delenv("HELIC_FWD_PF_TILES")
+    assert torch.equal(Y9, Y8)
+    err = _rel(c.from_gpu_block(Y9), oh.apply(c.o, c.V, X))
+    print(f"[forward 9 tiles] rel err {err:.2e}", flush=True)
+    assert err < TOL64
+
+
 def test_general_and_specialised_angular_kernels_agree(tiny, monkeypatch):
     """The general LDS-FFT angular kernel and the specialised convolution
     kernel compute the same operator (both are checked against the oracle
